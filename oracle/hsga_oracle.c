@@ -1,0 +1,623 @@
+/*
+ * hsga_oracle.c -- plain, slow, single-threaded CPU oracle for the island-model
+ * genetic algorithm with hereditary-stratigraphy surface annotations
+ * (Moreno et al., "Trackable Agent-based Evolution Models at Wafer Scale").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * helper with the HIP implementation; both sides implement the Philox4x32-10
+ * generator separately from its published definition.
+ *
+ * Everything here is integer arithmetic; the HIP path must agree bit for bit.
+ *
+ * Where the paper is silent (it leaves the steady and tilted indexing
+ * algorithms undefined, and gives no random-number mapping), this file follows
+ * one fixed reading, stated at each function.  Under that reading:
+ *
+ *   - Philox4x32-10 is pinned by known answers from an independent library
+ *     implementation.
+ *   - The site rule is pinned by brute force against the retention criteria
+ *     that the paper states in words (Methods, "Distributed Phylogenetic
+ *     Tracking" and "Surface-based Hereditary Stratigraphy Algorithms").
+ *   - The GA step has no closed form and no paper run to compare with:
+ *     "parity unpinned" against the paper.  It is pinned by special cases,
+ *     invariants and the pedigree.
+ *   - The MRCA bounds are pinned against the true pedigree on tiny runs.
+ *
+ * Build:  gcc -O2 -std=c11 -shared -fPIC -o liboracle.so hsga_oracle.c
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EMPTY 0xffffffffu
+
+/* surface kinds (policies) */
+enum { ORC_STEADY = 0, ORC_TILTED = 1, ORC_HYBRID = 2 };
+/* purpose tags carried in the fourth Philox counter word */
+enum { ORC_BIRTH = 0, ORC_EMIGRATE = 1, ORC_IMMIGRATE = 2, ORC_SAMPLE = 3 };
+/* torus directions */
+enum { ORC_NORTH = 0, ORC_SOUTH = 1, ORC_WEST = 2, ORC_EAST = 3 };
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random numbers:
+ * as easy as 1, 2, 3").  Ten rounds; each round multiplies counter words 0
+ * and 2 by the two Philox constants, then permutes and mixes in the key; the
+ * key is bumped by the two Weyl constants between rounds.                    */
+void orc_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                uint64_t seed, uint32_t out[4])
+{
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Map a 32-bit word onto [0, n): the high word of w * n. */
+uint32_t orc_mulhi(uint32_t w, uint32_t n)
+{
+    return (uint32_t)(((uint64_t)w * n) >> 32);
+}
+
+static unsigned bitlen64(uint64_t x)
+{
+    unsigned b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+static unsigned ctz64(uint64_t x)
+{
+    unsigned c = 0;
+    while (!(x & 1)) { c++; x >>= 1; }
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Retention target D(u) of one sub-surface with m sites at local time u,
+ * i.e. when item u is being deposited.  Returns 1 when item t (t <= u) is
+ * in D(u).
+ *
+ * Steady policy ("retained time points distributed evenly across history",
+ * Methods, Distributed Phylogenetic Tracking): keep every multiple of the
+ * spacing g(u) = 2^bitlen(floor(u / (m-1))), plus u itself.
+ *
+ * Tilted policy ("more recent time points are preferred", same passage): item
+ * t sits on level h = ctz(t+1), i.e. t+1 = (2c+1) * 2^h.  Level h holds
+ * n_h(u) = (u + 1 + 2^h) >> (h+1) items up to u.  Keep the r = floor(m / B)
+ * most recent items of each level, B = bitlen(u+1) being the number of
+ * levels present.                                                           */
+int orc_in_D(uint32_t policy, uint32_t m, uint64_t u, uint64_t t)
+{
+    if (t > u)
+        return 0;
+    if (policy == ORC_STEADY) {
+        uint64_t q = u / (m - 1);
+        uint64_t spacing = (uint64_t)1 << bitlen64(q);
+        return (t % spacing == 0) || (t == u);
+    } else {
+        unsigned B = bitlen64(u + 1);
+        uint64_t r = m / B;
+        unsigned h = ctz64(t + 1);
+        uint64_t c = (t + 1) >> (h + 1);
+        uint64_t n_h = (u + 1 + ((uint64_t)1 << h)) >> (h + 1);
+        return c + r >= n_h;
+    }
+}
+
+/* Which sub-surface item T goes to, its local time and its first site.
+ * Steady and tilted kinds use one sub-surface of S sites with u = T.  The
+ * hybrid kind gives half of the sites to each policy (same passage): sites
+ * [0, S/2) take the even T with u = T/2 under the steady policy; sites
+ * [S/2, S) take the odd T with u = (T-1)/2 under the tilted policy.          */
+static void sub_surface(uint32_t kind, uint32_t S, uint64_t T,
+                        uint32_t *policy, uint32_t *m, uint64_t *u,
+                        uint32_t *offset)
+{
+    if (kind == ORC_HYBRID) {
+        *m = S / 2;
+        if (T % 2 == 0) {
+            *policy = ORC_STEADY; *u = T / 2; *offset = 0;
+        } else {
+            *policy = ORC_TILTED; *u = (T - 1) / 2; *offset = S / 2;
+        }
+    } else {
+        *policy = kind; *m = S; *u = T; *offset = 0;
+    }
+}
+
+/* Local time of the item stored (as a global deposit time) at a site. */
+static uint64_t local_time(uint32_t kind, uint32_t t_global)
+{
+    return kind == ORC_HYBRID ? (uint64_t)(t_global / 2) : (uint64_t)t_global;
+}
+
+/* Last deposit time T that the rule can place (inclusive).  Tilted needs
+ * r >= 1, i.e. bitlen(u+1) <= m, i.e. u <= 2^m - 2; the 32-bit generation
+ * counter caps every kind at T <= 2^32 - 2 (the child counter is T+1).     */
+uint64_t orc_horizon(uint32_t kind, uint32_t S)
+{
+    uint64_t cap = 0xfffffffeull;
+    uint64_t h = cap;
+    if (kind == ORC_TILTED) {
+        if (S < 33)
+            h = ((uint64_t)1 << S) - 2;
+    } else if (kind == ORC_HYBRID) {
+        uint32_t m = S / 2;
+        if (m < 33) {
+            uint64_t umax = ((uint64_t)1 << m) - 2;   /* last tilted local time */
+            h = 2 * umax + 2;                          /* next odd T is out     */
+        }
+    }
+    return h < cap ? h : cap;
+}
+
+/* Surface placement (Methods, Surface-based Hereditary Stratigraphy
+ * Algorithms): a fixed-width buffer, items stay where they are written until
+ * overwritten, pruning happens by overwrite.  Reading: while the sub-surface
+ * is filling (u < m) item u goes to its own site u; afterwards it goes to the
+ * lowest site whose item has left D(u).  L holds global deposit times.
+ * Returns the site, or -1 if no site is evictable (beyond the horizon).     */
+int orc_place(uint32_t kind, uint32_t S, const uint32_t *L, uint32_t T)
+{
+    uint32_t policy, m, offset;
+    uint64_t u;
+    sub_surface(kind, S, T, &policy, &m, &u, &offset);
+    if (u < m)
+        return (int)(offset + u);
+    for (uint32_t k = 0; k < m; k++) {
+        uint32_t tg = L[offset + k];
+        if (tg == ORC_EMPTY)
+            return (int)(offset + k);
+        if (!orc_in_D(policy, m, u, local_time(kind, tg)))
+            return (int)(offset + k);
+    }
+    return -1;
+}
+
+/* Layout after T ingests (items 0..T-1), by replaying the placements from an
+ * empty surface.  Timestamps are not stored: they follow from the site index
+ * and the elapsed generation count alone (Methods, Distributed Phylogenetic
+ * Tracking).  Returns 0, or -1 beyond the horizon.                          */
+int orc_layout(uint32_t kind, uint32_t S, uint32_t T, uint32_t *L)
+{
+    for (uint32_t k = 0; k < S; k++)
+        L[k] = ORC_EMPTY;
+    for (uint64_t t = 0; t < T; t++) {
+        int site = orc_place(kind, S, L, (uint32_t)t);
+        if (site < 0)
+            return -1;
+        L[site] = (uint32_t)t;
+    }
+    return 0;
+}
+
+/* Sites chosen for items T0 .. T0+n-1, replaying from empty. */
+int orc_site_sequence(uint32_t kind, uint32_t S, uint32_t T0, uint32_t n,
+                      int32_t *sites)
+{
+    uint32_t L[64];
+    if (S > 64 || orc_layout(kind, S, T0, L) != 0)
+        return -1;
+    for (uint32_t j = 0; j < n; j++) {
+        int site = orc_place(kind, S, L, T0 + j);
+        sites[j] = site;
+        if (site < 0)
+            return -1;
+        L[site] = T0 + j;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The island-model GA (Methods, Asynchronous Island-model Genetic Algorithm;
+ * Genome Model).  Islands sit on a W x H torus, island i = y*W + x, agent
+ * a = i*N + j.  An agent record is (trait, generation counter, S one-bit
+ * differentia sites); site k is bit k&31 of surface word k>>5.              */
+typedef struct {
+    uint32_t W, H, N, S, kind, tournament, mut_thr, mut_span, migrants;
+    int32_t mut_lo;
+    uint64_t seed;
+    uint32_t I, A, SW;
+    uint32_t g;                       /* generations elapsed                  */
+    uint32_t *trait, *counter, *surf; /* A, A, A*SW (agent-major)             */
+    uint32_t *src;                    /* pedigree: P_g index of each agent     */
+    int has_outbox;                   /* O_g exists (g > 0 and migration on)   */
+    uint32_t *ob_dir, *ob_trait, *ob_counter, *ob_surf, *ob_src;
+    uint32_t L[64];                   /* run layout L_g (global times)         */
+    /* optional pedigree: for generations 1..ped_gens, parent index in the
+       previous generation and the differentia bit drawn at birth            */
+    uint32_t ped_gens;
+    uint32_t *ped_parent;             /* (ped_gens) * A                        */
+    uint8_t *ped_bit;                 /* (ped_gens) * A                        */
+    /* scratch */
+    uint32_t *q_trait, *q_counter, *q_surf, *q_src;
+    uint32_t *n_trait, *n_counter, *n_surf, *n_src;
+} orc_run;
+
+static uint32_t neighbour(const orc_run *r, uint32_t i, uint32_t d)
+{
+    uint32_t x = i % r->W, y = i / r->W;
+    switch (d) {
+    case ORC_NORTH: y = (y + r->H - 1) % r->H; break;
+    case ORC_SOUTH: y = (y + 1) % r->H; break;
+    case ORC_WEST:  x = (x + r->W - 1) % r->W; break;
+    default:        x = (x + 1) % r->W; break;
+    }
+    return y * r->W + x;
+}
+
+static uint32_t opposite(uint32_t d)
+{
+    return d ^ 1u;   /* north<->south, west<->east */
+}
+
+void orc_destroy(void *handle)
+{
+    orc_run *r = (orc_run *)handle;
+    if (!r)
+        return;
+    free(r->trait); free(r->counter); free(r->surf); free(r->src);
+    free(r->ob_dir); free(r->ob_trait); free(r->ob_counter); free(r->ob_surf);
+    free(r->ob_src);
+    free(r->ped_parent); free(r->ped_bit);
+    free(r->q_trait); free(r->q_counter); free(r->q_surf); free(r->q_src);
+    free(r->n_trait); free(r->n_counter); free(r->n_surf); free(r->n_src);
+    free(r);
+}
+
+/* Founders (generation 0): trait 0, counter 0, empty surface; no outboxes.
+ * Founders carry no differentia: item t is deposited at the birth of the
+ * generation-(t+1) individual (Distributed Phylogenetic Tracking: offspring
+ * receive a new differentia on birth).  Returns NULL on an invalid config.  */
+void *orc_create(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kind,
+                 uint32_t tournament, uint32_t mut_thr, int32_t mut_lo,
+                 int32_t mut_hi, uint32_t migrants, uint64_t seed,
+                 uint32_t ped_gens)
+{
+    if (W == 0 || H == 0 || N == 0 || N > 64 || (S != 32 && S != 64) ||
+        kind > ORC_HYBRID || (tournament != 0 && tournament != 2) ||
+        mut_lo > mut_hi || (int64_t)mut_hi - mut_lo + 1 > 0xffffffffll ||
+        migrants > 1)
+        return NULL;
+    orc_run *r = (orc_run *)calloc(1, sizeof(orc_run));
+    r->W = W; r->H = H; r->N = N; r->S = S; r->kind = kind;
+    r->tournament = tournament; r->mut_thr = mut_thr; r->mut_lo = mut_lo;
+    r->mut_span = (uint32_t)((int64_t)mut_hi - mut_lo + 1);
+    r->migrants = migrants; r->seed = seed;
+    r->I = W * H; r->A = r->I * N; r->SW = S / 32;
+    size_t A = r->A, I = r->I, SW = r->SW;
+    r->trait = calloc(A, 4); r->counter = calloc(A, 4);
+    r->surf = calloc(A * SW, 4); r->src = calloc(A, 4);
+    r->ob_dir = calloc(I, 4); r->ob_trait = calloc(I, 4);
+    r->ob_counter = calloc(I, 4); r->ob_surf = calloc(I * SW, 4);
+    r->ob_src = calloc(I, 4);
+    r->q_trait = calloc(N, 4); r->q_counter = calloc(N, 4);
+    r->q_surf = calloc(N * SW, 4); r->q_src = calloc(N, 4);
+    r->n_trait = calloc(A, 4); r->n_counter = calloc(A, 4);
+    r->n_surf = calloc(A * SW, 4); r->n_src = calloc(A, 4);
+    if (!r->trait || !r->counter || !r->surf || !r->src || !r->ob_dir ||
+        !r->ob_trait || !r->ob_counter || !r->ob_surf || !r->ob_src ||
+        !r->q_trait || !r->q_counter || !r->q_surf || !r->q_src ||
+        !r->n_trait || !r->n_counter || !r->n_surf || !r->n_src) {
+        orc_destroy(r);
+        return NULL;
+    }
+    r->ped_gens = ped_gens;
+    if (ped_gens) {
+        r->ped_parent = calloc((size_t)ped_gens * A, 4);
+        r->ped_bit = calloc((size_t)ped_gens * A, 1);
+        if (!r->ped_parent || !r->ped_bit) {
+            orc_destroy(r);
+            return NULL;
+        }
+    }
+    for (uint32_t a = 0; a < r->A; a++)
+        r->src[a] = a;
+    for (uint32_t k = 0; k < 64; k++)
+        r->L[k] = ORC_EMPTY;
+    r->g = 0;
+    r->has_outbox = 0;
+    return r;
+}
+
+/* One generation, (P_g, O_g) -> (P_{g+1}, O_{g+1}), island by island, in the
+ * paper's order: migration first, then selection, mutation and the
+ * annotation update (Asynchronous Island-model Genetic Algorithm).
+ * Returns 0, -1 beyond the horizon, -2 on a broken invariant.               */
+static int step_one(orc_run *r)
+{
+    const uint32_t N = r->N, SW = r->SW, g = r->g;
+    uint32_t w[4];
+
+    /* The surface site for this generation's births.  Every parent carries
+     * counter g, so every birth deposits item g at the same site: the
+     * placement is computed once for the whole population (Results, Surface
+     * Algorithm Benchmark: synchronous generations can cache placements).   */
+    if ((uint64_t)g > orc_horizon(r->kind, r->S))
+        return -1;
+    int site = orc_place(r->kind, r->S, r->L, g);
+    if (site < 0)
+        return -1;
+
+    for (uint32_t i = 0; i < r->I; i++) {
+        /* Q := this island's members of P_g */
+        for (uint32_t j = 0; j < N; j++) {
+            uint32_t a = i * N + j;
+            r->q_trait[j] = r->trait[a];
+            r->q_counter[j] = r->counter[a];
+            for (uint32_t s = 0; s < SW; s++)
+                r->q_surf[j * SW + s] = r->surf[(size_t)a * SW + s];
+            r->q_src[j] = a;
+        }
+
+        /* Immigration: each neighbour's emigrant that was sent our way
+         * replaces a randomly chosen member; applied north, south, west,
+         * east.  Genomes are copied, not moved.                             */
+        if (r->migrants && r->has_outbox) {
+            orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);
+            for (uint32_t d = 0; d < 4; d++) {
+                uint32_t nb = neighbour(r, i, d);
+                if (r->ob_dir[nb] == opposite(d)) {
+                    uint32_t slot = orc_mulhi(w[d], N);
+                    r->q_trait[slot] = r->ob_trait[nb];
+                    r->q_counter[slot] = r->ob_counter[nb];
+                    for (uint32_t s = 0; s < SW; s++)
+                        r->q_surf[slot * SW + s] = r->ob_surf[(size_t)nb * SW + s];
+                    r->q_src[slot] = r->ob_src[nb];
+                }
+            }
+        }
+
+        /* Births: each slot of the next generation gets a parent by
+         * tournament selection (the higher trait of two uniform draws; a tie
+         * keeps the first draw) or, when neutral, by one uniform draw; the
+         * child copies the parent's record, mutates its trait with
+         * probability mut_thr / 2^32 by a uniform integer in
+         * [mut_lo, mut_hi], increments the generation counter, and writes a
+         * fresh one-bit differentia at this generation's site.              */
+        for (uint32_t j = 0; j < N; j++) {
+            orc_philox(j, i, g, ORC_BIRTH, r->seed, w);
+            uint32_t p = orc_mulhi(w[0], N);
+            if (r->tournament == 2) {
+                uint32_t b = orc_mulhi(w[1], N);
+                if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])
+                    p = b;
+            }
+            uint32_t T = r->q_counter[p];
+            if (T != g)
+                return -2;
+            uint32_t delta = 0;
+            if (w[2] < r->mut_thr)
+                delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
+            uint32_t a = i * N + j;
+            r->n_trait[a] = r->q_trait[p] + delta;
+            r->n_counter[a] = T + 1;
+            for (uint32_t s = 0; s < SW; s++)
+                r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];
+            uint32_t bit = w[3] & 1u;
+            uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / 32];
+            *word = (*word & ~(1u << (site % 32))) | (bit << (site % 32));
+            r->n_src[a] = r->q_src[p];
+            if (g < r->ped_gens) {
+                r->ped_parent[(size_t)g * r->A + a] = r->q_src[p];
+                r->ped_bit[(size_t)g * r->A + a] = (uint8_t)bit;
+            }
+        }
+    }
+
+    /* P_{g+1} becomes current */
+    memcpy(r->trait, r->n_trait, (size_t)r->A * 4);
+    memcpy(r->counter, r->n_counter, (size_t)r->A * 4);
+    memcpy(r->surf, r->n_surf, (size_t)r->A * SW * 4);
+    for (uint32_t a = 0; a < r->A; a++)
+        r->src[a] = a;
+    r->L[site] = g;
+
+    /* Emigration: a copy of a uniformly chosen member of the new population
+     * goes into the island's outbox, addressed to a uniformly chosen
+     * cardinal neighbour; it is read in the next generation.                */
+    if (r->migrants) {
+        for (uint32_t i = 0; i < r->I; i++) {
+            orc_philox(0, i, g, ORC_EMIGRATE, r->seed, w);
+            uint32_t e = orc_mulhi(w[0], N);
+            uint32_t a = i * N + e;
+            r->ob_dir[i] = w[1] >> 30;
+            r->ob_trait[i] = r->trait[a];
+            r->ob_counter[i] = r->counter[a];
+            for (uint32_t s = 0; s < SW; s++)
+                r->ob_surf[(size_t)i * SW + s] = r->surf[(size_t)a * SW + s];
+            r->ob_src[i] = a;
+        }
+        r->has_outbox = 1;
+    }
+    r->g = g + 1;
+    return 0;
+}
+
+/* Advance n generations (the paper's main loop runs until a generation
+ * count is reached).  Returns 0, -1 beyond the horizon, -2 on a broken
+ * invariant, -3 if n would pass the end of the pedigree record.            */
+int orc_step(void *handle, uint32_t n)
+{
+    orc_run *r = (orc_run *)handle;
+    if (r->ped_gens && (uint64_t)r->g + n > r->ped_gens)
+        return -3;
+    for (uint32_t k = 0; k < n; k++) {
+        int rc = step_one(r);
+        if (rc)
+            return rc;
+    }
+    return 0;
+}
+
+uint32_t orc_generation(void *handle) { return ((orc_run *)handle)->g; }
+uint32_t orc_num_agents(void *handle) { return ((orc_run *)handle)->A; }
+
+void orc_read_agents(void *handle, uint32_t *trait, uint32_t *counter,
+                     uint32_t *surf)
+{
+    orc_run *r = (orc_run *)handle;
+    memcpy(trait, r->trait, (size_t)r->A * 4);
+    memcpy(counter, r->counter, (size_t)r->A * 4);
+    memcpy(surf, r->surf, (size_t)r->A * r->SW * 4);
+}
+
+/* Outbox O_g (to be read at step g).  Returns 0 when there is none.        */
+int orc_read_outbox(void *handle, uint32_t *dir, uint32_t *trait,
+                    uint32_t *counter, uint32_t *surf, uint32_t *src)
+{
+    orc_run *r = (orc_run *)handle;
+    if (!r->has_outbox)
+        return 0;
+    memcpy(dir, r->ob_dir, (size_t)r->I * 4);
+    memcpy(trait, r->ob_trait, (size_t)r->I * 4);
+    memcpy(counter, r->ob_counter, (size_t)r->I * 4);
+    memcpy(surf, r->ob_surf, (size_t)r->I * r->SW * 4);
+    if (src)
+        memcpy(src, r->ob_src, (size_t)r->I * 4);
+    return 1;
+}
+
+void orc_read_layout(void *handle, uint32_t *L)
+{
+    orc_run *r = (orc_run *)handle;
+    memcpy(L, r->L, (size_t)r->S * 4);
+}
+
+/* Pedigree of generation gen (1..ped_gens): parent index in P_{gen-1} and
+ * the differentia bit drawn at each birth.                                  */
+int orc_read_pedigree(void *handle, uint32_t gen, uint32_t *parent,
+                      uint8_t *bit)
+{
+    orc_run *r = (orc_run *)handle;
+    if (gen == 0 || gen > r->ped_gens || gen > r->g)
+        return -1;
+    memcpy(parent, r->ped_parent + (size_t)(gen - 1) * r->A, (size_t)r->A * 4);
+    memcpy(bit, r->ped_bit + (size_t)(gen - 1) * r->A, (size_t)r->A);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* End-of-run sampling (Results, On-hardware Trial: end-state genomes are
+ * sampled, then subsampled).  Reading: a stratified sample; agent k is drawn
+ * uniformly from the k-th of n equal strata of the population.  When the
+ * population is not larger than n, every agent is taken.  Returns the
+ * number of indices written.                                                */
+uint32_t orc_sample(uint64_t seed, uint32_t A, uint32_t n, uint32_t T,
+                    uint32_t *idx)
+{
+    if (A <= n) {
+        for (uint32_t k = 0; k < A; k++)
+            idx[k] = k;
+        return A;
+    }
+    uint32_t w[4];
+    for (uint32_t k = 0; k < n; k++) {
+        uint32_t lo = (uint32_t)((uint64_t)k * A / n);
+        uint32_t hi = (uint32_t)((uint64_t)(k + 1) * A / n);
+        orc_philox(k, 0, T, ORC_SAMPLE, seed, w);
+        idx[k] = lo + orc_mulhi(w[0], hi - lo);
+    }
+    return n;
+}
+
+static uint32_t site_bit(const uint32_t *s, uint32_t k)
+{
+    return (s[k / 32] >> (k % 32)) & 1u;
+}
+
+/* MRCA-generation bounds from two annotations (Distributed Phylogenetic
+ * Tracking: mismatching differentiae delimit the extent of common ancestry;
+ * one-bit differentiae can collide and overstate relatedness).
+ *
+ * Written out from the definition: C = the deposit times retained by both
+ * annotations, ascending; t* = the first t in C whose bits differ.  A
+ * mismatch at t shows the two generation-(t+1) ancestors differ, so the
+ * MRCA's generation is at most t*:  ub = t*, or min(Ta, Tb) if nothing
+ * differs.  The last agreeing t before t* (or the last of C) gives
+ * lb = t + 1, or 0 when there is none.  lb assumes no collision.  La and Lb
+ * are the two layouts (orc_layout of each annotation's counter).          */
+int orc_mrca_pair(uint32_t S, uint32_t Ta, const uint32_t *sa,
+                  const uint32_t *La, uint32_t Tb, const uint32_t *sb,
+                  const uint32_t *Lb, uint32_t *lb, uint32_t *ub)
+{
+    /* common deposit times with their sites in each annotation */
+    uint32_t ct[64], ka[64], kb[64];
+    uint32_t nc = 0;
+    for (uint32_t x = 0; x < S; x++) {
+        if (La[x] == ORC_EMPTY)
+            continue;
+        for (uint32_t y = 0; y < S; y++) {
+            if (Lb[y] == La[x]) {
+                ct[nc] = La[x]; ka[nc] = x; kb[nc] = y; nc++;
+                break;
+            }
+        }
+    }
+    /* ascending order of time (insertion sort: at most 64 items) */
+    for (uint32_t p = 1; p < nc; p++) {
+        uint32_t t = ct[p], x = ka[p], y = kb[p];
+        uint32_t q = p;
+        while (q > 0 && ct[q - 1] > t) {
+            ct[q] = ct[q - 1]; ka[q] = ka[q - 1]; kb[q] = kb[q - 1]; q--;
+        }
+        ct[q] = t; ka[q] = x; kb[q] = y;
+    }
+    int have_last = 0;
+    uint32_t last = 0;
+    for (uint32_t p = 0; p < nc; p++) {
+        if (site_bit(sa, ka[p]) != site_bit(sb, kb[p])) {
+            *ub = ct[p];
+            *lb = have_last ? last + 1 : 0;
+            return 0;
+        }
+        have_last = 1;
+        last = ct[p];
+    }
+    *ub = Ta < Tb ? Ta : Tb;
+    *lb = have_last ? last + 1 : 0;
+    return 0;
+}
+
+/* All ordered pairs of n annotations: lb and ub are n*n, row-major (row a,
+ * column b).  Surfaces are agent-major, S/32 words per agent.  Layouts are
+ * replayed per annotation.  Returns 0, or -1 beyond the horizon / no memory. */
+int orc_mrca_allpairs(uint32_t kind, uint32_t S, uint32_t n,
+                      const uint32_t *counters, const uint32_t *surf,
+                      uint32_t *lb, uint32_t *ub)
+{
+    uint32_t SW = S / 32;
+    uint32_t *L = (uint32_t *)malloc((size_t)n * S * 4);
+    if (!L)
+        return -1;
+    for (uint32_t a = 0; a < n; a++) {
+        /* reuse the previous layout when the counter repeats */
+        if (a > 0 && counters[a] == counters[a - 1]) {
+            memcpy(L + (size_t)a * S, L + (size_t)(a - 1) * S, (size_t)S * 4);
+        } else if (orc_layout(kind, S, counters[a], L + (size_t)a * S) != 0) {
+            free(L);
+            return -1;
+        }
+    }
+    for (uint32_t a = 0; a < n; a++)
+        for (uint32_t b = 0; b < n; b++)
+            orc_mrca_pair(S, counters[a], surf + (size_t)a * SW,
+                          L + (size_t)a * S, counters[b], surf + (size_t)b * SW,
+                          L + (size_t)b * S, lb + (size_t)a * n + b,
+                          ub + (size_t)a * n + b);
+    free(L);
+    return 0;
+}
