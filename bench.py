@@ -1,0 +1,218 @@
+"""Benchmark of the island-model GA hot path on one MI355X.
+
+One "step" is one whole run of the paper-scale plain workload: 512x1024
+islands x 32 agents (16.8 M agents), 64-site hybrid surface, tournament of
+two, mutation p = 0.01 in [-8, 8], one migrant per island per generation,
+10,000 generations; then a stratified 4,096-agent sample and its all-pairs
+MRCA-generation bounds (16.8 M pairs).  Inputs are synthetic (the founders
+are generated on the device; the paper's workloads are synthetic too).
+
+Prints one JSON line:
+  value     agent-replications/s over the timed steps (births only)
+  roofline  the step kernel's algorithmic HBM bytes per launch over its
+            average launch duration (HIP events on the run's stream)
+  cpu_baseline  the plain C oracle on a bounded sample of the same
+            workload (the first generations from the founders).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       [--generations G] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_c2_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_10861_amd", "csrc", f)
+                  for f in ("hsga_kernels.hip", "hsga_device.hpp")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_generation(spec) -> int:
+    """Read every parent record, write every child record; each island's
+    outbox entry (record + direction word) is written once and read once."""
+    rec = 8 + spec.surface_sites // 8
+    islands = spec.grid_w * spec.grid_h
+    return 2 * spec.agents * rec + 2 * islands * (rec + 4)
+
+
+def measured_traffic(spec):
+    """HBM bytes per step launch from the committed rocprofv3 counter
+    summary, or None when it is absent or the kernel changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(spec, budget_s: float = 12.0):
+    """The oracle, single-threaded, on the first generations of the same
+    workload until the time budget is spent."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import hsga_oracle as orc
+    if not os.path.exists(orc.LIB):
+        orc.build()
+    r = orc.Run(spec.grid_w, spec.grid_h, spec.pop_per_island, spec.surface_sites,
+                orc.KINDS[spec.surface_kind], spec.tournament_size, spec.mut_threshold,
+                spec.mut_lo, spec.mut_hi, spec.migrants_per_island, spec.seed)
+    gens = 0
+    t0 = time.perf_counter()
+    while True:
+        r.step(1)
+        gens += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or gens >= 200:
+            break
+    r.close()
+    return {
+        "value": spec.agents * gens / el,
+        "unit": "agent-replications/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{spec.name}: the first {gens} generations from the founders "
+                   f"({spec.agents * gens:,} births in {el:.1f} s), plain C oracle, "
+                   "one thread"),
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--generations", type=int, default=0,
+                    help="override the run length (profiling only; not the benchmark)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the runs are single-GPU by design)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2404_10861_amd as hs
+    from paper_2404_10861_amd import workloads as wl
+
+    spec = wl.c2()
+    if args.generations:
+        spec.generations = args.generations
+    n_sample = 4096
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    cfg = hs.Config(**spec.config_kwargs())
+    gens_per_launch = spec.generations
+    need = hs.footprint_bytes(cfg, gens_per_launch)
+    arena = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-arena.data_ptr()) % 256
+    arena_view = arena[off:off + need]
+    ws = hs.MrcaWorkspace(spec.surface_sites, n_sample, dev)
+    lb = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
+    ub = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
+
+    def one_run(timed: bool):
+        run = hs.Run(cfg, max_gens_per_launch=gens_per_launch, device=dev, stream=stream,
+                     arena=arena_view)
+        run.set_kernel_timing(timed)
+        run.step(spec.generations)
+        _, cnt, srf = run.sample(n_sample)
+        hs.mrca_bounds(spec.surface_kind, spec.surface_sites, cnt, srf, workspace=ws,
+                       stream=stream, lb=lb, ub=ub)
+        return run
+
+    for _ in range(args.warmup):
+        r = one_run(False)
+        r.sync()
+        r.close()
+    torch.cuda.synchronize()
+    runs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        runs.append(one_run(True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+
+    kern_ms = 0.0
+    launches = 0
+    for r in runs:
+        ms, n = r.kernel_time()
+        kern_ms += ms
+        launches += n
+        r.close()
+    if hs.mrca_status(ws, stream) != 0:
+        raise RuntimeError("MRCA query reported an error")
+
+    reps = spec.agents * spec.generations * args.steps
+    value = reps / elapsed
+    bytes_per_launch = algorithmic_bytes_per_generation(spec)
+    avg_launch_s = kern_ms / 1000.0 / max(launches, 1)
+    achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
+    line = {
+        "metric": "agent-replications/sec",
+        "value": value,
+        "unit": "agent-replications/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (founders generated on the device from the seed)",
+        "config": {
+            "workload": spec.name,
+            "torus": f"{spec.grid_w}x{spec.grid_h}",
+            "agents": spec.agents,
+            "agents_per_island": spec.pop_per_island,
+            "surface": f"{spec.surface_kind}-{spec.surface_sites}",
+            "generations": spec.generations,
+            "selection": "tournament-2",
+            "mrca_sample": n_sample,
+            "seed": spec.seed,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic(spec),
+            "kernel": "step_kernel<2,true,true>",
+            "avg_launch_us": avg_launch_s * 1e6,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+        "context": {
+            "paper_cs2_replications_per_s": 3.18e11,
+            "paper_note": "Cerebras CS-2, 750x750 PEs x 32 agents, float genome, tournament 5",
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

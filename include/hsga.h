@@ -1,0 +1,221 @@
+/*
+ * hsga.h -- C ABI of libhsga.so: an island-model genetic algorithm whose
+ * agents carry hereditary-stratigraphy surface annotations, run on one
+ * AMD Instinct MI355X (gfx950) with hand-written HIP kernels.
+ *
+ * The method is the one of Moreno et al., "Trackable Agent-based Evolution
+ * Models at Wafer Scale":
+ *   - islands of agents on a 2-D torus exchange migrants with their four
+ *     cardinal neighbours; each generation does migration first, then
+ *     tournament selection, mutation and the annotation update (Methods,
+ *     Asynchronous Island-model Genetic Algorithm);
+ *   - each birth deposits a fresh one-bit differentia into one site of a
+ *     fixed-width "surface" chosen by a steady, tilted or hybrid policy
+ *     (Methods, Distributed Phylogenetic Tracking; Surface-based Hereditary
+ *     Stratigraphy Algorithms);
+ *   - mismatching differentiae of two annotations bound the generation of
+ *     their most recent common ancestor (Distributed Phylogenetic Tracking).
+ *
+ * Conventions shared by every call:
+ *   - Memory.  The library never allocates or frees device memory.  The
+ *     caller owns one device arena per run (sized by ga_footprint_bytes) and
+ *     every other device buffer it passes in.  Host buffers are caller-owned.
+ *   - Streams.  hip_stream is a hipStream_t borrowed from the caller (NULL
+ *     means the null stream).  Device work is enqueued on it and returns
+ *     without waiting, unless a call says it blocks.
+ *   - Errors.  Every int-returning call returns a ga_status.  Nothing
+ *     aborts or throws across the ABI.  ga_last_error() gives the text of
+ *     the calling thread's last failure.
+ *   - Threading.  A run handle is used by one host thread at a time.
+ *   - Determinism.  Results are a function of the configuration and the
+ *     seed alone.  They do not depend on launch shapes, chunking or timing.
+ */
+#ifndef HSGA_H
+#define HSGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GA_OK = 0,
+    GA_EINVAL = -1,    /* invalid argument or configuration                */
+    GA_ENOMEM = -2,    /* caller-provided buffer or arena too small        */
+    GA_EHORIZON = -3,  /* the site rule cannot place that many generations */
+    GA_EDEVICE = -4,   /* a HIP call failed (text in ga_last_error)        */
+    GA_EBUSY = -5      /* pool admission refused: footprint does not fit   */
+} ga_status;
+
+/* Surface site-selection policy (Distributed Phylogenetic Tracking):
+ * steady spreads retained time points evenly over history, tilted prefers
+ * recent ones, hybrid gives half of the sites to each.                     */
+typedef enum { GA_STEADY = 0, GA_TILTED = 1, GA_HYBRID = 2 } ga_surface_kind;
+
+/* Marker for a surface site that holds no differentia yet. */
+#define GA_EMPTY_SITE 0xffffffffu
+
+typedef struct ga_config {
+    uint32_t struct_size;         /* sizeof(ga_config)                         */
+    uint32_t grid_w, grid_h;      /* torus of islands; island i = y*w + x      */
+    uint32_t pop_per_island;      /* N agents per island, 1..64                */
+    uint32_t surface_sites;       /* S one-bit sites: 32 or 64                 */
+    uint32_t surface_kind;        /* ga_surface_kind                           */
+    uint32_t tournament_size;     /* 2 = tournament of two; 0 = neutral        */
+    uint32_t mut_threshold;       /* mutate iff a uniform 32-bit word is below
+                                     this; p = 0.01 -> 42949672               */
+    int32_t mut_lo, mut_hi;       /* inclusive trait-delta range, e.g. -8, 8   */
+    uint32_t migrants_per_island; /* 1, or 0 to switch migration off           */
+    uint32_t reserved;            /* must be 0                                 */
+    uint64_t seed;                /* Philox4x32-10 key                         */
+} ga_config;
+
+typedef struct ga_run ga_run;
+
+/* ------------------------------------------------------------------------
+ * Runs (Asynchronous Island-model Genetic Algorithm; Genome Model).
+ *
+ * Device state of a run, carved from the caller's arena:
+ *   - two ping-pong populations, structure of arrays: trait[A],
+ *     counter[A], surface word planes [S/32][A] (A = w*h*N agents);
+ *   - two ping-pong outboxes, one 32-byte entry per island;
+ *   - the run's surface layout (deposit time of each site) and a site
+ *     schedule of max_gens_per_launch words.
+ * An agent record is (uint32 trait, uint32 generation counter, S one-bit
+ * differentia sites); site k is bit k&31 of surface word k>>5.
+ * ------------------------------------------------------------------------ */
+
+/* Arena bytes needed by ga_create for this configuration; 0 if invalid.
+ * max_gens_per_launch bounds the generations ga_step schedules at once
+ * (0 selects the default of 4096).                                         */
+size_t ga_footprint_bytes(const ga_config *cfg, uint32_t max_gens_per_launch);
+
+/* Validate cfg, carve the arena (dev_arena: device pointer, 256-byte
+ * aligned, arena_bytes >= ga_footprint_bytes) and enqueue the founders on
+ * hip_stream: trait 0, counter 0, all sites 0, empty layout, no outboxes.
+ * Founders carry no differentia; generation g's births deposit item g.
+ * Errors: GA_EINVAL (S not 32/64, N = 0 or > 64, empty grid, mut_lo >
+ * mut_hi, tournament not 0/2, migrants > 1, reserved != 0), GA_ENOMEM
+ * (arena too small), GA_EDEVICE.  *out is owned by the caller until
+ * ga_destroy.                                                              */
+int ga_create(const ga_config *cfg, void *dev_arena, size_t arena_bytes,
+              uint32_t max_gens_per_launch, void *hip_stream, ga_run **out);
+
+/* Enqueue n generations (the paper's main loop halts on a generation
+ * count).  Each generation, island by island: immigrants from the previous
+ * generation's outboxes replace random members (north, south, west, east
+ * order); every slot of the next population is born from a tournament (or
+ * neutral) parent, with trait mutation and one differentia written at the
+ * site the surface policy picks for this generation; then a copy of a
+ * random new member is posted to a random neighbour.  Returns at once.
+ * Errors: GA_EHORIZON if generation T + n - 1 is past the site rule's
+ * horizon (nothing is enqueued), GA_EDEVICE.                               */
+int ga_step(ga_run *run, uint32_t n);
+
+/* Block until all work enqueued for the run has finished. */
+int ga_sync(ga_run *run);
+
+/* Generations enqueued so far (the counter value of every agent). */
+int ga_generation(const ga_run *run, uint32_t *T);
+
+/* Blocking copy of agents [first, first + count) of the current
+ * population into host buffers: trait[count], counter[count],
+ * surface_words[count * S/32] (agent-major).  Any pointer may be NULL.
+ * Errors: GA_EINVAL (range), GA_EDEVICE.                                   */
+int ga_read_agents(ga_run *run, uint32_t first, uint32_t count,
+                   uint32_t *trait, uint32_t *counter, uint32_t *surface_words);
+
+/* Blocking copy of the outbox entries [first, first + count) that the next
+ * generation will read: destination direction (0 north, 1 south, 2 west,
+ * 3 east), and the emigrant's trait, counter and surface words (agent-
+ * major).  *valid is 0 when no outbox exists yet (generation 0, or
+ * migration off); the buffers are then untouched.                         */
+int ga_read_outbox(ga_run *run, uint32_t first, uint32_t count,
+                   uint32_t *dir, uint32_t *trait, uint32_t *counter,
+                   uint32_t *surface_words, int *valid);
+
+/* Blocking copy of the run's layout: the deposit time held by each of the
+ * S sites, GA_EMPTY_SITE if none (Distributed Phylogenetic Tracking:
+ * timestamps follow from the site index and the generation count).        */
+int ga_read_layout(ga_run *run, uint32_t *layout);
+
+/* Enqueue a stratified sample of the current population (Results,
+ * On-hardware Trial: end-state genomes are sampled): agent k is drawn
+ * uniformly from the k-th of n equal strata; if the population has at
+ * most n agents, all of them are taken in order.  Writes device buffers
+ * idx[n_taken], counter[n_taken], surface_words[n_taken * S/32]
+ * (agent-major), the input layout of hstrat_mrca_bounds.  *n_taken (host)
+ * is min(n, A).  Errors: GA_EINVAL (n = 0 or NULL buffers), GA_EDEVICE.    */
+int ga_sample(ga_run *run, uint32_t n, uint32_t *dev_idx, uint32_t *dev_counter,
+              uint32_t *dev_surface_words, uint32_t *n_taken);
+
+/* Release the host handle.  Does not free (or touch) the arena; work still
+ * enqueued on the stream keeps using it, so sync first when reusing it.    */
+void ga_destroy(ga_run *run);
+
+/* Text of the calling thread's last failure ("" if none). */
+const char *ga_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * MRCA-generation bounds (Distributed Phylogenetic Tracking: mismatching
+ * differentiae delimit the extent of common ancestry; Results, Clade
+ * Reconstruction Trial: one-bit differentiae overstate relatedness).
+ *
+ * For annotations a, b with counters Ta, Tb: C = deposit times retained by
+ * both (ascending), t* = the first t in C where the bits differ.
+ *   ub = t*, or min(Ta, Tb) if no retained bit differs;
+ *   lb = 1 + the last t in C before t* (the last of C if no mismatch),
+ *        or 0 if there is none.
+ * ub never falls below the true MRCA generation; lb does only when a
+ * one-bit differentia matched by chance.  An annotation against itself
+ * gives (T, T).
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes hstrat_mrca_bounds needs for n annotations. */
+size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n);
+
+/* Enqueue all n*n ordered pairs.  counter: device, n words; surface_words:
+ * device, n * S/32 words, agent-major; lb, ub: device, n*n words each,
+ * row-major (row a, column b); workspace: device, 256-byte aligned,
+ * >= hstrat_mrca_workspace_bytes(S, n).  Annotations must share kind and S.
+ * Counters may differ; when all are equal a faster route is taken on the
+ * device, with identical results.  Errors: GA_EINVAL (kind, S, n = 0,
+ * NULL pointers), GA_ENOMEM (workspace too small), GA_EHORIZON (a counter
+ * past the horizon is reported through the flag word at the start of the
+ * workspace, see hstrat_mrca_status), GA_EDEVICE.                          */
+int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n,
+                       const uint32_t *counter, const uint32_t *surface_words,
+                       uint32_t *lb, uint32_t *ub, void *workspace,
+                       size_t workspace_bytes, void *hip_stream);
+
+/* Blocking: status of the last hstrat_mrca_bounds run on this workspace
+ * (GA_OK, or GA_EHORIZON when a counter was past the horizon, in which
+ * case lb/ub are unspecified).                                             */
+int hstrat_mrca_status(const void *workspace, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Instrumentation
+ * ------------------------------------------------------------------------ */
+
+/* Enable (1) or disable (0) HIP-event timing of the step kernel launches
+ * of this run.  Events bracket each batch of consecutive step launches on
+ * the run's stream.                                                        */
+int ga_set_kernel_timing(ga_run *run, int enable);
+
+/* Blocking: total milliseconds and number of step-kernel launches timed
+ * since timing was enabled (or last reset with reset = 1).                 */
+int ga_kernel_time(ga_run *run, double *ms, uint64_t *launches, int reset);
+
+/* Launch shape the run uses: islands per wavefront (1..32) and
+ * workgroup size in threads (64..1024, multiple of 64); 0 keeps the
+ * current value.  Results do not depend on it.                             */
+int ga_set_launch_shape(ga_run *run, uint32_t islands_per_wave,
+                        uint32_t block_threads);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSGA_H */

@@ -621,3 +621,38 @@ int orc_mrca_allpairs(uint32_t kind, uint32_t S, uint32_t n,
     free(L);
     return 0;
 }
+
+/* Selected rows of the all-pairs matrix: lb and ub are nrows * n, row r
+ * holding annotation rows[r] against every annotation b.  Same definition
+ * as orc_mrca_allpairs; used to check sampled outputs of large matrices.  */
+int orc_mrca_rows(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,
+                  const uint32_t *surf, uint32_t nrows, const uint32_t *rows,
+                  uint32_t *lb, uint32_t *ub)
+{
+    uint32_t SW = S / 32;
+    uint32_t *L = (uint32_t *)malloc((size_t)n * S * 4);
+    if (!L)
+        return -1;
+    for (uint32_t a = 0; a < n; a++) {
+        if (a > 0 && counters[a] == counters[a - 1]) {
+            memcpy(L + (size_t)a * S, L + (size_t)(a - 1) * S, (size_t)S * 4);
+        } else if (orc_layout(kind, S, counters[a], L + (size_t)a * S) != 0) {
+            free(L);
+            return -1;
+        }
+    }
+    for (uint32_t r = 0; r < nrows; r++) {
+        uint32_t a = rows[r];
+        if (a >= n) {
+            free(L);
+            return -1;
+        }
+        for (uint32_t b = 0; b < n; b++)
+            orc_mrca_pair(S, counters[a], surf + (size_t)a * SW,
+                          L + (size_t)a * S, counters[b], surf + (size_t)b * SW,
+                          L + (size_t)b * S, lb + (size_t)r * n + b,
+                          ub + (size_t)r * n + b);
+    }
+    free(L);
+    return 0;
+}

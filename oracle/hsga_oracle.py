@@ -97,6 +97,9 @@ def load():
     lib.orc_mrca_allpairs.argtypes = [ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_uint32, u32p, u32p, u32p, u32p]
     lib.orc_mrca_allpairs.restype = ctypes.c_int
+    lib.orc_mrca_rows.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                  u32p, u32p, ctypes.c_uint32, u32p, u32p, u32p]
+    lib.orc_mrca_rows.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -258,6 +261,21 @@ def mrca_allpairs(kind: int, S: int, counters, surfaces):
                                   _p(lb), _p(ub))
     if rc:
         raise ValueError("beyond the horizon")
+    return lb, ub
+
+
+def mrca_rows(kind: int, S: int, counters, surfaces, rows):
+    """Rows `rows` of the all-pairs matrices (len(rows) x n)."""
+    counters = np.ascontiguousarray(counters, np.uint32)
+    surfaces = np.ascontiguousarray(surfaces, np.uint32).reshape(-1)
+    rows = np.ascontiguousarray(rows, np.uint32)
+    n = counters.shape[0]
+    lb = np.zeros((len(rows), n), np.uint32)
+    ub = np.zeros((len(rows), n), np.uint32)
+    rc = load().orc_mrca_rows(kind, S, n, _p(counters), _p(surfaces), len(rows), _p(rows),
+                              _p(lb), _p(ub))
+    if rc:
+        raise ValueError("beyond the horizon or row out of range")
     return lb, ub
 
 

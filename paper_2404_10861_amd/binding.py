@@ -1,0 +1,331 @@
+"""ctypes binding of libhsga.so (declared in include/hsga.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory (uint8 arenas, output tensors)
+and streams.  There is no CPU fallback: loading fails loudly when the built
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch  # imported first: the library then binds to torch's HIP runtime
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhsga.so")
+
+GA_OK, GA_EINVAL, GA_ENOMEM, GA_EHORIZON, GA_EDEVICE, GA_EBUSY = 0, -1, -2, -3, -4, -5
+STEADY, TILTED, HYBRID = 0, 1, 2
+KINDS = {"steady": STEADY, "tilted": TILTED, "hybrid": HYBRID}
+EMPTY_SITE = 0xFFFFFFFF
+
+# Every exported entry point of include/hsga.h.
+EXPORTS = (
+    "ga_footprint_bytes", "ga_create", "ga_step", "ga_sync", "ga_generation",
+    "ga_read_agents", "ga_read_outbox", "ga_read_layout", "ga_sample",
+    "ga_destroy", "ga_last_error", "hstrat_mrca_workspace_bytes",
+    "hstrat_mrca_bounds", "hstrat_mrca_status", "ga_set_kernel_timing",
+    "ga_kernel_time", "ga_set_launch_shape",
+)
+
+
+class HsgaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class ga_config(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("grid_w", ctypes.c_uint32),
+        ("grid_h", ctypes.c_uint32),
+        ("pop_per_island", ctypes.c_uint32),
+        ("surface_sites", ctypes.c_uint32),
+        ("surface_kind", ctypes.c_uint32),
+        ("tournament_size", ctypes.c_uint32),
+        ("mut_threshold", ctypes.c_uint32),
+        ("mut_lo", ctypes.c_int32),
+        ("mut_hi", ctypes.c_int32),
+        ("migrants_per_island", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_vp = ctypes.c_void_p
+
+
+def load_library():
+    """Load libhsga.so (built in-tree by paper_2404_10861_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"HIP library not built: {LIB_PATH}; run python -m paper_2404_10861_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    cfgp = ctypes.POINTER(ga_config)
+    sig = {
+        "ga_footprint_bytes": (ctypes.c_size_t, [cfgp, ctypes.c_uint32]),
+        "ga_create": (ctypes.c_int, [cfgp, _vp, ctypes.c_size_t, ctypes.c_uint32, _vp,
+                                     ctypes.POINTER(_vp)]),
+        "ga_step": (ctypes.c_int, [_vp, ctypes.c_uint32]),
+        "ga_sync": (ctypes.c_int, [_vp]),
+        "ga_generation": (ctypes.c_int, [_vp, _u32p]),
+        "ga_read_agents": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp]),
+        "ga_read_outbox": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp,
+                                          _vp, ctypes.POINTER(ctypes.c_int)]),
+        "ga_read_layout": (ctypes.c_int, [_vp, _vp]),
+        "ga_sample": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _u32p]),
+        "ga_destroy": (None, [_vp]),
+        "ga_last_error": (ctypes.c_char_p, []),
+        "hstrat_mrca_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
+        "hstrat_mrca_bounds": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                              _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "hstrat_mrca_status": (ctypes.c_int, [_vp, _vp]),
+        "ga_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "ga_kernel_time": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
+        "ga_set_launch_shape": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != GA_OK:
+        raise HsgaError(rc, load_library().ga_last_error().decode())
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _ptr(arr: np.ndarray):
+    return arr.ctypes.data_as(_vp)
+
+
+@dataclass
+class Config:
+    """GA configuration (ga_config).  Kinds: 'steady', 'tilted', 'hybrid'."""
+    grid_w: int
+    grid_h: int
+    pop_per_island: int = 32
+    surface_sites: int = 32
+    surface_kind: str = "steady"
+    tournament_size: int = 2
+    mut_threshold: int = 42949672
+    mut_lo: int = -8
+    mut_hi: int = 8
+    migrants_per_island: int = 1
+    seed: int = 1
+
+    @property
+    def kind(self) -> int:
+        return KINDS[self.surface_kind]
+
+    @property
+    def islands(self) -> int:
+        return self.grid_w * self.grid_h
+
+    @property
+    def agents(self) -> int:
+        return self.islands * self.pop_per_island
+
+    def to_c(self) -> ga_config:
+        c = ga_config()
+        c.struct_size = ctypes.sizeof(ga_config)
+        c.grid_w, c.grid_h = self.grid_w, self.grid_h
+        c.pop_per_island = self.pop_per_island
+        c.surface_sites = self.surface_sites
+        c.surface_kind = self.kind
+        c.tournament_size = self.tournament_size
+        c.mut_threshold = self.mut_threshold
+        c.mut_lo, c.mut_hi = self.mut_lo, self.mut_hi
+        c.migrants_per_island = self.migrants_per_island
+        c.reserved = 0
+        c.seed = self.seed
+        return c
+
+
+def footprint_bytes(cfg: Config, max_gens_per_launch: int = 0) -> int:
+    c = cfg.to_c()
+    n = load_library().ga_footprint_bytes(ctypes.byref(c), max_gens_per_launch)
+    if n == 0:
+        raise HsgaError(GA_EINVAL, load_library().ga_last_error().decode())
+    return int(n)
+
+
+def _aligned_bytes(nbytes: int, device) -> tuple:
+    """A uint8 device tensor with a 256-byte aligned window of nbytes."""
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+class Run:
+    """One GA run on the GPU; the arena is a torch uint8 tensor it owns
+    (or the caller's, via ``arena``)."""
+
+    def __init__(self, cfg: Config, max_gens_per_launch: int = 0, device="cuda",
+                 stream=None, arena: torch.Tensor | None = None):
+        lib = load_library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        need = footprint_bytes(cfg, max_gens_per_launch)
+        if arena is None:
+            self._arena, ptr = _aligned_bytes(need, self.device)
+            nbytes = need
+        else:
+            if arena.dtype != torch.uint8 or not arena.is_cuda:
+                raise ValueError("arena must be a CUDA uint8 tensor")
+            self._arena, ptr, nbytes = arena, arena.data_ptr(), arena.numel()
+        self._c = cfg.to_c()
+        h = _vp()
+        _check(lib.ga_create(ctypes.byref(self._c), _vp(ptr), nbytes, max_gens_per_launch,
+                             _vp(_stream_handle(self.stream)), ctypes.byref(h)))
+        self._h = h
+        self.S = cfg.surface_sites
+        self.SW = self.S // 32
+        self.A = cfg.agents
+        self.I = cfg.islands
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ga_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def generation(self) -> int:
+        T = ctypes.c_uint32()
+        _check(load_library().ga_generation(self._h, ctypes.byref(T)))
+        return T.value
+
+    def step(self, n: int = 1):
+        _check(load_library().ga_step(self._h, n))
+
+    def sync(self):
+        _check(load_library().ga_sync(self._h))
+
+    def agents(self, first: int = 0, count: int | None = None):
+        """(trait, counter, surface[count, S/32]) as numpy uint32 (blocking)."""
+        if count is None:
+            count = self.A - first
+        t = np.zeros(count, np.uint32)
+        c = np.zeros(count, np.uint32)
+        s = np.zeros((count, self.SW), np.uint32)
+        _check(load_library().ga_read_agents(self._h, first, count, _ptr(t), _ptr(c), _ptr(s)))
+        return t, c, s
+
+    def outbox(self, first: int = 0, count: int | None = None):
+        """(dir, trait, counter, surface[count, S/32]) or None (blocking)."""
+        if count is None:
+            count = self.I - first
+        d = np.zeros(count, np.uint32)
+        t = np.zeros(count, np.uint32)
+        c = np.zeros(count, np.uint32)
+        s = np.zeros((count, self.SW), np.uint32)
+        valid = ctypes.c_int()
+        _check(load_library().ga_read_outbox(self._h, first, count, _ptr(d), _ptr(t), _ptr(c),
+                                             _ptr(s), ctypes.byref(valid)))
+        return (d, t, c, s) if valid.value else None
+
+    def layout(self) -> np.ndarray:
+        L = np.zeros(self.S, np.uint32)
+        _check(load_library().ga_read_layout(self._h, _ptr(L)))
+        return L
+
+    def sample(self, n: int):
+        """Stratified sample on the device: (idx, counter, surface[n, S/32])
+        as int32 CUDA tensors holding the uint32 bit patterns."""
+        idx = torch.empty(n, dtype=torch.int32, device=self.device)
+        cnt = torch.empty(n, dtype=torch.int32, device=self.device)
+        srf = torch.empty((n, self.SW), dtype=torch.int32, device=self.device)
+        taken = ctypes.c_uint32()
+        _check(load_library().ga_sample(self._h, n, _vp(idx.data_ptr()), _vp(cnt.data_ptr()),
+                                        _vp(srf.data_ptr()), ctypes.byref(taken)))
+        k = taken.value
+        return idx[:k], cnt[:k], srf[:k]
+
+    def set_kernel_timing(self, enable: bool = True):
+        _check(load_library().ga_set_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_time(self, reset: bool = False):
+        """(milliseconds, launches) of the timed step kernels (blocking)."""
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        _check(load_library().ga_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n),
+                                             1 if reset else 0))
+        return ms.value, n.value
+
+    def set_launch_shape(self, islands_per_wave: int = 0, block_threads: int = 0):
+        _check(load_library().ga_set_launch_shape(self._h, islands_per_wave, block_threads))
+
+
+class MrcaWorkspace:
+    """Device workspace for mrca_bounds, reusable across calls."""
+
+    def __init__(self, S: int, n: int, device="cuda"):
+        need = int(load_library().hstrat_mrca_workspace_bytes(S, n))
+        self._buf, self.ptr = _aligned_bytes(need, device)
+        self.nbytes = need
+        self.S, self.n = S, n
+
+
+def mrca_bounds(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
+                workspace: MrcaWorkspace | None = None, stream=None,
+                lb: torch.Tensor | None = None, ub: torch.Tensor | None = None):
+    """All ordered pairs of MRCA-generation bounds on the device.
+
+    counter: int32 CUDA tensor [n] (uint32 bit patterns); surface_words:
+    int32 CUDA tensor [n, S/32].  Returns (lb, ub) int32 CUDA tensors [n, n].
+    """
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    n = counter.shape[0]
+    dev = counter.device
+    if counter.dtype != torch.int32 or surface_words.dtype != torch.int32:
+        raise ValueError("counter and surface_words must be int32 tensors")
+    counter = counter.contiguous()
+    surface_words = surface_words.contiguous()
+    if workspace is None or workspace.n < n or workspace.S != S:
+        workspace = MrcaWorkspace(S, n, dev)
+    if lb is None:
+        lb = torch.empty((n, n), dtype=torch.int32, device=dev)
+    if ub is None:
+        ub = torch.empty((n, n), dtype=torch.int32, device=dev)
+    lib = load_library()
+    _check(lib.hstrat_mrca_bounds(kind, S, n, _vp(counter.data_ptr()),
+                                  _vp(surface_words.data_ptr()), _vp(lb.data_ptr()),
+                                  _vp(ub.data_ptr()), _vp(workspace.ptr), workspace.nbytes,
+                                  _vp(_stream_handle(stream))))
+    return lb, ub
+
+
+def mrca_status(workspace: MrcaWorkspace, stream=None) -> int:
+    rc = load_library().hstrat_mrca_status(_vp(workspace.ptr), _vp(_stream_handle(stream)))
+    return rc
+
+
+def as_u32(t: torch.Tensor) -> np.ndarray:
+    """Device int32 tensor -> host numpy uint32 (bit-preserving)."""
+    return t.detach().cpu().numpy().view(np.uint32)

@@ -1,0 +1,419 @@
+// hsga_api.cpp -- the C ABI of libhsga.so (include/hsga.h): configuration
+// checks, arena carving, launch sequencing and error reporting.  All
+// arithmetic of the method runs in the kernels of hsga_kernels.hip; this
+// file only validates, carves memory and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hsga.h"
+#include "hsga_device.hpp"
+#include "hsga_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(GA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr uint32_t kDefaultGens = 4096;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carve {
+    size_t trait, counter, surf, outbox, layout, sites, total;
+};
+
+// Byte offsets of each buffer in the arena.
+Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens) {
+    const size_t A = (size_t)I * N;
+    const size_t SW = S / 32;
+    Carve c;
+    size_t off = 0;
+    c.trait = off;   off += 2 * align_up(A * 4);
+    c.counter = off; off += 2 * align_up(A * 4);
+    c.surf = off;    off += 2 * align_up(SW * A * 4);
+    c.outbox = off;  off += 2 * align_up((size_t)I * hsga::kOutboxWords * 4);
+    c.layout = off;  off += align_up(64 * 4);
+    c.sites = off;   off += align_up((size_t)gens * 4);
+    c.total = off;
+    return c;
+}
+
+int validate(const ga_config* cfg) {
+    if (!cfg) return fail(GA_EINVAL, "config is NULL");
+    if (cfg->struct_size != sizeof(ga_config))
+        return fail(GA_EINVAL, "config struct_size does not match this library");
+    if (cfg->grid_w == 0 || cfg->grid_h == 0) return fail(GA_EINVAL, "empty torus");
+    if (cfg->grid_w > 65535 || cfg->grid_h > 65535)
+        return fail(GA_EINVAL, "torus side above 65535 islands");
+    if (cfg->pop_per_island == 0 || cfg->pop_per_island > 64)
+        return fail(GA_EINVAL, "pop_per_island must be 1..64");
+    const uint64_t A = (uint64_t)cfg->grid_w * cfg->grid_h * cfg->pop_per_island;
+    if (A > (1ull << 30)) return fail(GA_EINVAL, "more than 2^30 agents");
+    if (cfg->surface_sites != 32 && cfg->surface_sites != 64)
+        return fail(GA_EINVAL, "surface_sites must be 32 or 64");
+    if (cfg->surface_kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
+    if (cfg->tournament_size != 0 && cfg->tournament_size != 2)
+        return fail(GA_EINVAL, "tournament_size must be 2 (tournament) or 0 (neutral)");
+    if (cfg->mut_lo > cfg->mut_hi) return fail(GA_EINVAL, "mut_lo > mut_hi");
+    if ((int64_t)cfg->mut_hi - cfg->mut_lo + 1 > 0xffffffffll)
+        return fail(GA_EINVAL, "mutation range wider than 2^32 - 1");
+    if (cfg->migrants_per_island > 1) return fail(GA_EINVAL, "migrants_per_island must be 0 or 1");
+    if (cfg->reserved != 0) return fail(GA_EINVAL, "reserved must be 0");
+    return GA_OK;
+}
+
+}  // namespace
+
+struct ga_run {
+    ga_config cfg;
+    uint32_t I, A, N, S, SW;
+    hipStream_t stream;
+    uint32_t* trait[2];
+    uint32_t* counter[2];
+    uint32_t* surf[2];
+    uint32_t* outbox[2];
+    uint32_t* layout;
+    uint32_t* sites;
+    uint32_t gens;       // site schedule capacity
+    uint32_t T;          // generations enqueued
+    uint64_t horizon;
+    uint32_t K;          // islands per wavefront
+    uint32_t block;      // workgroup threads
+    bool timing;
+    struct Span { hipEvent_t start, stop; uint32_t launches; };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> spare;
+};
+
+namespace {
+
+hipEvent_t take_event(ga_run* r) {
+    if (!r->spare.empty()) {
+        hipEvent_t e = r->spare.back();
+        r->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+uint32_t default_islands_per_wave(uint32_t N) {
+    (void)N;
+    return 32;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ga_footprint_bytes(const ga_config* cfg, uint32_t max_gens_per_launch) {
+    if (validate(cfg) != GA_OK) return 0;
+    const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
+    return carve(cfg->grid_w * cfg->grid_h, cfg->pop_per_island, cfg->surface_sites, gens).total;
+}
+
+int ga_create(const ga_config* cfg, void* dev_arena, size_t arena_bytes,
+              uint32_t max_gens_per_launch, void* hip_stream, ga_run** out) {
+    if (!out) return fail(GA_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc != GA_OK) return rc;
+    if (!dev_arena) return fail(GA_EINVAL, "arena is NULL");
+    if ((uintptr_t)dev_arena % kAlign) return fail(GA_EINVAL, "arena not 256-byte aligned");
+    const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
+    const uint32_t I = cfg->grid_w * cfg->grid_h;
+    const Carve c = carve(I, cfg->pop_per_island, cfg->surface_sites, gens);
+    if (arena_bytes < c.total)
+        return fail(GA_ENOMEM, "arena of " + std::to_string(arena_bytes) + " bytes, need " +
+                                   std::to_string(c.total));
+    ga_run* r = new (std::nothrow) ga_run();
+    if (!r) return fail(GA_ENOMEM, "host allocation failed");
+    r->cfg = *cfg;
+    r->I = I;
+    r->N = cfg->pop_per_island;
+    r->A = I * r->N;
+    r->S = cfg->surface_sites;
+    r->SW = r->S / 32;
+    r->stream = static_cast<hipStream_t>(hip_stream);
+    uint8_t* base = static_cast<uint8_t*>(dev_arena);
+    const size_t A = r->A;
+    for (int b = 0; b < 2; ++b) {
+        r->trait[b] = reinterpret_cast<uint32_t*>(base + c.trait + b * align_up(A * 4));
+        r->counter[b] = reinterpret_cast<uint32_t*>(base + c.counter + b * align_up(A * 4));
+        r->surf[b] = reinterpret_cast<uint32_t*>(base + c.surf + b * align_up(r->SW * A * 4));
+        r->outbox[b] = reinterpret_cast<uint32_t*>(
+            base + c.outbox + b * align_up((size_t)I * hsga::kOutboxWords * 4));
+    }
+    r->layout = reinterpret_cast<uint32_t*>(base + c.layout);
+    r->sites = reinterpret_cast<uint32_t*>(base + c.sites);
+    r->gens = gens;
+    r->T = 0;
+    r->horizon = hsga::horizon_of(cfg->surface_kind, r->S);
+    r->K = default_islands_per_wave(r->N);
+    r->block = 256;
+    r->timing = false;
+    hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
+                                         r->layout, r->S, r->stream);
+    if (e != hipSuccess) {
+        delete r;
+        return hip_fail(e, "founders launch");
+    }
+    *out = r;
+    return GA_OK;
+}
+
+int ga_step(ga_run* r, uint32_t n) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    if (n == 0) return GA_OK;
+    if ((uint64_t)r->T + n - 1 > r->horizon)
+        return fail(GA_EHORIZON, "generation " + std::to_string((uint64_t)r->T + n - 1) +
+                                     " is past the site rule's horizon " +
+                                     std::to_string(r->horizon));
+    const ga_config& cfg = r->cfg;
+    const bool sel = cfg.tournament_size == 2;
+    const bool mig = cfg.migrants_per_island != 0;
+    while (n > 0) {
+        const uint32_t G = n < r->gens ? n : r->gens;
+        hipError_t e = hsga::launch_site_schedule(cfg.surface_kind, r->S, r->layout, r->sites,
+                                                  r->T, G, r->stream);
+        if (e != hipSuccess) return hip_fail(e, "site schedule launch");
+        ga_run::Span span{nullptr, nullptr, G};
+        if (r->timing) {
+            span.start = take_event(r);
+            span.stop = take_event(r);
+            if (!span.start || !span.stop) return fail(GA_EDEVICE, "hipEventCreate failed");
+            e = hipEventRecord(span.start, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        for (uint32_t k = 0; k < G; ++k) {
+            const uint32_t g = r->T + k;
+            const int src = g & 1, dst = (g + 1) & 1;
+            hsga::StepParams p;
+            p.in_trait = r->trait[src];
+            p.in_counter = r->counter[src];
+            p.in_surf = r->surf[src];
+            p.out_trait = r->trait[dst];
+            p.out_counter = r->counter[dst];
+            p.out_surf = r->surf[dst];
+            p.ob_in = r->outbox[src];
+            p.ob_out = r->outbox[dst];
+            p.site = r->sites + k;
+            p.W = cfg.grid_w;
+            p.H = cfg.grid_h;
+            p.N = r->N;
+            p.I = r->I;
+            p.A = r->A;
+            p.g = g;
+            p.k0 = (uint32_t)cfg.seed;
+            p.k1 = (uint32_t)(cfg.seed >> 32);
+            p.mut_thr = cfg.mut_threshold;
+            p.mut_lo = cfg.mut_lo;
+            p.mut_span = (uint32_t)((int64_t)cfg.mut_hi - cfg.mut_lo + 1);
+            p.has_inbox = (mig && g > 0) ? 1u : 0u;
+            p.K = r->K;
+            e = hsga::launch_step(p, r->SW, sel, mig, r->block, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+        }
+        if (r->timing) {
+            e = hipEventRecord(span.stop, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            r->spans.push_back(span);
+        }
+        r->T += G;
+        n -= G;
+    }
+    return GA_OK;
+}
+
+int ga_sync(ga_run* r) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return GA_OK;
+}
+
+int ga_generation(const ga_run* r, uint32_t* T) {
+    if (!r || !T) return fail(GA_EINVAL, "NULL argument");
+    *T = r->T;
+    return GA_OK;
+}
+
+int ga_read_agents(ga_run* r, uint32_t first, uint32_t count, uint32_t* trait, uint32_t* counter,
+                   uint32_t* surface_words) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    if ((uint64_t)first + count > r->A) return fail(GA_EINVAL, "agent range out of bounds");
+    if (count == 0) return GA_OK;
+    const int cur = r->T & 1;
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (trait) {
+        e = hipMemcpy(trait, r->trait[cur] + first, (size_t)count * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy trait");
+    }
+    if (counter) {
+        e = hipMemcpy(counter, r->counter[cur] + first, (size_t)count * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy counter");
+    }
+    if (surface_words) {
+        std::vector<uint32_t> plane(count);
+        for (uint32_t w = 0; w < r->SW; ++w) {
+            e = hipMemcpy(plane.data(), r->surf[cur] + (size_t)w * r->A + first, (size_t)count * 4,
+                          hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy surface");
+            for (uint32_t k = 0; k < count; ++k) surface_words[(size_t)k * r->SW + w] = plane[k];
+        }
+    }
+    return GA_OK;
+}
+
+int ga_read_outbox(ga_run* r, uint32_t first, uint32_t count, uint32_t* dir, uint32_t* trait,
+                   uint32_t* counter, uint32_t* surface_words, int* valid) {
+    if (!r || !valid) return fail(GA_EINVAL, "NULL argument");
+    if ((uint64_t)first + count > r->I) return fail(GA_EINVAL, "island range out of bounds");
+    *valid = (r->cfg.migrants_per_island != 0 && r->T > 0) ? 1 : 0;
+    if (!*valid || count == 0) return GA_OK;
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    std::vector<uint32_t> entries((size_t)count * hsga::kOutboxWords);
+    e = hipMemcpy(entries.data(), r->outbox[r->T & 1] + (size_t)first * hsga::kOutboxWords,
+                  entries.size() * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy outbox");
+    for (uint32_t k = 0; k < count; ++k) {
+        const uint32_t* en = &entries[(size_t)k * hsga::kOutboxWords];
+        if (dir) dir[k] = en[0];
+        if (trait) trait[k] = en[1];
+        if (counter) counter[k] = en[2];
+        if (surface_words)
+            for (uint32_t w = 0; w < r->SW; ++w) surface_words[(size_t)k * r->SW + w] = en[3 + w];
+    }
+    return GA_OK;
+}
+
+int ga_read_layout(ga_run* r, uint32_t* layout) {
+    if (!r || !layout) return fail(GA_EINVAL, "NULL argument");
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    e = hipMemcpy(layout, r->layout, (size_t)r->S * 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy layout");
+    return GA_OK;
+}
+
+int ga_sample(ga_run* r, uint32_t n, uint32_t* dev_idx, uint32_t* dev_counter,
+              uint32_t* dev_surface_words, uint32_t* n_taken) {
+    if (!r || !n_taken) return fail(GA_EINVAL, "NULL argument");
+    if (n == 0 || !dev_idx || !dev_counter || !dev_surface_words)
+        return fail(GA_EINVAL, "empty sample or NULL buffer");
+    const int cur = r->T & 1;
+    hipError_t e = hsga::launch_sample(r->counter[cur], r->surf[cur], r->A, r->SW, n, r->T,
+                                       (uint32_t)r->cfg.seed, (uint32_t)(r->cfg.seed >> 32),
+                                       dev_idx, dev_counter, dev_surface_words, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "sample launch");
+    *n_taken = r->A <= n ? r->A : n;
+    return GA_OK;
+}
+
+void ga_destroy(ga_run* r) {
+    if (!r) return;
+    for (auto& s : r->spans) {
+        hipEventDestroy(s.start);
+        hipEventDestroy(s.stop);
+    }
+    for (auto e : r->spare) hipEventDestroy(e);
+    delete r;
+}
+
+const char* ga_last_error(void) { return g_last_error.c_str(); }
+
+size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n) {
+    return hsga::MrcaWorkspace::bytes(S, n);
+}
+
+int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                       const uint32_t* surface_words, uint32_t* lb, uint32_t* ub, void* workspace,
+                       size_t workspace_bytes, void* hip_stream) {
+    if (kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
+    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+    if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
+    if (!counter || !surface_words || !lb || !ub || !workspace)
+        return fail(GA_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < hsga::MrcaWorkspace::bytes(S, n))
+        return fail(GA_ENOMEM, "workspace too small");
+    hipError_t e = hsga::launch_mrca(kind, S, n, counter, surface_words, lb, ub, workspace,
+                                     static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "mrca launch");
+    return GA_OK;
+}
+
+int hstrat_mrca_status(const void* workspace, void* hip_stream) {
+    if (!workspace) return fail(GA_EINVAL, "workspace is NULL");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t status = 0;
+    e = hipMemcpy(&status, workspace, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy status");
+    if (status == 2) return fail(GA_EHORIZON, "a counter is past the site rule's horizon");
+    return GA_OK;
+}
+
+int ga_set_kernel_timing(ga_run* r, int enable) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    r->timing = enable != 0;
+    return GA_OK;
+}
+
+int ga_kernel_time(ga_run* r, double* ms, uint64_t* launches, int reset) {
+    if (!r || !ms || !launches) return fail(GA_EINVAL, "NULL argument");
+    double total = 0.0;
+    uint64_t count = 0;
+    for (auto& s : r->spans) {
+        hipError_t e = hipEventSynchronize(s.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float span_ms = 0.f;
+        e = hipEventElapsedTime(&span_ms, s.start, s.stop);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        total += span_ms;
+        count += s.launches;
+    }
+    *ms = total;
+    *launches = count;
+    if (reset) {
+        for (auto& s : r->spans) {
+            r->spare.push_back(s.start);
+            r->spare.push_back(s.stop);
+        }
+        r->spans.clear();
+    }
+    return GA_OK;
+}
+
+int ga_set_launch_shape(ga_run* r, uint32_t islands_per_wave, uint32_t block_threads) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    if (islands_per_wave) {
+        if (islands_per_wave > 32) return fail(GA_EINVAL, "islands_per_wave must be 1..32");
+        r->K = islands_per_wave;
+    }
+    if (block_threads) {
+        if (block_threads % 64 || block_threads > 1024)
+            return fail(GA_EINVAL, "block_threads must be a multiple of 64, at most 1024");
+        r->block = block_threads;
+    }
+    return GA_OK;
+}
+
+}  // extern "C"

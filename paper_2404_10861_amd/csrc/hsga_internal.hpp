@@ -1,0 +1,58 @@
+// hsga_internal.hpp -- launchers shared between the kernel translation unit
+// and the C-ABI host runtime.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsga {
+
+struct StepParams {
+    const uint32_t* in_trait;
+    const uint32_t* in_counter;
+    const uint32_t* in_surf;   // S/32 planes of A words
+    uint32_t* out_trait;
+    uint32_t* out_counter;
+    uint32_t* out_surf;
+    const uint32_t* ob_in;     // I entries of 8 words (read at generation g)
+    uint32_t* ob_out;          // I entries of 8 words (written for g + 1)
+    const uint32_t* site;      // this generation's surface site
+    uint32_t W, H, N, I, A;
+    uint32_t g;
+    uint32_t k0, k1;           // Philox key (seed)
+    uint32_t mut_thr;
+    int32_t mut_lo;
+    uint32_t mut_span;         // mut_hi - mut_lo + 1
+    uint32_t has_inbox;        // outboxes of generation g exist
+    uint32_t K;                // islands per wavefront (1..32)
+};
+
+hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,
+                           uint32_t SW, uint32_t* layout, uint32_t S, hipStream_t stream);
+
+hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
+                                uint32_t T0, uint32_t G, hipStream_t stream);
+
+hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
+                       uint32_t block_threads, hipStream_t stream);
+
+hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
+                         uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,
+                         uint32_t* counter_out, uint32_t* surf_out, hipStream_t stream);
+
+// Workspace layout of the MRCA kernels (bytes).
+struct MrcaWorkspace {
+    static constexpr size_t kHeader = 2048;   // flags, T, F, rank tables
+    static size_t bytes(uint32_t S, uint32_t n) {
+        const size_t ranked = ((size_t)n * 8 + 255) & ~(size_t)255;
+        const size_t layouts = ((size_t)n * S * 4 + 255) & ~(size_t)255;
+        const size_t sites = ((size_t)n * S + 255) & ~(size_t)255;
+        return kHeader + ranked + layouts + sites;
+    }
+};
+
+hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                       const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
+                       hipStream_t stream);
+
+}  // namespace hsga

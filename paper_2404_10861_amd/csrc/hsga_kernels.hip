@@ -1,0 +1,534 @@
+// hsga_kernels.hip -- gfx950 kernels of the island-model GA with
+// hereditary-stratigraphy surface annotations, and their launchers.
+//
+// Device state is structure-of-arrays: trait[A], counter[A] and the S/32
+// surface word planes [S/32][A], agent a = island * N + slot.  Consecutive
+// lanes own consecutive agents, so every population read and write is a
+// contiguous 256-byte wavefront access per plane.
+#include "hsga_device.hpp"
+#include "hsga_internal.hpp"
+
+namespace hsga {
+
+// ---------------------------------------------------------------------------
+// Founders (Genome Model; Distributed Phylogenetic Tracking): trait 0,
+// counter 0, every site 0, and an empty layout.  Founders carry no
+// differentia; item g is deposited by generation g's births.
+__global__ __launch_bounds__(256) void founders_kernel(uint32_t* __restrict__ trait,
+                                                      uint32_t* __restrict__ counter,
+                                                      uint32_t* __restrict__ surf, uint32_t A,
+                                                      uint32_t SW, uint32_t* __restrict__ layout,
+                                                      uint32_t S) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t a = first; a < A; a += stride) {
+        trait[a] = 0u;
+        counter[a] = 0u;
+        for (uint32_t w = 0; w < SW; ++w) surf[(size_t)w * A + a] = 0u;
+    }
+    if (first < S) layout[first] = kEmpty;
+}
+
+hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,
+                           uint32_t SW, uint32_t* layout, uint32_t S, hipStream_t stream) {
+    uint32_t blocks = (A + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(founders_kernel, dim3(blocks), dim3(256), 0, stream, trait, counter, surf,
+                       A, SW, layout, S);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Site schedule.  In a synchronous run every parent of generation T carries
+// counter T, so the surface site is the same for the whole population and
+// is computed once per generation (Results, Surface Algorithm Benchmark:
+// synchronous simulations can cache placements for a whole
+// subpopulation).  One wavefront, lane k = site k: for T = T0 .. T0+G-1
+// the placement is a ballot over the lanes whose item left the target,
+// then a bit scan; the run's layout is carried in registers and written
+// back at the end.
+__global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32_t S,
+                                                           uint32_t* __restrict__ layout,
+                                                           uint32_t* __restrict__ sites,
+                                                           uint32_t T0, uint32_t G) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t held = lane < S ? layout[lane] : kEmpty;
+    for (uint32_t k = 0; k < G; ++k) {
+        const uint32_t T = T0 + k;
+        const int site = place_in_wave(kind, S, T, held, lane);
+        if ((int)lane == site) held = T;
+        if (lane == 0) sites[k] = (uint32_t)site;
+    }
+    if (lane < S) layout[lane] = held;
+}
+
+hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
+                                uint32_t T0, uint32_t G, hipStream_t stream) {
+    hipLaunchKernelGGL(site_schedule_kernel, dim3(1), dim3(64), 0, stream, kind, S, layout,
+                       sites, T0, G);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One generation, (P_g, O_g) -> (P_{g+1}, O_{g+1}) (Methods, Asynchronous
+// Island-model Genetic Algorithm).
+//
+// Each wavefront owns K consecutive islands.  Lanes are agents: an island
+// of N agents is a group of N lanes, 64/N islands per pass.
+//  1. Island pass (migration on): lane l < K draws island l's immigration
+//     block and reads its four neighbours' outbox directions; lane K + l
+//     draws its emigration block.  Plans stay in registers and are
+//     broadcast with shuffles, so the island draws cost one pass per K
+//     islands.
+//  2. Per pass: load the island's records (coalesced), overwrite the slots
+//     chosen for immigrants with the neighbours' emigrants (north, south,
+//     west, east; a later one wins), draw one Philox block per birth, pick
+//     the parent by a tournament of two over the island's lanes
+//     (ds_bpermute shuffles), copy its record, mutate the trait, increment
+//     the counter, write the differentia bit at this generation's site,
+//     store the child (coalesced) and, in the lane of the chosen emigrant,
+//     post its copy to the outbox for g + 1.
+// Immigration plan word (lane l < K): bits 0..3 = direction d delivers,
+// bits 4+6d .. 9+6d = slot for direction d.  Emigration word (lane K + l):
+// bits 0..7 = emigrant slot, 8..9 = direction, 16..31 = island x.
+template <int SW, bool SEL, bool MIGR>
+__global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves_per_block = blockDim.x >> 6;
+    const uint32_t blk = xcd_local_block(blockIdx.x, gridDim.x);
+    const uint32_t wave = blk * waves_per_block + (threadIdx.x >> 6);
+    const uint32_t K = p.K, N = p.N, W = p.W;
+    const uint32_t first = wave * K;
+    if (first >= p.I) return;
+    const uint32_t nisl = min(K, p.I - first);
+    const uint32_t per_pass = 64u / N;
+    const uint32_t site = *p.site;
+    const uint32_t site_word = site >> 5, site_shift = site & 31u;
+
+    uint32_t plan = 0;
+    if (MIGR) {
+        const bool imm = lane < K;
+        const uint32_t il = imm ? lane : lane - K;
+        const uint32_t isl = first + il;
+        if (lane < 2u * K && il < nisl) {
+            const uint4 w = philox4x32_10(make_uint4(0u, isl, p.g, imm ? kImmigrate : kEmigrate),
+                                          p.k0, p.k1);
+            const uint32_t x = isl % W;
+            if (imm) {
+                if (p.has_inbox) {
+                    const uint32_t north = isl >= W ? isl - W : isl + p.I - W;
+                    const uint32_t south = isl + W < p.I ? isl + W : isl + W - p.I;
+                    const uint32_t west = x > 0 ? isl - 1 : isl + W - 1;
+                    const uint32_t east = x + 1 < W ? isl + 1 : isl + 1 - W;
+                    // a neighbour delivers when its emigrant was sent our way
+                    const uint32_t dn = p.ob_in[(size_t)north * kOutboxWords];
+                    const uint32_t ds = p.ob_in[(size_t)south * kOutboxWords];
+                    const uint32_t dw = p.ob_in[(size_t)west * kOutboxWords];
+                    const uint32_t de = p.ob_in[(size_t)east * kOutboxWords];
+                    plan = (dn == 1u ? 1u : 0u) | (ds == 0u ? 2u : 0u) | (dw == 3u ? 4u : 0u) |
+                           (de == 2u ? 8u : 0u);
+                    plan |= word_below(w.x, N) << 4;
+                    plan |= word_below(w.y, N) << 10;
+                    plan |= word_below(w.z, N) << 16;
+                    plan |= word_below(w.w, N) << 22;
+                }
+            } else {
+                plan = word_below(w.x, N) | ((w.y >> 30) << 8) | (x << 16);
+            }
+        }
+    }
+
+    const uint32_t grp = lane / N;
+    const uint32_t j = lane - grp * N;
+    const uint32_t base = grp * N;
+    const bool lane_used = grp < per_pass;
+    const size_t A = p.A;
+
+    for (uint32_t it = 0; it * per_pass < nisl; ++it) {
+        const uint32_t il = it * per_pass + grp;
+        const bool active = lane_used && il < nisl;
+        const uint32_t isl = first + il;
+        const uint32_t a = isl * N + j;
+
+        uint32_t tr = 0, ct = 0, s[SW];
+#pragma unroll
+        for (int w = 0; w < SW; ++w) s[w] = 0;
+        if (active) {
+            tr = p.in_trait[a];
+            ct = p.in_counter[a];
+#pragma unroll
+            for (int w = 0; w < SW; ++w) s[w] = p.in_surf[w * A + a];
+        }
+
+        uint32_t em = 0;
+        if (MIGR) {
+            const uint32_t il_c = il < K ? il : 0u;
+            const uint32_t pl = __shfl(plan, (int)il_c);
+            em = __shfl(plan, (int)(K + il_c));
+            int src = -1;
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                if (((pl >> d) & 1u) && ((pl >> (4 + 6 * d)) & 63u) == j) src = d;
+            if (active && src >= 0) {
+                const uint32_t x = em >> 16;
+                uint32_t nb;
+                if (src == 0) nb = isl >= W ? isl - W : isl + p.I - W;
+                else if (src == 1) nb = isl + W < p.I ? isl + W : isl + W - p.I;
+                else if (src == 2) nb = x > 0 ? isl - 1 : isl + W - 1;
+                else nb = x + 1 < W ? isl + 1 : isl + 1 - W;
+                const uint32_t* e = p.ob_in + (size_t)nb * kOutboxWords;
+                tr = e[1];
+                ct = e[2];
+#pragma unroll
+                for (int w = 0; w < SW; ++w) s[w] = e[3 + w];
+            }
+        }
+
+        // birth: selection, replication, mutation, surface ingest
+        const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
+        uint32_t par = word_below(r.x, N);
+        uint32_t ptrait = __shfl(tr, (int)(base + par));
+        if (SEL) {
+            const uint32_t pb = word_below(r.y, N);
+            const uint32_t tb = __shfl(tr, (int)(base + pb));
+            if ((int32_t)tb > (int32_t)ptrait) {
+                par = pb;
+                ptrait = tb;
+            }
+        }
+        const uint32_t pcount = __shfl(ct, (int)(base + par));
+        uint32_t ps[SW];
+#pragma unroll
+        for (int w = 0; w < SW; ++w) ps[w] = __shfl(s[w], (int)(base + par));
+
+        const uint32_t delta =
+            r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo) : 0u;
+        const uint32_t ctrait = ptrait + delta;
+        const uint32_t ccount = pcount + 1u;
+        const uint32_t bit = r.w & 1u;
+#pragma unroll
+        for (int w = 0; w < SW; ++w)
+            if ((uint32_t)w == site_word)
+                ps[w] = (ps[w] & ~(1u << site_shift)) | (bit << site_shift);
+
+        if (active) {
+            p.out_trait[a] = ctrait;
+            p.out_counter[a] = ccount;
+#pragma unroll
+            for (int w = 0; w < SW; ++w) p.out_surf[w * A + a] = ps[w];
+            if (MIGR && j == (em & 0xffu)) {
+                uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
+                uint4 lo4 = make_uint4((em >> 8) & 3u, ctrait, ccount, ps[0]);
+                uint4 hi4 = make_uint4(SW > 1 ? ps[SW - 1] : 0u, 0u, 0u, 0u);
+                *reinterpret_cast<uint4*>(o) = lo4;
+                *reinterpret_cast<uint4*>(o + 4) = hi4;
+            }
+        }
+    }
+}
+
+template <int SW, bool SEL, bool MIGR>
+static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
+    const uint32_t waves = (p.I + p.K - 1) / p.K;
+    const uint32_t wpb = block_threads / 64;
+    const uint32_t blocks = (waves + wpb - 1) / wpb;
+    hipLaunchKernelGGL((step_kernel<SW, SEL, MIGR>), dim3(blocks), dim3(block_threads), 0, stream,
+                       p);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
+                       uint32_t block_threads, hipStream_t stream) {
+    if (SW == 1) {
+        if (selection)
+            return migration ? launch_step_t<1, true, true>(p, block_threads, stream)
+                             : launch_step_t<1, true, false>(p, block_threads, stream);
+        return migration ? launch_step_t<1, false, true>(p, block_threads, stream)
+                         : launch_step_t<1, false, false>(p, block_threads, stream);
+    }
+    if (selection)
+        return migration ? launch_step_t<2, true, true>(p, block_threads, stream)
+                         : launch_step_t<2, true, false>(p, block_threads, stream);
+    return migration ? launch_step_t<2, false, true>(p, block_threads, stream)
+                     : launch_step_t<2, false, false>(p, block_threads, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Stratified end-of-run sample (Results, On-hardware Trial): agent k is
+// drawn uniformly from the k-th of n equal strata; every agent when A <= n.
+__global__ __launch_bounds__(256) void sample_kernel(const uint32_t* __restrict__ counter,
+                                                    const uint32_t* __restrict__ surf, uint32_t A,
+                                                    uint32_t SW, uint32_t n, uint32_t T,
+                                                    uint32_t k0, uint32_t k1,
+                                                    uint32_t* __restrict__ idx_out,
+                                                    uint32_t* __restrict__ counter_out,
+                                                    uint32_t* __restrict__ surf_out) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t taken = A <= n ? A : n;
+    if (k >= taken) return;
+    uint32_t a = k;
+    if (A > n) {
+        const uint32_t lo = (uint32_t)((uint64_t)k * A / n);
+        const uint32_t hi = (uint32_t)((uint64_t)(k + 1) * A / n);
+        const uint4 w = philox4x32_10(make_uint4(k, 0u, T, kSample), k0, k1);
+        a = lo + word_below(w.x, hi - lo);
+    }
+    idx_out[k] = a;
+    counter_out[k] = counter[a];
+    for (uint32_t w = 0; w < SW; ++w) surf_out[(size_t)k * SW + w] = surf[(size_t)w * A + a];
+}
+
+hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
+                         uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,
+                         uint32_t* counter_out, uint32_t* surf_out, hipStream_t stream) {
+    const uint32_t taken = A <= n ? A : n;
+    const uint32_t blocks = (taken + 255) / 256;
+    hipLaunchKernelGGL(sample_kernel, dim3(blocks ? blocks : 1), dim3(256), 0, stream, counter,
+                       surf, A, SW, n, T, k0, k1, idx_out, counter_out, surf_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// MRCA-generation bounds (Distributed Phylogenetic Tracking: mismatching
+// differentiae delimit common ancestry).
+//
+// Workspace header words.
+constexpr uint32_t kWsStatus = 0;  // 0 all counters equal, 1 mixed, 2 past horizon
+constexpr uint32_t kWsT = 1;
+constexpr uint32_t kWsF = 2;
+constexpr uint32_t kWsPerm = 64;    // site of each time rank (ascending time)
+constexpr uint32_t kWsTimes = 128;  // deposit time of each rank
+constexpr uint32_t kWsLbTab = 192;  // 65 entries: lb when the first mismatch is rank r (64: none)
+constexpr uint32_t kWsUbTab = 320;  // 65 entries: ub likewise
+constexpr uint32_t kWsStatusMixed = 1, kWsStatusHorizon = 2;
+
+// Rank of this lane's time among the S lanes (ascending; empty sites last,
+// ties by lane).  All 64 lanes call it.
+__device__ __forceinline__ uint32_t time_rank(uint32_t held, uint32_t lane, uint32_t S) {
+    uint32_t rank = 0;
+    for (uint32_t q = 0; q < S; ++q) {
+        const uint32_t tq = __shfl(held, (int)q);
+        rank += (tq < held || (tq == held && q < lane)) ? 1u : 0u;
+    }
+    return rank;
+}
+
+// Layout after T ingests, replayed in the wavefront (lane = site).
+__device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uint32_t T,
+                                                  uint32_t lane) {
+    uint32_t held = kEmpty;
+    for (uint32_t t = 0; t < T; ++t) {
+        const int site = place_in_wave(kind, S, t, held, lane);
+        if ((int)lane == site) held = t;
+    }
+    return held;
+}
+
+// One wavefront: classify the counters; when all are equal, replay the
+// shared layout once, order its sites by deposit time and tabulate the
+// bounds for every possible first-mismatch rank.
+__global__ __launch_bounds__(64) void mrca_prepare_kernel(uint32_t kind, uint32_t S, uint32_t n,
+                                                         const uint32_t* __restrict__ counter,
+                                                         uint32_t* __restrict__ ws) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t T0 = counter[0];
+    const uint64_t hz = horizon_of(kind, S);
+    bool same = true, past = false;
+    for (uint32_t k = lane; k < n; k += 64) {
+        const uint32_t c = counter[k];
+        same = same && c == T0;
+        past = past || c > kMaxReplayGenerations || (c > 0 && (uint64_t)(c - 1) > hz);
+    }
+    const bool any_past = __ballot(past) != 0;
+    const bool all_same = __ballot(!same) == 0;
+    if (any_past || !all_same) {
+        if (lane == 0) {
+            ws[kWsStatus] = any_past ? kWsStatusHorizon : kWsStatusMixed;
+            ws[kWsT] = T0;
+        }
+        return;
+    }
+    const uint32_t held = replay_layout(kind, S, T0, lane);
+    const uint32_t rank = time_rank(held, lane, S);
+    const uint32_t F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
+    __shared__ uint32_t times[64];
+    if (lane < S) {
+        times[rank] = held;
+        ws[kWsPerm + rank] = lane;
+        ws[kWsTimes + rank] = held;
+    }
+    __syncthreads();
+    // first mismatch at rank r: ub = times[r], lb = times[r-1] + 1 (0 if r = 0);
+    // no mismatch (entry 64): ub = T, lb = times[F-1] + 1 (0 if F = 0)
+    ws[kWsLbTab + lane] = lane == 0 ? 0u : (lane < S ? times[lane - 1] + 1u : 0u);
+    ws[kWsUbTab + lane] = lane < S ? times[lane] : 0u;
+    if (lane == 0) {
+        ws[kWsLbTab + 64] = F > 0 ? times[F - 1] + 1u : 0u;
+        ws[kWsUbTab + 64] = T0;
+        ws[kWsT] = T0;
+        ws[kWsF] = F;
+        ws[kWsStatus] = 0;
+    }
+}
+
+// Fast route: each annotation's bits in ascending-time order, packed in 64 bits.
+__global__ __launch_bounds__(256) void mrca_rank_kernel(uint32_t S, uint32_t n,
+                                                       const uint32_t* __restrict__ surf,
+                                                       const uint32_t* __restrict__ ws,
+                                                       uint64_t* __restrict__ ranked) {
+    if (ws[kWsStatus] != 0) return;
+    __shared__ uint32_t perm[64];
+    if (threadIdx.x < 64) perm[threadIdx.x] = ws[kWsPerm + threadIdx.x];
+    __syncthreads();
+    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const uint32_t F = ws[kWsF];
+    const uint32_t SW = S >> 5;
+    const uint64_t s = SW == 2 ? ((uint64_t)surf[(size_t)a * 2 + 1] << 32) | surf[(size_t)a * 2]
+                               : (uint64_t)surf[a];
+    uint64_t bits = 0;
+    for (uint32_t r = 0; r < F; ++r) bits |= ((s >> perm[r]) & 1ull) << r;
+    ranked[a] = bits;
+}
+
+// Fast route, all ordered pairs: x = P_a xor P_b; the first set bit is the
+// rank of the first mismatch.  Each thread owns 4 adjacent columns of 4
+// rows, so stores are 16-byte and a wavefront writes 1 KiB contiguously.
+constexpr uint32_t kPairRows = 4;
+__global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n,
+                                                           const uint64_t* __restrict__ ranked,
+                                                           const uint32_t* __restrict__ ws,
+                                                           uint32_t* __restrict__ lb,
+                                                           uint32_t* __restrict__ ub) {
+    if (ws[kWsStatus] != 0) return;
+    __shared__ uint32_t lbt[65], ubt[65];
+    if (threadIdx.x < 65) {
+        lbt[threadIdx.x] = ws[kWsLbTab + threadIdx.x];
+        ubt[threadIdx.x] = ws[kWsUbTab + threadIdx.x];
+    }
+    __syncthreads();
+    const uint32_t c0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4u;
+    if (c0 >= n) return;
+    const uint32_t a0 = blockIdx.y * kPairRows;
+    uint64_t pb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pb[q] = c0 + q < n ? ranked[c0 + q] : 0ull;
+    const bool vec = (n & 3u) == 0;
+    for (uint32_t rr = 0; rr < kPairRows; ++rr) {
+        const uint32_t a = a0 + rr;
+        if (a >= n) break;
+        const uint64_t pa = ranked[a];
+        uint32_t l[4], u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t x = pa ^ pb[q];
+            const uint32_t idx = x ? (uint32_t)(__ffsll((long long)x) - 1) : 64u;
+            l[q] = lbt[idx];
+            u[q] = ubt[idx];
+        }
+        const size_t off = (size_t)a * n + c0;
+        if (vec) {
+            *reinterpret_cast<uint4*>(lb + off) = make_uint4(l[0], l[1], l[2], l[3]);
+            *reinterpret_cast<uint4*>(ub + off) = make_uint4(u[0], u[1], u[2], u[3]);
+        } else {
+            for (uint32_t q = 0; q < 4 && c0 + q < n; ++q) {
+                lb[off + q] = l[q];
+                ub[off + q] = u[q];
+            }
+        }
+    }
+}
+
+// General route (counters differ): one wavefront per annotation replays its
+// own layout and stores its retained times in ascending order with their
+// sites.
+__global__ __launch_bounds__(64) void mrca_layouts_kernel(uint32_t kind, uint32_t S, uint32_t n,
+                                                         const uint32_t* __restrict__ counter,
+                                                         const uint32_t* __restrict__ ws,
+                                                         uint32_t* __restrict__ times,
+                                                         uint8_t* __restrict__ sites) {
+    if (ws[kWsStatus] != kWsStatusMixed) return;
+    const uint32_t a = blockIdx.x;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t held = replay_layout(kind, S, counter[a], lane);
+    const uint32_t rank = time_rank(held, lane, S);
+    if (lane < S) {
+        times[(size_t)a * S + rank] = held;
+        sites[(size_t)a * S + rank] = (uint8_t)lane;
+    }
+}
+
+// General route, all ordered pairs: merge the two ascending time lists,
+// comparing bits on common times until the first mismatch.
+__global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
+    uint32_t S, uint32_t n, const uint32_t* __restrict__ counter,
+    const uint32_t* __restrict__ surf, const uint32_t* __restrict__ times,
+    const uint8_t* __restrict__ sites, const uint32_t* __restrict__ ws, uint32_t* __restrict__ lb,
+    uint32_t* __restrict__ ub) {
+    if (ws[kWsStatus] != kWsStatusMixed) return;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t a = blockIdx.y;
+    if (b >= n) return;
+    const uint32_t SW = S >> 5;
+    const uint64_t sa = SW == 2 ? ((uint64_t)surf[(size_t)a * 2 + 1] << 32) | surf[(size_t)a * 2]
+                                : (uint64_t)surf[a];
+    const uint64_t sb = SW == 2 ? ((uint64_t)surf[(size_t)b * 2 + 1] << 32) | surf[(size_t)b * 2]
+                                : (uint64_t)surf[b];
+    const uint32_t* ta = times + (size_t)a * S;
+    const uint32_t* tb = times + (size_t)b * S;
+    const uint8_t* ka = sites + (size_t)a * S;
+    const uint8_t* kb = sites + (size_t)b * S;
+    uint32_t i = 0, k = 0;
+    bool have_last = false, mismatch = false;
+    uint32_t last = 0, tstar = 0;
+    while (i < S && k < S) {
+        const uint32_t x = ta[i], y = tb[k];
+        if (x == kEmpty || y == kEmpty) break;
+        if (x == y) {
+            if (((sa >> ka[i]) & 1ull) != ((sb >> kb[k]) & 1ull)) {
+                mismatch = true;
+                tstar = x;
+                break;
+            }
+            have_last = true;
+            last = x;
+            ++i;
+            ++k;
+        } else if (x < y) {
+            ++i;
+        } else {
+            ++k;
+        }
+    }
+    const uint32_t Ta = counter[a], Tb = counter[b];
+    const size_t off = (size_t)a * n + b;
+    ub[off] = mismatch ? tstar : (Ta < Tb ? Ta : Tb);
+    lb[off] = have_last ? last + 1u : 0u;
+}
+
+hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                       const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
+                       hipStream_t stream) {
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    uint32_t* ws = reinterpret_cast<uint32_t*>(base);
+    uint64_t* ranked = reinterpret_cast<uint64_t*>(base + MrcaWorkspace::kHeader);
+    const size_t ranked_bytes = ((size_t)n * 8 + 255) & ~(size_t)255;
+    uint32_t* times = reinterpret_cast<uint32_t*>(base + MrcaWorkspace::kHeader + ranked_bytes);
+    const size_t times_bytes = ((size_t)n * S * 4 + 255) & ~(size_t)255;
+    uint8_t* sites = base + MrcaWorkspace::kHeader + ranked_bytes + times_bytes;
+
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, kind, S, n, counter,
+                       ws);
+    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S, n, surf,
+                       ws, ranked);
+    hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
+                       dim3(256), 0, stream, n, ranked, ws, lb, ub);
+    hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, kind, S, n, counter, ws,
+                       times, sites);
+    hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, n), dim3(256), 0, stream,
+                       S, n, counter, surf, times, sites, ws, lb, ub);
+    return hipGetLastError();
+}
+
+}  // namespace hsga

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit for
+bit on every agent word, outbox entry and layout site.  Everything here is
+integer work, so the tolerance is zero.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"steady": 0, "tilted": 1, "hybrid": 2}
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_10861_amd as hs
+    hs.load_library()
+    return hs
+
+
+def make_pair(hs, orc, W, H, N, S, kind, tournament=2, migrants=1, seed=1,
+              mut_thr=42949672, mut_lo=-8, mut_hi=8, gens_per_launch=0):
+    cfg = hs.Config(W, H, N, S, kind, tournament, mut_thr, mut_lo, mut_hi, migrants, seed)
+    g = hs.Run(cfg, max_gens_per_launch=gens_per_launch)
+    o = orc.Run(W, H, N, S, KIND[kind], tournament, mut_thr, mut_lo, mut_hi, migrants, seed)
+    return g, o
+
+
+def assert_same_state(g, o, where=""):
+    gt, gc, gs = g.agents()
+    ot, oc, os_ = o.agents()
+    assert np.array_equal(gt, ot), f"trait differs {where}: first at {np.argmax(gt != ot)}"
+    assert np.array_equal(gc, oc), f"counter differs {where}"
+    assert np.array_equal(gs, os_), f"surface differs {where}: first agent {np.argmax(np.any(gs != os_, axis=1))}"
+    assert np.array_equal(g.layout(), o.layout()), f"layout differs {where}"
+    gob, oob = g.outbox(), o.outbox()
+    assert (gob is None) == (oob is None), where
+    if gob is not None:
+        for x, y, name in zip(gob, oob[:4], ("dir", "trait", "counter", "surface")):
+            assert np.array_equal(x, y), f"outbox {name} differs {where}"
+
+
+def test_c1_every_generation(hs, orc):
+    """The CPU-scale workload, compared after every generation."""
+    g, o = make_pair(hs, orc, 8, 8, 32, 32, "steady", seed=1, gens_per_launch=64)
+    assert_same_state(g, o, "at founders")
+    for gen in range(1, 1001):
+        g.step(1)
+        o.step(1)
+        if gen <= 100 or gen % 10 == 0:
+            assert_same_state(g, o, f"at generation {gen}")
+    assert_same_state(g, o, "at generation 1000")
+
+
+@pytest.mark.parametrize("kind", ["steady", "tilted", "hybrid"])
+@pytest.mark.parametrize("S", [32, 64])
+@pytest.mark.parametrize("tournament", [2, 0])
+def test_kinds_sizes_treatments(hs, orc, kind, S, tournament):
+    g, o = make_pair(hs, orc, 6, 5, 16, S, kind, tournament=tournament, seed=7)
+    for chunk in (1, 2, 37, 160):
+        g.step(chunk)
+        o.step(chunk)
+        assert_same_state(g, o, f"{kind} S={S} T={g.generation}")
+
+
+@pytest.mark.parametrize("W,H,N", [(1, 1, 8), (2, 1, 4), (1, 3, 64), (5, 3, 3), (7, 9, 48),
+                                   (33, 2, 1), (3, 35, 2), (4, 4, 64), (13, 11, 32), (9, 7, 17)])
+def test_torus_shapes_and_population_sizes(hs, orc, W, H, N):
+    """Degenerate tori (1x1, 2x1, 1x3), populations that do not divide the
+    wavefront (3, 17, 48), and island counts that leave ragged tails."""
+    g, o = make_pair(hs, orc, W, H, N, 64, "hybrid", seed=3)
+    g.step(90)
+    o.step(90)
+    assert_same_state(g, o, f"{W}x{H}x{N}")
+
+
+def test_migration_off(hs, orc):
+    g, o = make_pair(hs, orc, 8, 4, 32, 32, "tilted", migrants=0, seed=5)
+    g.step(200)
+    o.step(200)
+    assert_same_state(g, o)
+    assert g.outbox() is None
+
+
+def test_no_mutation_and_wide_mutation(hs, orc):
+    for thr, lo, hi in ((0, -8, 8), (2**32 - 1, -1000, 1000), (2**31, 0, 0)):
+        g, o = make_pair(hs, orc, 4, 4, 32, 32, "steady", seed=11, mut_thr=thr, mut_lo=lo,
+                         mut_hi=hi)
+        g.step(50)
+        o.step(50)
+        assert_same_state(g, o, f"thr={thr} [{lo},{hi}]")
+
+
+@pytest.mark.parametrize("K,block", [(1, 64), (2, 128), (3, 256), (8, 1024), (16, 192),
+                                     (32, 256), (32, 1024)])
+def test_launch_shape_invariance(hs, orc, K, block):
+    g, o = make_pair(hs, orc, 16, 12, 32, 64, "hybrid", seed=13)
+    g.set_launch_shape(K, block)
+    g.step(75)
+    o.step(75)
+    assert_same_state(g, o, f"K={K} block={block}")
+
+
+def test_chunked_site_schedule(hs, orc):
+    """Schedules split across launches (3 generations per launch)."""
+    g, o = make_pair(hs, orc, 4, 4, 16, 32, "tilted", seed=17, gens_per_launch=3)
+    g.step(100)
+    o.step(100)
+    assert_same_state(g, o)
+
+
+@pytest.mark.parametrize("tournament", [2, 0])
+def test_treatment_pair_scaled_down_full_length(hs, orc, tournament):
+    """The treatment-pair workload on a 12x12 torus, its full 20,000
+    generations (the 256x256 version is checked by properties below)."""
+    g, o = make_pair(hs, orc, 12, 12, 64, 32, "tilted", tournament=tournament, seed=1)
+    g.step(20000)
+    o.step(20000)
+    assert_same_state(g, o)
+
+
+def test_paper_scale_prefix(hs, orc):
+    """The 16.8 M-agent hybrid workload, every word after 3 generations, in
+    the launch configuration the benchmark uses."""
+    g, o = make_pair(hs, orc, 512, 1024, 32, 64, "hybrid", seed=1)
+    g.step(3)
+    o.step(3)
+    assert_same_state(g, o)
+
+
+def test_horizon_is_refused(hs):
+    cfg = hs.Config(2, 2, 4, 32, "hybrid", seed=1)
+    g = hs.Run(cfg)
+    with pytest.raises(hs.HsgaError) as e:
+        g.step(2 * (2**16 - 2) + 3 + 1)
+    assert e.value.status == -3
+    assert g.generation == 0
+
+
+def test_invalid_configs(hs):
+    for bad in (dict(grid_w=0, grid_h=4), dict(grid_w=4, grid_h=4, pop_per_island=65),
+                dict(grid_w=4, grid_h=4, surface_sites=48),
+                dict(grid_w=4, grid_h=4, tournament_size=3),
+                dict(grid_w=4, grid_h=4, mut_lo=2, mut_hi=1)):
+        with pytest.raises(hs.HsgaError) as e:
+            hs.Run(hs.Config(**bad))
+        assert e.value.status == -1
+
+
+def test_determinism_across_runs(hs):
+    cfg = hs.Config(16, 16, 32, 64, "hybrid", seed=99)
+    a = hs.Run(cfg)
+    b = hs.Run(cfg)
+    b.set_launch_shape(5, 512)
+    a.step(300)
+    b.step(300)
+    for x, y in zip(a.agents(), b.agents()):
+        assert np.array_equal(x, y)

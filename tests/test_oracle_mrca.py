@@ -122,6 +122,17 @@ def test_bounds_with_unequal_counters_match_pairwise(orc):
                 assert ub[a, b] <= min(counters[a], counters[b])
 
 
+def test_rows_equal_allpairs(orc):
+    rng = np.random.default_rng(8)
+    counters = np.full(40, 500, np.uint32)
+    counters[5:9] = [0, 17, 499, 501]
+    surf = rng.integers(0, 2**32, size=(40, 2), dtype=np.uint64).astype(np.uint32)
+    lb, ub = orc.mrca_allpairs(2, 64, counters, surf)
+    rows = [0, 6, 39, 7, 7]
+    rlb, rub = orc.mrca_rows(2, 64, counters, surf, rows)
+    assert np.array_equal(rlb, lb[rows]) and np.array_equal(rub, ub[rows])
+
+
 @pytest.mark.parametrize("A,n", [(2048, 1024), (4194304, 4096), (1000, 1000),
                                  (500, 1024), (7, 3)])
 def test_stratified_sample(orc, A, n):
