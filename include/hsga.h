@@ -208,11 +208,14 @@ int ga_set_kernel_timing(ga_run *run, int enable);
  * since timing was enabled (or last reset with reset = 1).                 */
 int ga_kernel_time(ga_run *run, double *ms, uint64_t *launches, int reset);
 
-/* Launch shape the run uses: islands per wavefront (1..32) and
- * workgroup size in threads (64..1024, multiple of 64); 0 keeps the
- * current value.  Results do not depend on it.                             */
-int ga_set_launch_shape(ga_run *run, uint32_t islands_per_wave,
-                        uint32_t block_threads);
+/* Launch shape of the step kernel: threads per workgroup (multiple of 64,
+ * 64..1024) and agents per thread (1, 2 or 4; must divide pop_per_island;
+ * 4 gives 16-byte population loads and stores).  A workgroup handles a
+ * tile of block_threads * agents_per_thread / N whole islands staged in
+ * LDS (at most 64 KiB).  0 keeps the current value.  Results do not depend
+ * on the shape.  Errors: GA_EINVAL.                                        */
+int ga_set_launch_shape(ga_run *run, uint32_t block_threads,
+                        uint32_t agents_per_thread);
 
 #ifdef __cplusplus
 }

@@ -277,8 +277,8 @@ class Run:
                                              1 if reset else 0))
         return ms.value, n.value
 
-    def set_launch_shape(self, islands_per_wave: int = 0, block_threads: int = 0):
-        _check(load_library().ga_set_launch_shape(self._h, islands_per_wave, block_threads))
+    def set_launch_shape(self, block_threads: int = 0, agents_per_thread: int = 0):
+        _check(load_library().ga_set_launch_shape(self._h, block_threads, agents_per_thread))
 
 
 class MrcaWorkspace:

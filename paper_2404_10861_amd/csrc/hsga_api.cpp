@@ -91,7 +91,7 @@ struct ga_run {
     uint32_t gens;       // site schedule capacity
     uint32_t T;          // generations enqueued
     uint64_t horizon;
-    uint32_t K;          // islands per wavefront
+    uint32_t apt;        // agents per thread (1, 2, 4; divides N)
     uint32_t block;      // workgroup threads
     bool timing;
     struct Span { hipEvent_t start, stop; uint32_t launches; };
@@ -112,10 +112,14 @@ hipEvent_t take_event(ga_run* r) {
     return e;
 }
 
-uint32_t default_islands_per_wave(uint32_t N) {
-    (void)N;
-    return 32;
+uint32_t default_agents_per_thread(uint32_t N) {
+    return N % 4 == 0 ? 4u : (N % 2 == 0 ? 2u : 1u);
 }
+
+// Islands per workgroup tile and the tile's LDS bytes for a launch shape.
+uint32_t tile_islands(uint32_t block, uint32_t apt, uint32_t N) { return block * apt / N; }
+
+constexpr size_t kMaxStepLds = 65536;
 
 }  // namespace
 
@@ -164,7 +168,7 @@ int ga_create(const ga_config* cfg, void* dev_arena, size_t arena_bytes,
     r->gens = gens;
     r->T = 0;
     r->horizon = hsga::horizon_of(cfg->surface_kind, r->S);
-    r->K = default_islands_per_wave(r->N);
+    r->apt = default_agents_per_thread(r->N);
     r->block = 256;
     r->timing = false;
     hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
@@ -225,8 +229,9 @@ int ga_step(ga_run* r, uint32_t n) {
             p.mut_lo = cfg.mut_lo;
             p.mut_span = (uint32_t)((int64_t)cfg.mut_hi - cfg.mut_lo + 1);
             p.has_inbox = (mig && g > 0) ? 1u : 0u;
-            p.K = r->K;
-            e = hsga::launch_step(p, r->SW, sel, mig, r->block, r->stream);
+            p.tile_isl = tile_islands(r->block, r->apt, r->N);
+            p.div_magic = ((1u << 20) + r->N - 1) / r->N;
+            e = hsga::launch_step(p, r->SW, sel, mig, r->apt, r->block, r->stream);
             if (e != hipSuccess) return hip_fail(e, "step launch");
         }
         if (r->timing) {
@@ -402,17 +407,18 @@ int ga_kernel_time(ga_run* r, double* ms, uint64_t* launches, int reset) {
     return GA_OK;
 }
 
-int ga_set_launch_shape(ga_run* r, uint32_t islands_per_wave, uint32_t block_threads) {
+int ga_set_launch_shape(ga_run* r, uint32_t block_threads, uint32_t agents_per_thread) {
     if (!r) return fail(GA_EINVAL, "run is NULL");
-    if (islands_per_wave) {
-        if (islands_per_wave > 32) return fail(GA_EINVAL, "islands_per_wave must be 1..32");
-        r->K = islands_per_wave;
-    }
-    if (block_threads) {
-        if (block_threads % 64 || block_threads > 1024)
-            return fail(GA_EINVAL, "block_threads must be a multiple of 64, at most 1024");
-        r->block = block_threads;
-    }
+    const uint32_t block = block_threads ? block_threads : r->block;
+    const uint32_t apt = agents_per_thread ? agents_per_thread : r->apt;
+    if (block % 64 || block < 64 || block > 1024)
+        return fail(GA_EINVAL, "block_threads must be a multiple of 64 in 64..1024");
+    if ((apt != 1 && apt != 2 && apt != 4) || r->N % apt)
+        return fail(GA_EINVAL, "agents_per_thread must be 1, 2 or 4 and divide pop_per_island");
+    if (hsga::step_lds_bytes(tile_islands(block, apt, r->N), r->N, r->SW) > kMaxStepLds)
+        return fail(GA_EINVAL, "tile needs more than 64 KiB of LDS");
+    r->block = block;
+    r->apt = apt;
     return GA_OK;
 }
 

@@ -24,8 +24,12 @@ struct StepParams {
     int32_t mut_lo;
     uint32_t mut_span;         // mut_hi - mut_lo + 1
     uint32_t has_inbox;        // outboxes of generation g exist
-    uint32_t K;                // islands per wavefront (1..32)
+    uint32_t tile_isl;         // islands per workgroup tile
+    uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
 };
+
+// LDS bytes of one step workgroup.
+size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW);
 
 hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,
                            uint32_t SW, uint32_t* layout, uint32_t S, hipStream_t stream);
@@ -33,8 +37,10 @@ hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, u
 hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
                                 uint32_t T0, uint32_t G, hipStream_t stream);
 
+// agents_per_thread (1, 2 or 4) must divide N; tile_isl * N <= block_threads *
+// agents_per_thread.
 hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
-                       uint32_t block_threads, hipStream_t stream);
+                       uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
 
 hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
                          uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,

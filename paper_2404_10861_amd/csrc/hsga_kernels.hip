@@ -74,184 +74,251 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 // One generation, (P_g, O_g) -> (P_{g+1}, O_{g+1}) (Methods, Asynchronous
 // Island-model Genetic Algorithm).
 //
-// Each wavefront owns K consecutive islands.  Lanes are agents: an island
-// of N agents is a group of N lanes, 64/N islands per pass.
-//  1. Island pass (migration on): lane l < K draws island l's immigration
-//     block and reads its four neighbours' outbox directions; lane K + l
-//     draws its emigration block.  Plans stay in registers and are
-//     broadcast with shuffles, so the island draws cost one pass per K
-//     islands.
-//  2. Per pass: load the island's records (coalesced), overwrite the slots
-//     chosen for immigrants with the neighbours' emigrants (north, south,
-//     west, east; a later one wins), draw one Philox block per birth, pick
-//     the parent by a tournament of two over the island's lanes
-//     (ds_bpermute shuffles), copy its record, mutate the trait, increment
-//     the counter, write the differentia bit at this generation's site,
-//     store the child (coalesced) and, in the lane of the chosen emigrant,
-//     post its copy to the outbox for g + 1.
-// Immigration plan word (lane l < K): bits 0..3 = direction d delivers,
-// bits 4+6d .. 9+6d = slot for direction d.  Emigration word (lane K + l):
-// bits 0..7 = emigrant slot, 8..9 = direction, 16..31 = island x.
-template <int SW, bool SEL, bool MIGR>
-__global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t waves_per_block = blockDim.x >> 6;
-    const uint32_t blk = xcd_local_block(blockIdx.x, gridDim.x);
-    const uint32_t wave = blk * waves_per_block + (threadIdx.x >> 6);
-    const uint32_t K = p.K, N = p.N, W = p.W;
-    const uint32_t first = wave * K;
-    if (first >= p.I) return;
-    const uint32_t nisl = min(K, p.I - first);
-    const uint32_t per_pass = 64u / N;
-    const uint32_t site = *p.site;
-    const uint32_t site_word = site >> 5, site_shift = site & 31u;
+// One workgroup per tile of whole islands; the tile's population is staged
+// in LDS as structure-of-arrays planes.
+//  1. Each thread loads APT consecutive agents of every plane with one
+//     16-byte (APT = 4) load per plane; meanwhile the island pass draws one
+//     immigration and one emigration Philox block per island and reads the
+//     four neighbours' outbox directions.
+//  2. Records go to LDS; after a barrier, one thread per island copies the
+//     neighbours' emigrants that were addressed to it over the chosen slots,
+//     north, south, west, east (a later one wins).
+//  3. After a second barrier each thread gives birth to its APT agents: one
+//     Philox block each, a tournament of two read from the island's LDS
+//     traits, the parent record copied from LDS, trait mutation, counter
+//     increment and the differentia bit written at this generation's site.
+//     The thread holding the chosen emigrant posts its copy to the outbox
+//     for g + 1.  Children leave with one 16-byte store per plane.
+// Immigration plan word: bits 0..3 = direction d delivers, bits 4+6d ..
+// 9+6d = slot for direction d.  Emigration word: bits 0..7 = slot, 8..9 =
+// direction.
+template <int APT>
+struct Lanes {
+    uint32_t v[APT];
+};
 
-    uint32_t plan = 0;
+template <int APT>
+__device__ __forceinline__ Lanes<APT> load_lanes(const uint32_t* __restrict__ src) {
+    Lanes<APT> r;
+    if constexpr (APT == 4) {
+        const uint4 x = *reinterpret_cast<const uint4*>(src);
+        r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
+    } else if constexpr (APT == 2) {
+        const uint2 x = *reinterpret_cast<const uint2*>(src);
+        r.v[0] = x.x; r.v[1] = x.y;
+    } else {
+        r.v[0] = *src;
+    }
+    return r;
+}
+
+template <int APT>
+__device__ __forceinline__ void store_lanes(uint32_t* __restrict__ dst, const Lanes<APT>& r) {
+    if constexpr (APT == 4) {
+        *reinterpret_cast<uint4*>(dst) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+    } else if constexpr (APT == 2) {
+        *reinterpret_cast<uint2*>(dst) = make_uint2(r.v[0], r.v[1]);
+    } else {
+        *dst = r.v[0];
+    }
+}
+
+// Island index of a neighbour: 0 north, 1 south, 2 west, 3 east (torus).
+__device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint32_t d, uint32_t W,
+                                                 uint32_t I) {
+    if (d == 0) return isl >= W ? isl - W : isl + I - W;
+    if (d == 1) return isl + W < I ? isl + W : isl + W - I;
+    if (d == 2) return x > 0 ? isl - 1 : isl + W - 1;
+    return x + 1 < W ? isl + 1 : isl + 1 - W;
+}
+
+template <int SW, bool SEL, bool MIGR, int APT>
+__global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t N = p.N, W = p.W;
+    const uint32_t TA = p.tile_isl * N;                // agents in a full tile
+    uint32_t* l_trait = lds;
+    uint32_t* l_count = lds + TA;
+    uint32_t* l_surf = lds + 2 * TA;                   // SW planes of TA words
+    uint32_t* l_plan = lds + (2 + SW) * TA;            // tile_isl words
+    uint32_t* l_emig = l_plan + p.tile_isl;            // tile_isl words
+
+    const uint32_t tile = xcd_local_block(blockIdx.x, gridDim.x);
+    const uint32_t first_isl = tile * p.tile_isl;
+    const uint32_t nisl = min(p.tile_isl, p.I - first_isl);
+    const uint32_t nag = nisl * N;
+    const size_t a0 = (size_t)first_isl * N;
+    const size_t A = p.A;
+    const uint32_t t = threadIdx.x;
+    const uint32_t la0 = t * APT;
+    const bool mine = la0 < nag;
+
+    // 1. this thread's agents, every plane
+    Lanes<APT> tr, ct, sf[SW];
+    if (mine) {
+        tr = load_lanes<APT>(p.in_trait + a0 + la0);
+        ct = load_lanes<APT>(p.in_counter + a0 + la0);
+#pragma unroll
+        for (int w = 0; w < SW; ++w) sf[w] = load_lanes<APT>(p.in_surf + w * A + a0 + la0);
+    }
     if (MIGR) {
-        const bool imm = lane < K;
-        const uint32_t il = imm ? lane : lane - K;
-        const uint32_t isl = first + il;
-        if (lane < 2u * K && il < nisl) {
-            const uint4 w = philox4x32_10(make_uint4(0u, isl, p.g, imm ? kImmigrate : kEmigrate),
-                                          p.k0, p.k1);
-            const uint32_t x = isl % W;
+        for (uint32_t b = t; b < 2 * nisl; b += blockDim.x) {
+            const bool imm = b < nisl;
+            const uint32_t il = imm ? b : b - nisl;
+            const uint32_t isl = first_isl + il;
+            const uint4 w4 = philox4x32_10(make_uint4(0u, isl, p.g, imm ? kImmigrate : kEmigrate),
+                                           p.k0, p.k1);
             if (imm) {
+                uint32_t plan = 0;
                 if (p.has_inbox) {
-                    const uint32_t north = isl >= W ? isl - W : isl + p.I - W;
-                    const uint32_t south = isl + W < p.I ? isl + W : isl + W - p.I;
-                    const uint32_t west = x > 0 ? isl - 1 : isl + W - 1;
-                    const uint32_t east = x + 1 < W ? isl + 1 : isl + 1 - W;
+                    const uint32_t x = isl % W;
                     // a neighbour delivers when its emigrant was sent our way
-                    const uint32_t dn = p.ob_in[(size_t)north * kOutboxWords];
-                    const uint32_t ds = p.ob_in[(size_t)south * kOutboxWords];
-                    const uint32_t dw = p.ob_in[(size_t)west * kOutboxWords];
-                    const uint32_t de = p.ob_in[(size_t)east * kOutboxWords];
+                    const uint32_t dn = p.ob_in[(size_t)neighbour_of(isl, x, 0, W, p.I) * kOutboxWords];
+                    const uint32_t ds = p.ob_in[(size_t)neighbour_of(isl, x, 1, W, p.I) * kOutboxWords];
+                    const uint32_t dw = p.ob_in[(size_t)neighbour_of(isl, x, 2, W, p.I) * kOutboxWords];
+                    const uint32_t de = p.ob_in[(size_t)neighbour_of(isl, x, 3, W, p.I) * kOutboxWords];
                     plan = (dn == 1u ? 1u : 0u) | (ds == 0u ? 2u : 0u) | (dw == 3u ? 4u : 0u) |
                            (de == 2u ? 8u : 0u);
-                    plan |= word_below(w.x, N) << 4;
-                    plan |= word_below(w.y, N) << 10;
-                    plan |= word_below(w.z, N) << 16;
-                    plan |= word_below(w.w, N) << 22;
+                    plan |= word_below(w4.x, N) << 4;
+                    plan |= word_below(w4.y, N) << 10;
+                    plan |= word_below(w4.z, N) << 16;
+                    plan |= word_below(w4.w, N) << 22;
                 }
+                l_plan[il] = plan;
             } else {
-                plan = word_below(w.x, N) | ((w.y >> 30) << 8) | (x << 16);
+                l_emig[il] = word_below(w4.x, N) | ((w4.y >> 30) << 8);
             }
         }
     }
 
-    const uint32_t grp = lane / N;
-    const uint32_t j = lane - grp * N;
-    const uint32_t base = grp * N;
-    const bool lane_used = grp < per_pass;
-    const size_t A = p.A;
-
-    for (uint32_t it = 0; it * per_pass < nisl; ++it) {
-        const uint32_t il = it * per_pass + grp;
-        const bool active = lane_used && il < nisl;
-        const uint32_t isl = first + il;
-        const uint32_t a = isl * N + j;
-
-        uint32_t tr = 0, ct = 0, s[SW];
+    // 2. stage the tile in LDS, then overwrite immigrant slots
+    if (mine) {
+        store_lanes<APT>(l_trait + la0, tr);
+        store_lanes<APT>(l_count + la0, ct);
 #pragma unroll
-        for (int w = 0; w < SW; ++w) s[w] = 0;
-        if (active) {
-            tr = p.in_trait[a];
-            ct = p.in_counter[a];
+        for (int w = 0; w < SW; ++w) store_lanes<APT>(l_surf + w * TA + la0, sf[w]);
+    }
+    __syncthreads();
+    if (MIGR) {
+        if (p.has_inbox) {
+            for (uint32_t il = t; il < nisl; il += blockDim.x) {
+                const uint32_t plan = l_plan[il];
+                if ((plan & 15u) == 0) continue;
+                const uint32_t isl = first_isl + il;
+                const uint32_t x = isl % W;
+                uint4 lo[4], hi[4];
 #pragma unroll
-            for (int w = 0; w < SW; ++w) s[w] = p.in_surf[w * A + a];
-        }
-
-        uint32_t em = 0;
-        if (MIGR) {
-            const uint32_t il_c = il < K ? il : 0u;
-            const uint32_t pl = __shfl(plan, (int)il_c);
-            em = __shfl(plan, (int)(K + il_c));
-            int src = -1;
+                for (int d = 0; d < 4; ++d) {
+                    if ((plan >> d) & 1u) {
+                        const uint32_t* e =
+                            p.ob_in + (size_t)neighbour_of(isl, x, d, W, p.I) * kOutboxWords;
+                        lo[d] = *reinterpret_cast<const uint4*>(e);
+                        if (SW > 1) hi[d] = *reinterpret_cast<const uint4*>(e + 4);
+                    }
+                }
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
-                if (((pl >> d) & 1u) && ((pl >> (4 + 6 * d)) & 63u) == j) src = d;
-            if (active && src >= 0) {
-                const uint32_t x = em >> 16;
-                uint32_t nb;
-                if (src == 0) nb = isl >= W ? isl - W : isl + p.I - W;
-                else if (src == 1) nb = isl + W < p.I ? isl + W : isl + W - p.I;
-                else if (src == 2) nb = x > 0 ? isl - 1 : isl + W - 1;
-                else nb = x + 1 < W ? isl + 1 : isl + 1 - W;
-                const uint32_t* e = p.ob_in + (size_t)nb * kOutboxWords;
-                tr = e[1];
-                ct = e[2];
-#pragma unroll
-                for (int w = 0; w < SW; ++w) s[w] = e[3 + w];
+                for (int d = 0; d < 4; ++d) {
+                    if ((plan >> d) & 1u) {
+                        const uint32_t la = il * N + ((plan >> (4 + 6 * d)) & 63u);
+                        l_trait[la] = lo[d].y;
+                        l_count[la] = lo[d].z;
+                        l_surf[la] = lo[d].w;
+                        if (SW > 1) l_surf[TA + la] = hi[d].x;
+                    }
+                }
             }
         }
+        __syncthreads();
+    }
 
-        // birth: selection, replication, mutation, surface ingest
+    // 3. births
+    const uint32_t site = *p.site;
+    const uint32_t site_word = site >> 5, site_shift = site & 31u;
+    if (!mine) return;
+    Lanes<APT> ctr, ccn, csf[SW];
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        const uint32_t la = la0 + q;
+        const uint32_t il = (la * p.div_magic) >> 20;   // la / N, exact for la < 4096
+        const uint32_t j = la - il * N;
+        const uint32_t isl = first_isl + il;
         const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
-        uint32_t par = word_below(r.x, N);
-        uint32_t ptrait = __shfl(tr, (int)(base + par));
+        const uint32_t base = il * N;
+        uint32_t par = base + word_below(r.x, N);
+        uint32_t ptrait = l_trait[par];
         if (SEL) {
-            const uint32_t pb = word_below(r.y, N);
-            const uint32_t tb = __shfl(tr, (int)(base + pb));
+            const uint32_t pb = base + word_below(r.y, N);
+            const uint32_t tb = l_trait[pb];
             if ((int32_t)tb > (int32_t)ptrait) {
                 par = pb;
                 ptrait = tb;
             }
         }
-        const uint32_t pcount = __shfl(ct, (int)(base + par));
-        uint32_t ps[SW];
-#pragma unroll
-        for (int w = 0; w < SW; ++w) ps[w] = __shfl(s[w], (int)(base + par));
-
         const uint32_t delta =
             r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo) : 0u;
-        const uint32_t ctrait = ptrait + delta;
-        const uint32_t ccount = pcount + 1u;
+        ctr.v[q] = ptrait + delta;
+        ccn.v[q] = l_count[par] + 1u;
         const uint32_t bit = r.w & 1u;
 #pragma unroll
-        for (int w = 0; w < SW; ++w)
-            if ((uint32_t)w == site_word)
-                ps[w] = (ps[w] & ~(1u << site_shift)) | (bit << site_shift);
-
-        if (active) {
-            p.out_trait[a] = ctrait;
-            p.out_counter[a] = ccount;
-#pragma unroll
-            for (int w = 0; w < SW; ++w) p.out_surf[w * A + a] = ps[w];
-            if (MIGR && j == (em & 0xffu)) {
+        for (int w = 0; w < SW; ++w) {
+            const uint32_t word = l_surf[w * TA + par];
+            csf[w].v[q] = (uint32_t)w == site_word
+                              ? (word & ~(1u << site_shift)) | (bit << site_shift)
+                              : word;
+        }
+        if (MIGR) {
+            const uint32_t em = l_emig[il];
+            if (j == (em & 0xffu)) {
                 uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
-                uint4 lo4 = make_uint4((em >> 8) & 3u, ctrait, ccount, ps[0]);
-                uint4 hi4 = make_uint4(SW > 1 ? ps[SW - 1] : 0u, 0u, 0u, 0u);
-                *reinterpret_cast<uint4*>(o) = lo4;
-                *reinterpret_cast<uint4*>(o + 4) = hi4;
+                *reinterpret_cast<uint4*>(o) =
+                    make_uint4((em >> 8) & 3u, ctr.v[q], ccn.v[q], csf[0].v[q]);
+                *reinterpret_cast<uint4*>(o + 4) =
+                    make_uint4(SW > 1 ? csf[SW - 1].v[q] : 0u, 0u, 0u, 0u);
             }
         }
     }
+    store_lanes<APT>(p.out_trait + a0 + la0, ctr);
+    store_lanes<APT>(p.out_counter + a0 + la0, ccn);
+#pragma unroll
+    for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
 }
 
-template <int SW, bool SEL, bool MIGR>
+size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
+    return ((size_t)(2 + SW) * tile_isl * N + 2 * (size_t)tile_isl) * 4;
+}
+
+template <int SW, bool SEL, bool MIGR, int APT>
 static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
-    const uint32_t waves = (p.I + p.K - 1) / p.K;
-    const uint32_t wpb = block_threads / 64;
-    const uint32_t blocks = (waves + wpb - 1) / wpb;
-    hipLaunchKernelGGL((step_kernel<SW, SEL, MIGR>), dim3(blocks), dim3(block_threads), 0, stream,
-                       p);
+    const uint32_t tiles = (p.I + p.tile_isl - 1) / p.tile_isl;
+    const size_t lds = step_lds_bytes(p.tile_isl, p.N, SW);
+    hipLaunchKernelGGL((step_kernel<SW, SEL, MIGR, APT>), dim3(tiles), dim3(block_threads), lds,
+                       stream, p);
     return hipGetLastError();
 }
 
+template <int SW, bool SEL, bool MIGR>
+static hipError_t launch_step_apt(const StepParams& p, uint32_t apt, uint32_t block_threads,
+                                  hipStream_t stream) {
+    if (apt == 4) return launch_step_t<SW, SEL, MIGR, 4>(p, block_threads, stream);
+    if (apt == 2) return launch_step_t<SW, SEL, MIGR, 2>(p, block_threads, stream);
+    return launch_step_t<SW, SEL, MIGR, 1>(p, block_threads, stream);
+}
+
 hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
-                       uint32_t block_threads, hipStream_t stream) {
+                       uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream) {
+    const uint32_t apt = agents_per_thread;
     if (SW == 1) {
         if (selection)
-            return migration ? launch_step_t<1, true, true>(p, block_threads, stream)
-                             : launch_step_t<1, true, false>(p, block_threads, stream);
-        return migration ? launch_step_t<1, false, true>(p, block_threads, stream)
-                         : launch_step_t<1, false, false>(p, block_threads, stream);
+            return migration ? launch_step_apt<1, true, true>(p, apt, block_threads, stream)
+                             : launch_step_apt<1, true, false>(p, apt, block_threads, stream);
+        return migration ? launch_step_apt<1, false, true>(p, apt, block_threads, stream)
+                         : launch_step_apt<1, false, false>(p, apt, block_threads, stream);
     }
     if (selection)
-        return migration ? launch_step_t<2, true, true>(p, block_threads, stream)
-                         : launch_step_t<2, true, false>(p, block_threads, stream);
-    return migration ? launch_step_t<2, false, true>(p, block_threads, stream)
-                     : launch_step_t<2, false, false>(p, block_threads, stream);
+        return migration ? launch_step_apt<2, true, true>(p, apt, block_threads, stream)
+                         : launch_step_apt<2, true, false>(p, apt, block_threads, stream);
+    return migration ? launch_step_apt<2, false, true>(p, apt, block_threads, stream)
+                     : launch_step_apt<2, false, false>(p, apt, block_threads, stream);
 }
 
 // ---------------------------------------------------------------------------

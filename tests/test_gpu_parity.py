@@ -93,14 +93,24 @@ def test_no_mutation_and_wide_mutation(hs, orc):
         assert_same_state(g, o, f"thr={thr} [{lo},{hi}]")
 
 
-@pytest.mark.parametrize("K,block", [(1, 64), (2, 128), (3, 256), (8, 1024), (16, 192),
-                                     (32, 256), (32, 1024)])
-def test_launch_shape_invariance(hs, orc, K, block):
+@pytest.mark.parametrize("block,apt", [(64, 1), (128, 2), (256, 4), (1024, 2), (192, 2),
+                                       (1024, 1), (512, 4), (64, 4)])
+def test_launch_shape_invariance(hs, orc, block, apt):
     g, o = make_pair(hs, orc, 16, 12, 32, 64, "hybrid", seed=13)
-    g.set_launch_shape(K, block)
+    g.set_launch_shape(block, apt)
     g.step(75)
     o.step(75)
-    assert_same_state(g, o, f"K={K} block={block}")
+    assert_same_state(g, o, f"block={block} apt={apt}")
+
+
+def test_launch_shape_rejects_bad_shapes(hs):
+    g = hs.Run(hs.Config(4, 4, 48, 32, "steady"))
+    for block, apt in ((100, 4), (2048, 4), (256, 3), (256, 32)):
+        with pytest.raises(hs.HsgaError):
+            g.set_launch_shape(block, apt)
+    g2 = hs.Run(hs.Config(4, 4, 17, 32, "steady"))
+    with pytest.raises(hs.HsgaError):
+        g2.set_launch_shape(256, 2)       # 2 does not divide 17
 
 
 def test_chunked_site_schedule(hs, orc):
@@ -153,7 +163,7 @@ def test_determinism_across_runs(hs):
     cfg = hs.Config(16, 16, 32, 64, "hybrid", seed=99)
     a = hs.Run(cfg)
     b = hs.Run(cfg)
-    b.set_launch_shape(5, 512)
+    b.set_launch_shape(512, 2)
     a.step(300)
     b.step(300)
     for x, y in zip(a.agents(), b.agents()):
