@@ -169,7 +169,7 @@ int ga_create(const ga_config* cfg, void* dev_arena, size_t arena_bytes,
     r->T = 0;
     r->horizon = hsga::horizon_of(cfg->surface_kind, r->S);
     r->apt = default_agents_per_thread(r->N);
-    r->block = 256;
+    r->block = r->apt == 4 ? 64u : 256u;   // small tiles: more workgroups in flight per CU
     r->timing = false;
     hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
                                          r->layout, r->S, r->stream);
@@ -335,10 +335,10 @@ int ga_sample(ga_run* r, uint32_t n, uint32_t* dev_idx, uint32_t* dev_counter,
 void ga_destroy(ga_run* r) {
     if (!r) return;
     for (auto& s : r->spans) {
-        hipEventDestroy(s.start);
-        hipEventDestroy(s.stop);
+        (void)hipEventDestroy(s.start);
+        (void)hipEventDestroy(s.stop);
     }
-    for (auto e : r->spare) hipEventDestroy(e);
+    for (auto e : r->spare) (void)hipEventDestroy(e);
     delete r;
 }
 

@@ -20,7 +20,12 @@ constexpr uint32_t kOutboxWords = 8;
 // 0 and 2 with the Philox multipliers, swaps the halves across the two
 // lanes of the block and folds in the key; the key advances by the Weyl
 // increments after every round.  The key is wave-uniform, so its schedule
-// stays in scalar registers.
+// stays in scalar registers.  Each three-way XOR is one v_bitop3_b32
+// (truth table 0x96) on gfx950.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
@@ -28,7 +33,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
         const uint64_t prod1 = (uint64_t)c.z * 0xCD9E8D57u;
         const uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
         const uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        c = make_uint4(xor3(hi1, c.y, k0), lo1, xor3(hi0, c.w, k1), lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }

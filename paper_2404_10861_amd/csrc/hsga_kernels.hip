@@ -97,17 +97,22 @@ struct Lanes {
     uint32_t v[APT];
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Population planes stream through once per generation: global accesses
+// carry the non-temporal hint.  LDS accesses are APT-word aligned.
 template <int APT>
 __device__ __forceinline__ Lanes<APT> load_lanes(const uint32_t* __restrict__ src) {
     Lanes<APT> r;
     if constexpr (APT == 4) {
-        const uint4 x = *reinterpret_cast<const uint4*>(src);
+        const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
         r.v[0] = x.x; r.v[1] = x.y; r.v[2] = x.z; r.v[3] = x.w;
     } else if constexpr (APT == 2) {
-        const uint2 x = *reinterpret_cast<const uint2*>(src);
+        const u32x2 x = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(src));
         r.v[0] = x.x; r.v[1] = x.y;
     } else {
-        r.v[0] = *src;
+        r.v[0] = __builtin_nontemporal_load(src);
     }
     return r;
 }
@@ -115,9 +120,23 @@ __device__ __forceinline__ Lanes<APT> load_lanes(const uint32_t* __restrict__ sr
 template <int APT>
 __device__ __forceinline__ void store_lanes(uint32_t* __restrict__ dst, const Lanes<APT>& r) {
     if constexpr (APT == 4) {
-        *reinterpret_cast<uint4*>(dst) = make_uint4(r.v[0], r.v[1], r.v[2], r.v[3]);
+        u32x4 x = {r.v[0], r.v[1], r.v[2], r.v[3]};
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(dst));
     } else if constexpr (APT == 2) {
-        *reinterpret_cast<uint2*>(dst) = make_uint2(r.v[0], r.v[1]);
+        u32x2 x = {r.v[0], r.v[1]};
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x2*>(dst));
+    } else {
+        __builtin_nontemporal_store(r.v[0], dst);
+    }
+}
+
+template <int APT>
+__device__ __forceinline__ void lds_store_lanes(uint32_t* dst, const Lanes<APT>& r) {
+    if constexpr (APT == 4) {
+        *reinterpret_cast<u32x4*>(__builtin_assume_aligned(dst, 16)) =
+            u32x4{r.v[0], r.v[1], r.v[2], r.v[3]};
+    } else if constexpr (APT == 2) {
+        *reinterpret_cast<u32x2*>(__builtin_assume_aligned(dst, 8)) = u32x2{r.v[0], r.v[1]};
     } else {
         *dst = r.v[0];
     }
@@ -134,9 +153,9 @@ __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint3
 
 template <int SW, bool SEL, bool MIGR, int APT>
 __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const uint32_t N = p.N, W = p.W;
-    const uint32_t TA = p.tile_isl * N;                // agents in a full tile
+    const uint32_t TA = (p.tile_isl * N + 3u) & ~3u;   // plane stride (16-byte multiple)
     uint32_t* l_trait = lds;
     uint32_t* l_count = lds + TA;
     uint32_t* l_surf = lds + 2 * TA;                   // SW planes of TA words
@@ -193,10 +212,10 @@ __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
 
     // 2. stage the tile in LDS, then overwrite immigrant slots
     if (mine) {
-        store_lanes<APT>(l_trait + la0, tr);
-        store_lanes<APT>(l_count + la0, ct);
+        lds_store_lanes<APT>(l_trait + la0, tr);
+        lds_store_lanes<APT>(l_count + la0, ct);
 #pragma unroll
-        for (int w = 0; w < SW; ++w) store_lanes<APT>(l_surf + w * TA + la0, sf[w]);
+        for (int w = 0; w < SW; ++w) lds_store_lanes<APT>(l_surf + w * TA + la0, sf[w]);
     }
     __syncthreads();
     if (MIGR) {
@@ -284,7 +303,8 @@ __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
 }
 
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
-    return ((size_t)(2 + SW) * tile_isl * N + 2 * (size_t)tile_isl) * 4;
+    const size_t TA = ((size_t)tile_isl * N + 3) & ~(size_t)3;
+    return ((2 + SW) * TA + 2 * (size_t)tile_isl) * 4;
 }
 
 template <int SW, bool SEL, bool MIGR, int APT>
