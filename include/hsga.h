@@ -208,6 +208,13 @@ int ga_set_kernel_timing(ga_run *run, int enable);
  * since timing was enabled (or last reset with reset = 1).                 */
 int ga_kernel_time(ga_run *run, double *ms, uint64_t *launches, int reset);
 
+/* A plain device-to-device copy of `bytes` bytes (multiple of 16; both
+ * pointers 16-byte aligned), one 16-byte load and store per lane, no cache
+ * hints.  Not part of the method: it measures the attainable HBM bandwidth
+ * next to the step kernel and calibrates hardware byte counters against a
+ * kernel of known traffic.  Enqueued on hip_stream.  Errors: GA_EINVAL.   */
+int ga_probe_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 /* Launch shape of the step kernel: threads per workgroup (multiple of 64,
  * 64..1024) and agents per thread (1, 2 or 4; must divide pop_per_island;
  * 4 gives 16-byte population loads and stores).  A workgroup handles a

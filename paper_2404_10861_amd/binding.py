@@ -28,7 +28,7 @@ EXPORTS = (
     "ga_read_agents", "ga_read_outbox", "ga_read_layout", "ga_sample",
     "ga_destroy", "ga_last_error", "hstrat_mrca_workspace_bytes",
     "hstrat_mrca_bounds", "hstrat_mrca_status", "ga_set_kernel_timing",
-    "ga_kernel_time", "ga_set_launch_shape",
+    "ga_kernel_time", "ga_set_launch_shape", "ga_probe_copy",
 )
 
 
@@ -93,6 +93,7 @@ def load_library():
         "ga_kernel_time": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
         "ga_set_launch_shape": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
+        "ga_probe_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -324,6 +325,14 @@ def mrca_bounds(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor
 def mrca_status(workspace: MrcaWorkspace, stream=None) -> int:
     rc = load_library().hstrat_mrca_status(_vp(workspace.ptr), _vp(_stream_handle(stream)))
     return rc
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    """Plain 16-byte-per-lane device copy of src into dst (instrumentation)."""
+    nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size()) & ~15
+    _check(load_library().ga_probe_copy(_vp(src.data_ptr()), _vp(dst.data_ptr()), nbytes,
+                                        _vp(_stream_handle(stream))))
+    return nbytes
 
 
 def as_u32(t: torch.Tensor) -> np.ndarray:

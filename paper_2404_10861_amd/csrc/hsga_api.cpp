@@ -407,6 +407,15 @@ int ga_kernel_time(ga_run* r, double* ms, uint64_t* launches, int reset) {
     return GA_OK;
 }
 
+int ga_probe_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+    if (!src || !dst) return fail(GA_EINVAL, "NULL pointer");
+    if (bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)dst % 16)
+        return fail(GA_EINVAL, "copy needs 16-byte multiples and alignment");
+    hipError_t e = hsga::launch_probe_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "copy launch");
+    return GA_OK;
+}
+
 int ga_set_launch_shape(ga_run* r, uint32_t block_threads, uint32_t agents_per_thread) {
     if (!r) return fail(GA_EINVAL, "run is NULL");
     const uint32_t block = block_threads ? block_threads : r->block;

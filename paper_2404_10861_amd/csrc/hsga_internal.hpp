@@ -46,6 +46,8 @@ hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t
                          uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,
                          uint32_t* counter_out, uint32_t* surf_out, hipStream_t stream);
 
+hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+
 // Workspace layout of the MRCA kernels (bytes).
 struct MrcaWorkspace {
     static constexpr size_t kHeader = 2048;   // flags, T, F, rank tables

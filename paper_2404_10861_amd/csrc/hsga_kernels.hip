@@ -342,6 +342,26 @@ hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool mi
 }
 
 // ---------------------------------------------------------------------------
+// Plain streaming copy (instrumentation): one 16-byte load and store per
+// lane per iteration, grid-stride.
+__global__ __launch_bounds__(256) void probe_copy_kernel(const uint4* __restrict__ src,
+                                                        uint4* __restrict__ dst, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = src[i];
+}
+
+hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
+    const size_t n16 = bytes / 16;
+    size_t blocks = (n16 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_copy_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Stratified end-of-run sample (Results, On-hardware Trial): agent k is
 // drawn uniformly from the k-th of n equal strata; every agent when A <= n.
 __global__ __launch_bounds__(256) void sample_kernel(const uint32_t* __restrict__ counter,

@@ -1,0 +1,175 @@
+"""Summaries of rocprofv3 output for the profiles/ directory.
+
+Reads the CSV files rocprofv3 writes (--kernel-trace --stats, and --pmc
+FETCH_SIZE or WRITE_SIZE runs) and writes short text summaries:
+
+  python -m paper_2404_10861_amd.profiling stats DIR --out FILE.md --cmd "..."
+  python -m paper_2404_10861_amd.profiling traffic --fetch DIR --write DIR
+        --copy-bytes B --kernel step_kernel --bytes-per-launch X
+        --out FILE.json --md FILE.md --cmd "..." --cmd "..."
+
+The traffic summary scales each counter by what the same counter reads for
+the plain copy kernel of known size (bytes read, bytes written), giving HBM
+bytes per launch of the step kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_10861_amd", "csrc", f)
+                  for f in ("hsga_kernels.hip", "hsga_device.hpp")]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _find(d: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[-1]
+
+
+def kernel_stats(d: str):
+    rows = []
+    with open(_find(d, "kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append(r)
+    return rows
+
+
+def counter_values(d: str, counter: str):
+    """{kernel name: [value per dispatch]} of one counter."""
+    out: dict[str, list[float]] = {}
+    with open(_find(d, "counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _pick(values: dict, needle: str):
+    keys = [k for k in values if needle in k]
+    if not keys:
+        raise KeyError(f"no kernel matching {needle!r}: {list(values)}")
+    vals = []
+    for k in keys:
+        vals.extend(values[k])
+    return keys, vals
+
+
+def cmd_stats(a):
+    rows = kernel_stats(a.dir)
+    lines = [f"# rocprofv3 kernel statistics: {a.title}", "", "Command:", ""]
+    for c in a.cmd:
+        lines.append(f"    {c}")
+    lines += ["", "| kernel | calls | average us | min us | max us | total ms | % |",
+              "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"]
+        if len(name) > 90:
+            name = name[:87] + "..."
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    text = "\n".join(lines) + "\n"
+    with open(a.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+def cmd_traffic(a):
+    fetch = counter_values(a.fetch, "FETCH_SIZE")
+    write = counter_values(a.write, "WRITE_SIZE")
+    _, cf = _pick(fetch, "probe_copy")
+    _, cw = _pick(write, "probe_copy")
+    copy_kib = a.copy_bytes / 1024.0
+    f_factor = copy_kib / statistics.median(cf)
+    w_factor = copy_kib / statistics.median(cw)
+    names, sf = _pick(fetch, a.kernel)
+    _, sw = _pick(write, a.kernel)
+    # the first dispatch of a run reads no outboxes; use the median
+    fetch_b = statistics.median(sf) * 1024.0 * f_factor
+    write_b = statistics.median(sw) * 1024.0 * w_factor
+    rec = {
+        "kernel": a.kernel,
+        "kernel_names": names,
+        "kernel_hash": kernel_hash(),
+        "fetch_kib_per_dispatch_median": statistics.median(sf),
+        "write_kib_per_dispatch_median": statistics.median(sw),
+        "dispatches": len(sf),
+        "copy_bytes": a.copy_bytes,
+        "copy_fetch_kib_median": statistics.median(cf),
+        "copy_write_kib_median": statistics.median(cw),
+        "fetch_scale": f_factor,
+        "write_scale": w_factor,
+        "fetch_bytes_per_launch": fetch_b,
+        "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "algorithmic_bytes_per_launch": a.bytes_per_launch,
+        "traffic_over_algorithmic": (fetch_b + write_b) / a.bytes_per_launch,
+        "commands": a.cmd,
+    }
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"# HBM traffic of `{a.kernel}`: {a.title}", "", "Commands:", ""]
+    for c in a.cmd:
+        lines.append(f"    {c}")
+    lines += ["",
+              f"- copy kernel of {a.copy_bytes} bytes: FETCH_SIZE {rec['copy_fetch_kib_median']:.0f} KiB, "
+              f"WRITE_SIZE {rec['copy_write_kib_median']:.0f} KiB per dispatch -> scale "
+              f"{f_factor:.4f} (fetch), {w_factor:.4f} (write)",
+              f"- step kernel ({len(sf)} dispatches, median): FETCH_SIZE "
+              f"{rec['fetch_kib_per_dispatch_median']:.0f} KiB, WRITE_SIZE "
+              f"{rec['write_kib_per_dispatch_median']:.0f} KiB",
+              f"- HBM bytes per launch: read {fetch_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB "
+              f"= {(fetch_b + write_b) / 1e6:.1f} MB",
+              f"- algorithmic bytes per launch: {a.bytes_per_launch / 1e6:.1f} MB; measured / "
+              f"algorithmic = {rec['traffic_over_algorithmic']:.3f}",
+              f"- kernel source hash: {rec['kernel_hash']}", ""]
+    with open(a.md, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="")
+    s.add_argument("--cmd", action="append", default=[])
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--kernel", default="step_kernel")
+    t.add_argument("--bytes-per-launch", type=float, required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--md", required=True)
+    t.add_argument("--title", default="")
+    t.add_argument("--cmd", action="append", default=[])
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        cmd_stats(a)
+    else:
+        cmd_traffic(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
