@@ -196,6 +196,75 @@ int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n,
 int hstrat_mrca_status(const void *workspace, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Batched and served runs: a pool of runs of any sizes, surfaces and
+ * treatments sharing one caller-owned device arena and one stream.  An
+ * advance enqueues one site-schedule launch for all active runs, then one
+ * step launch per generation covering every active run's tiles; each run
+ * takes the same steps as under ga_step, so its results are identical to
+ * running it alone.  Admission is by footprint: a run gets a first-fit
+ * range of the arena or is refused.  Runs are identified by small integer
+ * ids, reused after release.  All work is ordered on the pool's stream.
+ * ------------------------------------------------------------------------ */
+typedef struct ga_pool ga_pool;
+
+/* Arena bytes the pool keeps for its own tables (max_runs <= 256). */
+size_t ga_pool_overhead_bytes(uint32_t max_runs);
+
+/* dev_arena: device, 256-byte aligned, at least ga_pool_overhead_bytes;
+ * the rest holds runs.  max_gens_per_launch caps the generations of one
+ * advance (0: 4096) and sizes each run's site schedule.  hip_stream must
+ * be a created stream (not the null stream) for hipGraph replay.
+ * Errors: GA_EINVAL, GA_ENOMEM (arena below the overhead), GA_EDEVICE.    */
+int ga_pool_create(void *dev_arena, size_t arena_bytes, uint32_t max_runs,
+                   uint32_t max_gens_per_launch, void *hip_stream, ga_pool **out);
+
+/* Arena bytes a run of cfg takes in this pool (0 if cfg is invalid). */
+size_t ga_pool_footprint(const ga_pool *pool, const ga_config *cfg);
+
+/* Admit a run of cfg that stops after n_generations and enqueue its
+ * founders.  Errors: GA_EINVAL (cfg, n = 0), GA_EHORIZON (n past the
+ * site rule's horizon), GA_EBUSY (no free slot or no free range of its
+ * footprint; nothing is changed).                                          */
+int ga_pool_admit(ga_pool *pool, const ga_config *cfg, uint32_t n_generations,
+                  uint32_t *id);
+
+/* Enqueue up to max_gens generations of every admitted run that has not
+ * reached its generation count; *gens_enqueued (may be NULL) receives the
+ * largest number enqueued for any run (0 when none is active).            */
+int ga_pool_advance(ga_pool *pool, uint32_t max_gens, uint32_t *gens_enqueued);
+
+/* Ids of runs whose last generation has been enqueued and that were not
+ * reported before (at most cap).  Work enqueued later on the pool's stream
+ * (ga_sample, hstrat_mrca_bounds) sees their final state; host reads
+ * block until it is reached.                                              */
+int ga_pool_poll(ga_pool *pool, uint32_t *ids, uint32_t cap, uint32_t *n);
+
+/* The run handle of an admitted run, owned by the pool until release: use
+ * it with ga_generation, ga_read_agents, ga_read_outbox, ga_read_layout,
+ * ga_sample (not with ga_step or ga_destroy).                              */
+int ga_pool_run(ga_pool *pool, uint32_t id, ga_run **run);
+
+/* Return the run's arena range and slot.  Work already enqueued on the
+ * pool's stream completes first; later runs reuse the memory after it.    */
+int ga_pool_release(ga_pool *pool, uint32_t id);
+
+/* Block until all work enqueued on the pool's stream has finished. */
+int ga_pool_sync(ga_pool *pool);
+
+/* Workgroup size of batched step launches (multiple of 64, 64..256; 0
+ * keeps it) and whether an advance replays a captured hipGraph of its
+ * launches when the run set's launch shape repeats (1) or launches
+ * directly (0).                                                            */
+int ga_pool_set_launch(ga_pool *pool, uint32_t block_threads, int use_graph);
+
+/* Occupancy: active runs, admitted runs, free bytes, largest free range. */
+int ga_pool_info(const ga_pool *pool, uint32_t *active, uint32_t *admitted,
+                 size_t *free_bytes, size_t *largest_free);
+
+/* Release every run and the pool's host state; the arena is untouched. */
+void ga_pool_destroy(ga_pool *pool);
+
+/* ------------------------------------------------------------------------
  * Instrumentation
  * ------------------------------------------------------------------------ */
 

@@ -29,6 +29,9 @@ EXPORTS = (
     "ga_destroy", "ga_last_error", "hstrat_mrca_workspace_bytes",
     "hstrat_mrca_bounds", "hstrat_mrca_status", "ga_set_kernel_timing",
     "ga_kernel_time", "ga_set_launch_shape", "ga_probe_copy",
+    "ga_pool_overhead_bytes", "ga_pool_create", "ga_pool_footprint", "ga_pool_admit",
+    "ga_pool_advance", "ga_pool_poll", "ga_pool_run", "ga_pool_release", "ga_pool_sync",
+    "ga_pool_set_launch", "ga_pool_info", "ga_pool_destroy",
 )
 
 
@@ -94,6 +97,20 @@ def load_library():
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
         "ga_set_launch_shape": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
         "ga_probe_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
+        "ga_pool_overhead_bytes": (ctypes.c_size_t, [ctypes.c_uint32]),
+        "ga_pool_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32,
+                                          _vp, ctypes.POINTER(_vp)]),
+        "ga_pool_footprint": (ctypes.c_size_t, [_vp, cfgp]),
+        "ga_pool_admit": (ctypes.c_int, [_vp, cfgp, ctypes.c_uint32, _u32p]),
+        "ga_pool_advance": (ctypes.c_int, [_vp, ctypes.c_uint32, _u32p]),
+        "ga_pool_poll": (ctypes.c_int, [_vp, _vp, ctypes.c_uint32, _u32p]),
+        "ga_pool_run": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.POINTER(_vp)]),
+        "ga_pool_release": (ctypes.c_int, [_vp, ctypes.c_uint32]),
+        "ga_pool_sync": (ctypes.c_int, [_vp]),
+        "ga_pool_set_launch": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_int]),
+        "ga_pool_info": (ctypes.c_int, [_vp, _u32p, _u32p, ctypes.POINTER(ctypes.c_size_t),
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+        "ga_pool_destroy": (None, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -176,56 +193,24 @@ def _aligned_bytes(nbytes: int, device) -> tuple:
     return buf, buf.data_ptr() + off
 
 
-class Run:
-    """One GA run on the GPU; the arena is a torch uint8 tensor it owns
-    (or the caller's, via ``arena``)."""
+class RunHandle:
+    """Read and sample operations on a run handle (owned or borrowed)."""
 
-    def __init__(self, cfg: Config, max_gens_per_launch: int = 0, device="cuda",
-                 stream=None, arena: torch.Tensor | None = None):
-        lib = load_library()
+    _h = None
+
+    def _setup(self, cfg: Config, device):
         self.cfg = cfg
         self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        need = footprint_bytes(cfg, max_gens_per_launch)
-        if arena is None:
-            self._arena, ptr = _aligned_bytes(need, self.device)
-            nbytes = need
-        else:
-            if arena.dtype != torch.uint8 or not arena.is_cuda:
-                raise ValueError("arena must be a CUDA uint8 tensor")
-            self._arena, ptr, nbytes = arena, arena.data_ptr(), arena.numel()
-        self._c = cfg.to_c()
-        h = _vp()
-        _check(lib.ga_create(ctypes.byref(self._c), _vp(ptr), nbytes, max_gens_per_launch,
-                             _vp(_stream_handle(self.stream)), ctypes.byref(h)))
-        self._h = h
         self.S = cfg.surface_sites
         self.SW = self.S // 32
         self.A = cfg.agents
         self.I = cfg.islands
-
-    def close(self):
-        if getattr(self, "_h", None):
-            load_library().ga_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
 
     @property
     def generation(self) -> int:
         T = ctypes.c_uint32()
         _check(load_library().ga_generation(self._h, ctypes.byref(T)))
         return T.value
-
-    def step(self, n: int = 1):
-        _check(load_library().ga_step(self._h, n))
-
-    def sync(self):
-        _check(load_library().ga_sync(self._h))
 
     def agents(self, first: int = 0, count: int | None = None):
         """(trait, counter, surface[count, S/32]) as numpy uint32 (blocking)."""
@@ -255,17 +240,61 @@ class Run:
         _check(load_library().ga_read_layout(self._h, _ptr(L)))
         return L
 
-    def sample(self, n: int):
+    def sample(self, n: int, out=None):
         """Stratified sample on the device: (idx, counter, surface[n, S/32])
         as int32 CUDA tensors holding the uint32 bit patterns."""
-        idx = torch.empty(n, dtype=torch.int32, device=self.device)
-        cnt = torch.empty(n, dtype=torch.int32, device=self.device)
-        srf = torch.empty((n, self.SW), dtype=torch.int32, device=self.device)
+        if out is None:
+            idx = torch.empty(n, dtype=torch.int32, device=self.device)
+            cnt = torch.empty(n, dtype=torch.int32, device=self.device)
+            srf = torch.empty((n, self.SW), dtype=torch.int32, device=self.device)
+        else:
+            idx, cnt, srf = out
         taken = ctypes.c_uint32()
         _check(load_library().ga_sample(self._h, n, _vp(idx.data_ptr()), _vp(cnt.data_ptr()),
                                         _vp(srf.data_ptr()), ctypes.byref(taken)))
         k = taken.value
         return idx[:k], cnt[:k], srf[:k]
+
+
+class Run(RunHandle):
+    """One GA run on the GPU; the arena is a torch uint8 tensor it owns
+    (or the caller's, via ``arena``)."""
+
+    def __init__(self, cfg: Config, max_gens_per_launch: int = 0, device="cuda",
+                 stream=None, arena: torch.Tensor | None = None):
+        lib = load_library()
+        self._setup(cfg, device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        need = footprint_bytes(cfg, max_gens_per_launch)
+        if arena is None:
+            self._arena, ptr = _aligned_bytes(need, self.device)
+            nbytes = need
+        else:
+            if arena.dtype != torch.uint8 or not arena.is_cuda:
+                raise ValueError("arena must be a CUDA uint8 tensor")
+            self._arena, ptr, nbytes = arena, arena.data_ptr(), arena.numel()
+        self._c = cfg.to_c()
+        h = _vp()
+        _check(lib.ga_create(ctypes.byref(self._c), _vp(ptr), nbytes, max_gens_per_launch,
+                             _vp(_stream_handle(self.stream)), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ga_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        _check(load_library().ga_step(self._h, n))
+
+    def sync(self):
+        _check(load_library().ga_sync(self._h))
 
     def set_kernel_timing(self, enable: bool = True):
         _check(load_library().ga_set_kernel_timing(self._h, 1 if enable else 0))
@@ -280,6 +309,104 @@ class Run:
 
     def set_launch_shape(self, block_threads: int = 0, agents_per_thread: int = 0):
         _check(load_library().ga_set_launch_shape(self._h, block_threads, agents_per_thread))
+
+
+class PoolRun(RunHandle):
+    """A run admitted to a Pool (borrowed handle, valid until released)."""
+
+    def __init__(self, pool: "Pool", run_id: int, cfg: Config):
+        h = _vp()
+        _check(load_library().ga_pool_run(pool._h, run_id, ctypes.byref(h)))
+        self._h = h
+        self.id = run_id
+        self._setup(cfg, pool.device)
+
+
+class Pool:
+    """Batched / served runs sharing one device arena and one stream."""
+
+    def __init__(self, arena_bytes: int, max_runs: int = 256, max_gens_per_launch: int = 0,
+                 device="cuda", stream=None, block_threads: int = 64, use_graph: bool = False):
+        lib = load_library()
+        self.device = torch.device(device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.device)
+        self.stream = stream
+        self._arena, ptr = _aligned_bytes(arena_bytes, self.device)
+        h = _vp()
+        _check(lib.ga_pool_create(_vp(ptr), arena_bytes, max_runs, max_gens_per_launch,
+                                  _vp(_stream_handle(stream)), ctypes.byref(h)))
+        self._h = h
+        self.cfgs: dict[int, Config] = {}
+        self._c: dict[int, ga_config] = {}
+        self.set_launch(block_threads, use_graph)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ga_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, block_threads: int = 0, use_graph: bool = False):
+        _check(load_library().ga_pool_set_launch(self._h, block_threads, 1 if use_graph else 0))
+
+    def footprint(self, cfg: Config) -> int:
+        c = cfg.to_c()
+        return int(load_library().ga_pool_footprint(self._h, ctypes.byref(c)))
+
+    def admit(self, cfg: Config, n_generations: int):
+        """The new run's id, or None when its footprint does not fit now."""
+        c = cfg.to_c()
+        rid = ctypes.c_uint32()
+        rc = load_library().ga_pool_admit(self._h, ctypes.byref(c), n_generations,
+                                          ctypes.byref(rid))
+        if rc == GA_EBUSY:
+            return None
+        _check(rc)
+        self.cfgs[rid.value] = cfg
+        self._c[rid.value] = c
+        return rid.value
+
+    def advance(self, max_gens: int) -> int:
+        n = ctypes.c_uint32()
+        _check(load_library().ga_pool_advance(self._h, max_gens, ctypes.byref(n)))
+        return n.value
+
+    def poll(self) -> list[int]:
+        ids = (ctypes.c_uint32 * 256)()
+        n = ctypes.c_uint32()
+        _check(load_library().ga_pool_poll(self._h, ctypes.cast(ids, _vp), 256, ctypes.byref(n)))
+        return [ids[i] for i in range(n.value)]
+
+    def run(self, run_id: int) -> PoolRun:
+        return PoolRun(self, run_id, self.cfgs[run_id])
+
+    def release(self, run_id: int):
+        _check(load_library().ga_pool_release(self._h, run_id))
+        self.cfgs.pop(run_id, None)
+        self._c.pop(run_id, None)
+
+    def sync(self):
+        _check(load_library().ga_pool_sync(self._h))
+
+    def info(self) -> dict:
+        a = ctypes.c_uint32()
+        u = ctypes.c_uint32()
+        fb = ctypes.c_size_t()
+        lf = ctypes.c_size_t()
+        _check(load_library().ga_pool_info(self._h, ctypes.byref(a), ctypes.byref(u),
+                                           ctypes.byref(fb), ctypes.byref(lf)))
+        return {"active": a.value, "admitted": u.value, "free_bytes": fb.value,
+                "largest_free": lf.value}
+
+
+def pool_overhead_bytes(max_runs: int) -> int:
+    return int(load_library().ga_pool_overhead_bytes(max_runs))
 
 
 class MrcaWorkspace:
@@ -308,7 +435,7 @@ def mrca_bounds(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor
         raise ValueError("counter and surface_words must be int32 tensors")
     counter = counter.contiguous()
     surface_words = surface_words.contiguous()
-    if workspace is None or workspace.n < n or workspace.S != S:
+    if workspace is None or workspace.n < n or workspace.S < S:
         workspace = MrcaWorkspace(S, n, dev)
     if lb is None:
         lb = torch.empty((n, n), dtype=torch.int32, device=dev)

@@ -12,7 +12,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhsga.so")
-SOURCES = [os.path.join(CSRC, "hsga_kernels.hip"), os.path.join(CSRC, "hsga_api.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("hsga_kernels.hip", "hsga_api.cpp", "hsga_pool.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

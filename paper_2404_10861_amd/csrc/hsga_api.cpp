@@ -10,13 +10,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hsga.h"
-#include "hsga_device.hpp"
-#include "hsga_internal.hpp"
+#include "hsga_host.hpp"
+
+namespace hsga_host {
 
 namespace {
-
 thread_local std::string g_last_error;
+}
 
 int fail(int status, const std::string& msg) {
     g_last_error = msg;
@@ -27,16 +27,8 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(GA_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-constexpr uint32_t kDefaultGens = 4096;
-constexpr size_t kAlign = 256;
+const char* last_error() { return g_last_error.c_str(); }
 
-size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
-
-struct Carve {
-    size_t trait, counter, surf, outbox, layout, sites, total;
-};
-
-// Byte offsets of each buffer in the arena.
 Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens) {
     const size_t A = (size_t)I * N;
     const size_t SW = S / 32;
@@ -76,28 +68,77 @@ int validate(const ga_config* cfg) {
     return GA_OK;
 }
 
+namespace {
+uint32_t default_agents_per_thread(uint32_t N) {
+    return N % 4 == 0 ? 4u : (N % 2 == 0 ? 2u : 1u);
+}
 }  // namespace
 
-struct ga_run {
-    ga_config cfg;
-    uint32_t I, A, N, S, SW;
-    hipStream_t stream;
-    uint32_t* trait[2];
-    uint32_t* counter[2];
-    uint32_t* surf[2];
-    uint32_t* outbox[2];
-    uint32_t* layout;
-    uint32_t* sites;
-    uint32_t gens;       // site schedule capacity
-    uint32_t T;          // generations enqueued
-    uint64_t horizon;
-    uint32_t apt;        // agents per thread (1, 2, 4; divides N)
-    uint32_t block;      // workgroup threads
-    bool timing;
-    struct Span { hipEvent_t start, stop; uint32_t launches; };
-    std::vector<Span> spans;
-    std::vector<hipEvent_t> spare;
-};
+int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipStream_t stream) {
+    const uint32_t I = cfg->grid_w * cfg->grid_h;
+    const Carve c = carve(I, cfg->pop_per_island, cfg->surface_sites, gens);
+    r->cfg = *cfg;
+    r->I = I;
+    r->N = cfg->pop_per_island;
+    r->A = I * r->N;
+    r->S = cfg->surface_sites;
+    r->SW = r->S / 32;
+    r->stream = stream;
+    const size_t A = r->A;
+    for (int b = 0; b < 2; ++b) {
+        r->trait[b] = reinterpret_cast<uint32_t*>(base + c.trait + b * align_up(A * 4));
+        r->counter[b] = reinterpret_cast<uint32_t*>(base + c.counter + b * align_up(A * 4));
+        r->surf[b] = reinterpret_cast<uint32_t*>(base + c.surf + b * align_up(r->SW * A * 4));
+        r->outbox[b] = reinterpret_cast<uint32_t*>(
+            base + c.outbox + b * align_up((size_t)I * hsga::kOutboxWords * 4));
+    }
+    r->layout = reinterpret_cast<uint32_t*>(base + c.layout);
+    r->sites = reinterpret_cast<uint32_t*>(base + c.sites);
+    r->gens = gens;
+    r->T = 0;
+    r->horizon = hsga::horizon_of(cfg->surface_kind, r->S);
+    r->apt = default_agents_per_thread(r->N);
+    r->block = r->apt == 4 ? 64u : 256u;   // small tiles: more workgroups in flight per CU
+    r->timing = false;
+    hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
+                                         r->layout, r->S, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "founders launch");
+    return GA_OK;
+}
+
+hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k) {
+    const ga_config& cfg = r->cfg;
+    const int src = g & 1, dst = (g + 1) & 1;
+    hsga::StepParams p;
+    p.in_trait = r->trait[src];
+    p.in_counter = r->counter[src];
+    p.in_surf = r->surf[src];
+    p.out_trait = r->trait[dst];
+    p.out_counter = r->counter[dst];
+    p.out_surf = r->surf[dst];
+    p.ob_in = r->outbox[src];
+    p.ob_out = r->outbox[dst];
+    p.site = r->sites + k;
+    p.W = cfg.grid_w;
+    p.H = cfg.grid_h;
+    p.N = r->N;
+    p.I = r->I;
+    p.A = r->A;
+    p.g = g;
+    p.k0 = (uint32_t)cfg.seed;
+    p.k1 = (uint32_t)(cfg.seed >> 32);
+    p.mut_thr = cfg.mut_threshold;
+    p.mut_lo = cfg.mut_lo;
+    p.mut_span = (uint32_t)((int64_t)cfg.mut_hi - cfg.mut_lo + 1);
+    p.has_inbox = (cfg.migrants_per_island != 0 && g > 0) ? 1u : 0u;
+    p.tile_isl = tile_islands(r->block, r->apt, r->N);
+    p.div_magic = ((1u << 20) + r->N - 1) / r->N;
+    return p;
+}
+
+}  // namespace hsga_host
+
+using namespace hsga_host;
 
 namespace {
 
@@ -111,15 +152,6 @@ hipEvent_t take_event(ga_run* r) {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
-
-uint32_t default_agents_per_thread(uint32_t N) {
-    return N % 4 == 0 ? 4u : (N % 2 == 0 ? 2u : 1u);
-}
-
-// Islands per workgroup tile and the tile's LDS bytes for a launch shape.
-uint32_t tile_islands(uint32_t block, uint32_t apt, uint32_t N) { return block * apt / N; }
-
-constexpr size_t kMaxStepLds = 65536;
 
 }  // namespace
 
@@ -147,35 +179,10 @@ int ga_create(const ga_config* cfg, void* dev_arena, size_t arena_bytes,
                                    std::to_string(c.total));
     ga_run* r = new (std::nothrow) ga_run();
     if (!r) return fail(GA_ENOMEM, "host allocation failed");
-    r->cfg = *cfg;
-    r->I = I;
-    r->N = cfg->pop_per_island;
-    r->A = I * r->N;
-    r->S = cfg->surface_sites;
-    r->SW = r->S / 32;
-    r->stream = static_cast<hipStream_t>(hip_stream);
-    uint8_t* base = static_cast<uint8_t*>(dev_arena);
-    const size_t A = r->A;
-    for (int b = 0; b < 2; ++b) {
-        r->trait[b] = reinterpret_cast<uint32_t*>(base + c.trait + b * align_up(A * 4));
-        r->counter[b] = reinterpret_cast<uint32_t*>(base + c.counter + b * align_up(A * 4));
-        r->surf[b] = reinterpret_cast<uint32_t*>(base + c.surf + b * align_up(r->SW * A * 4));
-        r->outbox[b] = reinterpret_cast<uint32_t*>(
-            base + c.outbox + b * align_up((size_t)I * hsga::kOutboxWords * 4));
-    }
-    r->layout = reinterpret_cast<uint32_t*>(base + c.layout);
-    r->sites = reinterpret_cast<uint32_t*>(base + c.sites);
-    r->gens = gens;
-    r->T = 0;
-    r->horizon = hsga::horizon_of(cfg->surface_kind, r->S);
-    r->apt = default_agents_per_thread(r->N);
-    r->block = r->apt == 4 ? 64u : 256u;   // small tiles: more workgroups in flight per CU
-    r->timing = false;
-    hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
-                                         r->layout, r->S, r->stream);
-    if (e != hipSuccess) {
+    rc = run_init(r, cfg, static_cast<uint8_t*>(dev_arena), gens, static_cast<hipStream_t>(hip_stream));
+    if (rc != GA_OK) {
         delete r;
-        return hip_fail(e, "founders launch");
+        return rc;
     }
     *out = r;
     return GA_OK;
@@ -205,32 +212,7 @@ int ga_step(ga_run* r, uint32_t n) {
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
         for (uint32_t k = 0; k < G; ++k) {
-            const uint32_t g = r->T + k;
-            const int src = g & 1, dst = (g + 1) & 1;
-            hsga::StepParams p;
-            p.in_trait = r->trait[src];
-            p.in_counter = r->counter[src];
-            p.in_surf = r->surf[src];
-            p.out_trait = r->trait[dst];
-            p.out_counter = r->counter[dst];
-            p.out_surf = r->surf[dst];
-            p.ob_in = r->outbox[src];
-            p.ob_out = r->outbox[dst];
-            p.site = r->sites + k;
-            p.W = cfg.grid_w;
-            p.H = cfg.grid_h;
-            p.N = r->N;
-            p.I = r->I;
-            p.A = r->A;
-            p.g = g;
-            p.k0 = (uint32_t)cfg.seed;
-            p.k1 = (uint32_t)(cfg.seed >> 32);
-            p.mut_thr = cfg.mut_threshold;
-            p.mut_lo = cfg.mut_lo;
-            p.mut_span = (uint32_t)((int64_t)cfg.mut_hi - cfg.mut_lo + 1);
-            p.has_inbox = (mig && g > 0) ? 1u : 0u;
-            p.tile_isl = tile_islands(r->block, r->apt, r->N);
-            p.div_magic = ((1u << 20) + r->N - 1) / r->N;
+            const hsga::StepParams p = step_params(r, r->T + k, k);
             e = hsga::launch_step(p, r->SW, sel, mig, r->apt, r->block, r->stream);
             if (e != hipSuccess) return hip_fail(e, "step launch");
         }
@@ -342,7 +324,7 @@ void ga_destroy(ga_run* r) {
     delete r;
 }
 
-const char* ga_last_error(void) { return g_last_error.c_str(); }
+const char* ga_last_error(void) { return last_error(); }
 
 size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n) {
     return hsga::MrcaWorkspace::bytes(S, n);

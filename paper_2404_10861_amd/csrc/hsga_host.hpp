@@ -1,0 +1,66 @@
+// hsga_host.hpp -- host-side pieces shared by the run API (hsga_api.cpp)
+// and the batched / served pool (hsga_pool.cpp).  Not part of the public
+// interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hsga.h"
+#include "hsga_device.hpp"
+#include "hsga_internal.hpp"
+
+struct ga_run {
+    ga_config cfg;
+    uint32_t I, A, N, S, SW;
+    hipStream_t stream;
+    uint32_t* trait[2];
+    uint32_t* counter[2];
+    uint32_t* surf[2];
+    uint32_t* outbox[2];
+    uint32_t* layout;
+    uint32_t* sites;
+    uint32_t gens;       // site schedule capacity
+    uint32_t T;          // generations enqueued
+    uint64_t horizon;
+    uint32_t apt;        // agents per thread (1, 2, 4; divides N)
+    uint32_t block;      // workgroup threads
+    bool timing;
+    struct Span { hipEvent_t start, stop; uint32_t launches; };
+    std::vector<Span> spans;
+    std::vector<hipEvent_t> spare;
+};
+
+namespace hsga_host {
+
+constexpr uint32_t kDefaultGens = 4096;
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxStepLds = 65536;
+
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+const char* last_error();
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Carve {
+    size_t trait, counter, surf, outbox, layout, sites, total;
+};
+
+// Byte offsets of each buffer of a run in its arena.
+Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens);
+
+// GA_OK, or GA_EINVAL with the reason in ga_last_error().
+int validate(const ga_config* cfg);
+
+// Fill r for cfg over the arena at base (already checked to hold
+// carve(...).total bytes) and enqueue the founders.
+int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipStream_t stream);
+
+inline uint32_t tile_islands(uint32_t block, uint32_t apt, uint32_t N) { return block * apt / N; }
+
+// Parameters of generation g (schedule slot k) of a run.
+hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k);
+
+}  // namespace hsga_host

@@ -28,6 +28,32 @@ struct StepParams {
     uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
 };
 
+// One run of a batched launch: a device-resident table entry, written by the
+// host before each batch.  The step of generation T0 + k uses ping-pong
+// buffers (T0 + k) & 1 -> (T0 + k + 1) & 1 and site sites[k]; a run with
+// k >= gens sits the launch out.
+struct BatchRun {
+    uint32_t* trait[2];
+    uint32_t* counter[2];
+    uint32_t* surf[2];
+    uint32_t* outbox[2];
+    uint32_t* sites;           // this batch's site schedule
+    uint32_t* layout;          // the run's layout (S words)
+    uint32_t W, H, N, I, A;
+    uint32_t T0, gens;
+    uint32_t k0, k1;
+    uint32_t mut_thr;
+    int32_t mut_lo;
+    uint32_t mut_span;
+    uint32_t kind, S;
+    uint32_t variant;          // bit 0: S = 64, bit 1: tournament, bit 2: migration,
+                               // bits 3..4: log2(agents per thread)
+    uint32_t tile_isl, div_magic;
+    uint32_t tile0;            // first tile of the run in the batched grid
+};
+
+constexpr uint32_t kMaxBatchRuns = 256;
+
 // LDS bytes of one step workgroup.
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW);
 
@@ -41,6 +67,12 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 // agents_per_thread.
 hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
+
+// Batched forms: tile0 holds nruns + 1 prefix offsets of the runs' tiles.
+hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipStream_t stream);
+hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,
+                             uint32_t total_tiles, uint32_t k, uint32_t block_threads,
+                             size_t lds_bytes, hipStream_t stream);
 
 hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
                          uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,

@@ -48,10 +48,8 @@ hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, u
 // the placement is a ballot over the lanes whose item left the target,
 // then a bit scan; the run's layout is carried in registers and written
 // back at the end.
-__global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32_t S,
-                                                           uint32_t* __restrict__ layout,
-                                                           uint32_t* __restrict__ sites,
-                                                           uint32_t T0, uint32_t G) {
+__device__ __forceinline__ void schedule_sites(uint32_t kind, uint32_t S, uint32_t* layout,
+                                               uint32_t* sites, uint32_t T0, uint32_t G) {
     const uint32_t lane = threadIdx.x;
     uint32_t held = lane < S ? layout[lane] : kEmpty;
     for (uint32_t k = 0; k < G; ++k) {
@@ -61,6 +59,13 @@ __global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32
         if (lane == 0) sites[k] = (uint32_t)site;
     }
     if (lane < S) layout[lane] = held;
+}
+
+__global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32_t S,
+                                                           uint32_t* __restrict__ layout,
+                                                           uint32_t* __restrict__ sites,
+                                                           uint32_t T0, uint32_t G) {
+    schedule_sites(kind, S, layout, sites, T0, G);
 }
 
 hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
@@ -151,9 +156,13 @@ __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint3
     return x + 1 < W ? isl + 1 : isl + 1 - W;
 }
 
+extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
+
+// One tile of one run.  Shared by the plain kernel (one run per launch) and
+// the batched kernel (many runs per launch).
 template <int SW, bool SEL, bool MIGR, int APT>
-__global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+__device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
+    uint32_t* lds = g_step_lds;
     const uint32_t N = p.N, W = p.W;
     const uint32_t TA = (p.tile_isl * N + 3u) & ~3u;   // plane stride (16-byte multiple)
     uint32_t* l_trait = lds;
@@ -162,7 +171,6 @@ __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
     uint32_t* l_plan = lds + (2 + SW) * TA;            // tile_isl words
     uint32_t* l_emig = l_plan + p.tile_isl;            // tile_isl words
 
-    const uint32_t tile = xcd_local_block(blockIdx.x, gridDim.x);
     const uint32_t first_isl = tile * p.tile_isl;
     const uint32_t nisl = min(p.tile_isl, p.I - first_isl);
     const uint32_t nag = nisl * N;
@@ -302,6 +310,11 @@ __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
     for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
 }
 
+template <int SW, bool SEL, bool MIGR, int APT>
+__global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
+    step_tile<SW, SEL, MIGR, APT>(p, xcd_local_block(blockIdx.x, gridDim.x));
+}
+
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
     const size_t TA = ((size_t)tile_isl * N + 3) & ~(size_t)3;
     return ((2 + SW) * TA + 2 * (size_t)tile_isl) * 4;
@@ -339,6 +352,88 @@ hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool mi
                          : launch_step_apt<2, true, false>(p, apt, block_threads, stream);
     return migration ? launch_step_apt<2, false, true>(p, apt, block_threads, stream)
                      : launch_step_apt<2, false, false>(p, apt, block_threads, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: many runs of different sizes, surfaces, treatments and
+// agents per thread in one launch per generation, sharing step_tile and
+// schedule_sites with the plain forms.
+__global__ __launch_bounds__(64) void batch_site_schedule_kernel(
+    const BatchRun* __restrict__ runs) {
+    const BatchRun& R = runs[blockIdx.x];
+    schedule_sites(R.kind, R.S, R.layout, R.sites, R.T0, R.gens);
+}
+
+hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipStream_t stream) {
+    if (nruns == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_site_schedule_kernel, dim3(nruns), dim3(64), 0, stream, runs);
+    return hipGetLastError();
+}
+
+template <int SW, bool SEL, bool MIGR>
+__device__ __forceinline__ void step_tile_apt(const StepParams& p, uint32_t tile, uint32_t apt_log2) {
+    if (apt_log2 == 2) step_tile<SW, SEL, MIGR, 4>(p, tile);
+    else if (apt_log2 == 1) step_tile<SW, SEL, MIGR, 2>(p, tile);
+    else step_tile<SW, SEL, MIGR, 1>(p, tile);
+}
+
+__global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __restrict__ runs,
+                                                         const uint32_t* __restrict__ tile0,
+                                                         uint32_t nruns, uint32_t k) {
+    __shared__ uint32_t s_tile0[kMaxBatchRuns + 1];
+    for (uint32_t i = threadIdx.x; i <= nruns; i += blockDim.x) s_tile0[i] = tile0[i];
+    __syncthreads();
+    const uint32_t tile = xcd_local_block(blockIdx.x, gridDim.x);
+    // the run owning this tile: last r with tile0[r] <= tile
+    uint32_t lo = 0, hi = nruns;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_tile0[mid] <= tile) lo = mid;
+        else hi = mid;
+    }
+    const BatchRun& R = runs[lo];
+    if (k >= R.gens) return;
+    const uint32_t g = R.T0 + k;
+    const uint32_t src = g & 1u, dst = (g + 1u) & 1u;
+    StepParams p;
+    p.in_trait = R.trait[src];
+    p.in_counter = R.counter[src];
+    p.in_surf = R.surf[src];
+    p.out_trait = R.trait[dst];
+    p.out_counter = R.counter[dst];
+    p.out_surf = R.surf[dst];
+    p.ob_in = R.outbox[src];
+    p.ob_out = R.outbox[dst];
+    p.site = R.sites + k;
+    p.W = R.W; p.H = R.H; p.N = R.N; p.I = R.I; p.A = R.A;
+    p.g = g;
+    p.k0 = R.k0; p.k1 = R.k1;
+    p.mut_thr = R.mut_thr; p.mut_lo = R.mut_lo; p.mut_span = R.mut_span;
+    const bool mig = (R.variant >> 2) & 1u;
+    p.has_inbox = (mig && g > 0) ? 1u : 0u;
+    p.tile_isl = R.tile_isl;
+    p.div_magic = R.div_magic;
+    const uint32_t t = tile - s_tile0[lo];
+    const uint32_t apt_log2 = (R.variant >> 3) & 3u;
+    switch (R.variant & 7u) {
+    case 0: step_tile_apt<1, false, false>(p, t, apt_log2); break;
+    case 1: step_tile_apt<2, false, false>(p, t, apt_log2); break;
+    case 2: step_tile_apt<1, true, false>(p, t, apt_log2); break;
+    case 3: step_tile_apt<2, true, false>(p, t, apt_log2); break;
+    case 4: step_tile_apt<1, false, true>(p, t, apt_log2); break;
+    case 5: step_tile_apt<2, false, true>(p, t, apt_log2); break;
+    case 6: step_tile_apt<1, true, true>(p, t, apt_log2); break;
+    default: step_tile_apt<2, true, true>(p, t, apt_log2); break;
+    }
+}
+
+hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,
+                             uint32_t total_tiles, uint32_t k, uint32_t block_threads,
+                             size_t lds_bytes, hipStream_t stream) {
+    if (nruns == 0 || total_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(batch_step_kernel, dim3(total_tiles), dim3(block_threads), lds_bytes,
+                       stream, runs, tile0, nruns, k);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

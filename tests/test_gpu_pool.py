@@ -1,0 +1,165 @@
+"""Batched and served runs: every run in a pool is bit-identical to the same
+run alone (and to the oracle), whatever else shares the launch; admission
+follows the HBM footprint; runs stop at their own generation counts."""
+import numpy as np
+import pytest
+
+from paper_2404_10861_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"steady": 0, "tilted": 1, "hybrid": 2}
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_10861_amd as hs
+    hs.load_library()
+    return hs
+
+
+def mixed_specs():
+    """A small batched set: uneven grids, all surface kinds and sizes,
+    both treatments, populations that do and do not divide the tile."""
+    shapes = [(16, 16, 16), (8, 16, 32), (12, 10, 64), (5, 3, 3), (7, 9, 48), (16, 8, 17),
+              (1, 1, 8), (33, 2, 1), (6, 6, 32), (4, 20, 16), (3, 3, 64), (10, 10, 2)]
+    specs = []
+    for r, (w, h, n) in enumerate(shapes):
+        specs.append(wl.RunSpec(w, h, n, (32, 64)[r % 2], ("steady", "tilted", "hybrid")[r % 3],
+                                2 if r < 6 else 0, 150 + 37 * r, seed=r + 1, name=f"mix {r}"))
+    return specs
+
+
+def alone_state(hs, spec):
+    run = hs.Run(hs.Config(**spec.config_kwargs()))
+    run.step(spec.generations)
+    st = (run.agents(), run.outbox(), run.layout())
+    run.close()
+    return st
+
+
+def same(a, b):
+    (at, ac, as_), aob, al = a
+    (bt, bc, bs), bob, bl = b
+    assert np.array_equal(at, bt) and np.array_equal(ac, bc) and np.array_equal(as_, bs)
+    assert np.array_equal(al, bl)
+    assert (aob is None) == (bob is None)
+    if aob is not None:
+        for x, y in zip(aob, bob):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("use_graph,block,chunk", [(False, 64, 64), (True, 64, 50),
+                                                   (False, 256, 1000), (True, 128, 17)])
+def test_batched_equals_alone(hs, use_graph, block, chunk):
+    specs = mixed_specs()
+    pool = hs.Pool(256 << 20, max_runs=32, max_gens_per_launch=128, block_threads=block,
+                   use_graph=use_graph)
+    ids = {}
+    for s in specs:
+        rid = pool.admit(hs.Config(**s.config_kwargs()), s.generations)
+        assert rid is not None
+        ids[rid] = s
+    done = []
+    while True:
+        n = pool.advance(chunk)
+        done += pool.poll()
+        if n == 0:
+            break
+    assert sorted(done) == sorted(ids)
+    for rid, s in ids.items():
+        run = pool.run(rid)
+        assert run.generation == s.generations
+        same((run.agents(), run.outbox(), run.layout()), alone_state(hs, s))
+    pool.close()
+
+
+def test_batched_matches_oracle(hs, orc):
+    specs = mixed_specs()[:5]
+    pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=64)
+    ids = {pool.admit(hs.Config(**s.config_kwargs()), s.generations): s for s in specs}
+    while pool.advance(64):
+        pass
+    for rid, s in ids.items():
+        o = orc.Run(s.grid_w, s.grid_h, s.pop_per_island, s.surface_sites, KIND[s.surface_kind],
+                    s.tournament_size, s.mut_threshold, s.mut_lo, s.mut_hi,
+                    s.migrants_per_island, s.seed)
+        o.step(s.generations)
+        for x, y in zip(pool.run(rid).agents(), o.agents()):
+            assert np.array_equal(x, y)
+        assert np.array_equal(pool.run(rid).layout(), o.layout())
+
+
+def test_admission_by_footprint(hs):
+    small = hs.Config(8, 8, 32, 32, "steady", seed=1)
+    big = hs.Config(256, 256, 64, 64, "hybrid", seed=2)
+    pool = hs.Pool(8 << 20, max_runs=4, max_gens_per_launch=64)
+    assert pool.footprint(big) > pool.info()["free_bytes"]
+    assert pool.admit(big, 10) is None                     # refused: does not fit
+    ids = []
+    while True:
+        rid = pool.admit(small, 10)
+        if rid is None:
+            break
+        ids.append(rid)
+    assert len(ids) == 4                                   # slots run out first
+    before = pool.info()
+    pool.release(ids[1])
+    after = pool.info()
+    assert after["free_bytes"] == before["free_bytes"] + pool.footprint(small)
+    assert pool.admit(small, 10) is not None
+    with pytest.raises(hs.HsgaError):
+        pool.admit(hs.Config(2, 2, 4, 32, "hybrid"), 2 * (2**16 - 2) + 4)   # past the horizon
+
+
+def test_runs_stop_at_their_own_counts(hs):
+    pool = hs.Pool(32 << 20, max_runs=8, max_gens_per_launch=40)
+    targets = {}
+    for n, g in ((16, 5), (32, 40), (64, 41), (16, 100)):
+        rid = pool.admit(hs.Config(4, 4, n, 32, "tilted", seed=n + g), g)
+        targets[rid] = g
+    seen = {}
+    step = 0
+    while True:
+        n = pool.advance(40)
+        step += 1
+        for rid in pool.poll():
+            assert rid not in seen
+            seen[rid] = step
+        if n == 0:
+            break
+    assert set(seen) == set(targets)
+    for rid, g in targets.items():
+        assert pool.run(rid).generation == g
+        assert seen[rid] == (g + 39) // 40
+    assert pool.info()["active"] == 0
+
+
+def test_served_results_equal_alone(hs):
+    """A burst of requests arriving while others are on the GPU: each
+    result (final records, sample, MRCA matrices) equals the request alone."""
+    from paper_2404_10861_amd import serve
+    reqs = []
+    for i, (w, h, s, kind, g) in enumerate([(8, 8, 32, "steady", 300), (16, 12, 64, "hybrid", 900),
+                                            (9, 7, 32, "tilted", 500), (32, 16, 64, "tilted", 1200),
+                                            (8, 24, 32, "hybrid", 250), (12, 12, 64, "steady", 700)]):
+        reqs.append(wl.RunSpec(w, h, 32, s, kind, 2, g, seed=i + 1, sample=64,
+                               arrival=0.02 * i, name=f"served {i}"))
+    pool = hs.Pool(64 << 20, max_runs=4, max_gens_per_launch=128)
+    rep = serve.serve(pool, reqs, chunk_gens=100, sample=64, keep_results=True,
+                      keep_agents=set(range(len(reqs))))
+    assert len(rep.results) == len(reqs)
+    for res in rep.results:
+        spec = reqs[res.index]
+        agents, idx, lb, ub = serve.run_alone(spec, sample=64)
+        got = rep.agents[res.index]
+        for x, y in zip(got, agents):
+            assert np.array_equal(x, y)
+        assert np.array_equal(res.sample_idx, idx)
+        assert np.array_equal(res.lb, lb) and np.array_equal(res.ub, ub)
+        assert res.latency > 0
+    s = rep.summary()
+    assert s["requests"] == len(reqs) and s["latency_p99_s"] >= s["latency_p50_s"]
