@@ -110,6 +110,13 @@ def main(argv=None) -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the run length (profiling only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=("plain", "batched", "served"), default="plain",
+                    help="plain: the paper-scale run (default); batched / served: the run "
+                         "sets of the batched and served workloads against sequential plain runs")
+    ap.add_argument("--time-scale", type=float, default=1.0,
+                    help="served mode: stretch (>1) or compress (<1) the arrival times")
+    ap.add_argument("--duration", type=float, default=120.0,
+                    help="served mode: seconds of arrivals (before time scaling)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -121,6 +128,24 @@ def main(argv=None) -> int:
 
     import paper_2404_10861_amd as hs
     from paper_2404_10861_amd import workloads as wl
+
+    if args.mode != "plain":
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        from paper_2404_10861_amd import benchmarks
+        if args.mode == "batched":
+            res = benchmarks.batched_vs_plain(wl.c4(), dev, torch.cuda.current_stream(dev))
+            metric = "agent-replications/sec (batched vs sequential plain)"
+            value = res["batched_replications_per_s"]
+        else:
+            reqs = wl.c5(duration=args.duration)
+            res = benchmarks.served_vs_plain(reqs, dev, time_scale=args.time_scale)
+            metric = "agent-replications/sec and p50/p99 run latency (served)"
+            value = res["served"]["replications_per_s"]
+        print(json.dumps({"metric": metric, "value": value, "unit": "agent-replications/s",
+                          "n_gpus": 1, "mode": args.mode, "dtype": "u32", "data": "synthetic",
+                          "result": res}), flush=True)
+        return 0
 
     spec = wl.c2()
     if args.generations:

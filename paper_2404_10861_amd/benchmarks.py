@@ -1,0 +1,147 @@
+"""Benchmarks of the batched and served forms against sequential plain runs.
+
+batched_vs_plain: the batched workload (64 runs) executed (i) one run after
+another with the plain API on one stream, (ii) as one pool with batched
+launches, its launch shape tuned online.  Aggregate agent-replications/s of
+each.
+
+served_vs_plain: the served request list replayed in real time (i) through
+the continuous-batching server (serve.py), (ii) through a plain server that
+runs one request at a time in arrival order.  Aggregate replications/s and
+p50/p99 latency from arrival to the MRCA result on the host.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import autotune
+from . import binding as hs
+from . import serve as srv
+
+
+def _arena_for(cfgs, gens, dev):
+    need = max(hs.footprint_bytes(c, gens) for c in cfgs)
+    buf = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf[off:off + need]
+
+
+def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool = True) -> dict:
+    cfgs = [hs.Config(**s.config_kwargs()) for s in specs]
+    reps = sum(s.replications for s in specs)
+    # (i) sequential plain runs, one arena reused in stream order
+    gmax = max(s.generations for s in specs)
+    _keep, arena = _arena_for(cfgs, gmax, dev)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for s, c in zip(specs, cfgs):
+        run = hs.Run(c, max_gens_per_launch=gmax, device=dev, stream=stream, arena=arena)
+        run.step(s.generations)
+        run.close()
+    torch.cuda.synchronize(dev)
+    t_plain = time.perf_counter() - t0
+    del _keep, arena
+    # (ii) one pool, batched launches
+    pstream = torch.cuda.Stream(dev)
+    probe = hs.Pool(1 << 20, max_runs=1, max_gens_per_launch=gens_per_launch, device=dev,
+                    stream=pstream)
+    total = sum(probe.footprint(c) for c in cfgs)
+    probe.close()
+    pool = hs.Pool(total + hs.pool_overhead_bytes(len(specs)) + (1 << 20), max_runs=len(specs),
+                   max_gens_per_launch=gens_per_launch, device=dev, stream=pstream)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for s, c in zip(specs, cfgs):
+        if pool.admit(c, s.generations) is None:
+            raise RuntimeError("pool sized too small")
+    choice = {"block_threads": 64, "gens_per_launch": 64, "use_graph": True}
+    if tune:
+        choice = autotune.tune_online(pool, key=autotune.signature(specs), use_cache=False)
+    else:
+        pool.set_launch(64, True)
+    G = choice["gens_per_launch"]
+    while pool.advance(G):
+        pass
+    pool.sync()
+    t_batch = time.perf_counter() - t0
+    done = pool.poll()
+    ok = len(done) == len(specs) and all(pool.run(i).generation == specs[i].generations
+                                         for i in range(len(specs)))
+    pool.close()
+    return {
+        "workload": f"{len(specs)} runs, {reps:,} agent-replications",
+        "replications": reps,
+        "plain_sequential_s": t_plain,
+        "plain_sequential_replications_per_s": reps / t_plain,
+        "batched_s": t_batch,
+        "batched_replications_per_s": reps / t_batch,
+        "batched_over_plain": t_plain / t_batch,
+        "tuned": {k: choice[k] for k in ("block_threads", "gens_per_launch", "use_graph")},
+        "tuner_trials": choice.get("trials", []),
+        "all_runs_finished": bool(ok),
+    }
+
+
+def plain_fifo_server(reqs, dev, stream, sample: int = 1024, time_scale: float = 1.0) -> dict:
+    """One request at a time, in arrival order, with the plain API."""
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
+    cfgs = {i: hs.Config(**reqs[i].config_kwargs()) for i in order}
+    gmax = max(r.generations for r in reqs)
+    _keep, arena = _arena_for(list(cfgs.values()), gmax, dev)
+    ws = hs.MrcaWorkspace(64, sample, dev)
+    lb = torch.empty((sample, sample), dtype=torch.int32, device=dev)
+    ub = torch.empty((sample, sample), dtype=torch.int32, device=dev)
+    lat = []
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for i in order:
+            r = reqs[i]
+            arr = r.arrival * time_scale
+            now = time.perf_counter() - t0
+            if now < arr:
+                time.sleep(arr - now)
+            run = hs.Run(cfgs[i], max_gens_per_launch=gmax, device=dev, stream=stream,
+                         arena=arena)
+            run.step(r.generations)
+            _, cnt, srf = run.sample(sample)
+            n = cnt.shape[0]
+            lv = lb[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32, device=dev)
+            uv = ub[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32, device=dev)
+            hs.mrca_bounds(r.surface_kind, r.surface_sites, cnt, srf, workspace=ws, stream=stream,
+                           lb=lv, ub=uv)
+            lv.cpu()
+            uv.cpu()
+            run.close()
+            lat.append(time.perf_counter() - t0 - arr)
+    wall = time.perf_counter() - t0
+    reps = sum(r.replications for r in reqs)
+    lat = np.array(lat)
+    return {"wall_s": wall, "replications_per_s": reps / wall,
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_max_s": float(lat.max())}
+
+
+def served_vs_plain(reqs, dev, chunk_gens: int = 256, time_scale: float = 1.0,
+                    pool_bytes: int = 16 << 30, plain: bool = True) -> dict:
+    pstream = torch.cuda.Stream(dev)
+    pool = hs.Pool(pool_bytes, max_runs=256, max_gens_per_launch=chunk_gens, device=dev,
+                   stream=pstream, block_threads=64, use_graph=False)
+    rep = srv.serve(pool, reqs, chunk_gens=chunk_gens, sample=1024, time_scale=time_scale)
+    pool.close()
+    out = {
+        "requests": len(reqs),
+        "time_scale": time_scale,
+        "offered_replications_per_s": sum(r.replications for r in reqs) /
+                                      (max(r.arrival for r in reqs) * time_scale),
+        "served": rep.summary(),
+    }
+    if plain:
+        out["plain_fifo"] = plain_fifo_server(reqs, dev, torch.cuda.Stream(dev),
+                                              time_scale=time_scale)
+        out["served_over_plain_throughput"] = (out["served"]["replications_per_s"] /
+                                               out["plain_fifo"]["replications_per_s"])
+    return out
