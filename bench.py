@@ -110,11 +110,13 @@ def main(argv=None) -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the run length (profiling only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("plain", "batched", "served"), default="plain",
+    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair"), default="plain",
                     help="plain: the paper-scale run (default); batched / served: the run "
                          "sets of the batched and served workloads against sequential plain runs")
     ap.add_argument("--time-scale", type=float, default=1.0,
                     help="served mode: stretch (>1) or compress (<1) the arrival times")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="served mode: skip the plain one-at-a-time server")
     ap.add_argument("--duration", type=float, default=120.0,
                     help="served mode: seconds of arrivals (before time scaling)")
     args = ap.parse_args(argv)
@@ -133,13 +135,20 @@ def main(argv=None) -> int:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         from paper_2404_10861_amd import benchmarks
-        if args.mode == "batched":
+        if args.mode == "pair":
+            res = benchmarks.treatment_pair([wl.c3(True), wl.c3(False)], dev,
+                                            torch.cuda.current_stream(dev))
+            metric = "agent-replications/sec (treatment pair) and MRCA query time"
+            value = res["selection"]["replications_per_s"]
+        elif args.mode == "batched":
             res = benchmarks.batched_vs_plain(wl.c4(), dev, torch.cuda.current_stream(dev))
             metric = "agent-replications/sec (batched vs sequential plain)"
             value = res["batched_replications_per_s"]
         else:
             reqs = wl.c5(duration=args.duration)
-            res = benchmarks.served_vs_plain(reqs, dev, time_scale=args.time_scale)
+            res = benchmarks.served_vs_plain(
+                reqs, dev, time_scale=args.time_scale, plain=not args.no_plain,
+                progress=lambda text: print(text, file=sys.stderr, flush=True))
             metric = "agent-replications/sec and p50/p99 run latency (served)"
             value = res["served"]["replications_per_s"]
         print(json.dumps({"metric": metric, "value": value, "unit": "agent-replications/s",

@@ -85,7 +85,8 @@ def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool 
     }
 
 
-def plain_fifo_server(reqs, dev, stream, sample: int = 1024, time_scale: float = 1.0) -> dict:
+def plain_fifo_server(reqs, dev, stream, sample: int = 1024, time_scale: float = 1.0,
+                      progress=None) -> dict:
     """One request at a time, in arrival order, with the plain API."""
     order = sorted(range(len(reqs)), key=lambda i: reqs[i].arrival)
     cfgs = {i: hs.Config(**reqs[i].config_kwargs()) for i in order}
@@ -96,8 +97,12 @@ def plain_fifo_server(reqs, dev, stream, sample: int = 1024, time_scale: float =
     ub = torch.empty((sample, sample), dtype=torch.int32, device=dev)
     lat = []
     t0 = time.perf_counter()
+    next_note = 10.0
     with torch.cuda.stream(stream):
         for i in order:
+            if progress is not None and time.perf_counter() - t0 >= next_note:
+                progress(f"plain t={time.perf_counter() - t0:.0f}s done={len(lat)}")
+                next_note += 10.0
             r = reqs[i]
             arr = r.arrival * time_scale
             now = time.perf_counter() - t0
@@ -126,11 +131,12 @@ def plain_fifo_server(reqs, dev, stream, sample: int = 1024, time_scale: float =
 
 
 def served_vs_plain(reqs, dev, chunk_gens: int = 256, time_scale: float = 1.0,
-                    pool_bytes: int = 16 << 30, plain: bool = True) -> dict:
+                    pool_bytes: int = 16 << 30, plain: bool = True, progress=None) -> dict:
     pstream = torch.cuda.Stream(dev)
     pool = hs.Pool(pool_bytes, max_runs=256, max_gens_per_launch=chunk_gens, device=dev,
                    stream=pstream, block_threads=64, use_graph=False)
-    rep = srv.serve(pool, reqs, chunk_gens=chunk_gens, sample=1024, time_scale=time_scale)
+    rep = srv.serve(pool, reqs, chunk_gens=chunk_gens, sample=1024, time_scale=time_scale,
+                    progress=progress)
     pool.close()
     out = {
         "requests": len(reqs),
@@ -141,7 +147,49 @@ def served_vs_plain(reqs, dev, chunk_gens: int = 256, time_scale: float = 1.0,
     }
     if plain:
         out["plain_fifo"] = plain_fifo_server(reqs, dev, torch.cuda.Stream(dev),
-                                              time_scale=time_scale)
+                                              time_scale=time_scale, progress=progress)
         out["served_over_plain_throughput"] = (out["served"]["replications_per_s"] /
                                                out["plain_fifo"]["replications_per_s"])
+    return out
+
+
+def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
+    """The treatment pair (selection, neutral): each run, its stratified
+    sample and all-pairs MRCA bounds; mean bounds over distinct pairs per
+    treatment (selection sweeps make common ancestry more recent)."""
+    out = {}
+    ws = hs.MrcaWorkspace(max(s.surface_sites for s in specs), n_sample, dev)
+    lb = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
+    ub = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
+    for s in specs:
+        cfg = hs.Config(**s.config_kwargs())
+        run = hs.Run(cfg, max_gens_per_launch=s.generations, device=dev, stream=stream)
+        run.set_kernel_timing(True)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        run.step(s.generations)
+        _, cnt, srf = run.sample(n_sample)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        hs.mrca_bounds(s.surface_kind, s.surface_sites, cnt, srf, workspace=ws, stream=stream,
+                       lb=lb, ub=ub)
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        wall = time.perf_counter() - t0
+        ms, launches = run.kernel_time()
+        l_h = hs.as_u32(lb).astype(np.float64)
+        u_h = hs.as_u32(ub).astype(np.float64)
+        off = ~np.eye(n_sample, dtype=bool)
+        out["selection" if s.tournament_size == 2 else "neutral"] = {
+            "replications_per_s": s.replications / wall,
+            "wall_s": wall,
+            "step_kernel_avg_us": ms * 1000.0 / max(launches, 1),
+            "mrca_query_ms": e0.elapsed_time(e1),
+            "mrca_pairs": n_sample * n_sample,
+            "mean_lb": float(l_h[off].mean()),
+            "mean_ub": float(u_h[off].mean()),
+            "mean_trait": float(run.agents(0, 65536)[0].view(np.int32).mean()),
+        }
+        run.close()
     return out

@@ -80,13 +80,15 @@ def run_alone(spec, sample: int = 1024, device="cuda", stream=None):
 
 
 def serve(pool: hs.Pool, requests, chunk_gens: int = 256, sample: int = 1024,
-          keep_results: bool = False, time_scale: float = 1.0, keep_agents=None) -> ServeReport:
+          keep_results: bool = False, time_scale: float = 1.0, keep_agents=None,
+          progress=None) -> ServeReport:
     """Serve `requests` (sorted or not) in real time.
 
     time_scale stretches (>1) or compresses (<1) the arrival times.
     keep_results keeps each run's lb/ub matrices and sample indices on the
     host; keep_agents (a set of request indices) also keeps their final
-    records in `report.agents`.
+    records in `report.agents`.  progress(text), if given, is called about
+    every 10 s with the loop's state.
     """
     dev = pool.device
     stream = pool.stream
@@ -104,8 +106,13 @@ def serve(pool: hs.Pool, requests, chunk_gens: int = 256, sample: int = 1024,
     report = ServeReport()
     keep_agents = keep_agents or set()
     t0 = time.perf_counter()
+    next_note = 10.0
     while pending or waiting or active:
         now = time.perf_counter() - t0
+        if progress is not None and now >= next_note:
+            progress(f"served t={now:.0f}s done={len(report.results)} active={len(active)} "
+                     f"waiting={len(waiting)} pending={len(pending)}")
+            next_note += 10.0
         while pending and pending[0][1].arrival * time_scale <= now:
             i, spec = pending.popleft()
             waiting.append((i, spec, spec.arrival * time_scale))
