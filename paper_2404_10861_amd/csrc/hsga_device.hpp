@@ -69,48 +69,104 @@ __device__ __forceinline__ SubSurface sub_surface(uint32_t kind, uint32_t S, uin
     return s;
 }
 
-// Is item t (local time, t <= u) part of the retention target D(u) of an
-// m-site sub-surface?  Steady: multiples of 2^bitlen(u/(m-1)), plus u.
-// Tilted: on each level h = ctz(t+1) keep the floor(m/bitlen(u+1)) most
-// recent items.
-__device__ __forceinline__ bool retained_target(uint32_t policy, uint32_t m, uint32_t u,
-                                                uint32_t t) {
+// Local time at which item t (local deposit time) leaves the retention
+// target D(u) of an m-site sub-surface, kNever if it stays as long as the
+// 32-bit counter runs.  Membership is monotone (D(u) without u is a subset
+// of D(u-1)), so "t is out of D(u)" is exactly "u >= leave_time(t)".
+//   Steady, D(u) = multiples of g(u) = 2^bitlen(floor(u/(m-1))) plus u:
+//     for u > t, t stays while g(u) divides t, i.e. floor(u/(m-1)) <
+//     2^ctz(t), i.e. u < (m-1) * 2^ctz(t); item 0 never leaves.
+//   Tilted, D(u) = the r(u) = floor(m / bitlen(u+1)) most recent items of
+//     each level h = ctz(t+1), t+1 = (2c+1) 2^h: t leaves at the first u
+//     with n_h(u) = (u + 1 + 2^h) >> (h+1) > c + r(u).  Within one epoch of
+//     bitlen(u+1) = B, r is constant, so that u is
+//     max((c+r+1) 2^(h+1) - 2^h - 1, first u of the epoch).
+constexpr uint32_t kNever = 0xffffffffu;
+
+__host__ __device__ inline uint32_t leave_time(uint32_t policy, uint32_t m, uint32_t t) {
     if (policy == kSteady) {
-        const uint32_t q = u / (m - 1u);
-        const uint32_t spacing_bits = q ? 32u - (uint32_t)__clz((int)q) : 0u;  // < 30 for m >= 16
-        return ((t & ((1u << spacing_bits) - 1u)) == 0u) || t == u;
+        if (t == 0) return kNever;
+        const uint64_t e = (uint64_t)(m - 1) << __builtin_ctz(t);
+        const uint64_t x = e > (uint64_t)t + 1 ? e : (uint64_t)t + 1;
+        return x >= kNever ? kNever : (uint32_t)x;
     }
-    const uint32_t r = m / bit_length64((uint64_t)u + 1u);
-    const uint32_t h = (uint32_t)__ffs((int)(t + 1u)) - 1u;
-    const uint64_t c = ((uint64_t)t + 1u) >> (h + 1);
-    const uint64_t n_h = ((uint64_t)u + 1u + (1ull << h)) >> (h + 1);
-    return c + r >= n_h;
+    const uint32_t h = (uint32_t)__builtin_ctz(t + 1u);
+    const uint64_t c = ((uint64_t)t + 1) >> (h + 1);
+    const uint64_t t1 = (uint64_t)t + 1;
+    uint32_t B = 64u - (uint32_t)__builtin_clzll(t1 + 1);   // epoch of u = t + 1
+    for (; B <= m && B < 34; ++B) {
+        const uint64_t r = m / B;
+        const uint64_t need = ((c + r + 1) << (h + 1)) - (1ull << h) - 1;
+        const uint64_t first = (1ull << (B - 1)) - 1;
+        uint64_t u = need > first ? need : first;
+        if (u < t1) u = t1;
+        if (u <= (1ull << B) - 2) return u >= kNever ? kNever : (uint32_t)u;
+    }
+    return kNever;   // stays until past the horizon
 }
 
 // One placement across the wavefront: lane k holds the deposit time of
-// site k (global time, kEmpty if unfilled).  Returns the site that item T
-// goes to: T's own local slot while its sub-surface fills, otherwise the
-// lowest site of the sub-surface whose item has left the target (ballot +
-// bit scan).  Returns -1 when no site is evictable (past the horizon).
-// Must be called by all 64 lanes with a uniform T.
+// site k (global time, kEmpty if unfilled) and the local time its item
+// leaves the target (0 if unfilled).  Item T goes to its own local slot
+// while its sub-surface fills, otherwise to the lowest site of the
+// sub-surface whose item has left the target (ballot + bit scan); -1 if
+// none (past the horizon).  The chosen lane takes (T, new_leave), the leave
+// time of item T.  Must be called by all 64 lanes with uniform arguments.
 __device__ __forceinline__ int place_in_wave(uint32_t kind, uint32_t S, uint32_t T,
-                                             uint32_t lane_time, uint32_t lane) {
+                                             uint32_t new_leave, uint32_t& lane_time,
+                                             uint32_t& lane_leave, uint32_t lane) {
     const SubSurface s = sub_surface(kind, S, T);
-    if (s.u < s.m)
-        return (int)(s.offset + s.u);
-    bool evictable = false;
-    if (lane >= s.offset && lane < s.offset + s.m) {
-        if (lane_time == kEmpty) {
-            evictable = true;
-        } else {
-            const uint32_t t_local = kind == kHybrid ? lane_time >> 1 : lane_time;
-            evictable = !retained_target(s.policy, s.m, s.u, t_local);
-        }
+    int site;
+    if (s.u < s.m) {
+        site = (int)(s.offset + s.u);
+    } else {
+        const bool evictable = lane >= s.offset && lane < s.offset + s.m && s.u >= lane_leave;
+        const uint64_t mask = __ballot(evictable);
+        site = mask ? (int)(__ffsll((long long)mask) - 1) : -1;
     }
-    const uint64_t mask = __ballot(evictable);
-    if (mask == 0)
-        return -1;
-    return (int)(__ffsll((long long)mask) - 1);
+    if ((int)lane == site) {
+        lane_time = T;
+        lane_leave = new_leave;
+    }
+    return site;
+}
+
+// Leave time of item T in its own sub-surface.
+__device__ __forceinline__ uint32_t item_leave_time(uint32_t kind, uint32_t S, uint32_t T) {
+    const SubSurface s = sub_surface(kind, S, T);
+    return leave_time(s.policy, s.m, s.u);
+}
+
+// Places items T0 .. T0+G-1 in blocks of 64: each lane first computes the
+// leave time of one item of the block (in parallel), then the 64 serial
+// placements read it with readlane.  site_out(k, site) is called by lane
+// k % 64 once per item.  Must be called by all 64 lanes.
+template <typename SiteOut>
+__device__ __forceinline__ void place_items(uint32_t kind, uint32_t S, uint32_t T0, uint32_t G,
+                                            uint32_t& lane_time, uint32_t& lane_leave,
+                                            uint32_t lane, SiteOut site_out) {
+    for (uint32_t base = 0; base < G; base += 64) {
+        const uint32_t n = G - base < 64 ? G - base : 64;
+        const uint32_t mine = lane < n ? item_leave_time(kind, S, T0 + base + lane) : 0u;
+        int my_site = -1;
+        for (uint32_t j = 0; j < n; ++j) {
+            const uint32_t nl = (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)j);
+            const int site = place_in_wave(kind, S, T0 + base + j, nl, lane_time, lane_leave, lane);
+            if (lane == j) my_site = site;
+        }
+        if (lane < n) site_out(base + lane, my_site);
+    }
+}
+
+// Leave time of the item a lane holds (at the start of a schedule or replay).
+__device__ __forceinline__ uint32_t lane_leave_time(uint32_t kind, uint32_t S, uint32_t lane,
+                                                    uint32_t lane_time) {
+    if (lane_time == kEmpty || lane >= S) return 0u;
+    if (kind == kHybrid) {
+        const bool tilted_half = lane >= (S >> 1);
+        return leave_time(tilted_half ? kTilted : kSteady, S >> 1, lane_time >> 1);
+    }
+    return leave_time(kind, S, lane_time);
 }
 
 // The MRCA kernels replay layouts on the device, one placement per

@@ -52,12 +52,9 @@ __device__ __forceinline__ void schedule_sites(uint32_t kind, uint32_t S, uint32
                                                uint32_t* sites, uint32_t T0, uint32_t G) {
     const uint32_t lane = threadIdx.x;
     uint32_t held = lane < S ? layout[lane] : kEmpty;
-    for (uint32_t k = 0; k < G; ++k) {
-        const uint32_t T = T0 + k;
-        const int site = place_in_wave(kind, S, T, held, lane);
-        if ((int)lane == site) held = T;
-        if (lane == 0) sites[k] = (uint32_t)site;
-    }
+    uint32_t leave = lane_leave_time(kind, S, lane, held);
+    place_items(kind, S, T0, G, held, leave, lane,
+                [&](uint32_t k, int site) { sites[k] = (uint32_t)site; });
     if (lane < S) layout[lane] = held;
 }
 
@@ -519,11 +516,8 @@ __device__ __forceinline__ uint32_t time_rank(uint32_t held, uint32_t lane, uint
 // Layout after T ingests, replayed in the wavefront (lane = site).
 __device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uint32_t T,
                                                   uint32_t lane) {
-    uint32_t held = kEmpty;
-    for (uint32_t t = 0; t < T; ++t) {
-        const int site = place_in_wave(kind, S, t, held, lane);
-        if ((int)lane == site) held = t;
-    }
+    uint32_t held = kEmpty, leave = 0;
+    place_items(kind, S, 0, T, held, leave, lane, [](uint32_t, int) {});
     return held;
 }
 

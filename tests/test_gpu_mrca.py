@@ -115,3 +115,19 @@ def test_treatment_pair_full_scale_sample(hs, orc):
     assert np.array_equal(lb, lb.T) and np.array_equal(ub, ub.T)
     assert np.all(np.diag(lb) == 20000) and np.all(np.diag(ub) == 20000)
     assert np.all(lb <= ub)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_long_replays(hs, orc, kind):
+    """Layouts replayed on the device for counters up to 70,000, shared and
+    mixed."""
+    rng = np.random.default_rng(10 + kind)
+    counters = np.array([70000, 65536, 65535, 40001, 20000, 131, 64, 0], np.uint32)
+    surf = rng.integers(0, 2**32, size=(len(counters), 2), dtype=np.uint64).astype(np.uint32)
+    lb, ub = gpu_bounds(hs, kind, 64, counters, surf)
+    olb, oub = orc.mrca_allpairs(kind, 64, counters, surf)
+    assert np.array_equal(lb, olb) and np.array_equal(ub, oub)
+    same = np.full(6, 70000, np.uint32)
+    lb, ub = gpu_bounds(hs, kind, 64, same, surf[:6])
+    olb, oub = orc.mrca_allpairs(kind, 64, same, surf[:6])
+    assert np.array_equal(lb, olb) and np.array_equal(ub, oub)

@@ -168,3 +168,17 @@ def test_determinism_across_runs(hs):
     b.step(300)
     for x, y in zip(a.agents(), b.agents()):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("kind", ["steady", "tilted", "hybrid"])
+@pytest.mark.parametrize("S", [32, 64])
+def test_site_schedule_past_2_16(hs, orc, kind, S):
+    """The device schedule (leave-time form of the retention target) equals
+    the oracle's placement over 70,000 generations, in uneven chunks."""
+    g = hs.Run(hs.Config(1, 1, 2, S, kind, seed=3), max_gens_per_launch=9000)
+    done = 0
+    for chunk in (1, 31, 33, 5000, 9000, 30000, 25935):
+        g.step(chunk)
+        done += chunk
+        assert np.array_equal(g.layout(), orc.layout(KIND[kind], S, done)), done
+    assert done == 70000
