@@ -656,3 +656,191 @@ int orc_mrca_rows(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counter
     free(L);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Trie reconstruction and phylometrics of n annotations sharing a counter
+ * T (Distributed Phylogenetic Tracking: the record of differentiae makes
+ * reconstruction a trie-building procedure; Results, On-hardware Trial:
+ * treatments are compared by sum branch length and mean evolutionary
+ * distinctiveness).
+ *
+ * Reading: each annotation is read as its bits in ascending deposit time
+ * (times t_0 < ... < t_{F-1} of the shared layout).  They are inserted into a
+ * binary trie, one level per retained time.  A trie node where the
+ * annotations below it split on the bit of time t_d becomes a tree node at
+ * time t_d (the MRCA upper bound of the pairs it separates); annotations
+ * with identical bits hang from one node at time T; each annotation is a
+ * leaf at time T; chains of one-child trie nodes are collapsed; the root is
+ * the first branching node.
+ *
+ * Output: out[0] = sum of branch lengths; out[1] = sum over unordered
+ * pairs of (T - time of their tree MRCA); out[2] = root time; out[3] =
+ * number of internal nodes; ed[n] (may be NULL) = each leaf's evolutionary
+ * distinctiveness (fair proportion: every edge's length shared equally by
+ * the leaves below it), in double.  Returns 0, -1 if the counters differ
+ * or are past the horizon, -2 on no memory.                                */
+typedef struct {
+    int child[2];
+    int leaf_first;     /* first annotation index at a depth-F node, or -1 */
+    int nleaves;        /* annotations below                               */
+} orc_trie_node;
+
+typedef struct {
+    orc_trie_node *nodes;
+    int count, cap;
+} orc_trie;
+
+static int trie_new(orc_trie *t)
+{
+    if (t->count == t->cap) {
+        int cap = t->cap ? 2 * t->cap : 1024;
+        orc_trie_node *p = (orc_trie_node *)realloc(t->nodes, (size_t)cap * sizeof(*p));
+        if (!p)
+            return -1;
+        t->nodes = p;
+        t->cap = cap;
+    }
+    orc_trie_node *nd = &t->nodes[t->count];
+    nd->child[0] = nd->child[1] = -1;
+    nd->leaf_first = -1;
+    nd->nleaves = 0;
+    return t->count++;
+}
+
+typedef struct {
+    const uint32_t *times;   /* ascending retained times */
+    uint32_t F, T;
+    const orc_trie *trie;
+    const int *leaf_next;    /* annotations sharing a depth-F node */
+    uint64_t sbl;
+    uint64_t pair_sum;
+    uint32_t root_time;
+    int have_root;
+    uint64_t internal;
+    double *ed;
+} orc_phylo_ctx;
+
+/* Walk the trie from node v at depth d, whose nearest tree ancestor sits at
+ * time parent_t (or none at the very top).  acc_ed is the ED accumulated by
+ * the path above v.  Adds every edge, every pair's MRCA depth and every
+ * leaf's ED.                                                                */
+static void phylo_walk(orc_phylo_ctx *c, int v, uint32_t d, int has_parent,
+                       uint32_t parent_t, double acc_ed)
+{
+    const orc_trie_node *nd = &c->trie->nodes[v];
+    if (d == c->F) {
+        /* annotations with identical bits */
+        int k = nd->nleaves;
+        uint32_t here = c->T;
+        double ed_here = acc_ed;
+        if (k >= 2) {
+            /* a tree node at T with k leaf children (zero-length edges) */
+            if (has_parent) {
+                c->sbl += here - parent_t;
+                ed_here += (double)(here - parent_t) / k;
+            } else if (!c->have_root) {
+                c->have_root = 1;
+                c->root_time = here;
+            }
+            c->internal += 1;
+            /* pairs inside: MRCA at T, contributes T - T = 0 */
+        }
+        for (int a = nd->leaf_first; a >= 0; a = c->leaf_next[a]) {
+            double e = ed_here;
+            if (k == 1 && has_parent) {
+                c->sbl += c->T - parent_t;
+                e += (double)(c->T - parent_t);
+            }
+            if (c->ed)
+                c->ed[a] = e;
+        }
+        return;
+    }
+    int c0 = nd->child[0], c1 = nd->child[1];
+    if (c0 >= 0 && c1 >= 0) {
+        /* branching: a tree node at t_d */
+        uint32_t here = c->times[d];
+        double ed_here = acc_ed;
+        if (has_parent) {
+            c->sbl += here - parent_t;
+            ed_here += (double)(here - parent_t) / nd->nleaves;
+        } else if (!c->have_root) {
+            c->have_root = 1;
+            c->root_time = here;
+        }
+        c->internal += 1;
+        uint64_t n0 = (uint64_t)c->trie->nodes[c0].nleaves;
+        uint64_t n1 = (uint64_t)c->trie->nodes[c1].nleaves;
+        c->pair_sum += n0 * n1 * (uint64_t)(c->T - here);
+        phylo_walk(c, c0, d + 1, 1, here, ed_here);
+        phylo_walk(c, c1, d + 1, 1, here, ed_here);
+    } else {
+        phylo_walk(c, c0 >= 0 ? c0 : c1, d + 1, has_parent, parent_t, acc_ed);
+    }
+}
+
+int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,
+                      const uint32_t *surf, uint64_t out[4], double *ed)
+{
+    uint32_t SW = S / 32;
+    for (uint32_t a = 1; a < n; a++)
+        if (counters[a] != counters[0])
+            return -1;
+    uint32_t T = n ? counters[0] : 0;
+    uint32_t L[64];
+    if (orc_layout(kind, S, T, L) != 0)
+        return -1;
+    /* retained sites in ascending deposit time */
+    uint32_t times[64], sites[64], F = 0;
+    for (uint32_t k = 0; k < S; k++) {
+        if (L[k] == ORC_EMPTY)
+            continue;
+        uint32_t q = F++;
+        while (q > 0 && times[q - 1] > L[k]) {
+            times[q] = times[q - 1];
+            sites[q] = sites[q - 1];
+            q--;
+        }
+        times[q] = L[k];
+        sites[q] = k;
+    }
+    orc_trie trie = {0};
+    int *leaf_next = (int *)malloc((size_t)(n ? n : 1) * sizeof(int));
+    if (!leaf_next || trie_new(&trie) < 0) {
+        free(leaf_next);
+        free(trie.nodes);
+        return -2;
+    }
+    for (uint32_t a = 0; a < n; a++) {
+        int v = 0;
+        trie.nodes[v].nleaves++;
+        for (uint32_t r = 0; r < F; r++) {
+            uint32_t b = site_bit(surf + (size_t)a * SW, sites[r]);
+            if (trie.nodes[v].child[b] < 0) {
+                int w = trie_new(&trie);
+                if (w < 0) {
+                    free(leaf_next);
+                    free(trie.nodes);
+                    return -2;
+                }
+                trie.nodes[v].child[b] = w;
+            }
+            v = trie.nodes[v].child[b];
+            trie.nodes[v].nleaves++;
+        }
+        leaf_next[a] = trie.nodes[v].leaf_first;
+        trie.nodes[v].leaf_first = (int)a;
+    }
+    orc_phylo_ctx c = {times, F, T, &trie, leaf_next, 0, 0, 0, 0, 0, ed};
+    if (n > 0)
+        phylo_walk(&c, 0, 0, 0, 0, 0.0);
+    if (!c.have_root)
+        c.root_time = T;
+    out[0] = c.sbl;
+    out[1] = c.pair_sum;
+    out[2] = c.root_time;
+    out[3] = c.internal;
+    free(leaf_next);
+    free(trie.nodes);
+    return 0;
+}

@@ -100,6 +100,10 @@ def load():
     lib.orc_mrca_rows.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                   u32p, u32p, ctypes.c_uint32, u32p, u32p, u32p]
     lib.orc_mrca_rows.restype = ctypes.c_int
+    lib.orc_phylo_metrics.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      u32p, u32p, ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.orc_phylo_metrics.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -277,6 +281,23 @@ def mrca_rows(kind: int, S: int, counters, surfaces, rows):
     if rc:
         raise ValueError("beyond the horizon or row out of range")
     return lb, ub
+
+
+def phylo_metrics(kind: int, S: int, counters, surfaces):
+    """Trie reconstruction of annotations sharing a counter: (sum of branch
+    lengths, sum over pairs of T - MRCA time, root time, internal nodes,
+    per-leaf evolutionary distinctiveness)."""
+    counters = np.ascontiguousarray(counters, np.uint32)
+    surfaces = np.ascontiguousarray(surfaces, np.uint32).reshape(-1)
+    n = counters.shape[0]
+    out = np.zeros(4, np.uint64)
+    ed = np.zeros(max(n, 1), np.float64)
+    rc = load().orc_phylo_metrics(kind, S, n, _p(counters), _p(surfaces),
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                  ed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise ValueError("counters differ, past the horizon, or no memory")
+    return int(out[0]), int(out[1]), int(out[2]), int(out[3]), ed[:n].copy()
 
 
 # --------------------------------------------------------------------------
