@@ -196,6 +196,39 @@ int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n,
 int hstrat_mrca_status(const void *workspace, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Trie reconstruction and phylometrics (Distributed Phylogenetic Tracking:
+ * the record of differentiae turns reconstruction into trie building;
+ * Results, On-hardware Trial: treatments compared by sum branch length and
+ * mean evolutionary distinctiveness).
+ *
+ * For n annotations sharing one counter T: each annotation is read as its
+ * bits in ascending deposit time (t_0 < ... < t_{F-1}, the retained times)
+ * and inserted into a binary trie.  A branching trie node whose subtrees
+ * split on the bit of t_d is a tree node at time t_d (the MRCA upper bound
+ * of every pair it separates); identical annotations hang from one node at
+ * T; annotations are leaves at T; one-child chains are collapsed; the root
+ * is the first branching node.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of hstrat_phylo_metrics for n annotations. */
+size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n);
+
+/* Enqueue the reconstruction.  counter, surface_words: as for
+ * hstrat_mrca_bounds (n <= 65535).  out: device, 6 uint64 words:
+ *   [0] sum of branch lengths (the mean evolutionary distinctiveness under
+ *       fair proportion is this sum / n),
+ *   [1] sum over unordered pairs of (T - the time of their tree MRCA)
+ *       (mean pairwise distance = 2 * [1] / (n(n-1)/2)),
+ *   [2] root time, [3] internal nodes,
+ *   [4] status: 0 ok, 1 counters differ (not reconstructed), 2 past the
+ *       horizon, [5] n.
+ * Errors: GA_EINVAL, GA_ENOMEM (workspace), GA_EDEVICE.                    */
+int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n,
+                         const uint32_t *counter, const uint32_t *surface_words,
+                         uint64_t *out, void *workspace, size_t workspace_bytes,
+                         void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batched and served runs: a pool of runs of any sizes, surfaces and
  * treatments sharing one caller-owned device arena and one stream.  An
  * advance enqueues one site-schedule launch for all active runs, then one

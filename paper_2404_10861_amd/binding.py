@@ -32,6 +32,7 @@ EXPORTS = (
     "ga_pool_overhead_bytes", "ga_pool_create", "ga_pool_footprint", "ga_pool_admit",
     "ga_pool_advance", "ga_pool_poll", "ga_pool_run", "ga_pool_release", "ga_pool_sync",
     "ga_pool_set_launch", "ga_pool_info", "ga_pool_destroy",
+    "hstrat_phylo_workspace_bytes", "hstrat_phylo_metrics",
 )
 
 
@@ -111,6 +112,9 @@ def load_library():
         "ga_pool_info": (ctypes.c_int, [_vp, _u32p, _u32p, ctypes.POINTER(ctypes.c_size_t),
                                         ctypes.POINTER(ctypes.c_size_t)]),
         "ga_pool_destroy": (None, [_vp]),
+        "hstrat_phylo_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
+        "hstrat_phylo_metrics": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                                _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -447,6 +451,37 @@ def mrca_bounds(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor
                                   _vp(ub.data_ptr()), _vp(workspace.ptr), workspace.nbytes,
                                   _vp(_stream_handle(stream))))
     return lb, ub
+
+
+def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
+                  stream=None) -> dict:
+    """Trie reconstruction of annotations sharing a counter, on the device.
+
+    Returns the six result words (blocking copy to the host) and the derived
+    means: sum_branch_length, pair_sum, root_time, internal_nodes, status,
+    n, mean_ed (= sum_branch_length / n under fair proportion) and
+    mean_pairwise_distance."""
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    n = counter.shape[0]
+    dev = counter.device
+    counter = counter.contiguous()
+    surface_words = surface_words.contiguous()
+    need = int(load_library().hstrat_phylo_workspace_bytes(S, n))
+    buf, ptr = _aligned_bytes(need, dev)
+    out = torch.zeros(6, dtype=torch.int64, device=dev)
+    _check(load_library().hstrat_phylo_metrics(kind, S, n, _vp(counter.data_ptr()),
+                                               _vp(surface_words.data_ptr()),
+                                               _vp(out.data_ptr()), _vp(ptr), need,
+                                               _vp(_stream_handle(stream))))
+    w = out.cpu().numpy().view(np.uint64)
+    del buf
+    res = {"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
+           "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5])}
+    npairs = n * (n - 1) // 2
+    res["mean_ed"] = res["sum_branch_length"] / n
+    res["mean_pairwise_distance"] = 2.0 * res["pair_sum"] / npairs if npairs else 0.0
+    return res
 
 
 def mrca_status(workspace: MrcaWorkspace, stream=None) -> int:

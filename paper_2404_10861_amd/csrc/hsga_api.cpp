@@ -347,6 +347,26 @@ int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* co
     return GA_OK;
 }
 
+size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n) {
+    return hsga::phylo_workspace_bytes(S, n);
+}
+
+int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                         const uint32_t* surface_words, uint64_t* out, void* workspace,
+                         size_t workspace_bytes, void* hip_stream) {
+    if (kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
+    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+    if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
+    if (!counter || !surface_words || !out || !workspace) return fail(GA_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < hsga::phylo_workspace_bytes(S, n))
+        return fail(GA_ENOMEM, "workspace too small");
+    hipError_t e = hsga::launch_phylo(kind, S, n, counter, surface_words, out, workspace,
+                                      static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "phylo launch");
+    return GA_OK;
+}
+
 int hstrat_mrca_status(const void* workspace, void* hip_stream) {
     if (!workspace) return fail(GA_EINVAL, "workspace is NULL");
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));

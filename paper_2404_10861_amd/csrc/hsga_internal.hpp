@@ -91,6 +91,10 @@ struct MrcaWorkspace {
     }
 };
 
+size_t phylo_workspace_bytes(uint32_t S, uint32_t n);
+hipError_t launch_phylo(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                        const uint32_t* surf, uint64_t* out, void* workspace, hipStream_t stream);
+
 hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
                        hipStream_t stream);

@@ -703,6 +703,181 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
     lb[off] = have_last ? last + 1u : 0u;
 }
 
+// ---------------------------------------------------------------------------
+// Trie reconstruction and phylometrics of annotations sharing a counter
+// (Distributed Phylogenetic Tracking: reconstruction is a trie over the
+// record of differentiae; Results, On-hardware Trial: sum branch length and
+// mean evolutionary distinctiveness).  Annotations read as their bits in
+// ascending deposit time are sorted lexicographically; neighbours in that
+// order share a prefix of d_i = LCP(i, i+1) retained items, and the trie's
+// branching nodes are exactly these boundaries (runs of identical
+// annotations give one node at T).  A node at depth d sits at time
+// tau(d) = t_d (the MRCA upper bound of the pairs it separates), tau(F) = T.
+//   leaf i hangs from the deeper of boundaries i-1, i;
+//   a node hangs from the deeper of its nearest strictly shallower
+//   boundaries on either side (none: the root);
+//   pairs (a, b) meet at the shallowest boundary between them, so the sum
+//   over pairs of T - tau(MRCA) is a sum over all boundary ranges of their
+//   minimum, counted by nearest-smaller spans.
+constexpr uint32_t kPhyloOutWords = 6;   // sbl, pair sum, root, internal, status, n
+
+__global__ __launch_bounds__(256) void phylo_keys_kernel(uint32_t n, uint32_t npad,
+                                                        const uint64_t* __restrict__ ranked,
+                                                        const uint32_t* __restrict__ ws,
+                                                        uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ idx) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    keys[i] = i < n ? __brevll(ranked[i]) : ~0ull;   // bit of rank r at position 63 - r
+    idx[i] = i < n ? i : 0xffffffffu;
+}
+
+// One workgroup: bitonic sort of (key, index) over npad (a power of two)
+// entries held in global memory.
+__global__ __launch_bounds__(1024) void phylo_sort_kernel(uint32_t npad,
+                                                         const uint32_t* __restrict__ ws,
+                                                         uint64_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ idx) {
+    if (ws[kWsStatus] != 0) return;
+    for (uint32_t k = 2; k <= npad; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < npad / 2; t += blockDim.x) {
+                const uint32_t i = (t / j) * 2 * j + (t % j);
+                const uint32_t l = i + j;
+                const bool up = (i & k) == 0;
+                const uint64_t ki = keys[i], kl = keys[l];
+                const uint32_t ii = idx[i], il = idx[l];
+                const bool greater = ki > kl || (ki == kl && ii > il);
+                if (greater == up) {
+                    keys[i] = kl; keys[l] = ki;
+                    idx[i] = il; idx[l] = ii;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void phylo_metrics_kernel(uint32_t n,
+                                                           const uint32_t* __restrict__ ws,
+                                                           const uint64_t* __restrict__ keys,
+                                                           uint8_t* __restrict__ depth,
+                                                           uint32_t* __restrict__ left,
+                                                           uint32_t* __restrict__ right,
+                                                           uint32_t* __restrict__ rstrict,
+                                                           uint32_t* __restrict__ stack,
+                                                           uint64_t* __restrict__ out) {
+    const uint32_t status = ws[kWsStatus];
+    if (status != 0) {
+        if (threadIdx.x == 0) {
+            out[0] = out[1] = out[2] = out[3] = 0;
+            out[4] = status;
+            out[5] = n;
+        }
+        return;
+    }
+    const uint32_t T = ws[kWsT], F = ws[kWsF];
+    const uint32_t* times = ws + kWsTimes;
+    const uint32_t m = n - 1;                              // boundaries
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+        const uint64_t x = keys[i] ^ keys[i + 1];
+        const uint32_t d = x ? (uint32_t)__clzll((long long)x) : 64u;
+        depth[i] = (uint8_t)(d < F ? d : F);
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    auto tau = [&](uint32_t d) -> uint64_t { return d < F ? times[d] : T; };
+    // nearest boundary to the left with a strictly smaller depth
+    uint32_t top = 0;
+    for (uint32_t b = 0; b < m; ++b) {
+        while (top && depth[stack[top - 1]] >= depth[b]) --top;
+        left[b] = top ? stack[top - 1] : 0xffffffffu;
+        stack[top++] = b;
+    }
+    // nearest to the right: strictly smaller, and smaller or equal
+    top = 0;
+    for (uint32_t b = m; b-- > 0;) {
+        while (top && depth[stack[top - 1]] >= depth[b]) --top;
+        rstrict[b] = top ? stack[top - 1] : 0xffffffffu;
+        stack[top++] = b;
+    }
+    top = 0;
+    for (uint32_t b = m; b-- > 0;) {
+        while (top && depth[stack[top - 1]] > depth[b]) --top;
+        right[b] = top ? stack[top - 1] : m;
+        stack[top++] = b;
+    }
+    uint64_t sbl = 0, pairs = 0, internal = 0;
+    uint32_t dmin = F;
+    for (uint32_t b = 0; b < m; ++b) {
+        const uint32_t d = depth[b];
+        dmin = d < dmin ? d : dmin;
+        // pairs meeting at b (b the rightmost shallowest boundary between them)
+        const uint64_t nl = (uint64_t)b - (left[b] == 0xffffffffu ? (uint64_t)-1 : left[b]);
+        const uint64_t nr = (uint64_t)right[b] - b;
+        pairs += (T - tau(d)) * nl * nr;
+        // one node per run of equal depth (only identical annotations repeat)
+        if (b > 0 && depth[b - 1] == d) continue;
+        ++internal;
+        const uint32_t L = left[b], R = rstrict[b];
+        if (L == 0xffffffffu && R == 0xffffffffu) continue;   // the root
+        uint32_t pd;
+        if (L == 0xffffffffu) pd = depth[R];
+        else if (R == 0xffffffffu) pd = depth[L];
+        else pd = depth[L] > depth[R] ? depth[L] : depth[R];
+        sbl += tau(d) - tau(pd);
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t pd = 0;
+        bool any = false;
+        if (i > 0) { pd = depth[i - 1]; any = true; }
+        if (i < m) { pd = any && pd > depth[i] ? pd : depth[i]; any = true; }
+        if (any) sbl += T - tau(pd);
+    }
+    out[0] = sbl;
+    out[1] = pairs;
+    out[2] = n > 1 ? tau(dmin) : T;
+    out[3] = internal;
+    out[4] = 0;
+    out[5] = n;
+}
+
+size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
+    size_t npad = 1;
+    while (npad < n) npad <<= 1;
+    const size_t a = (MrcaWorkspace::bytes(S, n) + 255) & ~(size_t)255;
+    return a + npad * 8 + npad * 4 + (size_t)n * (1 + 4 * 4) + 1024;
+}
+
+hipError_t launch_phylo(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                        const uint32_t* surf, uint64_t* out, void* workspace,
+                        hipStream_t stream) {
+    uint8_t* base = static_cast<uint8_t*>(workspace);
+    uint32_t* ws = reinterpret_cast<uint32_t*>(base);
+    uint64_t* ranked = reinterpret_cast<uint64_t*>(base + MrcaWorkspace::kHeader);
+    size_t npad = 1;
+    while (npad < n) npad <<= 1;
+    size_t off = (MrcaWorkspace::bytes(S, n) + 255) & ~(size_t)255;
+    uint64_t* keys = reinterpret_cast<uint64_t*>(base + off);   off += npad * 8;
+    uint32_t* idx = reinterpret_cast<uint32_t*>(base + off);    off += npad * 4;
+    uint32_t* left = reinterpret_cast<uint32_t*>(base + off);   off += (size_t)n * 4;
+    uint32_t* right = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
+    uint32_t* rstr = reinterpret_cast<uint32_t*>(base + off);   off += (size_t)n * 4;
+    uint32_t* stack = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
+    uint8_t* depth = base + off;
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, kind, S, n, counter, ws);
+    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S, n, surf,
+                       ws, ranked);
+    hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
+                       stream, n, (uint32_t)npad, ranked, ws, keys, idx);
+    hipLaunchKernelGGL(phylo_sort_kernel, dim3(1), dim3(1024), 0, stream, (uint32_t)npad, ws,
+                       keys, idx);
+    hipLaunchKernelGGL(phylo_metrics_kernel, dim3(1), dim3(256), 0, stream, n, ws, keys, depth,
+                       left, right, rstr, stack, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
                        hipStream_t stream) {
