@@ -155,8 +155,9 @@ def served_vs_plain(reqs, dev, chunk_gens: int = 256, time_scale: float = 1.0,
 
 def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
     """The treatment pair (selection, neutral): each run, its stratified
-    sample and all-pairs MRCA bounds; mean bounds over distinct pairs per
-    treatment (selection sweeps make common ancestry more recent)."""
+    sample, all-pairs MRCA bounds and the reconstructed tree's phylometrics
+    (sum branch length, mean evolutionary distinctiveness, mean pairwise
+    distance); selection sweeps make common ancestry more recent."""
     out = {}
     ws = hs.MrcaWorkspace(max(s.surface_sites for s in specs), n_sample, dev)
     lb = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
@@ -175,6 +176,9 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
         hs.mrca_bounds(s.surface_kind, s.surface_sites, cnt, srf, workspace=ws, stream=stream,
                        lb=lb, ub=ub)
         e1.record(stream)
+        e2 = torch.cuda.Event(enable_timing=True)
+        phylo = hs.phylo_metrics(s.surface_kind, s.surface_sites, cnt, srf, stream=stream)
+        e2.record(stream)
         torch.cuda.synchronize(dev)
         wall = time.perf_counter() - t0
         ms, launches = run.kernel_time()
@@ -190,6 +194,12 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
             "mean_lb": float(l_h[off].mean()),
             "mean_ub": float(u_h[off].mean()),
             "mean_trait": float(run.agents(0, 65536)[0].view(np.int32).mean()),
+            "phylo_ms": e1.elapsed_time(e2),
+            "sum_branch_length": phylo["sum_branch_length"],
+            "mean_evolutionary_distinctiveness": phylo["mean_ed"],
+            "mean_pairwise_distance": phylo["mean_pairwise_distance"],
+            "root_time": phylo["root_time"],
+            "internal_nodes": phylo["internal_nodes"],
         }
         run.close()
     return out

@@ -465,17 +465,22 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
         kind = KINDS[kind]
     n = counter.shape[0]
     dev = counter.device
-    counter = counter.contiguous()
-    surface_words = surface_words.contiguous()
-    need = int(load_library().hstrat_phylo_workspace_bytes(S, n))
-    buf, ptr = _aligned_bytes(need, dev)
-    out = torch.zeros(6, dtype=torch.int64, device=dev)
-    _check(load_library().hstrat_phylo_metrics(kind, S, n, _vp(counter.data_ptr()),
-                                               _vp(surface_words.data_ptr()),
-                                               _vp(out.data_ptr()), _vp(ptr), need,
-                                               _vp(_stream_handle(stream))))
-    w = out.cpu().numpy().view(np.uint64)
-    del buf
+    if counter.dtype != torch.int32 or surface_words.dtype != torch.int32:
+        raise ValueError("counter and surface_words must be int32 tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    lib = load_library()
+    with torch.cuda.stream(stream):     # allocation, launch and copy in one stream order
+        counter = counter.contiguous()
+        surface_words = surface_words.contiguous()
+        need = int(lib.hstrat_phylo_workspace_bytes(S, n))
+        buf, ptr = _aligned_bytes(need, dev)
+        out = torch.zeros(6, dtype=torch.int64, device=dev)
+        _check(lib.hstrat_phylo_metrics(kind, S, n, _vp(counter.data_ptr()),
+                                        _vp(surface_words.data_ptr()), _vp(out.data_ptr()),
+                                        _vp(ptr), need, _vp(_stream_handle(stream))))
+        w = out.cpu().numpy().view(np.uint64)
+        del buf
     res = {"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
            "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5])}
     npairs = n * (n - 1) // 2
