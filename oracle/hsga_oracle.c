@@ -9,7 +9,11 @@
  * helper with the HIP implementation; both sides implement the Philox4x32-10
  * generator separately from its published definition.
  *
- * Everything here is integer arithmetic; the HIP path must agree bit for bit.
+ * The integer treatments are integer arithmetic throughout.  The float
+ * treatments (Results, On-hardware Trial) use a binary32 fitness and a
+ * half-normal draw evaluated in binary64 by one fixed sequence of correctly
+ * rounded operations (orc_half_normal), so the HIP path must agree bit for
+ * bit there too.
  *
  * Where the paper is silent (it leaves the steady and tilted indexing
  * algorithms undefined, and gives no random-number mapping), this file follows
@@ -25,8 +29,10 @@
  *     invariants and the pedigree.
  *   - The MRCA bounds are pinned against the true pedigree on tiny runs.
  *
- * Build:  gcc -O2 -std=c11 -shared -fPIC -o liboracle.so hsga_oracle.c
+ * Build:  gcc -O2 -std=c11 -ffp-contract=off -shared -fPIC -o liboracle.so
+ *         hsga_oracle.c -lm
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -36,7 +42,10 @@
 /* surface kinds (policies) */
 enum { ORC_STEADY = 0, ORC_TILTED = 1, ORC_HYBRID = 2 };
 /* purpose tags carried in the fourth Philox counter word */
-enum { ORC_BIRTH = 0, ORC_EMIGRATE = 1, ORC_IMMIGRATE = 2, ORC_SAMPLE = 3 };
+enum { ORC_BIRTH = 0, ORC_EMIGRATE = 1, ORC_IMMIGRATE = 2, ORC_SAMPLE = 3,
+       ORC_BIRTH_B = 4 /* second block of a float-treatment birth */ };
+/* fitness models */
+enum { ORC_INT_TRAIT = 0, ORC_FLOAT_FITNESS = 1 };
 /* torus directions */
 enum { ORC_NORTH = 0, ORC_SOUTH = 1, ORC_WEST = 2, ORC_EAST = 3 };
 
@@ -222,6 +231,117 @@ int orc_site_sequence(uint32_t kind, uint32_t S, uint32_t T0, uint32_t n,
 }
 
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* Half-normal draw for the float treatments (Results, On-hardware Trial:
+ * mutations change fitness by normally distributed amounts).  Box and
+ * Muller (1958): with U1, U2 independent uniform on (0, 1),
+ * Z = sqrt(-2 ln U1) cos(2 pi U2) is standard normal; its magnitude has the
+ * law of sqrt(-2 ln U1) cos(pi/2 U2), which is what is evaluated here:
+ *   U1 = (w_radius + 1/2) / 2^32,  U2 = (w_angle + 1/2) / 2^32.
+ * The value is DEFINED as the following binary64 evaluation, written only
+ * with correctly rounded operations (+, -, *, fma) and exact scalings by
+ * powers of two, so that any IEEE-754 implementation of the same steps
+ * returns the same bits:
+ *   ln U1:  U1 = m 2^(e-33), m in [sqrt(1/2), sqrt(2)];
+ *           ln m = 2 atanh(s), s = (m-1)/(m+1), the reciprocal by five
+ *           Newton steps from 1/2, atanh by its series to s^21;
+ *   sqrt:   y = q 4^k, q in [1, 4); 1/sqrt(q) by six Newton steps from
+ *           9/8 - 3q/16, then one correction of q * (1/sqrt q);
+ *   cos:    for U2 < 1/2, cos(pi/2 U2) by its series to x^18; otherwise
+ *           sin(pi/2 (1 - U2)) by its series to x^19.
+ * Against the exact function the relative error is below 1e-14.          */
+static double orc_pow2(int k)          /* 2^k, exact, |k| < 1000 */
+{
+    return ldexp(1.0, k);
+}
+
+static double orc_ln_u(uint32_t w)
+{
+    uint64_t v = 2ull * w + 1ull;      /* U = v / 2^33, v odd */
+    int e = 0;
+    while ((v >> (e + 1)) != 0)
+        e++;                           /* e = floor(log2 v) */
+    double m = (double)v * orc_pow2(-e);
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double d = m + 1.0, r = 0.5;
+    for (int k = 0; k < 5; k++) {
+        double t = fma(-d, r, 1.0);
+        r = fma(r, t, r);
+    }
+    double sv = (m - 1.0) * r;
+    double z = sv * sv;
+    static const double inv_odd[11] = {
+        1.0, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0, 1.0 / 9.0, 1.0 / 11.0,
+        1.0 / 13.0, 1.0 / 15.0, 1.0 / 17.0, 1.0 / 19.0, 1.0 / 21.0};
+    double p = inv_odd[10];
+    for (int k = 9; k >= 0; k--)
+        p = fma(p, z, inv_odd[k]);
+    double ln_m = (sv + sv) * p;
+    return fma((double)e - 33.0, 0.6931471805599453, ln_m);
+}
+
+static double orc_sqrt_pos(double y)   /* y > 0, normal */
+{
+    int ex;
+    (void)frexp(y, &ex);               /* y = f 2^ex, f in [1/2, 1) */
+    ex -= 1;                           /* y = f' 2^ex, f' in [1, 2) */
+    int k = (ex >= 0) ? ex / 2 : -((1 - ex) / 2);   /* floor(ex / 2) */
+    double q = y * orc_pow2(-2 * k);   /* in [1, 4) */
+    double h = 0.5 * q;
+    double r = fma(-0.1875, q, 1.125);
+    for (int i = 0; i < 6; i++)
+        r = fma(r, fma(-h, r * r, 0.5), r);
+    double sq = q * r;
+    sq = fma(fma(-sq, sq, q), 0.5 * r, sq);
+    return sq * orc_pow2(k);
+}
+
+static double orc_cos_quarter(uint32_t w)   /* cos(pi/2 U2) */
+{
+    static const double cos_c[10] = {
+        1.0, -1.0 / 2.0, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0,
+        -1.0 / 3628800.0, 1.0 / 479001600.0, -1.0 / 87178291200.0,
+        1.0 / 20922789888000.0, -1.0 / 6402373705728000.0};
+    static const double sin_c[10] = {
+        1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0,
+        -1.0 / 39916800.0, 1.0 / 6227020800.0, -1.0 / 1307674368000.0,
+        1.0 / 355687428096000.0, -1.0 / 121645100408832000.0};
+    uint64_t v = 2ull * w + 1ull;      /* U2 = v / 2^33 */
+    int use_sin = w >= 0x80000000u;
+    if (use_sin)
+        v = (1ull << 33) - v;          /* 1 - U2, exact */
+    double x = ((double)v * orc_pow2(-33)) * 1.5707963267948966;
+    double z = x * x;
+    const double *c = use_sin ? sin_c : cos_c;
+    double p = c[9];
+    for (int k = 8; k >= 0; k--)
+        p = fma(p, z, c[k]);
+    return use_sin ? x * p : p;
+}
+
+double orc_half_normal(uint32_t w_radius, uint32_t w_angle)
+{
+    double y = -2.0 * orc_ln_u(w_radius);
+    return orc_sqrt_pos(y) * orc_cos_quarter(w_angle);
+}
+
+static uint32_t f32_bits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+static float f32_of(uint32_t u)
+{
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
 /* The island-model GA (Methods, Asynchronous Island-model Genetic Algorithm;
  * Genome Model).  Islands sit on a W x H torus, island i = y*W + x, agent
  * a = i*N + j.  An agent record is (trait, generation counter, S one-bit
@@ -230,6 +350,9 @@ typedef struct {
     uint32_t W, H, N, S, kind, tournament, mut_thr, mut_span, migrants;
     int32_t mut_lo;
     uint64_t seed;
+    /* float treatments (orc_set_fitness) */
+    uint32_t model, del_thr, ben_thr;
+    float del_sigma, ben_sigma;
     uint32_t I, A, SW;
     uint32_t g;                       /* generations elapsed                  */
     uint32_t *trait, *counter, *surf; /* A, A, A*SW (agent-major)             */
@@ -333,6 +456,39 @@ void *orc_create(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kind,
     return r;
 }
 
+/* Float treatments (Results, On-hardware Trial; Asynchronous Island-model
+ * Genetic Algorithm).  model 1: the trait word is a binary32 fitness
+ * (founders 0.0); selection is a tournament of `tournament` uniform draws
+ * with replacement (0 or 1: one draw, neutral), the first draw of maximal
+ * fitness winning, so ties go to a uniformly random tied individual; a
+ * birth is deleterious with probability del_thr / 2^32 (fitness decreases
+ * by del_sigma |Z|) or beneficial with probability ben_thr / 2^32 (fitness
+ * increases by ben_sigma |Z|), never both; the sum and product are taken in
+ * binary64 and rounded once to binary32.  Returns 0, or -1 if invalid.    */
+int orc_set_fitness(void *handle, uint32_t model, uint32_t tournament,
+                    uint32_t del_thr, uint32_t ben_thr, float del_sigma,
+                    float ben_sigma)
+{
+    orc_run *r = (orc_run *)handle;
+    if (model > ORC_FLOAT_FITNESS)
+        return -1;
+    if (model == ORC_FLOAT_FITNESS) {
+        if (tournament > 5 || (uint64_t)del_thr + ben_thr > (1ull << 32) ||
+            !(del_sigma >= 0.0f && del_sigma <= 1048576.0f) ||
+            !(ben_sigma >= 0.0f && ben_sigma <= 1048576.0f))
+            return -1;
+    } else if (tournament != 0 && tournament != 2) {
+        return -1;
+    }
+    r->model = model;
+    r->tournament = tournament;
+    r->del_thr = del_thr;
+    r->ben_thr = ben_thr;
+    r->del_sigma = del_sigma;
+    r->ben_sigma = ben_sigma;
+    return 0;
+}
+
 /* One generation, (P_g, O_g) -> (P_{g+1}, O_{g+1}), island by island, in the
  * paper's order: migration first, then selection, mutation and the
  * annotation update (Asynchronous Island-model Genetic Algorithm).
@@ -389,25 +545,52 @@ static int step_one(orc_run *r)
          * [mut_lo, mut_hi], increments the generation counter, and writes a
          * fresh one-bit differentia at this generation's site.              */
         for (uint32_t j = 0; j < N; j++) {
+            uint32_t a = i * N + j;
+            uint32_t p, child_trait, bit;
             orc_philox(j, i, g, ORC_BIRTH, r->seed, w);
-            uint32_t p = orc_mulhi(w[0], N);
-            if (r->tournament == 2) {
-                uint32_t b = orc_mulhi(w[1], N);
-                if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])
-                    p = b;
+            if (r->model == ORC_INT_TRAIT) {
+                p = orc_mulhi(w[0], N);
+                if (r->tournament == 2) {
+                    uint32_t b = orc_mulhi(w[1], N);
+                    if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])
+                        p = b;
+                }
+                uint32_t delta = 0;
+                if (w[2] < r->mut_thr)
+                    delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
+                child_trait = r->q_trait[p] + delta;
+                bit = w[3] & 1u;
+            } else {
+                /* float treatments: candidates from words w0..w3, v0; the
+                 * class of the mutation from v1; |Z| from v2 (radius) and
+                 * v3 (angle); the differentia is bit 0 of v3            */
+                uint32_t v[4];
+                orc_philox(j, i, g, ORC_BIRTH_B, r->seed, v);
+                uint32_t words[5] = {w[0], w[1], w[2], w[3], v[0]};
+                uint32_t k = r->tournament < 1 ? 1 : r->tournament;
+                p = orc_mulhi(words[0], N);
+                for (uint32_t c = 1; c < k; c++) {
+                    uint32_t b = orc_mulhi(words[c], N);
+                    if (f32_of(r->q_trait[b]) > f32_of(r->q_trait[p]))
+                        p = b;
+                }
+                double f = (double)f32_of(r->q_trait[p]);
+                child_trait = r->q_trait[p];
+                if (v[1] < r->del_thr)
+                    child_trait = f32_bits((float)(f - (double)r->del_sigma *
+                                                          orc_half_normal(v[2], v[3])));
+                else if ((uint64_t)v[1] + r->ben_thr >= (1ull << 32))
+                    child_trait = f32_bits((float)(f + (double)r->ben_sigma *
+                                                          orc_half_normal(v[2], v[3])));
+                bit = v[3] & 1u;
             }
             uint32_t T = r->q_counter[p];
             if (T != g)
                 return -2;
-            uint32_t delta = 0;
-            if (w[2] < r->mut_thr)
-                delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
-            uint32_t a = i * N + j;
-            r->n_trait[a] = r->q_trait[p] + delta;
+            r->n_trait[a] = child_trait;
             r->n_counter[a] = T + 1;
             for (uint32_t s = 0; s < SW; s++)
                 r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];
-            uint32_t bit = w[3] & 1u;
             uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / 32];
             *word = (*word & ~(1u << (site % 32))) | (bit << (site % 32));
             r->n_src[a] = r->q_src[p];

@@ -23,7 +23,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 EMPTY = 0xFFFFFFFF
 STEADY, TILTED, HYBRID = 0, 1, 2
 KINDS = {"steady": STEADY, "tilted": TILTED, "hybrid": HYBRID}
-BIRTH, EMIGRATE, IMMIGRATE, SAMPLE = 0, 1, 2, 3
+BIRTH, EMIGRATE, IMMIGRATE, SAMPLE, BIRTH_B = 0, 1, 2, 3, 4
+INT_TRAIT, FLOAT_FITNESS = 0, 1
 
 _lib = None
 
@@ -34,8 +35,8 @@ u8p = ctypes.POINTER(ctypes.c_uint8)
 
 def build() -> str:
     """Compile the oracle (plain C, -O2, scalar) into liboracle.so."""
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-           "-o", LIB + ".tmp", SRC]
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-Wall", "-Wextra", "-shared",
+           "-fPIC", "-o", LIB + ".tmp", SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
@@ -70,6 +71,10 @@ def load():
                                [ctypes.c_uint32, ctypes.c_uint64,
                                 ctypes.c_uint32])
     lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_set_fitness.argtypes = [ctypes.c_void_p] + [ctypes.c_uint32] * 4 + [ctypes.c_float] * 2
+    lib.orc_set_fitness.restype = ctypes.c_int
+    lib.orc_half_normal.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.orc_half_normal.restype = ctypes.c_double
     lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     lib.orc_step.restype = ctypes.c_int
     lib.orc_generation.argtypes = [ctypes.c_void_p]
@@ -125,6 +130,16 @@ def mulhi(w: int, n: int) -> int:
     return int(load().orc_mulhi(w, n))
 
 
+def half_normal(w_radius: int, w_angle: int) -> float:
+    """|Z| of one Box-Muller draw from two Philox words (float treatments)."""
+    return float(load().orc_half_normal(w_radius, w_angle))
+
+
+def as_f32(words) -> np.ndarray:
+    """binary32 view of trait words."""
+    return np.ascontiguousarray(words, np.uint32).view(np.float32)
+
+
 # --------------------------------------------------------------------------
 # Site rule
 
@@ -165,13 +180,19 @@ class Run:
     """One oracle run.  Parameters mirror the GA configuration."""
 
     def __init__(self, W, H, N, S, kind, tournament=2, mut_thr=42949672,
-                 mut_lo=-8, mut_hi=8, migrants=1, seed=1, pedigree_gens=0):
+                 mut_lo=-8, mut_hi=8, migrants=1, seed=1, pedigree_gens=0,
+                 fitness_model=INT_TRAIT, del_thr=0, ben_thr=0, del_sigma=1.0,
+                 ben_sigma=1.0):
         lib = load()
-        h = lib.orc_create(W, H, N, S, kind, tournament, mut_thr, mut_lo, mut_hi,
-                           migrants, seed, pedigree_gens)
+        h = lib.orc_create(W, H, N, S, kind, tournament if fitness_model == INT_TRAIT else 0,
+                           mut_thr, mut_lo, mut_hi, migrants, seed, pedigree_gens)
         if not h:
             raise ValueError("invalid oracle configuration")
         self._h = h
+        if lib.orc_set_fitness(h, fitness_model, tournament, del_thr, ben_thr, del_sigma,
+                               ben_sigma):
+            self.close()
+            raise ValueError("invalid oracle fitness configuration")
         self.W, self.H, self.N, self.S, self.kind = W, H, N, S, kind
         self.I = W * H
         self.A = self.I * N
