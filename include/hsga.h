@@ -57,19 +57,42 @@ typedef enum { GA_STEADY = 0, GA_TILTED = 1, GA_HYBRID = 2 } ga_surface_kind;
 /* Marker for a surface site that holds no differentia yet. */
 #define GA_EMPTY_SITE 0xffffffffu
 
+/* Fitness model.  GA_INT_TRAIT: the configured integer trait (signed
+ * comparison, uniform integer mutation).  GA_FLOAT_FITNESS: the paper's
+ * float treatments (Asynchronous Island-model Genetic Algorithm; Results,
+ * On-hardware Trial): the trait word holds a binary32 fitness, selection is
+ * a tournament of up to five, and a birth is deleterious (fitness decreases
+ * by del_sigma |Z|) or beneficial (increases by ben_sigma |Z|) with the
+ * configured probabilities, |Z| half-normal from a Box-Muller draw.        */
+typedef enum { GA_INT_TRAIT = 0, GA_FLOAT_FITNESS = 1 } ga_fitness_model;
+
 typedef struct ga_config {
-    uint32_t struct_size;         /* sizeof(ga_config)                         */
+    uint32_t struct_size;         /* sizeof(ga_config) = 80; 56 (a config
+                                     without the float fields) is accepted
+                                     and means GA_INT_TRAIT                   */
     uint32_t grid_w, grid_h;      /* torus of islands; island i = y*w + x      */
     uint32_t pop_per_island;      /* N agents per island, 1..64                */
     uint32_t surface_sites;       /* S one-bit sites: 32 or 64                 */
     uint32_t surface_kind;        /* ga_surface_kind                           */
-    uint32_t tournament_size;     /* 2 = tournament of two; 0 = neutral        */
-    uint32_t mut_threshold;       /* mutate iff a uniform 32-bit word is below
-                                     this; p = 0.01 -> 42949672               */
-    int32_t mut_lo, mut_hi;       /* inclusive trait-delta range, e.g. -8, 8   */
+    uint32_t tournament_size;     /* GA_INT_TRAIT: 2 = tournament of two,
+                                     0 = neutral.  GA_FLOAT_FITNESS: 1..5
+                                     draws (0 and 1 = neutral)                 */
+    uint32_t mut_threshold;       /* GA_INT_TRAIT: mutate iff a uniform 32-bit
+                                     word is below this; p = 0.01 -> 42949672 */
+    int32_t mut_lo, mut_hi;       /* GA_INT_TRAIT: inclusive trait-delta
+                                     range, e.g. -8, 8                         */
     uint32_t migrants_per_island; /* 1, or 0 to switch migration off           */
     uint32_t reserved;            /* must be 0                                 */
     uint64_t seed;                /* Philox4x32-10 key                         */
+    /* GA_FLOAT_FITNESS only (ignored otherwise): */
+    uint32_t fitness_model;       /* ga_fitness_model                          */
+    uint32_t del_threshold;       /* deleterious iff the class word < this;
+                                     p = 0.33 -> 1417339207                    */
+    uint32_t ben_threshold;       /* beneficial iff the class word >= 2^32 -
+                                     this; p = 0.003 -> 12884901; the two
+                                     thresholds sum to at most 2^32            */
+    float del_sigma, ben_sigma;   /* scales of |Z|, in [0, 2^20]               */
+    uint32_t reserved2;           /* must be 0                                 */
 } ga_config;
 
 typedef struct ga_run ga_run;
@@ -96,8 +119,10 @@ size_t ga_footprint_bytes(const ga_config *cfg, uint32_t max_gens_per_launch);
  * aligned, arena_bytes >= ga_footprint_bytes) and enqueue the founders on
  * hip_stream: trait 0, counter 0, all sites 0, empty layout, no outboxes.
  * Founders carry no differentia; generation g's births deposit item g.
- * Errors: GA_EINVAL (S not 32/64, N = 0 or > 64, empty grid, mut_lo >
- * mut_hi, tournament not 0/2, migrants > 1, reserved != 0), GA_ENOMEM
+ * Errors: GA_EINVAL (struct_size not 56/80, S not 32/64, N = 0 or > 64,
+ * empty grid, mut_lo > mut_hi, tournament not 0/2 (integer trait) or above
+ * 5 (float fitness), migrants > 1, reserved fields != 0, float thresholds
+ * summing above 2^32, a scale outside [0, 2^20]), GA_ENOMEM
  * (arena too small), GA_EDEVICE.  *out is owned by the caller until
  * ga_destroy.                                                              */
 int ga_create(const ga_config *cfg, void *dev_arena, size_t arena_bytes,

@@ -57,7 +57,16 @@ class ga_config(ctypes.Structure):
         ("migrants_per_island", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("fitness_model", ctypes.c_uint32),
+        ("del_threshold", ctypes.c_uint32),
+        ("ben_threshold", ctypes.c_uint32),
+        ("del_sigma", ctypes.c_float),
+        ("ben_sigma", ctypes.c_float),
+        ("reserved2", ctypes.c_uint32),
     ]
+
+
+FITNESS_MODELS = {"int": 0, "float": 1}
 
 
 _lib = None
@@ -141,7 +150,12 @@ def _ptr(arr: np.ndarray):
 
 @dataclass
 class Config:
-    """GA configuration (ga_config).  Kinds: 'steady', 'tilted', 'hybrid'."""
+    """GA configuration (ga_config).  Kinds: 'steady', 'tilted', 'hybrid'.
+
+    fitness_model 'int' is the integer trait (tournament_size 0 or 2, the
+    mut_* fields); 'float' is the paper's float treatments (tournament_size
+    0..5, del_threshold / ben_threshold class probabilities times 2^32,
+    del_sigma / ben_sigma scales of the half-normal change)."""
     grid_w: int
     grid_h: int
     pop_per_island: int = 32
@@ -153,6 +167,11 @@ class Config:
     mut_hi: int = 8
     migrants_per_island: int = 1
     seed: int = 1
+    fitness_model: str = "int"
+    del_threshold: int = 0
+    ben_threshold: int = 0
+    del_sigma: float = 1.0
+    ben_sigma: float = 1.0
 
     @property
     def kind(self) -> int:
@@ -179,6 +198,12 @@ class Config:
         c.migrants_per_island = self.migrants_per_island
         c.reserved = 0
         c.seed = self.seed
+        c.fitness_model = FITNESS_MODELS[self.fitness_model]
+        c.del_threshold = self.del_threshold
+        c.ben_threshold = self.ben_threshold
+        c.del_sigma = self.del_sigma
+        c.ben_sigma = self.ben_sigma
+        c.reserved2 = 0
         return c
 
 

@@ -4,6 +4,7 @@
 // file only validates, carves memory and enqueues.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -44,10 +45,16 @@ Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens) {
     return c;
 }
 
-int validate(const ga_config* cfg) {
-    if (!cfg) return fail(GA_EINVAL, "config is NULL");
-    if (cfg->struct_size != sizeof(ga_config))
+int validate(const ga_config* in, ga_config* out) {
+    if (!in) return fail(GA_EINVAL, "config is NULL");
+    constexpr uint32_t kIntOnlySize = offsetof(ga_config, fitness_model);
+    if (in->struct_size != sizeof(ga_config) && in->struct_size != kIntOnlySize)
         return fail(GA_EINVAL, "config struct_size does not match this library");
+    ga_config c;
+    std::memset(&c, 0, sizeof c);
+    std::memcpy(&c, in, in->struct_size);
+    c.struct_size = sizeof(ga_config);
+    const ga_config* cfg = &c;
     if (cfg->grid_w == 0 || cfg->grid_h == 0) return fail(GA_EINVAL, "empty torus");
     if (cfg->grid_w > 65535 || cfg->grid_h > 65535)
         return fail(GA_EINVAL, "torus side above 65535 islands");
@@ -58,13 +65,24 @@ int validate(const ga_config* cfg) {
     if (cfg->surface_sites != 32 && cfg->surface_sites != 64)
         return fail(GA_EINVAL, "surface_sites must be 32 or 64");
     if (cfg->surface_kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
-    if (cfg->tournament_size != 0 && cfg->tournament_size != 2)
-        return fail(GA_EINVAL, "tournament_size must be 2 (tournament) or 0 (neutral)");
-    if (cfg->mut_lo > cfg->mut_hi) return fail(GA_EINVAL, "mut_lo > mut_hi");
-    if ((int64_t)cfg->mut_hi - cfg->mut_lo + 1 > 0xffffffffll)
-        return fail(GA_EINVAL, "mutation range wider than 2^32 - 1");
+    if (cfg->fitness_model > GA_FLOAT_FITNESS) return fail(GA_EINVAL, "unknown fitness model");
+    if (cfg->fitness_model == GA_INT_TRAIT) {
+        if (cfg->tournament_size != 0 && cfg->tournament_size != 2)
+            return fail(GA_EINVAL, "tournament_size must be 2 (tournament) or 0 (neutral)");
+        if (cfg->mut_lo > cfg->mut_hi) return fail(GA_EINVAL, "mut_lo > mut_hi");
+        if ((int64_t)cfg->mut_hi - cfg->mut_lo + 1 > 0xffffffffll)
+            return fail(GA_EINVAL, "mutation range wider than 2^32 - 1");
+    } else {
+        if (cfg->tournament_size > 5) return fail(GA_EINVAL, "tournament_size must be 0..5");
+        if ((uint64_t)cfg->del_threshold + cfg->ben_threshold > (1ull << 32))
+            return fail(GA_EINVAL, "deleterious and beneficial thresholds sum above 2^32");
+        if (!(cfg->del_sigma >= 0.0f && cfg->del_sigma <= 1048576.0f) ||
+            !(cfg->ben_sigma >= 0.0f && cfg->ben_sigma <= 1048576.0f))
+            return fail(GA_EINVAL, "mutation scales must lie in [0, 2^20]");
+    }
     if (cfg->migrants_per_island > 1) return fail(GA_EINVAL, "migrants_per_island must be 0 or 1");
-    if (cfg->reserved != 0) return fail(GA_EINVAL, "reserved must be 0");
+    if (cfg->reserved != 0 || cfg->reserved2 != 0) return fail(GA_EINVAL, "reserved must be 0");
+    if (out) *out = c;
     return GA_OK;
 }
 
@@ -133,7 +151,17 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k) {
     p.has_inbox = (cfg.migrants_per_island != 0 && g > 0) ? 1u : 0u;
     p.tile_isl = tile_islands(r->block, r->apt, r->N);
     p.div_magic = ((1u << 20) + r->N - 1) / r->N;
+    p.tour = cfg.tournament_size > 1 ? cfg.tournament_size : 1u;
+    p.del_thr = cfg.del_threshold;
+    p.ben_thr = cfg.ben_threshold;
+    p.del_sigma = cfg.del_sigma;
+    p.ben_sigma = cfg.ben_sigma;
     return p;
+}
+
+uint32_t birth_model(const ga_config& cfg) {
+    if (cfg.fitness_model == GA_FLOAT_FITNESS) return hsga::kBirthFloat;
+    return cfg.tournament_size == 2 ? hsga::kBirthIntTournament : hsga::kBirthIntNeutral;
 }
 
 }  // namespace hsga_host
@@ -157,17 +185,20 @@ hipEvent_t take_event(ga_run* r) {
 
 extern "C" {
 
-size_t ga_footprint_bytes(const ga_config* cfg, uint32_t max_gens_per_launch) {
-    if (validate(cfg) != GA_OK) return 0;
+size_t ga_footprint_bytes(const ga_config* in, uint32_t max_gens_per_launch) {
+    ga_config cfg;
+    if (validate(in, &cfg) != GA_OK) return 0;
     const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
-    return carve(cfg->grid_w * cfg->grid_h, cfg->pop_per_island, cfg->surface_sites, gens).total;
+    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, cfg.surface_sites, gens).total;
 }
 
-int ga_create(const ga_config* cfg, void* dev_arena, size_t arena_bytes,
+int ga_create(const ga_config* in, void* dev_arena, size_t arena_bytes,
               uint32_t max_gens_per_launch, void* hip_stream, ga_run** out) {
     if (!out) return fail(GA_EINVAL, "out is NULL");
     *out = nullptr;
-    int rc = validate(cfg);
+    ga_config cfg_copy;
+    int rc = validate(in, &cfg_copy);
+    const ga_config* cfg = &cfg_copy;
     if (rc != GA_OK) return rc;
     if (!dev_arena) return fail(GA_EINVAL, "arena is NULL");
     if ((uintptr_t)dev_arena % kAlign) return fail(GA_EINVAL, "arena not 256-byte aligned");
@@ -196,7 +227,7 @@ int ga_step(ga_run* r, uint32_t n) {
                                      " is past the site rule's horizon " +
                                      std::to_string(r->horizon));
     const ga_config& cfg = r->cfg;
-    const bool sel = cfg.tournament_size == 2;
+    const uint32_t model = birth_model(cfg);
     const bool mig = cfg.migrants_per_island != 0;
     while (n > 0) {
         const uint32_t G = n < r->gens ? n : r->gens;
@@ -213,7 +244,7 @@ int ga_step(ga_run* r, uint32_t n) {
         }
         for (uint32_t k = 0; k < G; ++k) {
             const hsga::StepParams p = step_params(r, r->T + k, k);
-            e = hsga::launch_step(p, r->SW, sel, mig, r->apt, r->block, r->stream);
+            e = hsga::launch_step(p, r->SW, model, mig, r->apt, r->block, r->stream);
             if (e != hipSuccess) return hip_fail(e, "step launch");
         }
         if (r->timing) {

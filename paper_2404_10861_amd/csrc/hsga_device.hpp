@@ -12,6 +12,8 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kSteady = 0, kTilted = 1, kHybrid = 2;
 // Fourth Philox counter word: what the draw is for.
 constexpr uint32_t kBirth = 0, kEmigrate = 1, kImmigrate = 2, kSample = 3;
+// Second block of a float-treatment birth.
+constexpr uint32_t kBirthB = 4;
 // Outbox entry: dir, trait, counter, surface words (up to 2), padding.
 constexpr uint32_t kOutboxWords = 8;
 
@@ -43,6 +45,112 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // A uniform 32-bit word mapped onto [0, n).
 __device__ __forceinline__ uint32_t word_below(uint32_t w, uint32_t n) {
     return __umulhi(w, n);
+}
+
+// ---------------------------------------------------------------------------
+// Half-normal draw of the float treatments (Results, On-hardware Trial:
+// mutations change fitness by normally distributed amounts).  Box and
+// Muller (1958) give |Z| the law of sqrt(-2 ln U1) cos(pi/2 U2) for U1, U2
+// uniform on (0, 1); here U1 = (w_radius + 1/2) 2^-32 and U2 = (w_angle +
+// 1/2) 2^-32.  The draw is defined by one fixed binary64 evaluation made
+// only of correctly rounded +, -, *, fma and exact power-of-two scalings, so
+// every IEEE-754 machine that takes the same steps gets the same bits:
+//   ln U1: U1 = m 2^(e-33) with m in [sqrt(1/2), sqrt(2)]; ln m = 2 atanh s,
+//          s = (m-1)/(m+1), 1/(m+1) by five Newton steps from 1/2, atanh by
+//          its odd series through s^21;
+//   sqrt:  y = q 4^k, q in [1, 4); 1/sqrt q by six Newton steps from
+//          9/8 - 3q/16, sqrt q = q (1/sqrt q) plus one correction;
+//   cos:   cos(pi/2 U2) by its series through x^18 when U2 < 1/2, else
+//          sin(pi/2 (1 - U2)) by its series through x^19.
+// Contraction is off: every fused multiply-add below is written out.
+__device__ __forceinline__ double exact_pow2(int k) {   // 2^k, |k| < 1023
+    return __longlong_as_double((long long)(1023 + k) << 52);
+}
+
+__device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
+#pragma clang fp contract(off)
+    // ln U1
+    const uint64_t v = 2ull * w_radius + 1ull;
+    int e = 63 - __clzll((long long)v);
+    double m = (double)v * exact_pow2(-e);
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    const double d = m + 1.0;
+    double r = 0.5;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+    const double sv = (m - 1.0) * r;
+    const double z = sv * sv;
+    double p = 1.0 / 21.0;
+    p = __builtin_fma(p, z, 1.0 / 19.0);
+    p = __builtin_fma(p, z, 1.0 / 17.0);
+    p = __builtin_fma(p, z, 1.0 / 15.0);
+    p = __builtin_fma(p, z, 1.0 / 13.0);
+    p = __builtin_fma(p, z, 1.0 / 11.0);
+    p = __builtin_fma(p, z, 1.0 / 9.0);
+    p = __builtin_fma(p, z, 1.0 / 7.0);
+    p = __builtin_fma(p, z, 1.0 / 5.0);
+    p = __builtin_fma(p, z, 1.0 / 3.0);
+    p = __builtin_fma(p, z, 1.0);
+    const double ln_u = __builtin_fma((double)e - 33.0, 0.6931471805599453, (sv + sv) * p);
+    // sqrt(-2 ln U1)
+    const double y = -2.0 * ln_u;
+    const int ex = (int)((__double_as_longlong(y) >> 52) & 0x7ff) - 1023;   // floor(log2 y)
+    const int kq = ex >> 1;                                                 // floor(ex / 2)
+    const double q = y * exact_pow2(-2 * kq);
+    const double h = 0.5 * q;
+    double rs = __builtin_fma(-0.1875, q, 1.125);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) rs = __builtin_fma(rs, __builtin_fma(-h, rs * rs, 0.5), rs);
+    double sq = q * rs;
+    sq = __builtin_fma(__builtin_fma(-sq, sq, q), 0.5 * rs, sq);
+    const double radius = sq * exact_pow2(kq);
+    // cos(pi/2 U2)
+    const bool use_sin = w_angle >= 0x80000000u;
+    uint64_t va = 2ull * w_angle + 1ull;
+    if (use_sin) va = (1ull << 33) - va;
+    const double x = ((double)va * exact_pow2(-33)) * 1.5707963267948966;
+    const double x2 = x * x;
+    double c;
+    if (use_sin) {
+        c = -1.0 / 121645100408832000.0;
+        c = __builtin_fma(c, x2, 1.0 / 355687428096000.0);
+        c = __builtin_fma(c, x2, -1.0 / 1307674368000.0);
+        c = __builtin_fma(c, x2, 1.0 / 6227020800.0);
+        c = __builtin_fma(c, x2, -1.0 / 39916800.0);
+        c = __builtin_fma(c, x2, 1.0 / 362880.0);
+        c = __builtin_fma(c, x2, -1.0 / 5040.0);
+        c = __builtin_fma(c, x2, 1.0 / 120.0);
+        c = __builtin_fma(c, x2, -1.0 / 6.0);
+        c = __builtin_fma(c, x2, 1.0);
+        c = x * c;
+    } else {
+        c = -1.0 / 6402373705728000.0;
+        c = __builtin_fma(c, x2, 1.0 / 20922789888000.0);
+        c = __builtin_fma(c, x2, -1.0 / 87178291200.0);
+        c = __builtin_fma(c, x2, 1.0 / 479001600.0);
+        c = __builtin_fma(c, x2, -1.0 / 3628800.0);
+        c = __builtin_fma(c, x2, 1.0 / 40320.0);
+        c = __builtin_fma(c, x2, -1.0 / 720.0);
+        c = __builtin_fma(c, x2, 1.0 / 24.0);
+        c = __builtin_fma(c, x2, -1.0 / 2.0);
+        c = __builtin_fma(c, x2, 1.0);
+    }
+    return radius * c;
+}
+
+// Fitness of a float-treatment child: the parent's, moved down by
+// del_sigma |Z| (deleterious) or up by ben_sigma |Z| (beneficial), in
+// binary64, rounded once to binary32.
+__device__ __forceinline__ float mutate_fitness(float f, bool deleterious, float del_sigma,
+                                                float ben_sigma, uint32_t w_radius,
+                                                uint32_t w_angle) {
+#pragma clang fp contract(off)
+    const double z = half_normal(w_radius, w_angle);
+    const double fd = (double)f;
+    return deleterious ? (float)(fd - (double)del_sigma * z) : (float)(fd + (double)ben_sigma * z);
 }
 
 // Number of significant bits.

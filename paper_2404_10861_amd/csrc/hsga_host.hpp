@@ -52,7 +52,9 @@ struct Carve {
 Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens);
 
 // GA_OK, or GA_EINVAL with the reason in ga_last_error().
-int validate(const ga_config* cfg);
+// Check a caller's config (either accepted struct_size) and, if out is not
+// NULL, store it in the current layout with absent fields zero.
+int validate(const ga_config* in, ga_config* out);
 
 // Fill r for cfg over the arena at base (already checked to hold
 // carve(...).total bytes) and enqueue the founders.
@@ -62,5 +64,8 @@ inline uint32_t tile_islands(uint32_t block, uint32_t apt, uint32_t N) { return 
 
 // Parameters of generation g (schedule slot k) of a run.
 hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k);
+
+// hsga::BirthModel of a configuration.
+uint32_t birth_model(const ga_config& cfg);
 
 }  // namespace hsga_host

@@ -7,6 +7,13 @@
 
 namespace hsga {
 
+// How a birth picks its parent and changes the trait word.
+enum BirthModel : uint32_t {
+    kBirthIntNeutral = 0,      // integer trait, one uniform draw
+    kBirthIntTournament = 1,   // integer trait, tournament of two
+    kBirthFloat = 2,           // binary32 fitness, tournament of `tour`, half-normal mutations
+};
+
 struct StepParams {
     const uint32_t* in_trait;
     const uint32_t* in_counter;
@@ -26,6 +33,9 @@ struct StepParams {
     uint32_t has_inbox;        // outboxes of generation g exist
     uint32_t tile_isl;         // islands per workgroup tile
     uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
+    uint32_t tour;             // float model: tournament draws, 1..5
+    uint32_t del_thr, ben_thr; // float model: mutation class thresholds
+    float del_sigma, ben_sigma;
 };
 
 // One run of a batched launch: a device-resident table entry, written by the
@@ -46,8 +56,10 @@ struct BatchRun {
     int32_t mut_lo;
     uint32_t mut_span;
     uint32_t kind, S;
-    uint32_t variant;          // bit 0: S = 64, bit 1: tournament, bit 2: migration,
-                               // bits 3..4: log2(agents per thread)
+    uint32_t variant;          // bit 0: S = 64, bits 1..2: BirthModel, bit 3: migration,
+                               // bits 4..5: log2(agents per thread)
+    uint32_t tour, del_thr, ben_thr;
+    float del_sigma, ben_sigma;
     uint32_t tile_isl, div_magic;
     uint32_t tile0;            // first tile of the run in the batched grid
 };
@@ -65,14 +77,16 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 
 // agents_per_thread (1, 2 or 4) must divide N; tile_isl * N <= block_threads *
 // agents_per_thread.
-hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
+hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
 
 // Batched forms: tile0 holds nruns + 1 prefix offsets of the runs' tiles.
 hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipStream_t stream);
+// with_float: some run of the batch uses kBirthFloat (a separate kernel, so
+// that integer-only batches keep the integer kernel's register budget).
 hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,
                              uint32_t total_tiles, uint32_t k, uint32_t block_threads,
-                             size_t lds_bytes, hipStream_t stream);
+                             size_t lds_bytes, bool with_float, hipStream_t stream);
 
 hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
                          uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,

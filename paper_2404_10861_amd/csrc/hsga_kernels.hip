@@ -157,7 +157,7 @@ extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
 
 // One tile of one run.  Shared by the plain kernel (one run per launch) and
 // the batched kernel (many runs per launch).
-template <int SW, bool SEL, bool MIGR, int APT>
+template <int SW, uint32_t BM, bool MIGR, int APT>
 __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     uint32_t* lds = g_step_lds;
     const uint32_t N = p.N, W = p.W;
@@ -269,20 +269,47 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
         const uint32_t base = il * N;
         uint32_t par = base + word_below(r.x, N);
-        uint32_t ptrait = l_trait[par];
-        if (SEL) {
-            const uint32_t pb = base + word_below(r.y, N);
-            const uint32_t tb = l_trait[pb];
-            if ((int32_t)tb > (int32_t)ptrait) {
-                par = pb;
-                ptrait = tb;
+        uint32_t bit;
+        if constexpr (BM == kBirthFloat) {
+            // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x), the
+            // first of maximal fitness winning; mutation class from v.y,
+            // |Z| from v.z and v.w, differentia bit 0 of v.w
+            const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
+            float best = __uint_as_float(l_trait[par]);
+            const uint32_t words[4] = {r.y, r.z, r.w, v.x};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if ((uint32_t)c + 1u < p.tour) {
+                    const uint32_t cb = base + word_below(words[c], N);
+                    const float fc = __uint_as_float(l_trait[cb]);
+                    if (fc > best) {
+                        best = fc;
+                        par = cb;
+                    }
+                }
             }
+            const bool del = v.y < p.del_thr;
+            const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
+            ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
+                                                                     p.ben_sigma, v.z, v.w))
+                                    : __float_as_uint(best);
+            bit = v.w & 1u;
+        } else {
+            uint32_t ptrait = l_trait[par];
+            if constexpr (BM == kBirthIntTournament) {
+                const uint32_t pb = base + word_below(r.y, N);
+                const uint32_t tb = l_trait[pb];
+                if ((int32_t)tb > (int32_t)ptrait) {
+                    par = pb;
+                    ptrait = tb;
+                }
+            }
+            const uint32_t delta =
+                r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo) : 0u;
+            ctr.v[q] = ptrait + delta;
+            bit = r.w & 1u;
         }
-        const uint32_t delta =
-            r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo) : 0u;
-        ctr.v[q] = ptrait + delta;
         ccn.v[q] = l_count[par] + 1u;
-        const uint32_t bit = r.w & 1u;
 #pragma unroll
         for (int w = 0; w < SW; ++w) {
             const uint32_t word = l_surf[w * TA + par];
@@ -307,9 +334,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
 }
 
-template <int SW, bool SEL, bool MIGR, int APT>
+template <int SW, uint32_t BM, bool MIGR, int APT>
 __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
-    step_tile<SW, SEL, MIGR, APT>(p, xcd_local_block(blockIdx.x, gridDim.x));
+    step_tile<SW, BM, MIGR, APT>(p, xcd_local_block(blockIdx.x, gridDim.x));
 }
 
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
@@ -317,38 +344,47 @@ size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
     return ((2 + SW) * TA + 2 * (size_t)tile_isl) * 4;
 }
 
-template <int SW, bool SEL, bool MIGR, int APT>
+template <int SW, uint32_t BM, bool MIGR, int APT>
 static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
     const uint32_t tiles = (p.I + p.tile_isl - 1) / p.tile_isl;
     const size_t lds = step_lds_bytes(p.tile_isl, p.N, SW);
-    hipLaunchKernelGGL((step_kernel<SW, SEL, MIGR, APT>), dim3(tiles), dim3(block_threads), lds,
+    hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT>), dim3(tiles), dim3(block_threads), lds,
                        stream, p);
     return hipGetLastError();
 }
 
-template <int SW, bool SEL, bool MIGR>
+template <int SW, uint32_t BM, bool MIGR>
 static hipError_t launch_step_apt(const StepParams& p, uint32_t apt, uint32_t block_threads,
                                   hipStream_t stream) {
-    if (apt == 4) return launch_step_t<SW, SEL, MIGR, 4>(p, block_threads, stream);
-    if (apt == 2) return launch_step_t<SW, SEL, MIGR, 2>(p, block_threads, stream);
-    return launch_step_t<SW, SEL, MIGR, 1>(p, block_threads, stream);
+    if (apt == 4) return launch_step_t<SW, BM, MIGR, 4>(p, block_threads, stream);
+    if (apt == 2) return launch_step_t<SW, BM, MIGR, 2>(p, block_threads, stream);
+    return launch_step_t<SW, BM, MIGR, 1>(p, block_threads, stream);
 }
 
-hipError_t launch_step(const StepParams& p, uint32_t SW, bool selection, bool migration,
+template <int SW, uint32_t BM>
+static hipError_t launch_step_mig(const StepParams& p, bool migration, uint32_t apt,
+                                  uint32_t block_threads, hipStream_t stream) {
+    return migration ? launch_step_apt<SW, BM, true>(p, apt, block_threads, stream)
+                     : launch_step_apt<SW, BM, false>(p, apt, block_threads, stream);
+}
+
+template <int SW>
+static hipError_t launch_step_model(const StepParams& p, uint32_t birth_model, bool migration,
+                                    uint32_t apt, uint32_t block_threads, hipStream_t stream) {
+    if (birth_model == kBirthFloat)
+        return launch_step_mig<SW, kBirthFloat>(p, migration, apt, block_threads, stream);
+    if (birth_model == kBirthIntTournament)
+        return launch_step_mig<SW, kBirthIntTournament>(p, migration, apt, block_threads, stream);
+    return launch_step_mig<SW, kBirthIntNeutral>(p, migration, apt, block_threads, stream);
+}
+
+hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream) {
-    const uint32_t apt = agents_per_thread;
-    if (SW == 1) {
-        if (selection)
-            return migration ? launch_step_apt<1, true, true>(p, apt, block_threads, stream)
-                             : launch_step_apt<1, true, false>(p, apt, block_threads, stream);
-        return migration ? launch_step_apt<1, false, true>(p, apt, block_threads, stream)
-                         : launch_step_apt<1, false, false>(p, apt, block_threads, stream);
-    }
-    if (selection)
-        return migration ? launch_step_apt<2, true, true>(p, apt, block_threads, stream)
-                         : launch_step_apt<2, true, false>(p, apt, block_threads, stream);
-    return migration ? launch_step_apt<2, false, true>(p, apt, block_threads, stream)
-                     : launch_step_apt<2, false, false>(p, apt, block_threads, stream);
+    if (SW == 1)
+        return launch_step_model<1>(p, birth_model, migration, agents_per_thread, block_threads,
+                                    stream);
+    return launch_step_model<2>(p, birth_model, migration, agents_per_thread, block_threads,
+                                stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,13 +403,30 @@ hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipS
     return hipGetLastError();
 }
 
-template <int SW, bool SEL, bool MIGR>
+template <int SW, uint32_t BM, bool MIGR>
 __device__ __forceinline__ void step_tile_apt(const StepParams& p, uint32_t tile, uint32_t apt_log2) {
-    if (apt_log2 == 2) step_tile<SW, SEL, MIGR, 4>(p, tile);
-    else if (apt_log2 == 1) step_tile<SW, SEL, MIGR, 2>(p, tile);
-    else step_tile<SW, SEL, MIGR, 1>(p, tile);
+    if (apt_log2 == 2) step_tile<SW, BM, MIGR, 4>(p, tile);
+    else if (apt_log2 == 1) step_tile<SW, BM, MIGR, 2>(p, tile);
+    else step_tile<SW, BM, MIGR, 1>(p, tile);
 }
 
+template <uint32_t BM>
+__device__ __forceinline__ void step_tile_variant(const StepParams& p, uint32_t tile,
+                                                  uint32_t variant) {
+    const uint32_t apt_log2 = (variant >> 4) & 3u;
+    const bool mig = (variant >> 3) & 1u;
+    if (variant & 1u) {
+        if (mig) step_tile_apt<2, BM, true>(p, tile, apt_log2);
+        else step_tile_apt<2, BM, false>(p, tile, apt_log2);
+    } else {
+        if (mig) step_tile_apt<1, BM, true>(p, tile, apt_log2);
+        else step_tile_apt<1, BM, false>(p, tile, apt_log2);
+    }
+}
+
+// WITH_FLOAT: the batch may hold float-treatment runs.  Integer-only
+// batches use the instantiation without them, which needs fewer registers.
+template <bool WITH_FLOAT>
 __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __restrict__ runs,
                                                          const uint32_t* __restrict__ tile0,
                                                          uint32_t nruns, uint32_t k) {
@@ -406,30 +459,30 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.g = g;
     p.k0 = R.k0; p.k1 = R.k1;
     p.mut_thr = R.mut_thr; p.mut_lo = R.mut_lo; p.mut_span = R.mut_span;
-    const bool mig = (R.variant >> 2) & 1u;
+    const bool mig = (R.variant >> 3) & 1u;
     p.has_inbox = (mig && g > 0) ? 1u : 0u;
     p.tile_isl = R.tile_isl;
     p.div_magic = R.div_magic;
+    p.tour = R.tour;
+    p.del_thr = R.del_thr; p.ben_thr = R.ben_thr;
+    p.del_sigma = R.del_sigma; p.ben_sigma = R.ben_sigma;
     const uint32_t t = tile - s_tile0[lo];
-    const uint32_t apt_log2 = (R.variant >> 3) & 3u;
-    switch (R.variant & 7u) {
-    case 0: step_tile_apt<1, false, false>(p, t, apt_log2); break;
-    case 1: step_tile_apt<2, false, false>(p, t, apt_log2); break;
-    case 2: step_tile_apt<1, true, false>(p, t, apt_log2); break;
-    case 3: step_tile_apt<2, true, false>(p, t, apt_log2); break;
-    case 4: step_tile_apt<1, false, true>(p, t, apt_log2); break;
-    case 5: step_tile_apt<2, false, true>(p, t, apt_log2); break;
-    case 6: step_tile_apt<1, true, true>(p, t, apt_log2); break;
-    default: step_tile_apt<2, true, true>(p, t, apt_log2); break;
-    }
+    const uint32_t model = (R.variant >> 1) & 3u;
+    if (model == kBirthIntTournament) step_tile_variant<kBirthIntTournament>(p, t, R.variant);
+    else if (WITH_FLOAT && model == kBirthFloat) step_tile_variant<kBirthFloat>(p, t, R.variant);
+    else step_tile_variant<kBirthIntNeutral>(p, t, R.variant);
 }
 
 hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,
                              uint32_t total_tiles, uint32_t k, uint32_t block_threads,
-                             size_t lds_bytes, hipStream_t stream) {
+                             size_t lds_bytes, bool with_float, hipStream_t stream) {
     if (nruns == 0 || total_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_step_kernel, dim3(total_tiles), dim3(block_threads), lds_bytes,
-                       stream, runs, tile0, nruns, k);
+    if (with_float)
+        hipLaunchKernelGGL(batch_step_kernel<true>, dim3(total_tiles), dim3(block_threads),
+                           lds_bytes, stream, runs, tile0, nruns, k);
+    else
+        hipLaunchKernelGGL(batch_step_kernel<false>, dim3(total_tiles), dim3(block_threads),
+                           lds_bytes, stream, runs, tile0, nruns, k);
     return hipGetLastError();
 }
 

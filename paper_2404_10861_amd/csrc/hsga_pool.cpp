@@ -28,9 +28,10 @@ struct Slot {
 struct GraphKey {
     uint32_t nruns = 0, tiles = 0, gens = 0, block = 0;
     size_t lds = 0;
+    bool with_float = false;
     bool operator==(const GraphKey& o) const {
         return nruns == o.nruns && tiles == o.tiles && gens == o.gens && block == o.block &&
-               lds == o.lds;
+               lds == o.lds && with_float == o.with_float;
     }
 };
 
@@ -101,18 +102,19 @@ void drop_graph(ga_pool* p) {
 uint32_t variant_of(const ga_run& r) {
     uint32_t v = 0;
     if (r.SW == 2) v |= 1u;
-    if (r.cfg.tournament_size == 2) v |= 2u;
-    if (r.cfg.migrants_per_island) v |= 4u;
+    v |= birth_model(r.cfg) << 1;
+    if (r.cfg.migrants_per_island) v |= 8u;
     const uint32_t apt_log2 = r.apt == 4 ? 2u : (r.apt == 2 ? 1u : 0u);
-    return v | (apt_log2 << 3);
+    return v | (apt_log2 << 4);
 }
 
-int enqueue_launches(ga_pool* p, uint32_t nruns, uint32_t tiles, uint32_t gens, size_t lds) {
+int enqueue_launches(ga_pool* p, uint32_t nruns, uint32_t tiles, uint32_t gens, size_t lds,
+                     bool with_float) {
     hipError_t e = hsga::launch_batch_site_schedule(p->d_table, nruns, p->stream);
     if (e != hipSuccess) return hip_fail(e, "batched site schedule launch");
     for (uint32_t k = 0; k < gens; ++k) {
         e = hsga::launch_batch_step(p->d_table, p->d_tile0, nruns, tiles, k, p->block, lds,
-                                    p->stream);
+                                    with_float, p->stream);
         if (e != hipSuccess) return hip_fail(e, "batched step launch");
     }
     return GA_OK;
@@ -175,15 +177,17 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
     return GA_OK;
 }
 
-size_t ga_pool_footprint(const ga_pool* p, const ga_config* cfg) {
-    if (!p || validate(cfg) != GA_OK) return 0;
-    return carve(cfg->grid_w * cfg->grid_h, cfg->pop_per_island, cfg->surface_sites, p->gens)
-        .total;
+size_t ga_pool_footprint(const ga_pool* p, const ga_config* in) {
+    ga_config cfg;
+    if (!p || validate(in, &cfg) != GA_OK) return 0;
+    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, cfg.surface_sites, p->gens).total;
 }
 
-int ga_pool_admit(ga_pool* p, const ga_config* cfg, uint32_t n_generations, uint32_t* id) {
+int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint32_t* id) {
     if (!p || !id) return fail(GA_EINVAL, "NULL argument");
-    int rc = validate(cfg);
+    ga_config cfg_copy;
+    int rc = validate(in, &cfg_copy);
+    const ga_config* cfg = &cfg_copy;
     if (rc != GA_OK) return rc;
     if (n_generations == 0) return fail(GA_EINVAL, "a run needs at least one generation");
     if ((uint64_t)n_generations - 1 > hsga::horizon_of(cfg->surface_kind, cfg->surface_sites))
@@ -231,6 +235,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     }
     uint32_t tiles = 0, gens = 0;
     size_t lds = 0;
+    bool with_float = false;
     const uint32_t nruns = (uint32_t)active.size();
     for (uint32_t i = 0; i < nruns; ++i) {
         Slot& s = p->slots[active[i]];
@@ -255,6 +260,10 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         b.kind = r.cfg.surface_kind;
         b.S = r.S;
         b.variant = variant_of(r);
+        with_float = with_float || birth_model(r.cfg) == hsga::kBirthFloat;
+        b.tour = sp.tour;
+        b.del_thr = sp.del_thr; b.ben_thr = sp.ben_thr;
+        b.del_sigma = sp.del_sigma; b.ben_sigma = sp.ben_sigma;
         b.tile_isl = sp.tile_isl;
         b.div_magic = sp.div_magic;
         b.tile0 = tiles;
@@ -275,14 +284,14 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->staged_pending = true;
 
-    const GraphKey key{nruns, tiles, gens, p->block, lds};
+    const GraphKey key{nruns, tiles, gens, p->block, lds, with_float};
     int rc = GA_OK;
     if (p->use_graph && p->stream) {
         if (!(p->exec && p->key == key)) {
             drop_graph(p);
             e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            rc = enqueue_launches(p, nruns, tiles, gens, lds);
+            rc = enqueue_launches(p, nruns, tiles, gens, lds, with_float);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(p->stream, &graph);
             if (rc != GA_OK) {
@@ -301,7 +310,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         e = hipGraphLaunch(p->exec, p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        rc = enqueue_launches(p, nruns, tiles, gens, lds);
+        rc = enqueue_launches(p, nruns, tiles, gens, lds, with_float);
         if (rc != GA_OK) return rc;
     }
     for (uint32_t i = 0; i < nruns; ++i) {

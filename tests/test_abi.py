@@ -41,9 +41,12 @@ def test_binding_names_match_header():
 
 def test_config_struct_layout():
     import paper_2404_10861_amd.binding as b
-    # 12 uint32/int32 fields then a uint64 seed: 56 bytes, seed at offset 48
-    assert ctypes.sizeof(b.ga_config) == 56
+    # 12 uint32/int32 fields, a uint64 seed, then the six float-treatment
+    # words: 80 bytes, seed at offset 48, fitness_model at 56
+    assert ctypes.sizeof(b.ga_config) == 80
     assert b.ga_config.seed.offset == 48
+    assert b.ga_config.fitness_model.offset == 56
+    assert b.ga_config.del_sigma.offset == 68 and b.ga_config.reserved2.offset == 76
 
 
 def test_footprint_without_gpu():
@@ -57,3 +60,33 @@ def test_footprint_without_gpu():
     assert n < 2 * cfg.agents * 16 + 2 * cfg.islands * 32 + (1 << 20)
     with pytest.raises(hs.HsgaError):
         hs.footprint_bytes(hs.Config(0, 4))
+
+
+def test_config_versions_and_float_validation_without_gpu():
+    """Host-side validation: a 56-byte config (no float fields) is read as
+    the integer model; float-treatment fields are range-checked."""
+    if not os.path.exists(LIB):
+        pytest.skip("libhsga.so not built")
+    import paper_2404_10861_amd as hs
+    import paper_2404_10861_amd.binding as b
+    lib = b.load_library()
+    base = hs.Config(8, 8, 32, 32, "tilted")
+    c = base.to_c()
+    full = lib.ga_footprint_bytes(ctypes.byref(c), 0)
+    assert full > 0
+    c.struct_size = 56
+    c.fitness_model = 7            # beyond a 56-byte config: never read
+    assert lib.ga_footprint_bytes(ctypes.byref(c), 0) == full
+    c.struct_size = 60
+    assert lib.ga_footprint_bytes(ctypes.byref(c), 0) == 0
+    good = dict(fitness_model="float", tournament_size=5, del_threshold=1417339207,
+                ben_threshold=12884901, del_sigma=1.0, ben_sigma=1.0)
+    assert hs.footprint_bytes(hs.Config(8, 8, 32, 32, "tilted", **good)) == full
+    for bad in (dict(tournament_size=6), dict(del_threshold=2**31, ben_threshold=2**31 + 1),
+                dict(del_sigma=float("nan")), dict(ben_sigma=-0.5), dict(del_sigma=2.0**21)):
+        kw = dict(good)
+        kw.update(bad)
+        with pytest.raises(hs.HsgaError):
+            hs.footprint_bytes(hs.Config(8, 8, 32, 32, "tilted", **kw))
+    with pytest.raises(hs.HsgaError):
+        hs.footprint_bytes(hs.Config(8, 8, 32, 32, "tilted", tournament_size=5))

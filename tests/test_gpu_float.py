@@ -1,0 +1,158 @@
+"""GPU parity of the float treatments (binary32 fitness, tournament of up to
+five, deleterious and beneficial half-normal mutations) against the oracle,
+bit for bit: every generation of a small run, all surface kinds and sizes,
+tournament sizes, migration on and off, extreme thresholds and scales,
+every launch shape, batched pools mixing float and integer runs, and the
+paper's treatment pair (purifying-only vs adaptation-enabled) compared by
+the reconstructed trees."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+KIND = {"steady": 0, "tilted": 1, "hybrid": 2}
+P_DEL = 1417339207      # floor(0.33 * 2^32)
+P_BEN = 12884901        # floor(0.003 * 2^32)
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_10861_amd as hs
+    hs.load_library()
+    return hs
+
+
+def fcfg(hs, W, H, N, S, kind, tour=5, del_thr=P_DEL, ben_thr=P_BEN, sd=1.0, sb=1.0,
+         migrants=1, seed=3):
+    return hs.Config(W, H, N, S, kind, tournament_size=tour, migrants_per_island=migrants,
+                     seed=seed, fitness_model="float", del_threshold=del_thr,
+                     ben_threshold=ben_thr, del_sigma=sd, ben_sigma=sb)
+
+
+def oracle_for(orc, c):
+    return orc.Run(c.grid_w, c.grid_h, c.pop_per_island, c.surface_sites, KIND[c.surface_kind],
+                   tournament=c.tournament_size, migrants=c.migrants_per_island, seed=c.seed,
+                   fitness_model=1, del_thr=c.del_threshold, ben_thr=c.ben_threshold,
+                   del_sigma=c.del_sigma, ben_sigma=c.ben_sigma)
+
+
+def same_state(run, o):
+    for x, y in zip(run.agents(), o.agents()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(run.layout(), o.layout())
+
+
+def test_every_generation(hs, orc):
+    c = fcfg(hs, 8, 8, 32, 32, "hybrid", ben_thr=P_BEN * 30)
+    run = hs.Run(c)
+    o = oracle_for(orc, c)
+    for g in range(1, 161):
+        run.step(1)
+        o.step(1)
+        t_gpu = run.agents()[0]
+        t_orc = o.agents()[0]
+        assert np.array_equal(t_gpu, t_orc), f"generation {g}"
+    same_state(run, o)
+    ob, oo = run.outbox(), o.outbox()
+    for x, y in zip(ob, oo):
+        assert np.array_equal(x, y)
+    f = orc.as_f32(run.agents()[0])
+    assert np.all(np.isfinite(f)) and f.max() > 0   # selection keeps the gains
+
+
+@pytest.mark.parametrize("kind", ["steady", "tilted", "hybrid"])
+@pytest.mark.parametrize("S", [32, 64])
+@pytest.mark.parametrize("tour", [0, 1, 2, 3, 4, 5])
+def test_kinds_sizes_tournaments(hs, orc, kind, S, tour):
+    c = fcfg(hs, 6, 5, 16, S, kind, tour=tour, ben_thr=P_BEN * 10, seed=tour + 7)
+    run = hs.Run(c)
+    run.step(400)
+    o = oracle_for(orc, c)
+    o.step(400)
+    same_state(run, o)
+
+
+@pytest.mark.parametrize("params", [
+    dict(del_thr=0, ben_thr=0),                       # no mutation: fitness stays 0
+    dict(del_thr=2**32 - 1, ben_thr=0),               # almost every birth deleterious
+    dict(del_thr=0, ben_thr=2**32 - 1),               # almost every birth beneficial
+    dict(del_thr=2**31, ben_thr=2**31),               # the two classes cover every draw
+    dict(sd=0.0, sb=0.0),                             # zero scales
+    dict(sd=1048576.0, sb=3.0e-5),                    # extreme scales
+    dict(migrants=0),
+])
+def test_extreme_parameters(hs, orc, params):
+    kw = dict(tour=5)
+    kw.update(params)
+    c = fcfg(hs, 5, 7, 17, 64, "tilted", **kw)
+    run = hs.Run(c)
+    run.step(250)
+    o = oracle_for(orc, c)
+    o.step(250)
+    same_state(run, o)
+
+
+@pytest.mark.parametrize("block,apt", [(64, 1), (128, 2), (256, 4), (1024, 2), (64, 4)])
+def test_launch_shapes(hs, orc, block, apt):
+    c = fcfg(hs, 9, 7, 32, 64, "hybrid", ben_thr=P_BEN * 10)
+    run = hs.Run(c)
+    run.set_launch_shape(block, apt)
+    run.step(300)
+    o = oracle_for(orc, c)
+    o.step(300)
+    same_state(run, o)
+
+
+def test_long_run_scaled(hs, orc):
+    """The paper's trial shape scaled down: a 12x12 torus, 5,000
+    generations, both treatments."""
+    for ben in (0, P_BEN):
+        c = fcfg(hs, 12, 12, 32, 64, "hybrid", ben_thr=ben, seed=21)
+        run = hs.Run(c)
+        run.step(5000)
+        o = oracle_for(orc, c)
+        o.step(5000)
+        same_state(run, o)
+
+
+def test_batched_mix_equals_alone(hs):
+    specs = [
+        (fcfg(hs, 16, 8, 32, 64, "hybrid", seed=1), 300),
+        (hs.Config(8, 8, 32, 32, "steady", seed=2), 250),
+        (fcfg(hs, 5, 3, 17, 32, "tilted", tour=2, ben_thr=P_BEN * 50, seed=3), 410),
+        (fcfg(hs, 7, 9, 48, 64, "steady", tour=0, seed=4), 120),
+        (hs.Config(10, 10, 16, 64, "tilted", tournament_size=0, seed=5), 333),
+        (fcfg(hs, 1, 1, 8, 32, "hybrid", migrants=0, seed=6), 77),
+    ]
+    for use_graph in (False, True):
+        pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=64, use_graph=use_graph)
+        ids = {pool.admit(c, g): (c, g) for c, g in specs}
+        assert None not in ids
+        while pool.advance(64):
+            pass
+        for rid, (c, g) in ids.items():
+            alone = hs.Run(c)
+            alone.step(g)
+            for x, y in zip(pool.run(rid).agents(), alone.agents()):
+                assert np.array_equal(x, y)
+            alone.close()
+        pool.close()
+
+
+def test_treatment_pair_phylometrics(hs):
+    """Purifying-only vs adaptation-enabled (Results, On-hardware Trial):
+    the purifying-only tree has the larger sum of branch lengths and mean
+    evolutionary distinctiveness."""
+    res = {}
+    for name, ben in (("purifying", 0), ("adaptive", P_BEN)):
+        c = fcfg(hs, 64, 64, 32, 64, "hybrid", ben_thr=ben, seed=2024)
+        run = hs.Run(c)
+        run.step(20000)
+        _, cnt, srf = run.sample(4096)
+        res[name] = hs.phylo_metrics("hybrid", 64, cnt, srf)
+        assert res[name]["status"] == 0
+    assert res["purifying"]["sum_branch_length"] > res["adaptive"]["sum_branch_length"]
+    assert res["purifying"]["mean_ed"] > res["adaptive"]["mean_ed"]
