@@ -110,7 +110,8 @@ def main(argv=None) -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the run length (profiling only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair"), default="plain",
+    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair", "trial"),
+                    default="plain",
                     help="plain: the paper-scale run (default); batched / served: the run "
                          "sets of the batched and served workloads against sequential plain runs")
     ap.add_argument("--time-scale", type=float, default=1.0,
@@ -135,7 +136,16 @@ def main(argv=None) -> int:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         from paper_2404_10861_amd import benchmarks
-        if args.mode == "pair":
+        if args.mode == "trial":
+            gens = args.generations or 20000
+            res = benchmarks.treatment_pair(
+                [wl.trial(False, generations=gens), wl.trial(True, generations=gens)], dev,
+                torch.cuda.current_stream(dev), n_sample=10000,
+                labels=["purifying", "adaptive"], allpairs=False,
+                progress=lambda text: print(text, file=sys.stderr, flush=True))
+            metric = "agent-replications/sec (float trial) and phylometrics"
+            value = res["purifying"]["replications_per_s"]
+        elif args.mode == "pair":
             res = benchmarks.treatment_pair([wl.c3(True), wl.c3(False)], dev,
                                             torch.cuda.current_stream(dev))
             metric = "agent-replications/sec (treatment pair) and MRCA query time"
@@ -152,7 +162,9 @@ def main(argv=None) -> int:
             metric = "agent-replications/sec and p50/p99 run latency (served)"
             value = res["served"]["replications_per_s"]
         print(json.dumps({"metric": metric, "value": value, "unit": "agent-replications/s",
-                          "n_gpus": 1, "mode": args.mode, "dtype": "u32", "data": "synthetic",
+                          "n_gpus": 1, "mode": args.mode,
+                          "dtype": "u32,f32,f64" if args.mode == "trial" else "u32",
+                          "data": "synthetic",
                           "result": res}), flush=True)
         return 0
 

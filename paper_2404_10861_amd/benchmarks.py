@@ -153,18 +153,26 @@ def served_vs_plain(reqs, dev, chunk_gens: int = 256, time_scale: float = 1.0,
     return out
 
 
-def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
-    """The treatment pair (selection, neutral): each run, its stratified
-    sample, all-pairs MRCA bounds and the reconstructed tree's phylometrics
-    (sum branch length, mean evolutionary distinctiveness, mean pairwise
-    distance); selection sweeps make common ancestry more recent."""
+def treatment_pair(specs, dev, stream, n_sample: int = 4096, labels=None,
+                   allpairs: bool = True, progress=None) -> dict:
+    """A treatment pair: each run, its stratified sample, all-pairs MRCA
+    bounds (if allpairs) and the reconstructed tree's phylometrics (sum
+    branch length, mean evolutionary distinctiveness, mean pairwise
+    distance).  Integer pair (selection, neutral): selection sweeps make
+    common ancestry more recent.  Float trial (purifying-only,
+    adaptation-enabled): the purifying-only tree is the longer one."""
+    if labels is None:
+        labels = ["selection" if s.tournament_size == 2 else "neutral" for s in specs]
     out = {}
-    ws = hs.MrcaWorkspace(max(s.surface_sites for s in specs), n_sample, dev)
-    lb = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
-    ub = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev)
-    for s in specs:
+    ws = hs.MrcaWorkspace(max(s.surface_sites for s in specs), n_sample, dev) if allpairs else None
+    lb = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev) if allpairs else None
+    ub = torch.empty((n_sample, n_sample), dtype=torch.int32, device=dev) if allpairs else None
+    for s, label in zip(specs, labels):
+        if progress is not None:
+            progress(f"{label}: {s.name}, {s.generations} generations")
         cfg = hs.Config(**s.config_kwargs())
-        run = hs.Run(cfg, max_gens_per_launch=s.generations, device=dev, stream=stream)
+        run = hs.Run(cfg, max_gens_per_launch=min(s.generations, 4096), device=dev,
+                     stream=stream)
         run.set_kernel_timing(True)
         torch.cuda.synchronize(dev)
         t0 = time.perf_counter()
@@ -172,28 +180,24 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
         _, cnt, srf = run.sample(n_sample)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        hs.mrca_bounds(s.surface_kind, s.surface_sites, cnt, srf, workspace=ws, stream=stream,
-                       lb=lb, ub=ub)
-        e1.record(stream)
         e2 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if allpairs:
+            hs.mrca_bounds(s.surface_kind, s.surface_sites, cnt, srf, workspace=ws,
+                           stream=stream, lb=lb, ub=ub)
+        e1.record(stream)
         phylo = hs.phylo_metrics(s.surface_kind, s.surface_sites, cnt, srf, stream=stream)
         e2.record(stream)
         torch.cuda.synchronize(dev)
         wall = time.perf_counter() - t0
         ms, launches = run.kernel_time()
-        l_h = hs.as_u32(lb).astype(np.float64)
-        u_h = hs.as_u32(ub).astype(np.float64)
-        off = ~np.eye(n_sample, dtype=bool)
-        out["selection" if s.tournament_size == 2 else "neutral"] = {
+        trait = run.agents(0, 65536)[0]
+        rec = {
+            "workload": s.name,
             "replications_per_s": s.replications / wall,
             "wall_s": wall,
             "step_kernel_avg_us": ms * 1000.0 / max(launches, 1),
-            "mrca_query_ms": e0.elapsed_time(e1),
-            "mrca_pairs": n_sample * n_sample,
-            "mean_lb": float(l_h[off].mean()),
-            "mean_ub": float(u_h[off].mean()),
-            "mean_trait": float(run.agents(0, 65536)[0].view(np.int32).mean()),
+            "sample": int(cnt.shape[0]),
             "phylo_ms": e1.elapsed_time(e2),
             "sum_branch_length": phylo["sum_branch_length"],
             "mean_evolutionary_distinctiveness": phylo["mean_ed"],
@@ -201,5 +205,16 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096) -> dict:
             "root_time": phylo["root_time"],
             "internal_nodes": phylo["internal_nodes"],
         }
+        if s.fitness_model == "float":
+            rec["mean_fitness_first_65536"] = float(trait.view(np.float32).mean())
+        else:
+            rec["mean_trait_first_65536"] = float(trait.view(np.int32).mean())
+        if allpairs:
+            l_h = hs.as_u32(lb).astype(np.float64)
+            u_h = hs.as_u32(ub).astype(np.float64)
+            off = ~np.eye(n_sample, dtype=bool)
+            rec.update({"mrca_query_ms": e0.elapsed_time(e1), "mrca_pairs": n_sample * n_sample,
+                        "mean_lb": float(l_h[off].mean()), "mean_ub": float(u_h[off].mean())})
+        out[label] = rec
         run.close()
     return out

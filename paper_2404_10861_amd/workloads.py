@@ -20,6 +20,14 @@ synthetic simulations; there is no dataset to stand in for.
   log-uniform, random kind and 32/64 sites; 1,024-agent MRCA at completion.
 All runs: trait starts at 0, mutation p = 0.01 (threshold floor(0.01 * 2^32))
 adding a uniform integer in [-8, 8], one migrant per island per generation.
+
+* Float trial (after the paper's On-hardware Trial): 750x750 islands x 32
+  agents (18 M), 64-site tilted surface (the four-word genome: binary32
+  fitness, 32-bit counter, 64-bit surface), tournament of five, binary32
+  fitness from 0; purifying-only (33 % of births lose del_sigma |Z|) vs
+  adaptation-enabled (additionally 0.3 % gain ben_sigma |Z|), scales 1.0;
+  a 10,000-agent stratified sample is reconstructed into a tree.  The
+  paper ran 1,000,000 generations; the default here is 20,000.
 """
 from __future__ import annotations
 
@@ -29,6 +37,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 MUT_THRESHOLD = 42949672   # floor(0.01 * 2^32)
+P_DELETERIOUS = 1417339207  # floor(0.33 * 2^32)
+P_BENEFICIAL = 12884901     # floor(0.003 * 2^32)
 
 
 @dataclass
@@ -48,6 +58,11 @@ class RunSpec:
     sample: int = 0            # agents sampled for the end-of-run MRCA query
     arrival: float = 0.0       # seconds after the start (served workload)
     name: str = ""
+    fitness_model: str = "int"
+    del_threshold: int = 0
+    ben_threshold: int = 0
+    del_sigma: float = 1.0
+    ben_sigma: float = 1.0
 
     @property
     def agents(self) -> int:
@@ -62,7 +77,10 @@ class RunSpec:
                     surface_sites=self.surface_sites, surface_kind=self.surface_kind,
                     tournament_size=self.tournament_size, mut_threshold=self.mut_threshold,
                     mut_lo=self.mut_lo, mut_hi=self.mut_hi,
-                    migrants_per_island=self.migrants_per_island, seed=self.seed)
+                    migrants_per_island=self.migrants_per_island, seed=self.seed,
+                    fitness_model=self.fitness_model, del_threshold=self.del_threshold,
+                    ben_threshold=self.ben_threshold, del_sigma=self.del_sigma,
+                    ben_sigma=self.ben_sigma)
 
 
 def c1() -> RunSpec:
@@ -77,6 +95,15 @@ def c2() -> RunSpec:
 def c3(selection: bool) -> RunSpec:
     return RunSpec(256, 256, 64, 32, "tilted", 2 if selection else 0, 20000, seed=1, sample=4096,
                    name=f"C3 {'selection' if selection else 'neutral'} 256x256x64 tilted-32")
+
+
+def trial(adaptive: bool, side: int = 750, generations: int = 20000) -> RunSpec:
+    """One treatment of the float trial (purifying-only or adaptation-enabled)."""
+    name = "adaptation-enabled" if adaptive else "purifying-only"
+    return RunSpec(side, side, 32, 64, "tilted", 5, generations, seed=1, sample=10000,
+                   fitness_model="float", del_threshold=P_DELETERIOUS,
+                   ben_threshold=P_BENEFICIAL if adaptive else 0,
+                   name=f"float trial {name} {side}x{side}x32 tilted-64")
 
 
 C4_GRIDS = ((16, 16), (32, 64), (64, 64), (128, 256))
