@@ -43,9 +43,10 @@
 enum { ORC_STEADY = 0, ORC_TILTED = 1, ORC_HYBRID = 2 };
 /* purpose tags carried in the fourth Philox counter word */
 enum { ORC_BIRTH = 0, ORC_EMIGRATE = 1, ORC_IMMIGRATE = 2, ORC_SAMPLE = 3,
-       ORC_BIRTH_B = 4 /* second block of a float-treatment birth */ };
+       ORC_BIRTH_B = 4 /* second block of a float-treatment birth */,
+       ORC_FOUNDER = 5 /* founder tags */ };
 /* fitness models */
-enum { ORC_INT_TRAIT = 0, ORC_FLOAT_FITNESS = 1 };
+enum { ORC_INT_TRAIT = 0, ORC_FLOAT_FITNESS = 1, ORC_FOUNDER_TAG = 2 };
 /* torus directions */
 enum { ORC_NORTH = 0, ORC_SOUTH = 1, ORC_WEST = 2, ORC_EAST = 3 };
 
@@ -350,9 +351,12 @@ typedef struct {
     uint32_t W, H, N, S, kind, tournament, mut_thr, mut_span, migrants;
     int32_t mut_lo;
     uint64_t seed;
-    /* float treatments (orc_set_fitness) */
+    /* float treatments and founder tags (orc_set_fitness) */
     uint32_t model, del_thr, ben_thr;
     float del_sigma, ben_sigma;
+    /* annotation scheme: differentia width (1 or 8 bits per site) and the
+     * ingest interval (one deposit every `interval` generations)          */
+    uint32_t bits, interval;
     uint32_t I, A, SW;
     uint32_t g;                       /* generations elapsed                  */
     uint32_t *trait, *counter, *surf; /* A, A, A*SW (agent-major)             */
@@ -405,22 +409,51 @@ void orc_destroy(void *handle)
  * Founders carry no differentia: item t is deposited at the birth of the
  * generation-(t+1) individual (Distributed Phylogenetic Tracking: offspring
  * receive a new differentia on birth).  Returns NULL on an invalid config.  */
-void *orc_create(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kind,
-                 uint32_t tournament, uint32_t mut_thr, int32_t mut_lo,
-                 int32_t mut_hi, uint32_t migrants, uint64_t seed,
-                 uint32_t ped_gens)
+/* Annotation schemes: S sites of `bits` bits each (one-bit or byte
+ * differentiae, Distributed Phylogenetic Tracking: differentia width trades
+ * collisions for coverage), filling one or two 32-bit words, deposited
+ * every `interval` generations (Results, Surface Algorithm Benchmark:
+ * annotations may be updated only every n-th generation).                  */
+static int scheme_ok(uint32_t S, uint32_t bits, uint32_t interval)
 {
-    if (W == 0 || H == 0 || N == 0 || N > 64 || (S != 32 && S != 64) ||
+    if (interval == 0 || (bits != 1 && bits != 8))
+        return 0;
+    return S * bits == 32 || S * bits == 64;
+}
+
+/* Ingests made by an annotation with counter T: items at generations
+ * 0, interval, 2 interval, ... below T.                                    */
+static uint32_t ingests_of(uint32_t T, uint32_t interval)
+{
+    return (uint32_t)(((uint64_t)T + interval - 1) / interval);
+}
+
+/* Last generation that a run can step (inclusive): the next ingest after it
+ * would be past the site rule's horizon, or the counter would overflow.   */
+uint64_t orc_horizon_gen(uint32_t kind, uint32_t S, uint32_t interval)
+{
+    uint64_t h = orc_horizon(kind, S);
+    uint64_t g = (h + 1) * (uint64_t)interval - 1;
+    return g < 0xfffffffeull ? g : 0xfffffffeull;
+}
+
+void *orc_create_ex(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kind,
+                    uint32_t tournament, uint32_t mut_thr, int32_t mut_lo,
+                    int32_t mut_hi, uint32_t migrants, uint64_t seed,
+                    uint32_t ped_gens, uint32_t bits, uint32_t interval)
+{
+    if (W == 0 || H == 0 || N == 0 || N > 64 || !scheme_ok(S, bits, interval) ||
         kind > ORC_HYBRID || (tournament != 0 && tournament != 2) ||
         mut_lo > mut_hi || (int64_t)mut_hi - mut_lo + 1 > 0xffffffffll ||
         migrants > 1)
         return NULL;
     orc_run *r = (orc_run *)calloc(1, sizeof(orc_run));
     r->W = W; r->H = H; r->N = N; r->S = S; r->kind = kind;
+    r->bits = bits; r->interval = interval;
     r->tournament = tournament; r->mut_thr = mut_thr; r->mut_lo = mut_lo;
     r->mut_span = (uint32_t)((int64_t)mut_hi - mut_lo + 1);
     r->migrants = migrants; r->seed = seed;
-    r->I = W * H; r->A = r->I * N; r->SW = S / 32;
+    r->I = W * H; r->A = r->I * N; r->SW = S * bits / 32;
     size_t A = r->A, I = r->I, SW = r->SW;
     r->trait = calloc(A, 4); r->counter = calloc(A, 4);
     r->surf = calloc(A * SW, 4); r->src = calloc(A, 4);
@@ -456,6 +489,17 @@ void *orc_create(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kind,
     return r;
 }
 
+void *orc_create(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kind,
+                 uint32_t tournament, uint32_t mut_thr, int32_t mut_lo,
+                 int32_t mut_hi, uint32_t migrants, uint64_t seed,
+                 uint32_t ped_gens)
+{
+    if (S != 32 && S != 64)
+        return NULL;
+    return orc_create_ex(W, H, N, S, kind, tournament, mut_thr, mut_lo, mut_hi,
+                         migrants, seed, ped_gens, 1, 1);
+}
+
 /* Float treatments (Results, On-hardware Trial; Asynchronous Island-model
  * Genetic Algorithm).  model 1: the trait word is a binary32 fitness
  * (founders 0.0); selection is a tournament of `tournament` uniform draws
@@ -470,12 +514,15 @@ int orc_set_fitness(void *handle, uint32_t model, uint32_t tournament,
                     float ben_sigma)
 {
     orc_run *r = (orc_run *)handle;
-    if (model > ORC_FLOAT_FITNESS)
+    if (model > ORC_FOUNDER_TAG || r->g != 0)
         return -1;
     if (model == ORC_FLOAT_FITNESS) {
         if (tournament > 5 || (uint64_t)del_thr + ben_thr > (1ull << 32) ||
             !(del_sigma >= 0.0f && del_sigma <= 1048576.0f) ||
             !(ben_sigma >= 0.0f && ben_sigma <= 1048576.0f))
+            return -1;
+    } else if (model == ORC_FOUNDER_TAG) {
+        if (tournament != 0)
             return -1;
     } else if (tournament != 0 && tournament != 2) {
         return -1;
@@ -486,6 +533,15 @@ int orc_set_fitness(void *handle, uint32_t model, uint32_t tournament,
     r->ben_thr = ben_thr;
     r->del_sigma = del_sigma;
     r->ben_sigma = ben_sigma;
+    /* Founder tags (Genome Model; Results, Clade Reconstruction Trial): each
+     * founder's trait word is a random 16-bit identifier, inherited without
+     * mutation under neutral selection.  Tag of agent a: the low 16 bits of
+     * the first word of Philox block (a, 0, 0, FOUNDER).                    */
+    for (uint32_t a = 0; a < r->A; a++) {
+        uint32_t w[4];
+        orc_philox(a, 0, 0, ORC_FOUNDER, r->seed, w);
+        r->trait[a] = model == ORC_FOUNDER_TAG ? (w[0] & 0xffffu) : 0u;
+    }
     return 0;
 }
 
@@ -502,11 +558,19 @@ static int step_one(orc_run *r)
      * counter g, so every birth deposits item g at the same site: the
      * placement is computed once for the whole population (Results, Surface
      * Algorithm Benchmark: synchronous generations can cache placements).   */
-    if ((uint64_t)g > orc_horizon(r->kind, r->S))
-        return -1;
-    int site = orc_place(r->kind, r->S, r->L, g);
-    if (site < 0)
-        return -1;
+    /* With an ingest interval n, only generations g = n tau deposit (item
+     * tau of the site rule, in ingest units); the others copy the parent's
+     * annotation unchanged.                                                 */
+    int site = -1;
+    uint32_t tau = g / r->interval;
+    int ingest = g % r->interval == 0;
+    if (ingest) {
+        if ((uint64_t)tau > orc_horizon(r->kind, r->S))
+            return -1;
+        site = orc_place(r->kind, r->S, r->L, tau);
+        if (site < 0)
+            return -1;
+    }
 
     for (uint32_t i = 0; i < r->I; i++) {
         /* Q := this island's members of P_g */
@@ -548,7 +612,12 @@ static int step_one(orc_run *r)
             uint32_t a = i * N + j;
             uint32_t p, child_trait, bit;
             orc_philox(j, i, g, ORC_BIRTH, r->seed, w);
-            if (r->model == ORC_INT_TRAIT) {
+            if (r->model == ORC_FOUNDER_TAG) {
+                /* neutral; the tag is inherited unchanged */
+                p = orc_mulhi(w[0], N);
+                child_trait = r->q_trait[p];
+                bit = w[3];
+            } else if (r->model == ORC_INT_TRAIT) {
                 p = orc_mulhi(w[0], N);
                 if (r->tournament == 2) {
                     uint32_t b = orc_mulhi(w[1], N);
@@ -559,11 +628,11 @@ static int step_one(orc_run *r)
                 if (w[2] < r->mut_thr)
                     delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
                 child_trait = r->q_trait[p] + delta;
-                bit = w[3] & 1u;
+                bit = w[3];
             } else {
                 /* float treatments: candidates from words w0..w3, v0; the
                  * class of the mutation from v1; |Z| from v2 (radius) and
-                 * v3 (angle); the differentia is bit 0 of v3            */
+                 * v3 (angle); the differentia is the low bits of v3     */
                 uint32_t v[4];
                 orc_philox(j, i, g, ORC_BIRTH_B, r->seed, v);
                 uint32_t words[5] = {w[0], w[1], w[2], w[3], v[0]};
@@ -582,8 +651,10 @@ static int step_one(orc_run *r)
                 else if ((uint64_t)v[1] + r->ben_thr >= (1ull << 32))
                     child_trait = f32_bits((float)(f + (double)r->ben_sigma *
                                                           orc_half_normal(v[2], v[3])));
-                bit = v[3] & 1u;
+                bit = v[3];
             }
+            /* the differentia: the low `bits` bits of the drawn word */
+            bit &= r->bits == 8 ? 0xffu : 1u;
             uint32_t T = r->q_counter[p];
             if (T != g)
                 return -2;
@@ -591,8 +662,13 @@ static int step_one(orc_run *r)
             r->n_counter[a] = T + 1;
             for (uint32_t s = 0; s < SW; s++)
                 r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];
-            uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / 32];
-            *word = (*word & ~(1u << (site % 32))) | (bit << (site % 32));
+            if (ingest) {
+                uint32_t per_word = 32 / r->bits;
+                uint32_t shift = ((uint32_t)site % per_word) * r->bits;
+                uint32_t mask = (r->bits == 8 ? 0xffu : 1u) << shift;
+                uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / per_word];
+                *word = (*word & ~mask) | (bit << shift);
+            }
             r->n_src[a] = r->q_src[p];
             if (g < r->ped_gens) {
                 r->ped_parent[(size_t)g * r->A + a] = r->q_src[p];
@@ -607,7 +683,8 @@ static int step_one(orc_run *r)
     memcpy(r->surf, r->n_surf, (size_t)r->A * SW * 4);
     for (uint32_t a = 0; a < r->A; a++)
         r->src[a] = a;
-    r->L[site] = g;
+    if (ingest)
+        r->L[site] = tau;
 
     /* Emigration: a copy of a uniformly chosen member of the new population
      * goes into the island's outbox, addressed to a uniformly chosen
@@ -674,14 +751,17 @@ int orc_read_outbox(void *handle, uint32_t *dir, uint32_t *trait,
     return 1;
 }
 
+/* The run's layout as deposit generations (ingest index times interval),
+ * EMPTY for unfilled sites.                                                */
 void orc_read_layout(void *handle, uint32_t *L)
 {
     orc_run *r = (orc_run *)handle;
-    memcpy(L, r->L, (size_t)r->S * 4);
+    for (uint32_t k = 0; k < r->S; k++)
+        L[k] = r->L[k] == ORC_EMPTY ? ORC_EMPTY : r->L[k] * r->interval;
 }
 
 /* Pedigree of generation gen (1..ped_gens): parent index in P_{gen-1} and
- * the differentia bit drawn at each birth.                                  */
+ * the differentia drawn at each birth (whether or not it was deposited).   */
 int orc_read_pedigree(void *handle, uint32_t gen, uint32_t *parent,
                       uint8_t *bit)
 {
@@ -717,25 +797,29 @@ uint32_t orc_sample(uint64_t seed, uint32_t A, uint32_t n, uint32_t T,
     return n;
 }
 
-static uint32_t site_bit(const uint32_t *s, uint32_t k)
+/* Value held at site k of a surface of `bits`-bit differentiae. */
+static uint32_t site_value(const uint32_t *s, uint32_t k, uint32_t bits)
 {
-    return (s[k / 32] >> (k % 32)) & 1u;
+    uint32_t per_word = 32 / bits;
+    uint32_t mask = bits == 8 ? 0xffu : 1u;
+    return (s[k / per_word] >> ((k % per_word) * bits)) & mask;
 }
 
 /* MRCA-generation bounds from two annotations (Distributed Phylogenetic
  * Tracking: mismatching differentiae delimit the extent of common ancestry;
- * one-bit differentiae can collide and overstate relatedness).
+ * narrow differentiae can collide and overstate relatedness).
  *
  * Written out from the definition: C = the deposit times retained by both
- * annotations, ascending; t* = the first t in C whose bits differ.  A
- * mismatch at t shows the two generation-(t+1) ancestors differ, so the
+ * annotations, ascending; t* = the first t in C whose differentiae differ.
+ * A mismatch at t shows the two generation-(t+1) ancestors differ, so the
  * MRCA's generation is at most t*:  ub = t*, or min(Ta, Tb) if nothing
  * differs.  The last agreeing t before t* (or the last of C) gives
  * lb = t + 1, or 0 when there is none.  lb assumes no collision.  La and Lb
- * are the two layouts (orc_layout of each annotation's counter).          */
-int orc_mrca_pair(uint32_t S, uint32_t Ta, const uint32_t *sa,
-                  const uint32_t *La, uint32_t Tb, const uint32_t *sb,
-                  const uint32_t *Lb, uint32_t *lb, uint32_t *ub)
+ * are the two layouts in ingest units (orc_layout of each annotation's
+ * number of ingests); item tau was deposited at generation tau * interval.  */
+int orc_mrca_pair_x(uint32_t S, uint32_t bits, uint32_t interval, uint32_t Ta,
+                    const uint32_t *sa, const uint32_t *La, uint32_t Tb,
+                    const uint32_t *sb, const uint32_t *Lb, uint32_t *lb, uint32_t *ub)
 {
     /* common deposit times with their sites in each annotation */
     uint32_t ct[64], ka[64], kb[64];
@@ -762,82 +846,98 @@ int orc_mrca_pair(uint32_t S, uint32_t Ta, const uint32_t *sa,
     int have_last = 0;
     uint32_t last = 0;
     for (uint32_t p = 0; p < nc; p++) {
-        if (site_bit(sa, ka[p]) != site_bit(sb, kb[p])) {
-            *ub = ct[p];
+        uint32_t gen = ct[p] * interval;   /* deposit generation */
+        if (site_value(sa, ka[p], bits) != site_value(sb, kb[p], bits)) {
+            *ub = gen;
             *lb = have_last ? last + 1 : 0;
             return 0;
         }
         have_last = 1;
-        last = ct[p];
+        last = gen;
     }
     *ub = Ta < Tb ? Ta : Tb;
     *lb = have_last ? last + 1 : 0;
     return 0;
 }
 
-/* All ordered pairs of n annotations: lb and ub are n*n, row-major (row a,
- * column b).  Surfaces are agent-major, S/32 words per agent.  Layouts are
- * replayed per annotation.  Returns 0, or -1 beyond the horizon / no memory. */
-int orc_mrca_allpairs(uint32_t kind, uint32_t S, uint32_t n,
-                      const uint32_t *counters, const uint32_t *surf,
-                      uint32_t *lb, uint32_t *ub)
+int orc_mrca_pair(uint32_t S, uint32_t Ta, const uint32_t *sa,
+                  const uint32_t *La, uint32_t Tb, const uint32_t *sb,
+                  const uint32_t *Lb, uint32_t *lb, uint32_t *ub)
 {
-    uint32_t SW = S / 32;
-    uint32_t *L = (uint32_t *)malloc((size_t)n * S * 4);
+    return orc_mrca_pair_x(S, 1, 1, Ta, sa, La, Tb, sb, Lb, lb, ub);
+}
+
+/* Layouts (ingest units) of n annotations, one per counter. */
+static uint32_t *layouts_of(uint32_t kind, uint32_t S, uint32_t interval, uint32_t n,
+                            const uint32_t *counters)
+{
+    uint32_t *L = (uint32_t *)malloc((size_t)(n ? n : 1) * S * 4);
     if (!L)
-        return -1;
+        return NULL;
     for (uint32_t a = 0; a < n; a++) {
         /* reuse the previous layout when the counter repeats */
         if (a > 0 && counters[a] == counters[a - 1]) {
             memcpy(L + (size_t)a * S, L + (size_t)(a - 1) * S, (size_t)S * 4);
-        } else if (orc_layout(kind, S, counters[a], L + (size_t)a * S) != 0) {
+        } else if (orc_layout(kind, S, ingests_of(counters[a], interval),
+                              L + (size_t)a * S) != 0) {
             free(L);
-            return -1;
+            return NULL;
         }
     }
-    for (uint32_t a = 0; a < n; a++)
-        for (uint32_t b = 0; b < n; b++)
-            orc_mrca_pair(S, counters[a], surf + (size_t)a * SW,
-                          L + (size_t)a * S, counters[b], surf + (size_t)b * SW,
-                          L + (size_t)b * S, lb + (size_t)a * n + b,
-                          ub + (size_t)a * n + b);
-    free(L);
-    return 0;
+    return L;
 }
 
 /* Selected rows of the all-pairs matrix: lb and ub are nrows * n, row r
- * holding annotation rows[r] against every annotation b.  Same definition
- * as orc_mrca_allpairs; used to check sampled outputs of large matrices.  */
-int orc_mrca_rows(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,
-                  const uint32_t *surf, uint32_t nrows, const uint32_t *rows,
-                  uint32_t *lb, uint32_t *ub)
+ * holding annotation rows[r] against every annotation b; rows == NULL
+ * means every row (nrows = n).  Surfaces are agent-major, S*bits/32 words
+ * per agent.  Returns 0, or -1 beyond the horizon / bad row / no memory. */
+int orc_mrca_rows_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
+                    uint32_t n, const uint32_t *counters, const uint32_t *surf,
+                    uint32_t nrows, const uint32_t *rows, uint32_t *lb, uint32_t *ub)
 {
-    uint32_t SW = S / 32;
-    uint32_t *L = (uint32_t *)malloc((size_t)n * S * 4);
+    if (!scheme_ok(S, bits, interval))
+        return -1;
+    uint32_t SW = S * bits / 32;
+    uint32_t *L = layouts_of(kind, S, interval, n, counters);
     if (!L)
         return -1;
-    for (uint32_t a = 0; a < n; a++) {
-        if (a > 0 && counters[a] == counters[a - 1]) {
-            memcpy(L + (size_t)a * S, L + (size_t)(a - 1) * S, (size_t)S * 4);
-        } else if (orc_layout(kind, S, counters[a], L + (size_t)a * S) != 0) {
-            free(L);
-            return -1;
-        }
-    }
     for (uint32_t r = 0; r < nrows; r++) {
-        uint32_t a = rows[r];
+        uint32_t a = rows ? rows[r] : r;
         if (a >= n) {
             free(L);
             return -1;
         }
         for (uint32_t b = 0; b < n; b++)
-            orc_mrca_pair(S, counters[a], surf + (size_t)a * SW,
-                          L + (size_t)a * S, counters[b], surf + (size_t)b * SW,
-                          L + (size_t)b * S, lb + (size_t)r * n + b,
-                          ub + (size_t)r * n + b);
+            orc_mrca_pair_x(S, bits, interval, counters[a], surf + (size_t)a * SW,
+                            L + (size_t)a * S, counters[b], surf + (size_t)b * SW,
+                            L + (size_t)b * S, lb + (size_t)r * n + b,
+                            ub + (size_t)r * n + b);
     }
     free(L);
     return 0;
+}
+
+/* All ordered pairs of n annotations: lb and ub are n*n, row-major (row a,
+ * column b).                                                               */
+int orc_mrca_allpairs_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
+                        uint32_t n, const uint32_t *counters, const uint32_t *surf,
+                        uint32_t *lb, uint32_t *ub)
+{
+    return orc_mrca_rows_x(kind, S, bits, interval, n, counters, surf, n, NULL, lb, ub);
+}
+
+int orc_mrca_allpairs(uint32_t kind, uint32_t S, uint32_t n,
+                      const uint32_t *counters, const uint32_t *surf,
+                      uint32_t *lb, uint32_t *ub)
+{
+    return orc_mrca_allpairs_x(kind, S, 1, 1, n, counters, surf, lb, ub);
+}
+
+int orc_mrca_rows(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,
+                  const uint32_t *surf, uint32_t nrows, const uint32_t *rows,
+                  uint32_t *lb, uint32_t *ub)
+{
+    return orc_mrca_rows_x(kind, S, 1, 1, n, counters, surf, nrows, rows, lb, ub);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -847,14 +947,14 @@ int orc_mrca_rows(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counter
  * treatments are compared by sum branch length and mean evolutionary
  * distinctiveness).
  *
- * Reading: each annotation is read as its bits in ascending deposit time
- * (times t_0 < ... < t_{F-1} of the shared layout).  They are inserted into a
- * binary trie, one level per retained time.  A trie node where the
- * annotations below it split on the bit of time t_d becomes a tree node at
- * time t_d (the MRCA upper bound of the pairs it separates); annotations
- * with identical bits hang from one node at time T; each annotation is a
- * leaf at time T; chains of one-child trie nodes are collapsed; the root is
- * the first branching node.
+ * Reading: each annotation is read as its differentiae in ascending deposit
+ * time (times t_0 < ... < t_{F-1} of the shared layout).  They are inserted
+ * into a trie, one level per retained time, one child per differentia
+ * value.  A trie node whose annotations split on the differentia of time
+ * t_d becomes a tree node at time t_d (the MRCA upper bound of the pairs it
+ * separates); annotations with identical differentiae hang from one node
+ * at time T; each annotation is a leaf at time T; chains of one-child trie
+ * nodes are collapsed; the root is the first branching node.
  *
  * Output: out[0] = sum of branch lengths; out[1] = sum over unordered
  * pairs of (T - time of their tree MRCA); out[2] = root time; out[3] =
@@ -863,7 +963,8 @@ int orc_mrca_rows(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counter
  * the leaves below it), in double.  Returns 0, -1 if the counters differ
  * or are past the horizon, -2 on no memory.                                */
 typedef struct {
-    int child[2];
+    int first_child, next_sibling;
+    uint32_t value;     /* differentia value on the edge from the parent   */
     int leaf_first;     /* first annotation index at a depth-F node, or -1 */
     int nleaves;        /* annotations below                               */
 } orc_trie_node;
@@ -873,7 +974,7 @@ typedef struct {
     int count, cap;
 } orc_trie;
 
-static int trie_new(orc_trie *t)
+static int trie_new(orc_trie *t, uint32_t value)
 {
     if (t->count == t->cap) {
         int cap = t->cap ? 2 * t->cap : 1024;
@@ -884,14 +985,15 @@ static int trie_new(orc_trie *t)
         t->cap = cap;
     }
     orc_trie_node *nd = &t->nodes[t->count];
-    nd->child[0] = nd->child[1] = -1;
+    nd->first_child = nd->next_sibling = -1;
+    nd->value = value;
     nd->leaf_first = -1;
     nd->nleaves = 0;
     return t->count++;
 }
 
 typedef struct {
-    const uint32_t *times;   /* ascending retained times */
+    const uint32_t *times;   /* ascending retained deposit generations */
     uint32_t F, T;
     const orc_trie *trie;
     const int *leaf_next;    /* annotations sharing a depth-F node */
@@ -905,14 +1007,14 @@ typedef struct {
 
 /* Walk the trie from node v at depth d, whose nearest tree ancestor sits at
  * time parent_t (or none at the very top).  acc_ed is the ED accumulated by
- * the path above v.  Adds every edge, every pair's MRCA depth and every
+ * the path above v.  Adds every edge, every pair's MRCA time and every
  * leaf's ED.                                                                */
 static void phylo_walk(orc_phylo_ctx *c, int v, uint32_t d, int has_parent,
                        uint32_t parent_t, double acc_ed)
 {
     const orc_trie_node *nd = &c->trie->nodes[v];
     if (d == c->F) {
-        /* annotations with identical bits */
+        /* annotations with identical differentiae */
         int k = nd->nleaves;
         uint32_t here = c->T;
         double ed_here = acc_ed;
@@ -939,8 +1041,10 @@ static void phylo_walk(orc_phylo_ctx *c, int v, uint32_t d, int has_parent,
         }
         return;
     }
-    int c0 = nd->child[0], c1 = nd->child[1];
-    if (c0 >= 0 && c1 >= 0) {
+    int nchild = 0;
+    for (int w = nd->first_child; w >= 0; w = c->trie->nodes[w].next_sibling)
+        nchild++;
+    if (nchild >= 2) {
         /* branching: a tree node at t_d */
         uint32_t here = c->times[d];
         double ed_here = acc_ed;
@@ -952,26 +1056,33 @@ static void phylo_walk(orc_phylo_ctx *c, int v, uint32_t d, int has_parent,
             c->root_time = here;
         }
         c->internal += 1;
-        uint64_t n0 = (uint64_t)c->trie->nodes[c0].nleaves;
-        uint64_t n1 = (uint64_t)c->trie->nodes[c1].nleaves;
-        c->pair_sum += n0 * n1 * (uint64_t)(c->T - here);
-        phylo_walk(c, c0, d + 1, 1, here, ed_here);
-        phylo_walk(c, c1, d + 1, 1, here, ed_here);
+        /* pairs from different children meet here */
+        uint64_t seen = 0;
+        for (int w = nd->first_child; w >= 0; w = c->trie->nodes[w].next_sibling) {
+            uint64_t k = (uint64_t)c->trie->nodes[w].nleaves;
+            c->pair_sum += seen * k * (uint64_t)(c->T - here);
+            seen += k;
+        }
+        for (int w = nd->first_child; w >= 0; w = c->trie->nodes[w].next_sibling)
+            phylo_walk(c, w, d + 1, 1, here, ed_here);
     } else {
-        phylo_walk(c, c0 >= 0 ? c0 : c1, d + 1, has_parent, parent_t, acc_ed);
+        phylo_walk(c, nd->first_child, d + 1, has_parent, parent_t, acc_ed);
     }
 }
 
-int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,
-                      const uint32_t *surf, uint64_t out[4], double *ed)
+int orc_phylo_metrics_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
+                        uint32_t n, const uint32_t *counters, const uint32_t *surf,
+                        uint64_t out[4], double *ed)
 {
-    uint32_t SW = S / 32;
+    if (!scheme_ok(S, bits, interval))
+        return -1;
+    uint32_t SW = S * bits / 32;
     for (uint32_t a = 1; a < n; a++)
         if (counters[a] != counters[0])
             return -1;
     uint32_t T = n ? counters[0] : 0;
     uint32_t L[64];
-    if (orc_layout(kind, S, T, L) != 0)
+    if (orc_layout(kind, S, ingests_of(T, interval), L) != 0)
         return -1;
     /* retained sites in ascending deposit time */
     uint32_t times[64], sites[64], F = 0;
@@ -979,17 +1090,17 @@ int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *cou
         if (L[k] == ORC_EMPTY)
             continue;
         uint32_t q = F++;
-        while (q > 0 && times[q - 1] > L[k]) {
+        while (q > 0 && times[q - 1] > L[k] * interval) {
             times[q] = times[q - 1];
             sites[q] = sites[q - 1];
             q--;
         }
-        times[q] = L[k];
+        times[q] = L[k] * interval;
         sites[q] = k;
     }
     orc_trie trie = {0};
     int *leaf_next = (int *)malloc((size_t)(n ? n : 1) * sizeof(int));
-    if (!leaf_next || trie_new(&trie) < 0) {
+    if (!leaf_next || trie_new(&trie, 0) < 0) {
         free(leaf_next);
         free(trie.nodes);
         return -2;
@@ -998,17 +1109,21 @@ int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *cou
         int v = 0;
         trie.nodes[v].nleaves++;
         for (uint32_t r = 0; r < F; r++) {
-            uint32_t b = site_bit(surf + (size_t)a * SW, sites[r]);
-            if (trie.nodes[v].child[b] < 0) {
-                int w = trie_new(&trie);
+            uint32_t val = site_value(surf + (size_t)a * SW, sites[r], bits);
+            int w = trie.nodes[v].first_child;
+            while (w >= 0 && trie.nodes[w].value != val)
+                w = trie.nodes[w].next_sibling;
+            if (w < 0) {
+                w = trie_new(&trie, val);
                 if (w < 0) {
                     free(leaf_next);
                     free(trie.nodes);
                     return -2;
                 }
-                trie.nodes[v].child[b] = w;
+                trie.nodes[w].next_sibling = trie.nodes[v].first_child;
+                trie.nodes[v].first_child = w;
             }
-            v = trie.nodes[v].child[b];
+            v = w;
             trie.nodes[v].nleaves++;
         }
         leaf_next[a] = trie.nodes[v].leaf_first;
@@ -1026,4 +1141,10 @@ int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *cou
     free(leaf_next);
     free(trie.nodes);
     return 0;
+}
+
+int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,
+                      const uint32_t *surf, uint64_t out[4], double *ed)
+{
+    return orc_phylo_metrics_x(kind, S, 1, 1, n, counters, surf, out, ed);
 }

@@ -23,8 +23,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 EMPTY = 0xFFFFFFFF
 STEADY, TILTED, HYBRID = 0, 1, 2
 KINDS = {"steady": STEADY, "tilted": TILTED, "hybrid": HYBRID}
-BIRTH, EMIGRATE, IMMIGRATE, SAMPLE, BIRTH_B = 0, 1, 2, 3, 4
-INT_TRAIT, FLOAT_FITNESS = 0, 1
+BIRTH, EMIGRATE, IMMIGRATE, SAMPLE, BIRTH_B, FOUNDER = 0, 1, 2, 3, 4, 5
+INT_TRAIT, FLOAT_FITNESS, FOUNDER_TAG = 0, 1, 2
 
 _lib = None
 
@@ -71,6 +71,21 @@ def load():
                                [ctypes.c_uint32, ctypes.c_uint64,
                                 ctypes.c_uint32])
     lib.orc_create.restype = ctypes.c_void_p
+    lib.orc_create_ex.argtypes = ([ctypes.c_uint32] * 7 + [ctypes.c_int32] * 2 +
+                                  [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_uint32, ctypes.c_uint32])
+    lib.orc_create_ex.restype = ctypes.c_void_p
+    lib.orc_horizon_gen.argtypes = [ctypes.c_uint32] * 3
+    lib.orc_horizon_gen.restype = ctypes.c_uint64
+    lib.orc_mrca_rows_x.argtypes = ([ctypes.c_uint32] * 5 + [u32p, u32p, ctypes.c_uint32, u32p,
+                                                             u32p, u32p])
+    lib.orc_mrca_rows_x.restype = ctypes.c_int
+    lib.orc_mrca_allpairs_x.argtypes = [ctypes.c_uint32] * 5 + [u32p] * 4
+    lib.orc_mrca_allpairs_x.restype = ctypes.c_int
+    lib.orc_phylo_metrics_x.argtypes = ([ctypes.c_uint32] * 5 +
+                                        [u32p, u32p, ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.POINTER(ctypes.c_double)])
+    lib.orc_phylo_metrics_x.restype = ctypes.c_int
     lib.orc_set_fitness.argtypes = [ctypes.c_void_p] + [ctypes.c_uint32] * 4 + [ctypes.c_float] * 2
     lib.orc_set_fitness.restype = ctypes.c_int
     lib.orc_half_normal.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
@@ -182,10 +197,12 @@ class Run:
     def __init__(self, W, H, N, S, kind, tournament=2, mut_thr=42949672,
                  mut_lo=-8, mut_hi=8, migrants=1, seed=1, pedigree_gens=0,
                  fitness_model=INT_TRAIT, del_thr=0, ben_thr=0, del_sigma=1.0,
-                 ben_sigma=1.0):
+                 ben_sigma=1.0, bits=1, interval=1):
         lib = load()
-        h = lib.orc_create(W, H, N, S, kind, tournament if fitness_model == INT_TRAIT else 0,
-                           mut_thr, mut_lo, mut_hi, migrants, seed, pedigree_gens)
+        h = lib.orc_create_ex(W, H, N, S, kind,
+                              tournament if fitness_model == INT_TRAIT else 0,
+                              mut_thr, mut_lo, mut_hi, migrants, seed, pedigree_gens, bits,
+                              interval)
         if not h:
             raise ValueError("invalid oracle configuration")
         self._h = h
@@ -194,9 +211,10 @@ class Run:
             self.close()
             raise ValueError("invalid oracle fitness configuration")
         self.W, self.H, self.N, self.S, self.kind = W, H, N, S, kind
+        self.bits, self.interval = bits, interval
         self.I = W * H
         self.A = self.I * N
-        self.SW = S // 32
+        self.SW = S * bits // 32
         self.seed = seed
 
     def close(self):
@@ -275,21 +293,26 @@ def mrca_pair(S: int, Ta: int, sa, Tb: int, sb, kind: int):
     return int(lb[0]), int(ub[0])
 
 
-def mrca_allpairs(kind: int, S: int, counters, surfaces):
+def horizon_gen(kind: int, S: int, interval: int = 1) -> int:
+    """Last generation a run can step with this ingest interval."""
+    return int(load().orc_horizon_gen(kind, S, interval))
+
+
+def mrca_allpairs(kind: int, S: int, counters, surfaces, bits: int = 1, interval: int = 1):
     """lb, ub (n x n, row-major) over every ordered pair."""
     counters = np.ascontiguousarray(counters, np.uint32)
     surfaces = np.ascontiguousarray(surfaces, np.uint32).reshape(-1)
     n = counters.shape[0]
     lb = np.zeros((n, n), np.uint32)
     ub = np.zeros((n, n), np.uint32)
-    rc = load().orc_mrca_allpairs(kind, S, n, _p(counters), _p(surfaces),
-                                  _p(lb), _p(ub))
+    rc = load().orc_mrca_allpairs_x(kind, S, bits, interval, n, _p(counters), _p(surfaces),
+                                    _p(lb), _p(ub))
     if rc:
-        raise ValueError("beyond the horizon")
+        raise ValueError("beyond the horizon or invalid scheme")
     return lb, ub
 
 
-def mrca_rows(kind: int, S: int, counters, surfaces, rows):
+def mrca_rows(kind: int, S: int, counters, surfaces, rows, bits: int = 1, interval: int = 1):
     """Rows `rows` of the all-pairs matrices (len(rows) x n)."""
     counters = np.ascontiguousarray(counters, np.uint32)
     surfaces = np.ascontiguousarray(surfaces, np.uint32).reshape(-1)
@@ -297,14 +320,14 @@ def mrca_rows(kind: int, S: int, counters, surfaces, rows):
     n = counters.shape[0]
     lb = np.zeros((len(rows), n), np.uint32)
     ub = np.zeros((len(rows), n), np.uint32)
-    rc = load().orc_mrca_rows(kind, S, n, _p(counters), _p(surfaces), len(rows), _p(rows),
-                              _p(lb), _p(ub))
+    rc = load().orc_mrca_rows_x(kind, S, bits, interval, n, _p(counters), _p(surfaces),
+                                len(rows), _p(rows), _p(lb), _p(ub))
     if rc:
-        raise ValueError("beyond the horizon or row out of range")
+        raise ValueError("beyond the horizon, invalid scheme or row out of range")
     return lb, ub
 
 
-def phylo_metrics(kind: int, S: int, counters, surfaces):
+def phylo_metrics(kind: int, S: int, counters, surfaces, bits: int = 1, interval: int = 1):
     """Trie reconstruction of annotations sharing a counter: (sum of branch
     lengths, sum over pairs of T - MRCA time, root time, internal nodes,
     per-leaf evolutionary distinctiveness)."""
@@ -313,11 +336,11 @@ def phylo_metrics(kind: int, S: int, counters, surfaces):
     n = counters.shape[0]
     out = np.zeros(4, np.uint64)
     ed = np.zeros(max(n, 1), np.float64)
-    rc = load().orc_phylo_metrics(kind, S, n, _p(counters), _p(surfaces),
-                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
-                                  ed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    rc = load().orc_phylo_metrics_x(kind, S, bits, interval, n, _p(counters), _p(surfaces),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    ed.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     if rc:
-        raise ValueError("counters differ, past the horizon, or no memory")
+        raise ValueError("counters differ, past the horizon, invalid scheme, or no memory")
     return int(out[0]), int(out[1]), int(out[2]), int(out[3]), ed[:n].copy()
 
 
