@@ -63,8 +63,11 @@ typedef enum { GA_STEADY = 0, GA_TILTED = 1, GA_HYBRID = 2 } ga_surface_kind;
  * On-hardware Trial): the trait word holds a binary32 fitness, selection is
  * a tournament of up to five, and a birth is deleterious (fitness decreases
  * by del_sigma |Z|) or beneficial (increases by ben_sigma |Z|) with the
- * configured probabilities, |Z| half-normal from a Box-Muller draw.        */
-typedef enum { GA_INT_TRAIT = 0, GA_FLOAT_FITNESS = 1 } ga_fitness_model;
+ * configured probabilities, |Z| half-normal from a Box-Muller draw.
+ * GA_FOUNDER_TAG: the clade trial's genome (Genome Model; Results, Clade
+ * Reconstruction Trial): each founder's trait word is a random 16-bit tag,
+ * inherited without mutation under neutral selection (tournament_size 0). */
+typedef enum { GA_INT_TRAIT = 0, GA_FLOAT_FITNESS = 1, GA_FOUNDER_TAG = 2 } ga_fitness_model;
 
 typedef struct ga_config {
     uint32_t struct_size;         /* sizeof(ga_config) = 80; 56 (a config
@@ -72,7 +75,8 @@ typedef struct ga_config {
                                      and means GA_INT_TRAIT                   */
     uint32_t grid_w, grid_h;      /* torus of islands; island i = y*w + x      */
     uint32_t pop_per_island;      /* N agents per island, 1..64                */
-    uint32_t surface_sites;       /* S one-bit sites: 32 or 64                 */
+    uint32_t surface_sites;       /* S sites: 32 or 64 one-bit sites, or 4 or
+                                     8 byte sites (differentia_bits = 8)      */
     uint32_t surface_kind;        /* ga_surface_kind                           */
     uint32_t tournament_size;     /* GA_INT_TRAIT: 2 = tournament of two,
                                      0 = neutral.  GA_FLOAT_FITNESS: 1..5
@@ -82,7 +86,8 @@ typedef struct ga_config {
     int32_t mut_lo, mut_hi;       /* GA_INT_TRAIT: inclusive trait-delta
                                      range, e.g. -8, 8                         */
     uint32_t migrants_per_island; /* 1, or 0 to switch migration off           */
-    uint32_t reserved;            /* must be 0                                 */
+    uint32_t ingest_interval;     /* deposit a differentia every n-th
+                                     generation only (0 or 1: every one)      */
     uint64_t seed;                /* Philox4x32-10 key                         */
     /* GA_FLOAT_FITNESS only (ignored otherwise): */
     uint32_t fitness_model;       /* ga_fitness_model                          */
@@ -92,7 +97,8 @@ typedef struct ga_config {
                                      this; p = 0.003 -> 12884901; the two
                                      thresholds sum to at most 2^32            */
     float del_sigma, ben_sigma;   /* scales of |Z|, in [0, 2^20]               */
-    uint32_t reserved2;           /* must be 0                                 */
+    /* any fitness model: */
+    uint32_t differentia_bits;    /* 1 (0 means 1) or 8 bits per site          */
 } ga_config;
 
 typedef struct ga_run ga_run;
@@ -119,10 +125,11 @@ size_t ga_footprint_bytes(const ga_config *cfg, uint32_t max_gens_per_launch);
  * aligned, arena_bytes >= ga_footprint_bytes) and enqueue the founders on
  * hip_stream: trait 0, counter 0, all sites 0, empty layout, no outboxes.
  * Founders carry no differentia; generation g's births deposit item g.
- * Errors: GA_EINVAL (struct_size not 56/80, S not 32/64, N = 0 or > 64,
- * empty grid, mut_lo > mut_hi, tournament not 0/2 (integer trait) or above
- * 5 (float fitness), migrants > 1, reserved fields != 0, float thresholds
- * summing above 2^32, a scale outside [0, 2^20]), GA_ENOMEM
+ * Errors: GA_EINVAL (struct_size not 56/80, S * differentia_bits not 32 or
+ * 64, differentia_bits not 1/8, N = 0 or > 64, empty grid, mut_lo >
+ * mut_hi, tournament not 0/2 (integer trait), above 5 (float fitness) or
+ * not 0 (founder tags), migrants > 1, float thresholds summing above 2^32,
+ * a scale outside [0, 2^20]), GA_ENOMEM
  * (arena too small), GA_EDEVICE.  *out is owned by the caller until
  * ga_destroy.                                                              */
 int ga_create(const ga_config *cfg, void *dev_arena, size_t arena_bytes,
@@ -147,7 +154,8 @@ int ga_generation(const ga_run *run, uint32_t *T);
 
 /* Blocking copy of agents [first, first + count) of the current
  * population into host buffers: trait[count], counter[count],
- * surface_words[count * S/32] (agent-major).  Any pointer may be NULL.
+ * surface_words[count * W] (agent-major, W = S * differentia_bits / 32
+ * surface words per agent).  Any pointer may be NULL.
  * Errors: GA_EINVAL (range), GA_EDEVICE.                                   */
 int ga_read_agents(ga_run *run, uint32_t first, uint32_t count,
                    uint32_t *trait, uint32_t *counter, uint32_t *surface_words);
@@ -161,16 +169,17 @@ int ga_read_outbox(ga_run *run, uint32_t first, uint32_t count,
                    uint32_t *dir, uint32_t *trait, uint32_t *counter,
                    uint32_t *surface_words, int *valid);
 
-/* Blocking copy of the run's layout: the deposit time held by each of the
- * S sites, GA_EMPTY_SITE if none (Distributed Phylogenetic Tracking:
- * timestamps follow from the site index and the generation count).        */
+/* Blocking copy of the run's layout: the deposit generation held by each
+ * of the S sites, GA_EMPTY_SITE if none (Distributed Phylogenetic
+ * Tracking: timestamps follow from the site index and the generation
+ * count); with an ingest interval n these are multiples of n.             */
 int ga_read_layout(ga_run *run, uint32_t *layout);
 
 /* Enqueue a stratified sample of the current population (Results,
  * On-hardware Trial: end-state genomes are sampled): agent k is drawn
  * uniformly from the k-th of n equal strata; if the population has at
  * most n agents, all of them are taken in order.  Writes device buffers
- * idx[n_taken], counter[n_taken], surface_words[n_taken * S/32]
+ * idx[n_taken], counter[n_taken], surface_words[n_taken * W]
  * (agent-major), the input layout of hstrat_mrca_bounds.  *n_taken (host)
  * is min(n, A).  Errors: GA_EINVAL (n = 0 or NULL buffers), GA_EDEVICE.    */
 int ga_sample(ga_run *run, uint32_t n, uint32_t *dev_idx, uint32_t *dev_counter,
@@ -188,15 +197,29 @@ const char *ga_last_error(void);
  * differentiae delimit the extent of common ancestry; Results, Clade
  * Reconstruction Trial: one-bit differentiae overstate relatedness).
  *
- * For annotations a, b with counters Ta, Tb: C = deposit times retained by
- * both (ascending), t* = the first t in C where the bits differ.
- *   ub = t*, or min(Ta, Tb) if no retained bit differs;
+ * For annotations a, b with counters Ta, Tb: C = deposit generations
+ * retained by both (ascending), t* = the first t in C where the
+ * differentiae differ.
+ *   ub = t*, or min(Ta, Tb) if no retained differentia differs;
  *   lb = 1 + the last t in C before t* (the last of C if no mismatch),
  *        or 0 if there is none.
  * ub never falls below the true MRCA generation; lb does only when a
- * one-bit differentia matched by chance.  An annotation against itself
- * gives (T, T).
+ * differentia matched by chance.  An annotation against itself gives
+ * (1 + its last deposit, T): (T, T) when every generation deposits.
+ *
+ * The plain calls take one-bit differentiae deposited every generation;
+ * the _ex calls take an annotation scheme.
  * ------------------------------------------------------------------------ */
+
+/* An annotation scheme: the surface kind, S sites of differentia_bits bits
+ * each (1 with S = 32 or 64; 8 with S = 4 or 8), one deposit every
+ * ingest_interval generations (the ga_config fields of the runs).          */
+typedef struct hstrat_scheme {
+    uint32_t kind;             /* ga_surface_kind                           */
+    uint32_t sites;            /* S                                         */
+    uint32_t differentia_bits; /* 1 or 8                                    */
+    uint32_t ingest_interval;  /* >= 1                                      */
+} hstrat_scheme;
 
 /* Device workspace bytes hstrat_mrca_bounds needs for n annotations. */
 size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n);
@@ -214,6 +237,15 @@ int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n,
                        const uint32_t *counter, const uint32_t *surface_words,
                        uint32_t *lb, uint32_t *ub, void *workspace,
                        size_t workspace_bytes, void *hip_stream);
+
+/* hstrat_mrca_bounds for any annotation scheme (surface_words: n * W
+ * words, W = sites * differentia_bits / 32; workspace sized by
+ * hstrat_mrca_workspace_bytes(sites, n)).  Errors as hstrat_mrca_bounds,
+ * plus GA_EINVAL for an invalid scheme.                                    */
+int hstrat_mrca_bounds_ex(const hstrat_scheme *scheme, uint32_t n,
+                          const uint32_t *counter, const uint32_t *surface_words,
+                          uint32_t *lb, uint32_t *ub, void *workspace,
+                          size_t workspace_bytes, void *hip_stream);
 
 /* Blocking: status of the last hstrat_mrca_bounds run on this workspace
  * (GA_OK, or GA_EHORIZON when a counter was past the horizon, in which
@@ -252,6 +284,13 @@ int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n,
                          const uint32_t *counter, const uint32_t *surface_words,
                          uint64_t *out, void *workspace, size_t workspace_bytes,
                          void *hip_stream);
+
+/* hstrat_phylo_metrics for any annotation scheme.  With byte differentiae
+ * a trie node can split many ways (one tree node per distinct value).     */
+int hstrat_phylo_metrics_ex(const hstrat_scheme *scheme, uint32_t n,
+                            const uint32_t *counter, const uint32_t *surface_words,
+                            uint64_t *out, void *workspace, size_t workspace_bytes,
+                            void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched and served runs: a pool of runs of any sizes, surfaces and

@@ -33,6 +33,7 @@ EXPORTS = (
     "ga_pool_advance", "ga_pool_poll", "ga_pool_run", "ga_pool_release", "ga_pool_sync",
     "ga_pool_set_launch", "ga_pool_info", "ga_pool_destroy",
     "hstrat_phylo_workspace_bytes", "hstrat_phylo_metrics",
+    "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex",
 )
 
 
@@ -55,18 +56,27 @@ class ga_config(ctypes.Structure):
         ("mut_lo", ctypes.c_int32),
         ("mut_hi", ctypes.c_int32),
         ("migrants_per_island", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("ingest_interval", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
         ("fitness_model", ctypes.c_uint32),
         ("del_threshold", ctypes.c_uint32),
         ("ben_threshold", ctypes.c_uint32),
         ("del_sigma", ctypes.c_float),
         ("ben_sigma", ctypes.c_float),
-        ("reserved2", ctypes.c_uint32),
+        ("differentia_bits", ctypes.c_uint32),
     ]
 
 
-FITNESS_MODELS = {"int": 0, "float": 1}
+class hstrat_scheme(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_uint32),
+        ("sites", ctypes.c_uint32),
+        ("differentia_bits", ctypes.c_uint32),
+        ("ingest_interval", ctypes.c_uint32),
+    ]
+
+
+FITNESS_MODELS = {"int": 0, "float": 1, "tag": 2}
 
 
 _lib = None
@@ -124,6 +134,10 @@ def load_library():
         "hstrat_phylo_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
         "hstrat_phylo_metrics": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "hstrat_mrca_bounds_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp,
+                                                 ctypes.c_size_t, _vp]),
+        "hstrat_phylo_metrics_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp,
+                                                   ctypes.c_size_t, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -155,7 +169,10 @@ class Config:
     fitness_model 'int' is the integer trait (tournament_size 0 or 2, the
     mut_* fields); 'float' is the paper's float treatments (tournament_size
     0..5, del_threshold / ben_threshold class probabilities times 2^32,
-    del_sigma / ben_sigma scales of the half-normal change)."""
+    del_sigma / ben_sigma scales of the half-normal change); 'tag' gives
+    founders random 16-bit tags, inherited unchanged (tournament_size 0).
+    differentia_bits 1 (surface_sites 32 or 64) or 8 (surface_sites 4 or
+    8); ingest_interval n deposits every n-th generation only."""
     grid_w: int
     grid_h: int
     pop_per_island: int = 32
@@ -172,10 +189,21 @@ class Config:
     ben_threshold: int = 0
     del_sigma: float = 1.0
     ben_sigma: float = 1.0
+    differentia_bits: int = 1
+    ingest_interval: int = 1
 
     @property
     def kind(self) -> int:
         return KINDS[self.surface_kind]
+
+    @property
+    def surface_words(self) -> int:
+        return self.surface_sites * self.differentia_bits // 32
+
+    @property
+    def scheme(self) -> dict:
+        """Keyword arguments of mrca_bounds / phylo_metrics for this run."""
+        return {"bits": self.differentia_bits, "interval": self.ingest_interval}
 
     @property
     def islands(self) -> int:
@@ -196,14 +224,14 @@ class Config:
         c.mut_threshold = self.mut_threshold
         c.mut_lo, c.mut_hi = self.mut_lo, self.mut_hi
         c.migrants_per_island = self.migrants_per_island
-        c.reserved = 0
+        c.ingest_interval = self.ingest_interval
         c.seed = self.seed
         c.fitness_model = FITNESS_MODELS[self.fitness_model]
         c.del_threshold = self.del_threshold
         c.ben_threshold = self.ben_threshold
         c.del_sigma = self.del_sigma
         c.ben_sigma = self.ben_sigma
-        c.reserved2 = 0
+        c.differentia_bits = self.differentia_bits
         return c
 
 
@@ -231,7 +259,7 @@ class RunHandle:
         self.cfg = cfg
         self.device = torch.device(device)
         self.S = cfg.surface_sites
-        self.SW = self.S // 32
+        self.SW = cfg.surface_words
         self.A = cfg.agents
         self.I = cfg.islands
 
@@ -448,13 +476,21 @@ class MrcaWorkspace:
         self.S, self.n = S, n
 
 
+def _scheme(kind: int, S: int, bits: int, interval: int) -> hstrat_scheme:
+    sc = hstrat_scheme()
+    sc.kind, sc.sites, sc.differentia_bits, sc.ingest_interval = kind, S, bits, interval
+    return sc
+
+
 def mrca_bounds(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
                 workspace: MrcaWorkspace | None = None, stream=None,
-                lb: torch.Tensor | None = None, ub: torch.Tensor | None = None):
+                lb: torch.Tensor | None = None, ub: torch.Tensor | None = None,
+                bits: int = 1, interval: int = 1):
     """All ordered pairs of MRCA-generation bounds on the device.
 
     counter: int32 CUDA tensor [n] (uint32 bit patterns); surface_words:
-    int32 CUDA tensor [n, S/32].  Returns (lb, ub) int32 CUDA tensors [n, n].
+    int32 CUDA tensor [n, S * bits / 32].  bits / interval: the annotation
+    scheme (Config.scheme).  Returns (lb, ub) int32 CUDA tensors [n, n].
     """
     if isinstance(kind, str):
         kind = KINDS[kind]
@@ -471,15 +507,22 @@ def mrca_bounds(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor
     if ub is None:
         ub = torch.empty((n, n), dtype=torch.int32, device=dev)
     lib = load_library()
-    _check(lib.hstrat_mrca_bounds(kind, S, n, _vp(counter.data_ptr()),
-                                  _vp(surface_words.data_ptr()), _vp(lb.data_ptr()),
-                                  _vp(ub.data_ptr()), _vp(workspace.ptr), workspace.nbytes,
-                                  _vp(_stream_handle(stream))))
+    if bits == 1 and interval == 1:
+        _check(lib.hstrat_mrca_bounds(kind, S, n, _vp(counter.data_ptr()),
+                                      _vp(surface_words.data_ptr()), _vp(lb.data_ptr()),
+                                      _vp(ub.data_ptr()), _vp(workspace.ptr), workspace.nbytes,
+                                      _vp(_stream_handle(stream))))
+    else:
+        sc = _scheme(kind, S, bits, interval)
+        _check(lib.hstrat_mrca_bounds_ex(ctypes.byref(sc), n, _vp(counter.data_ptr()),
+                                         _vp(surface_words.data_ptr()), _vp(lb.data_ptr()),
+                                         _vp(ub.data_ptr()), _vp(workspace.ptr),
+                                         workspace.nbytes, _vp(_stream_handle(stream))))
     return lb, ub
 
 
 def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
-                  stream=None) -> dict:
+                  stream=None, bits: int = 1, interval: int = 1) -> dict:
     """Trie reconstruction of annotations sharing a counter, on the device.
 
     Returns the six result words (blocking copy to the host) and the derived
@@ -501,9 +544,16 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
         need = int(lib.hstrat_phylo_workspace_bytes(S, n))
         buf, ptr = _aligned_bytes(need, dev)
         out = torch.zeros(6, dtype=torch.int64, device=dev)
-        _check(lib.hstrat_phylo_metrics(kind, S, n, _vp(counter.data_ptr()),
-                                        _vp(surface_words.data_ptr()), _vp(out.data_ptr()),
-                                        _vp(ptr), need, _vp(_stream_handle(stream))))
+        if bits == 1 and interval == 1:
+            _check(lib.hstrat_phylo_metrics(kind, S, n, _vp(counter.data_ptr()),
+                                            _vp(surface_words.data_ptr()), _vp(out.data_ptr()),
+                                            _vp(ptr), need, _vp(_stream_handle(stream))))
+        else:
+            sc = _scheme(kind, S, bits, interval)
+            _check(lib.hstrat_phylo_metrics_ex(ctypes.byref(sc), n, _vp(counter.data_ptr()),
+                                               _vp(surface_words.data_ptr()),
+                                               _vp(out.data_ptr()), _vp(ptr), need,
+                                               _vp(_stream_handle(stream))))
         w = out.cpu().numpy().view(np.uint64)
         del buf
     res = {"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),

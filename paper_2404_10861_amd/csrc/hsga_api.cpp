@@ -30,9 +30,8 @@ int hip_fail(hipError_t e, const char* what) {
 
 const char* last_error() { return g_last_error.c_str(); }
 
-Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens) {
+Carve carve(uint32_t I, uint32_t N, uint32_t SW, uint32_t gens) {
     const size_t A = (size_t)I * N;
-    const size_t SW = S / 32;
     Carve c;
     size_t off = 0;
     c.trait = off;   off += 2 * align_up(A * 4);
@@ -62,10 +61,17 @@ int validate(const ga_config* in, ga_config* out) {
         return fail(GA_EINVAL, "pop_per_island must be 1..64");
     const uint64_t A = (uint64_t)cfg->grid_w * cfg->grid_h * cfg->pop_per_island;
     if (A > (1ull << 30)) return fail(GA_EINVAL, "more than 2^30 agents");
-    if (cfg->surface_sites != 32 && cfg->surface_sites != 64)
-        return fail(GA_EINVAL, "surface_sites must be 32 or 64");
+    if (c.differentia_bits == 0) c.differentia_bits = 1;
+    if (c.ingest_interval == 0) c.ingest_interval = 1;
+    if (cfg->differentia_bits != 1 && cfg->differentia_bits != 8)
+        return fail(GA_EINVAL, "differentia_bits must be 1 or 8");
+    if (cfg->surface_sites * cfg->differentia_bits != 32 &&
+        cfg->surface_sites * cfg->differentia_bits != 64)
+        return fail(GA_EINVAL, "surface_sites * differentia_bits must be 32 or 64");
     if (cfg->surface_kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
-    if (cfg->fitness_model > GA_FLOAT_FITNESS) return fail(GA_EINVAL, "unknown fitness model");
+    if (cfg->fitness_model > GA_FOUNDER_TAG) return fail(GA_EINVAL, "unknown fitness model");
+    if (cfg->fitness_model == GA_FOUNDER_TAG && cfg->tournament_size != 0)
+        return fail(GA_EINVAL, "founder tags need neutral selection (tournament_size 0)");
     if (cfg->fitness_model == GA_INT_TRAIT) {
         if (cfg->tournament_size != 0 && cfg->tournament_size != 2)
             return fail(GA_EINVAL, "tournament_size must be 2 (tournament) or 0 (neutral)");
@@ -81,7 +87,6 @@ int validate(const ga_config* in, ga_config* out) {
             return fail(GA_EINVAL, "mutation scales must lie in [0, 2^20]");
     }
     if (cfg->migrants_per_island > 1) return fail(GA_EINVAL, "migrants_per_island must be 0 or 1");
-    if (cfg->reserved != 0 || cfg->reserved2 != 0) return fail(GA_EINVAL, "reserved must be 0");
     if (out) *out = c;
     return GA_OK;
 }
@@ -94,13 +99,13 @@ uint32_t default_agents_per_thread(uint32_t N) {
 
 int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipStream_t stream) {
     const uint32_t I = cfg->grid_w * cfg->grid_h;
-    const Carve c = carve(I, cfg->pop_per_island, cfg->surface_sites, gens);
+    const Carve c = carve(I, cfg->pop_per_island, surface_words(*cfg), gens);
     r->cfg = *cfg;
     r->I = I;
     r->N = cfg->pop_per_island;
     r->A = I * r->N;
     r->S = cfg->surface_sites;
-    r->SW = r->S / 32;
+    r->SW = surface_words(*cfg);
     r->stream = stream;
     const size_t A = r->A;
     for (int b = 0; b < 2; ++b) {
@@ -114,17 +119,19 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
     r->sites = reinterpret_cast<uint32_t*>(base + c.sites);
     r->gens = gens;
     r->T = 0;
-    r->horizon = hsga::horizon_of(cfg->surface_kind, r->S);
+    r->horizon = hsga::horizon_gen_of(cfg->surface_kind, r->S, cfg->ingest_interval);
     r->apt = default_agents_per_thread(r->N);
     r->block = r->apt == 4 ? 64u : 256u;   // small tiles: more workgroups in flight per CU
     r->timing = false;
     hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
-                                         r->layout, r->S, r->stream);
+                                         r->layout, r->S, cfg->fitness_model == GA_FOUNDER_TAG,
+                                         (uint32_t)cfg->seed, (uint32_t)(cfg->seed >> 32),
+                                         r->stream);
     if (e != hipSuccess) return hip_fail(e, "founders launch");
     return GA_OK;
 }
 
-hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k) {
+hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t tau0) {
     const ga_config& cfg = r->cfg;
     const int src = g & 1, dst = (g + 1) & 1;
     hsga::StepParams p;
@@ -136,7 +143,9 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k) {
     p.out_surf = r->surf[dst];
     p.ob_in = r->outbox[src];
     p.ob_out = r->outbox[dst];
-    p.site = r->sites + k;
+    const uint32_t n = cfg.ingest_interval;
+    p.site = g % n == 0 ? r->sites + (g / n - tau0) : nullptr;
+    p.diff_log2 = cfg.differentia_bits == 8 ? 3u : 0u;
     p.W = cfg.grid_w;
     p.H = cfg.grid_h;
     p.N = r->N;
@@ -145,7 +154,8 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k) {
     p.g = g;
     p.k0 = (uint32_t)cfg.seed;
     p.k1 = (uint32_t)(cfg.seed >> 32);
-    p.mut_thr = cfg.mut_threshold;
+    // founder tags: neutral, inherited unchanged
+    p.mut_thr = cfg.fitness_model == GA_FOUNDER_TAG ? 0u : cfg.mut_threshold;
     p.mut_lo = cfg.mut_lo;
     p.mut_span = (uint32_t)((int64_t)cfg.mut_hi - cfg.mut_lo + 1);
     p.has_inbox = (cfg.migrants_per_island != 0 && g > 0) ? 1u : 0u;
@@ -161,6 +171,7 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k) {
 
 uint32_t birth_model(const ga_config& cfg) {
     if (cfg.fitness_model == GA_FLOAT_FITNESS) return hsga::kBirthFloat;
+    if (cfg.fitness_model == GA_FOUNDER_TAG) return hsga::kBirthIntNeutral;
     return cfg.tournament_size == 2 ? hsga::kBirthIntTournament : hsga::kBirthIntNeutral;
 }
 
@@ -189,7 +200,7 @@ size_t ga_footprint_bytes(const ga_config* in, uint32_t max_gens_per_launch) {
     ga_config cfg;
     if (validate(in, &cfg) != GA_OK) return 0;
     const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
-    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, cfg.surface_sites, gens).total;
+    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, surface_words(cfg), gens).total;
 }
 
 int ga_create(const ga_config* in, void* dev_arena, size_t arena_bytes,
@@ -204,7 +215,7 @@ int ga_create(const ga_config* in, void* dev_arena, size_t arena_bytes,
     if ((uintptr_t)dev_arena % kAlign) return fail(GA_EINVAL, "arena not 256-byte aligned");
     const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
     const uint32_t I = cfg->grid_w * cfg->grid_h;
-    const Carve c = carve(I, cfg->pop_per_island, cfg->surface_sites, gens);
+    const Carve c = carve(I, cfg->pop_per_island, surface_words(*cfg), gens);
     if (arena_bytes < c.total)
         return fail(GA_ENOMEM, "arena of " + std::to_string(arena_bytes) + " bytes, need " +
                                    std::to_string(c.total));
@@ -231,8 +242,10 @@ int ga_step(ga_run* r, uint32_t n) {
     const bool mig = cfg.migrants_per_island != 0;
     while (n > 0) {
         const uint32_t G = n < r->gens ? n : r->gens;
+        const uint32_t tau0 = hsga::ingests_of(r->T, cfg.ingest_interval);
+        const uint32_t count = hsga::ingests_of(r->T + G, cfg.ingest_interval) - tau0;
         hipError_t e = hsga::launch_site_schedule(cfg.surface_kind, r->S, r->layout, r->sites,
-                                                  r->T, G, r->stream);
+                                                  tau0, count, r->stream);
         if (e != hipSuccess) return hip_fail(e, "site schedule launch");
         ga_run::Span span{nullptr, nullptr, G};
         if (r->timing) {
@@ -243,7 +256,7 @@ int ga_step(ga_run* r, uint32_t n) {
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
         for (uint32_t k = 0; k < G; ++k) {
-            const hsga::StepParams p = step_params(r, r->T + k, k);
+            const hsga::StepParams p = step_params(r, r->T + k, tau0);
             e = hsga::launch_step(p, r->SW, model, mig, r->apt, r->block, r->stream);
             if (e != hipSuccess) return hip_fail(e, "step launch");
         }
@@ -328,6 +341,9 @@ int ga_read_layout(ga_run* r, uint32_t* layout) {
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     e = hipMemcpy(layout, r->layout, (size_t)r->S * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy layout");
+    // the device layout holds ingest indices; report deposit generations
+    for (uint32_t k = 0; k < r->S; ++k)
+        if (layout[k] != GA_EMPTY_SITE) layout[k] *= r->cfg.ingest_interval;
     return GA_OK;
 }
 
@@ -361,41 +377,75 @@ size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n) {
     return hsga::MrcaWorkspace::bytes(S, n);
 }
 
-int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
-                       const uint32_t* surface_words, uint32_t* lb, uint32_t* ub, void* workspace,
-                       size_t workspace_bytes, void* hip_stream) {
-    if (kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
-    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+namespace {
+int check_scheme(const hstrat_scheme* sc, hsga::Scheme* out) {
+    if (!sc) return fail(GA_EINVAL, "scheme is NULL");
+    if (sc->kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
+    if (sc->differentia_bits != 1 && sc->differentia_bits != 8)
+        return fail(GA_EINVAL, "differentia_bits must be 1 or 8");
+    if (sc->sites * sc->differentia_bits != 32 && sc->sites * sc->differentia_bits != 64)
+        return fail(GA_EINVAL, "sites * differentia_bits must be 32 or 64");
+    if (sc->ingest_interval == 0) return fail(GA_EINVAL, "ingest_interval must be >= 1");
+    *out = hsga::Scheme{sc->kind, sc->sites, sc->differentia_bits, sc->ingest_interval};
+    return GA_OK;
+}
+}  // namespace
+
+int hstrat_mrca_bounds_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_t* counter,
+                          const uint32_t* surface_words, uint32_t* lb, uint32_t* ub,
+                          void* workspace, size_t workspace_bytes, void* hip_stream) {
+    hsga::Scheme sc;
+    int rc = check_scheme(scheme, &sc);
+    if (rc != GA_OK) return rc;
     if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
     if (!counter || !surface_words || !lb || !ub || !workspace)
         return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::MrcaWorkspace::bytes(S, n))
+    if (workspace_bytes < hsga::MrcaWorkspace::bytes(sc.S, n))
         return fail(GA_ENOMEM, "workspace too small");
-    hipError_t e = hsga::launch_mrca(kind, S, n, counter, surface_words, lb, ub, workspace,
+    hipError_t e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace,
                                      static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "mrca launch");
     return GA_OK;
+}
+
+int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                       const uint32_t* surface_words, uint32_t* lb, uint32_t* ub, void* workspace,
+                       size_t workspace_bytes, void* hip_stream) {
+    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+    const hstrat_scheme sc{kind, S, 1, 1};
+    return hstrat_mrca_bounds_ex(&sc, n, counter, surface_words, lb, ub, workspace,
+                                 workspace_bytes, hip_stream);
 }
 
 size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n) {
     return hsga::phylo_workspace_bytes(S, n);
 }
 
-int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
-                         const uint32_t* surface_words, uint64_t* out, void* workspace,
-                         size_t workspace_bytes, void* hip_stream) {
-    if (kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
-    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+int hstrat_phylo_metrics_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_t* counter,
+                            const uint32_t* surface_words, uint64_t* out, void* workspace,
+                            size_t workspace_bytes, void* hip_stream) {
+    hsga::Scheme sc;
+    int rc = check_scheme(scheme, &sc);
+    if (rc != GA_OK) return rc;
     if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
     if (!counter || !surface_words || !out || !workspace) return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::phylo_workspace_bytes(S, n))
+    if (workspace_bytes < hsga::phylo_workspace_bytes(sc.S, n))
         return fail(GA_ENOMEM, "workspace too small");
-    hipError_t e = hsga::launch_phylo(kind, S, n, counter, surface_words, out, workspace,
+    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace,
                                       static_cast<hipStream_t>(hip_stream));
     if (e != hipSuccess) return hip_fail(e, "phylo launch");
     return GA_OK;
+}
+
+int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                         const uint32_t* surface_words, uint64_t* out, void* workspace,
+                         size_t workspace_bytes, void* hip_stream) {
+    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+    const hstrat_scheme sc{kind, S, 1, 1};
+    return hstrat_phylo_metrics_ex(&sc, n, counter, surface_words, out, workspace,
+                                   workspace_bytes, hip_stream);
 }
 
 int hstrat_mrca_status(const void* workspace, void* hip_stream) {

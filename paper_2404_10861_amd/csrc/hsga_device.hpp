@@ -12,8 +12,8 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kSteady = 0, kTilted = 1, kHybrid = 2;
 // Fourth Philox counter word: what the draw is for.
 constexpr uint32_t kBirth = 0, kEmigrate = 1, kImmigrate = 2, kSample = 3;
-// Second block of a float-treatment birth.
-constexpr uint32_t kBirthB = 4;
+// Second block of a float-treatment birth; founder tags.
+constexpr uint32_t kBirthB = 4, kFounder = 5;
 // Outbox entry: dir, trait, counter, surface words (up to 2), padding.
 constexpr uint32_t kOutboxWords = 8;
 
@@ -278,8 +278,14 @@ __device__ __forceinline__ uint32_t lane_leave_time(uint32_t kind, uint32_t S, u
 }
 
 // The MRCA kernels replay layouts on the device, one placement per
-// generation; counters above this bound are refused.
+// ingest; annotations with more ingests than this are refused.
 constexpr uint32_t kMaxReplayGenerations = 1u << 24;
+
+// Deposits made by an annotation with counter T (generations 0, interval,
+// 2 interval, ... below T).
+__host__ __device__ inline uint32_t ingests_of(uint32_t T, uint32_t interval) {
+    return (uint32_t)(((uint64_t)T + interval - 1) / interval);
+}
 
 // Last deposit time the rule can place for (kind, S): tilted needs
 // bitlen(u+1) <= m; the 32-bit counter caps every kind at 2^32 - 2.
@@ -289,6 +295,13 @@ __host__ __device__ inline uint64_t horizon_of(uint32_t kind, uint32_t S) {
     if (kind == kTilted && S < 33) h = (1ull << S) - 2;
     if (kind == kHybrid && (S >> 1) < 33) h = 2 * ((1ull << (S >> 1)) - 2) + 2;
     return h < cap ? h : cap;
+}
+
+// Last generation a run may step (inclusive): the next deposit after it
+// would be past the rule's horizon, or the counter would overflow.
+__host__ __device__ inline uint64_t horizon_gen_of(uint32_t kind, uint32_t S, uint32_t interval) {
+    const uint64_t g = (horizon_of(kind, S) + 1) * (uint64_t)interval - 1;
+    return g < 0xfffffffeull ? g : 0xfffffffeull;
 }
 
 // Maps workgroup IDs so that consecutive logical tiles land on the same XCD

@@ -48,8 +48,14 @@ struct Carve {
     size_t trait, counter, surf, outbox, layout, sites, total;
 };
 
-// Byte offsets of each buffer of a run in its arena.
-Carve carve(uint32_t I, uint32_t N, uint32_t S, uint32_t gens);
+// Byte offsets of each buffer of a run in its arena (SW surface words per
+// agent).
+Carve carve(uint32_t I, uint32_t N, uint32_t SW, uint32_t gens);
+
+// Surface words per agent of a validated config.
+inline uint32_t surface_words(const ga_config& c) {
+    return c.surface_sites * c.differentia_bits / 32;
+}
 
 // GA_OK, or GA_EINVAL with the reason in ga_last_error().
 // Check a caller's config (either accepted struct_size) and, if out is not
@@ -62,8 +68,9 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
 
 inline uint32_t tile_islands(uint32_t block, uint32_t apt, uint32_t N) { return block * apt / N; }
 
-// Parameters of generation g (schedule slot k) of a run.
-hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t k);
+// Parameters of generation g of a run whose current site schedule starts
+// at ingest tau0.
+hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t tau0);
 
 // hsga::BirthModel of a configuration.
 uint32_t birth_model(const ga_config& cfg);

@@ -7,6 +7,16 @@
 
 namespace hsga {
 
+// An annotation scheme (Distributed Phylogenetic Tracking: one-bit or byte
+// differentiae; Results, Surface Algorithm Benchmark: annotations updated
+// only every n-th generation): surface kind, S sites of `bits` bits (1 or
+// 8) filling S * bits / 32 words, one deposit every `interval` generations.
+// The site rule runs in ingest units: item tau is deposited at generation
+// tau * interval, and layouts hold tau.
+struct Scheme {
+    uint32_t kind, S, bits, interval;
+};
+
 // How a birth picks its parent and changes the trait word.
 enum BirthModel : uint32_t {
     kBirthIntNeutral = 0,      // integer trait, one uniform draw
@@ -23,7 +33,7 @@ struct StepParams {
     uint32_t* out_surf;
     const uint32_t* ob_in;     // I entries of 8 words (read at generation g)
     uint32_t* ob_out;          // I entries of 8 words (written for g + 1)
-    const uint32_t* site;      // this generation's surface site
+    const uint32_t* site;      // this generation's surface site; nullptr: no deposit
     uint32_t W, H, N, I, A;
     uint32_t g;
     uint32_t k0, k1;           // Philox key (seed)
@@ -33,6 +43,7 @@ struct StepParams {
     uint32_t has_inbox;        // outboxes of generation g exist
     uint32_t tile_isl;         // islands per workgroup tile
     uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
+    uint32_t diff_log2;        // log2 of the differentia width: 0 (bit) or 3 (byte)
     uint32_t tour;             // float model: tournament draws, 1..5
     uint32_t del_thr, ben_thr; // float model: mutation class thresholds
     float del_sigma, ben_sigma;
@@ -60,6 +71,8 @@ struct BatchRun {
                                // bits 4..5: log2(agents per thread)
     uint32_t tour, del_thr, ben_thr;
     float del_sigma, ben_sigma;
+    uint32_t interval;         // one deposit every `interval` generations
+    uint32_t diff_log2;        // 0: one-bit differentiae, 3: bytes
     uint32_t tile_isl, div_magic;
     uint32_t tile0;            // first tile of the run in the batched grid
 };
@@ -69,11 +82,15 @@ constexpr uint32_t kMaxBatchRuns = 256;
 // LDS bytes of one step workgroup.
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW);
 
+// tags: founders' trait words are random 16-bit founder tags (key k0, k1).
 hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,
-                           uint32_t SW, uint32_t* layout, uint32_t S, hipStream_t stream);
+                           uint32_t SW, uint32_t* layout, uint32_t S, bool tags, uint32_t k0,
+                           uint32_t k1, hipStream_t stream);
 
+// Sites of ingests tau0 .. tau0 + count - 1 (ingest units), from the run's
+// layout, which is advanced past them.
 hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
-                                uint32_t T0, uint32_t G, hipStream_t stream);
+                                uint32_t tau0, uint32_t count, hipStream_t stream);
 
 // agents_per_thread (1, 2 or 4) must divide N; tile_isl * N <= block_threads *
 // agents_per_thread.
@@ -106,10 +123,10 @@ struct MrcaWorkspace {
 };
 
 size_t phylo_workspace_bytes(uint32_t S, uint32_t n);
-hipError_t launch_phylo(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+hipError_t launch_phylo(const Scheme& sc, uint32_t n, const uint32_t* counter,
                         const uint32_t* surf, uint64_t* out, void* workspace, hipStream_t stream);
 
-hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+hipError_t launch_mrca(const Scheme& sc, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
                        hipStream_t stream);
 

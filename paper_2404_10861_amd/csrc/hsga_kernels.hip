@@ -13,16 +13,20 @@ namespace hsga {
 // ---------------------------------------------------------------------------
 // Founders (Genome Model; Distributed Phylogenetic Tracking): trait 0,
 // counter 0, every site 0, and an empty layout.  Founders carry no
-// differentia; item g is deposited by generation g's births.
+// differentia; item g is deposited by generation g's births.  With founder
+// tags (Results, Clade Reconstruction Trial) the trait word is instead a
+// random 16-bit identifier: the low half of the first word of Philox block
+// (a, 0, 0, founder).
 __global__ __launch_bounds__(256) void founders_kernel(uint32_t* __restrict__ trait,
                                                       uint32_t* __restrict__ counter,
                                                       uint32_t* __restrict__ surf, uint32_t A,
                                                       uint32_t SW, uint32_t* __restrict__ layout,
-                                                      uint32_t S) {
+                                                      uint32_t S, uint32_t tags, uint32_t k0,
+                                                      uint32_t k1) {
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t a = first; a < A; a += stride) {
-        trait[a] = 0u;
+        trait[a] = tags ? philox4x32_10(make_uint4(a, 0u, 0u, kFounder), k0, k1).x & 0xffffu : 0u;
         counter[a] = 0u;
         for (uint32_t w = 0; w < SW; ++w) surf[(size_t)w * A + a] = 0u;
     }
@@ -30,12 +34,13 @@ __global__ __launch_bounds__(256) void founders_kernel(uint32_t* __restrict__ tr
 }
 
 hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,
-                           uint32_t SW, uint32_t* layout, uint32_t S, hipStream_t stream) {
+                           uint32_t SW, uint32_t* layout, uint32_t S, bool tags, uint32_t k0,
+                           uint32_t k1, hipStream_t stream) {
     uint32_t blocks = (A + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(founders_kernel, dim3(blocks), dim3(256), 0, stream, trait, counter, surf,
-                       A, SW, layout, S);
+                       A, SW, layout, S, tags ? 1u : 0u, k0, k1);
     return hipGetLastError();
 }
 
@@ -44,16 +49,17 @@ hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, u
 // counter T, so the surface site is the same for the whole population and
 // is computed once per generation (Results, Surface Algorithm Benchmark:
 // synchronous simulations can cache placements for a whole
-// subpopulation).  One wavefront, lane k = site k: for T = T0 .. T0+G-1
-// the placement is a ballot over the lanes whose item left the target,
-// then a bit scan; the run's layout is carried in registers and written
-// back at the end.
+// subpopulation).  One wavefront, lane k = site k: for ingests
+// tau = tau0 .. tau0+count-1 (ingest units; every generation when the
+// interval is 1) the placement is a ballot over the lanes whose item left
+// the target, then a bit scan; the run's layout is carried in registers and
+// written back at the end.
 __device__ __forceinline__ void schedule_sites(uint32_t kind, uint32_t S, uint32_t* layout,
-                                               uint32_t* sites, uint32_t T0, uint32_t G) {
+                                               uint32_t* sites, uint32_t tau0, uint32_t count) {
     const uint32_t lane = threadIdx.x;
     uint32_t held = lane < S ? layout[lane] : kEmpty;
     uint32_t leave = lane_leave_time(kind, S, lane, held);
-    place_items(kind, S, T0, G, held, leave, lane,
+    place_items(kind, S, tau0, count, held, leave, lane,
                 [&](uint32_t k, int site) { sites[k] = (uint32_t)site; });
     if (lane < S) layout[lane] = held;
 }
@@ -61,14 +67,15 @@ __device__ __forceinline__ void schedule_sites(uint32_t kind, uint32_t S, uint32
 __global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32_t S,
                                                            uint32_t* __restrict__ layout,
                                                            uint32_t* __restrict__ sites,
-                                                           uint32_t T0, uint32_t G) {
-    schedule_sites(kind, S, layout, sites, T0, G);
+                                                           uint32_t tau0, uint32_t count) {
+    schedule_sites(kind, S, layout, sites, tau0, count);
 }
 
 hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
-                                uint32_t T0, uint32_t G, hipStream_t stream) {
+                                uint32_t tau0, uint32_t count, hipStream_t stream) {
+    if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(site_schedule_kernel, dim3(1), dim3(64), 0, stream, kind, S, layout,
-                       sites, T0, G);
+                       sites, tau0, count);
     return hipGetLastError();
 }
 
@@ -256,8 +263,15 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     }
 
     // 3. births
-    const uint32_t site = *p.site;
-    const uint32_t site_word = site >> 5, site_shift = site & 31u;
+    // this generation's deposit: word and bit offset of the site, none
+    // (no word matches) between ingests
+    uint32_t site_word = 0xffu, site_shift = 0u;
+    if (p.site) {
+        const uint32_t site = *p.site;
+        site_word = site >> (5u - p.diff_log2);
+        site_shift = (site << p.diff_log2) & 31u;
+    }
+    const uint32_t diff_mask = p.diff_log2 ? 0xffu : 1u;
     if (!mine) return;
     Lanes<APT> ctr, ccn, csf[SW];
 #pragma unroll
@@ -273,7 +287,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         if constexpr (BM == kBirthFloat) {
             // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x), the
             // first of maximal fitness winning; mutation class from v.y,
-            // |Z| from v.z and v.w, differentia bit 0 of v.w
+            // |Z| from v.z and v.w, differentia the low bits of v.w
             const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
             float best = __uint_as_float(l_trait[par]);
             const uint32_t words[4] = {r.y, r.z, r.w, v.x};
@@ -293,7 +307,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
             ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
                                                                      p.ben_sigma, v.z, v.w))
                                     : __float_as_uint(best);
-            bit = v.w & 1u;
+            bit = v.w & diff_mask;
         } else {
             uint32_t ptrait = l_trait[par];
             if constexpr (BM == kBirthIntTournament) {
@@ -307,14 +321,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
             const uint32_t delta =
                 r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo) : 0u;
             ctr.v[q] = ptrait + delta;
-            bit = r.w & 1u;
+            bit = r.w & diff_mask;
         }
         ccn.v[q] = l_count[par] + 1u;
 #pragma unroll
         for (int w = 0; w < SW; ++w) {
             const uint32_t word = l_surf[w * TA + par];
             csf[w].v[q] = (uint32_t)w == site_word
-                              ? (word & ~(1u << site_shift)) | (bit << site_shift)
+                              ? (word & ~(diff_mask << site_shift)) | (bit << site_shift)
                               : word;
         }
         if (MIGR) {
@@ -394,7 +408,9 @@ hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, b
 __global__ __launch_bounds__(64) void batch_site_schedule_kernel(
     const BatchRun* __restrict__ runs) {
     const BatchRun& R = runs[blockIdx.x];
-    schedule_sites(R.kind, R.S, R.layout, R.sites, R.T0, R.gens);
+    const uint32_t tau0 = ingests_of(R.T0, R.interval);
+    const uint32_t count = ingests_of(R.T0 + R.gens, R.interval) - tau0;
+    schedule_sites(R.kind, R.S, R.layout, R.sites, tau0, count);
 }
 
 hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipStream_t stream) {
@@ -454,7 +470,11 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.out_surf = R.surf[dst];
     p.ob_in = R.outbox[src];
     p.ob_out = R.outbox[dst];
-    p.site = R.sites + k;
+    // deposit iff g is a multiple of the interval; its site is entry
+    // g / interval - tau0 of this batch's schedule
+    p.site = g % R.interval == 0 ? R.sites + (g / R.interval - ingests_of(R.T0, R.interval))
+                                 : nullptr;
+    p.diff_log2 = R.diff_log2;
     p.W = R.W; p.H = R.H; p.N = R.N; p.I = R.I; p.A = R.A;
     p.g = g;
     p.k0 = R.k0; p.k1 = R.k1;
@@ -575,19 +595,22 @@ __device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uin
 }
 
 // One wavefront: classify the counters; when all are equal, replay the
-// shared layout once, order its sites by deposit time and tabulate the
-// bounds for every possible first-mismatch rank.
-__global__ __launch_bounds__(64) void mrca_prepare_kernel(uint32_t kind, uint32_t S, uint32_t n,
+// shared layout once (in ingest units), order its sites by deposit time and
+// tabulate the bounds, in generations, for every possible first-mismatch
+// rank.
+__global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
                                                          const uint32_t* __restrict__ counter,
                                                          uint32_t* __restrict__ ws) {
     const uint32_t lane = threadIdx.x;
+    const uint32_t S = sc.S;
     const uint32_t T0 = counter[0];
-    const uint64_t hz = horizon_of(kind, S);
+    const uint64_t hz = horizon_of(sc.kind, S);
     bool same = true, past = false;
     for (uint32_t k = lane; k < n; k += 64) {
         const uint32_t c = counter[k];
+        const uint32_t ing = ingests_of(c, sc.interval);
         same = same && c == T0;
-        past = past || c > kMaxReplayGenerations || (c > 0 && (uint64_t)(c - 1) > hz);
+        past = past || ing > kMaxReplayGenerations || (ing > 0 && (uint64_t)(ing - 1) > hz);
     }
     const bool any_past = __ballot(past) != 0;
     const bool all_same = __ballot(!same) == 0;
@@ -598,14 +621,15 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(uint32_t kind, uint32_
         }
         return;
     }
-    const uint32_t held = replay_layout(kind, S, T0, lane);
+    const uint32_t held = replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
     const uint32_t rank = time_rank(held, lane, S);
     const uint32_t F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
     __shared__ uint32_t times[64];
     if (lane < S) {
-        times[rank] = held;
+        const uint32_t gen = held == kEmpty ? kEmpty : held * sc.interval;   // deposit generation
+        times[rank] = gen;
         ws[kWsPerm + rank] = lane;
-        ws[kWsTimes + rank] = held;
+        ws[kWsTimes + rank] = gen;
     }
     __syncthreads();
     // first mismatch at rank r: ub = times[r], lb = times[r-1] + 1 (0 if r = 0);
@@ -621,8 +645,17 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(uint32_t kind, uint32_
     }
 }
 
-// Fast route: each annotation's bits in ascending-time order, packed in 64 bits.
-__global__ __launch_bounds__(256) void mrca_rank_kernel(uint32_t S, uint32_t n,
+// The annotation's surface words as one 64-bit value.
+__device__ __forceinline__ uint64_t surface64(const uint32_t* __restrict__ surf, uint32_t SW,
+                                              uint32_t a) {
+    return SW == 2 ? ((uint64_t)surf[(size_t)a * 2 + 1] << 32) | surf[(size_t)a * 2]
+                   : (uint64_t)surf[a];
+}
+
+// Fast route: each annotation's differentiae in ascending-time order, packed
+// in 64 bits (rank r at bit r for one-bit differentiae, at byte r for bytes).
+__global__ __launch_bounds__(256) void mrca_rank_kernel(uint32_t S, uint32_t diff_log2,
+                                                       uint32_t n,
                                                        const uint32_t* __restrict__ surf,
                                                        const uint32_t* __restrict__ ws,
                                                        uint64_t* __restrict__ ranked) {
@@ -633,19 +666,19 @@ __global__ __launch_bounds__(256) void mrca_rank_kernel(uint32_t S, uint32_t n,
     const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
     const uint32_t F = ws[kWsF];
-    const uint32_t SW = S >> 5;
-    const uint64_t s = SW == 2 ? ((uint64_t)surf[(size_t)a * 2 + 1] << 32) | surf[(size_t)a * 2]
-                               : (uint64_t)surf[a];
-    uint64_t bits = 0;
-    for (uint32_t r = 0; r < F; ++r) bits |= ((s >> perm[r]) & 1ull) << r;
-    ranked[a] = bits;
+    const uint64_t s = surface64(surf, (S << diff_log2) >> 5, a);
+    const uint64_t mask = diff_log2 ? 0xffull : 1ull;
+    uint64_t packed = 0;
+    for (uint32_t r = 0; r < F; ++r)
+        packed |= ((s >> (perm[r] << diff_log2)) & mask) << (r << diff_log2);
+    ranked[a] = packed;
 }
 
-// Fast route, all ordered pairs: x = P_a xor P_b; the first set bit is the
-// rank of the first mismatch.  Each thread owns 4 adjacent columns of 4
+// Fast route, all ordered pairs: x = P_a xor P_b; the first set bit gives
+// the rank of the first mismatch (its bit index, or its byte index).  Each thread owns 4 adjacent columns of 4
 // rows, so stores are 16-byte and a wavefront writes 1 KiB contiguously.
 constexpr uint32_t kPairRows = 4;
-__global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n,
+__global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n, uint32_t diff_log2,
                                                            const uint64_t* __restrict__ ranked,
                                                            const uint32_t* __restrict__ ws,
                                                            uint32_t* __restrict__ lb,
@@ -672,7 +705,8 @@ __global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint64_t x = pa ^ pb[q];
-            const uint32_t idx = x ? (uint32_t)(__ffsll((long long)x) - 1) : 64u;
+            const uint32_t idx =
+                x ? ((uint32_t)(__ffsll((long long)x) - 1) >> diff_log2) : 64u;
             l[q] = lbt[idx];
             u[q] = ubt[idx];
         }
@@ -690,9 +724,9 @@ __global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n,
 }
 
 // General route (counters differ): one wavefront per annotation replays its
-// own layout and stores its retained times in ascending order with their
-// sites.
-__global__ __launch_bounds__(64) void mrca_layouts_kernel(uint32_t kind, uint32_t S, uint32_t n,
+// own layout and stores its retained deposit generations in ascending order
+// with their sites.
+__global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc, uint32_t n,
                                                          const uint32_t* __restrict__ counter,
                                                          const uint32_t* __restrict__ ws,
                                                          uint32_t* __restrict__ times,
@@ -700,18 +734,19 @@ __global__ __launch_bounds__(64) void mrca_layouts_kernel(uint32_t kind, uint32_
     if (ws[kWsStatus] != kWsStatusMixed) return;
     const uint32_t a = blockIdx.x;
     const uint32_t lane = threadIdx.x;
-    const uint32_t held = replay_layout(kind, S, counter[a], lane);
+    const uint32_t S = sc.S;
+    const uint32_t held = replay_layout(sc.kind, S, ingests_of(counter[a], sc.interval), lane);
     const uint32_t rank = time_rank(held, lane, S);
     if (lane < S) {
-        times[(size_t)a * S + rank] = held;
+        times[(size_t)a * S + rank] = held == kEmpty ? kEmpty : held * sc.interval;
         sites[(size_t)a * S + rank] = (uint8_t)lane;
     }
 }
 
 // General route, all ordered pairs: merge the two ascending time lists,
-// comparing bits on common times until the first mismatch.
+// comparing differentiae on common times until the first mismatch.
 __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
-    uint32_t S, uint32_t n, const uint32_t* __restrict__ counter,
+    uint32_t S, uint32_t diff_log2, uint32_t n, const uint32_t* __restrict__ counter,
     const uint32_t* __restrict__ surf, const uint32_t* __restrict__ times,
     const uint8_t* __restrict__ sites, const uint32_t* __restrict__ ws, uint32_t* __restrict__ lb,
     uint32_t* __restrict__ ub) {
@@ -719,11 +754,10 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t a = blockIdx.y;
     if (b >= n) return;
-    const uint32_t SW = S >> 5;
-    const uint64_t sa = SW == 2 ? ((uint64_t)surf[(size_t)a * 2 + 1] << 32) | surf[(size_t)a * 2]
-                                : (uint64_t)surf[a];
-    const uint64_t sb = SW == 2 ? ((uint64_t)surf[(size_t)b * 2 + 1] << 32) | surf[(size_t)b * 2]
-                                : (uint64_t)surf[b];
+    const uint32_t SW = (S << diff_log2) >> 5;
+    const uint64_t sa = surface64(surf, SW, a);
+    const uint64_t sb = surface64(surf, SW, b);
+    const uint64_t mask = diff_log2 ? 0xffull : 1ull;
     const uint32_t* ta = times + (size_t)a * S;
     const uint32_t* tb = times + (size_t)b * S;
     const uint8_t* ka = sites + (size_t)a * S;
@@ -735,7 +769,8 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
         const uint32_t x = ta[i], y = tb[k];
         if (x == kEmpty || y == kEmpty) break;
         if (x == y) {
-            if (((sa >> ka[i]) & 1ull) != ((sb >> kb[k]) & 1ull)) {
+            if (((sa >> ((uint32_t)ka[i] << diff_log2)) & mask) !=
+                ((sb >> ((uint32_t)kb[k] << diff_log2)) & mask)) {
                 mismatch = true;
                 tstar = x;
                 break;
@@ -760,12 +795,16 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
 // Trie reconstruction and phylometrics of annotations sharing a counter
 // (Distributed Phylogenetic Tracking: reconstruction is a trie over the
 // record of differentiae; Results, On-hardware Trial: sum branch length and
-// mean evolutionary distinctiveness).  Annotations read as their bits in
-// ascending deposit time are sorted lexicographically; neighbours in that
-// order share a prefix of d_i = LCP(i, i+1) retained items, and the trie's
-// branching nodes are exactly these boundaries (runs of identical
-// annotations give one node at T).  A node at depth d sits at time
-// tau(d) = t_d (the MRCA upper bound of the pairs it separates), tau(F) = T.
+// mean evolutionary distinctiveness).  Annotations read as their
+// differentiae in ascending deposit time are sorted lexicographically;
+// neighbours in that order share a prefix of d_i = LCP(i, i+1) retained
+// items, and the trie's branching nodes are exactly these boundaries.  A
+// node at depth d sits at time tau(d) = t_d (the MRCA upper bound of the
+// pairs it separates), tau(F) = T (identical annotations).
+//   boundaries of one node: equal depth d with nothing shallower between
+//     (a many-way split, or a run of identical annotations); the node
+//     starts at the boundary whose nearest not-deeper left neighbour is
+//     strictly shallower;
 //   leaf i hangs from the deeper of boundaries i-1, i;
 //   a node hangs from the deeper of its nearest strictly shallower
 //   boundaries on either side (none: the root);
@@ -774,7 +813,10 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
 //   minimum, counted by nearest-smaller spans.
 constexpr uint32_t kPhyloOutWords = 6;   // sbl, pair sum, root, internal, status, n
 
+// Sort keys: rank 0 most significant (bit-reversed for one-bit
+// differentiae, byte-reversed for bytes).
 __global__ __launch_bounds__(256) void phylo_keys_kernel(uint32_t n, uint32_t npad,
+                                                        uint32_t diff_log2,
                                                         const uint64_t* __restrict__ ranked,
                                                         const uint32_t* __restrict__ ws,
                                                         uint64_t* __restrict__ keys,
@@ -782,7 +824,9 @@ __global__ __launch_bounds__(256) void phylo_keys_kernel(uint32_t n, uint32_t np
     if (ws[kWsStatus] != 0) return;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npad) return;
-    keys[i] = i < n ? __brevll(ranked[i]) : ~0ull;   // bit of rank r at position 63 - r
+    uint64_t key = ~0ull;
+    if (i < n) key = diff_log2 ? __builtin_bswap64(ranked[i]) : __brevll(ranked[i]);
+    keys[i] = key;
     idx[i] = i < n ? i : 0xffffffffu;
 }
 
@@ -812,14 +856,19 @@ __global__ __launch_bounds__(1024) void phylo_sort_kernel(uint32_t npad,
     }
 }
 
-__global__ __launch_bounds__(256) void phylo_metrics_kernel(uint32_t n,
+struct PhyloScratch {
+    uint8_t* depth;        // n - 1 boundary depths
+    uint32_t* left;        // nearest strictly shallower boundary on the left
+    uint32_t* left_le;     // nearest not-deeper boundary on the left
+    uint32_t* right;       // nearest not-deeper boundary on the right (m if none)
+    uint32_t* rstrict;     // nearest strictly shallower boundary on the right
+    uint32_t* stack;
+};
+
+__global__ __launch_bounds__(256) void phylo_metrics_kernel(uint32_t n, uint32_t diff_log2,
                                                            const uint32_t* __restrict__ ws,
                                                            const uint64_t* __restrict__ keys,
-                                                           uint8_t* __restrict__ depth,
-                                                           uint32_t* __restrict__ left,
-                                                           uint32_t* __restrict__ right,
-                                                           uint32_t* __restrict__ rstrict,
-                                                           uint32_t* __restrict__ stack,
+                                                           PhyloScratch sc,
                                                            uint64_t* __restrict__ out) {
     const uint32_t status = ws[kWsStatus];
     if (status != 0) {
@@ -833,32 +882,41 @@ __global__ __launch_bounds__(256) void phylo_metrics_kernel(uint32_t n,
     const uint32_t T = ws[kWsT], F = ws[kWsF];
     const uint32_t* times = ws + kWsTimes;
     const uint32_t m = n - 1;                              // boundaries
+    uint8_t* depth = sc.depth;
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
         const uint64_t x = keys[i] ^ keys[i + 1];
-        const uint32_t d = x ? (uint32_t)__clzll((long long)x) : 64u;
+        const uint32_t d = x ? ((uint32_t)__clzll((long long)x) >> diff_log2) : 64u;
         depth[i] = (uint8_t)(d < F ? d : F);
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
     auto tau = [&](uint32_t d) -> uint64_t { return d < F ? times[d] : T; };
-    // nearest boundary to the left with a strictly smaller depth
+    constexpr uint32_t kNone = 0xffffffffu;
+    uint32_t* stack = sc.stack;
+    // nearest to the left: strictly shallower, and not deeper
     uint32_t top = 0;
     for (uint32_t b = 0; b < m; ++b) {
         while (top && depth[stack[top - 1]] >= depth[b]) --top;
-        left[b] = top ? stack[top - 1] : 0xffffffffu;
+        sc.left[b] = top ? stack[top - 1] : kNone;
         stack[top++] = b;
     }
-    // nearest to the right: strictly smaller, and smaller or equal
+    top = 0;
+    for (uint32_t b = 0; b < m; ++b) {
+        while (top && depth[stack[top - 1]] > depth[b]) --top;
+        sc.left_le[b] = top ? stack[top - 1] : kNone;
+        stack[top++] = b;
+    }
+    // nearest to the right: strictly shallower, and not deeper
     top = 0;
     for (uint32_t b = m; b-- > 0;) {
         while (top && depth[stack[top - 1]] >= depth[b]) --top;
-        rstrict[b] = top ? stack[top - 1] : 0xffffffffu;
+        sc.rstrict[b] = top ? stack[top - 1] : kNone;
         stack[top++] = b;
     }
     top = 0;
     for (uint32_t b = m; b-- > 0;) {
         while (top && depth[stack[top - 1]] > depth[b]) --top;
-        right[b] = top ? stack[top - 1] : m;
+        sc.right[b] = top ? stack[top - 1] : m;
         stack[top++] = b;
     }
     uint64_t sbl = 0, pairs = 0, internal = 0;
@@ -867,17 +925,20 @@ __global__ __launch_bounds__(256) void phylo_metrics_kernel(uint32_t n,
         const uint32_t d = depth[b];
         dmin = d < dmin ? d : dmin;
         // pairs meeting at b (b the rightmost shallowest boundary between them)
-        const uint64_t nl = (uint64_t)b - (left[b] == 0xffffffffu ? (uint64_t)-1 : left[b]);
-        const uint64_t nr = (uint64_t)right[b] - b;
+        const uint32_t L = sc.left[b];
+        const uint64_t nl = (uint64_t)b - (L == kNone ? (uint64_t)-1 : L);
+        const uint64_t nr = (uint64_t)sc.right[b] - b;
         pairs += (T - tau(d)) * nl * nr;
-        // one node per run of equal depth (only identical annotations repeat)
-        if (b > 0 && depth[b - 1] == d) continue;
+        // a node starts here unless an equal-depth boundary of the same node
+        // lies to the left with nothing shallower between
+        const uint32_t Lq = sc.left_le[b];
+        if (Lq != kNone && depth[Lq] == d) continue;
         ++internal;
-        const uint32_t L = left[b], R = rstrict[b];
-        if (L == 0xffffffffu && R == 0xffffffffu) continue;   // the root
+        const uint32_t R = sc.rstrict[b];
+        if (L == kNone && R == kNone) continue;   // the root
         uint32_t pd;
-        if (L == 0xffffffffu) pd = depth[R];
-        else if (R == 0xffffffffu) pd = depth[L];
+        if (L == kNone) pd = depth[R];
+        else if (R == kNone) pd = depth[L];
         else pd = depth[L] > depth[R] ? depth[L] : depth[R];
         sbl += tau(d) - tau(pd);
     }
@@ -900,40 +961,45 @@ size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
     size_t npad = 1;
     while (npad < n) npad <<= 1;
     const size_t a = (MrcaWorkspace::bytes(S, n) + 255) & ~(size_t)255;
-    return a + npad * 8 + npad * 4 + (size_t)n * (1 + 4 * 4) + 1024;
+    return a + npad * 8 + npad * 4 + (size_t)n * (1 + 5 * 4) + 1024;
 }
 
-hipError_t launch_phylo(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
                         const uint32_t* surf, uint64_t* out, void* workspace,
                         hipStream_t stream) {
+    const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
     uint8_t* base = static_cast<uint8_t*>(workspace);
     uint32_t* ws = reinterpret_cast<uint32_t*>(base);
     uint64_t* ranked = reinterpret_cast<uint64_t*>(base + MrcaWorkspace::kHeader);
     size_t npad = 1;
     while (npad < n) npad <<= 1;
-    size_t off = (MrcaWorkspace::bytes(S, n) + 255) & ~(size_t)255;
+    size_t off = (MrcaWorkspace::bytes(scm.S, n) + 255) & ~(size_t)255;
     uint64_t* keys = reinterpret_cast<uint64_t*>(base + off);   off += npad * 8;
     uint32_t* idx = reinterpret_cast<uint32_t*>(base + off);    off += npad * 4;
-    uint32_t* left = reinterpret_cast<uint32_t*>(base + off);   off += (size_t)n * 4;
-    uint32_t* right = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
-    uint32_t* rstr = reinterpret_cast<uint32_t*>(base + off);   off += (size_t)n * 4;
-    uint32_t* stack = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
-    uint8_t* depth = base + off;
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, kind, S, n, counter, ws);
-    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S, n, surf,
-                       ws, ranked);
+    PhyloScratch sc;
+    sc.left = reinterpret_cast<uint32_t*>(base + off);     off += (size_t)n * 4;
+    sc.left_le = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
+    sc.right = reinterpret_cast<uint32_t*>(base + off);    off += (size_t)n * 4;
+    sc.rstrict = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
+    sc.stack = reinterpret_cast<uint32_t*>(base + off);    off += (size_t)n * 4;
+    sc.depth = base + off;
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
+    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, scm.S,
+                       diff_log2, n, surf, ws, ranked);
     hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
-                       stream, n, (uint32_t)npad, ranked, ws, keys, idx);
+                       stream, n, (uint32_t)npad, diff_log2, ranked, ws, keys, idx);
     hipLaunchKernelGGL(phylo_sort_kernel, dim3(1), dim3(1024), 0, stream, (uint32_t)npad, ws,
                        keys, idx);
-    hipLaunchKernelGGL(phylo_metrics_kernel, dim3(1), dim3(256), 0, stream, n, ws, keys, depth,
-                       left, right, rstr, stack, out);
+    hipLaunchKernelGGL(phylo_metrics_kernel, dim3(1), dim3(256), 0, stream, n, diff_log2, ws,
+                       keys, sc, out);
     return hipGetLastError();
 }
 
-hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
                        hipStream_t stream) {
+    const uint32_t S = scm.S;
+    const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
     uint8_t* base = static_cast<uint8_t*>(workspace);
     uint32_t* ws = reinterpret_cast<uint32_t*>(base);
     uint64_t* ranked = reinterpret_cast<uint64_t*>(base + MrcaWorkspace::kHeader);
@@ -942,16 +1008,15 @@ hipError_t launch_mrca(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* co
     const size_t times_bytes = ((size_t)n * S * 4 + 255) & ~(size_t)255;
     uint8_t* sites = base + MrcaWorkspace::kHeader + ranked_bytes + times_bytes;
 
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, kind, S, n, counter,
-                       ws);
-    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S, n, surf,
-                       ws, ranked);
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
+    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S,
+                       diff_log2, n, surf, ws, ranked);
     hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
-                       dim3(256), 0, stream, n, ranked, ws, lb, ub);
-    hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, kind, S, n, counter, ws,
+                       dim3(256), 0, stream, n, diff_log2, ranked, ws, lb, ub);
+    hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, scm, n, counter, ws,
                        times, sites);
     hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, n), dim3(256), 0, stream,
-                       S, n, counter, surf, times, sites, ws, lb, ub);
+                       S, diff_log2, n, counter, surf, times, sites, ws, lb, ub);
     return hipGetLastError();
 }
 

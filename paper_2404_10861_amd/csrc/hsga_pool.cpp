@@ -180,7 +180,7 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
 size_t ga_pool_footprint(const ga_pool* p, const ga_config* in) {
     ga_config cfg;
     if (!p || validate(in, &cfg) != GA_OK) return 0;
-    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, cfg.surface_sites, p->gens).total;
+    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, surface_words(cfg), p->gens).total;
 }
 
 int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint32_t* id) {
@@ -190,7 +190,8 @@ int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint3
     const ga_config* cfg = &cfg_copy;
     if (rc != GA_OK) return rc;
     if (n_generations == 0) return fail(GA_EINVAL, "a run needs at least one generation");
-    if ((uint64_t)n_generations - 1 > hsga::horizon_of(cfg->surface_kind, cfg->surface_sites))
+    if ((uint64_t)n_generations - 1 >
+        hsga::horizon_gen_of(cfg->surface_kind, cfg->surface_sites, cfg->ingest_interval))
         return fail(GA_EHORIZON, "generation count past the site rule's horizon");
     uint32_t slot = p->max_runs;
     for (uint32_t s = 0; s < p->max_runs; ++s)
@@ -242,7 +243,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         ga_run& r = s.run;
         r.block = p->block;
         const uint32_t g = std::min(G, s.target - r.T);
-        const hsga::StepParams sp = step_params(&r, r.T, 0);
+        const hsga::StepParams sp = step_params(&r, r.T, hsga::ingests_of(r.T, r.cfg.ingest_interval));
         hsga::BatchRun& b = p->h_table[i];
         for (int q = 0; q < 2; ++q) {
             b.trait[q] = r.trait[q];
@@ -264,6 +265,8 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         b.tour = sp.tour;
         b.del_thr = sp.del_thr; b.ben_thr = sp.ben_thr;
         b.del_sigma = sp.del_sigma; b.ben_sigma = sp.ben_sigma;
+        b.interval = r.cfg.ingest_interval;
+        b.diff_log2 = sp.diff_log2;
         b.tile_isl = sp.tile_isl;
         b.div_magic = sp.div_magic;
         b.tile0 = tiles;

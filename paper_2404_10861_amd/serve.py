@@ -73,7 +73,8 @@ def run_alone(spec, sample: int = 1024, device="cuda", stream=None):
     run = hs.Run(cfg, device=device, stream=stream)
     run.step(spec.generations)
     idx, cnt, srf = run.sample(sample)
-    lb, ub = hs.mrca_bounds(spec.surface_kind, spec.surface_sites, cnt, srf, stream=stream)
+    lb, ub = hs.mrca_bounds(spec.surface_kind, spec.surface_sites, cnt, srf, stream=stream,
+                            bits=spec.differentia_bits, interval=spec.ingest_interval)
     out = (run.agents(), hs.as_u32(idx), hs.as_u32(lb), hs.as_u32(ub))
     run.close()
     return out
@@ -141,7 +142,7 @@ def serve(pool: hs.Pool, requests, chunk_gens: int = 256, sample: int = 1024,
             for rid in finished:
                 i, spec, arr, adm = active[rid]
                 run = pool.run(rid)
-                sw = spec.surface_sites // 32
+                sw = spec.surface_sites * spec.differentia_bits // 32
                 idx, cnt, srf = run.sample(sample, out=(idx_buf, cnt_buf, srf_buf[sw]))
                 n = cnt.shape[0]
                 lb_v = lb_dev[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32,
@@ -149,7 +150,8 @@ def serve(pool: hs.Pool, requests, chunk_gens: int = 256, sample: int = 1024,
                 ub_v = ub_dev[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32,
                                                                        device=dev)
                 hs.mrca_bounds(spec.surface_kind, spec.surface_sites, cnt, srf,
-                               workspace=ws, stream=stream, lb=lb_v, ub=ub_v)
+                               workspace=ws, stream=stream, lb=lb_v, ub=ub_v,
+                               bits=spec.differentia_bits, interval=spec.ingest_interval)
                 lb_h = lb_v.to("cpu", non_blocking=False)
                 ub_h = ub_v.to("cpu", non_blocking=False)
                 res = Served(index=i, arrival=arr, admitted=adm,

@@ -63,6 +63,8 @@ class RunSpec:
     ben_threshold: int = 0
     del_sigma: float = 1.0
     ben_sigma: float = 1.0
+    differentia_bits: int = 1
+    ingest_interval: int = 1
 
     @property
     def agents(self) -> int:
@@ -80,7 +82,8 @@ class RunSpec:
                     migrants_per_island=self.migrants_per_island, seed=self.seed,
                     fitness_model=self.fitness_model, del_threshold=self.del_threshold,
                     ben_threshold=self.ben_threshold, del_sigma=self.del_sigma,
-                    ben_sigma=self.ben_sigma)
+                    ben_sigma=self.ben_sigma, differentia_bits=self.differentia_bits,
+                    ingest_interval=self.ingest_interval)
 
 
 def c1() -> RunSpec:

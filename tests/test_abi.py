@@ -46,7 +46,9 @@ def test_config_struct_layout():
     assert ctypes.sizeof(b.ga_config) == 80
     assert b.ga_config.seed.offset == 48
     assert b.ga_config.fitness_model.offset == 56
-    assert b.ga_config.del_sigma.offset == 68 and b.ga_config.reserved2.offset == 76
+    assert b.ga_config.del_sigma.offset == 68 and b.ga_config.differentia_bits.offset == 76
+    assert b.ga_config.ingest_interval.offset == 44
+    assert ctypes.sizeof(b.hstrat_scheme) == 16
 
 
 def test_footprint_without_gpu():

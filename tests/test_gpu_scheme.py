@@ -1,0 +1,236 @@
+"""GPU parity of annotation schemes and founder tags against the oracle (zero
+tolerance): byte differentiae (4 or 8 one-byte sites), coarsened ingest
+(a deposit every n-th generation), founder tags, through runs (every
+generation, all treatments, launch shapes, batched pools), the MRCA bounds
+(shared and mixed counters) and the reconstructed trees (many-way splits);
+plus the clade trial's properties and the horizon in generations."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+# (kind, S sites, bits per differentia, ingest interval)
+SCHEMES = [(0, 8, 8, 1), (1, 8, 8, 2), (2, 8, 8, 1), (0, 4, 8, 5), (1, 32, 1, 3),
+           (0, 64, 1, 4), (2, 32, 1, 2), (2, 64, 1, 7)]
+KINDS = ("steady", "tilted", "hybrid")
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_10861_amd as hs
+    hs.load_library()
+    return hs
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).cuda()
+
+
+def cfg(hs, W, H, N, kind, S, bits, interval, seed=1, **kw):
+    return hs.Config(W, H, N, S, KINDS[kind], seed=seed, differentia_bits=bits,
+                     ingest_interval=interval, **kw)
+
+
+def oracle_for(orc, c):
+    model = {"int": 0, "float": 1, "tag": 2}[c.fitness_model]
+    return orc.Run(c.grid_w, c.grid_h, c.pop_per_island, c.surface_sites, c.kind,
+                   tournament=c.tournament_size, mut_thr=c.mut_threshold, mut_lo=c.mut_lo,
+                   mut_hi=c.mut_hi, migrants=c.migrants_per_island, seed=c.seed,
+                   fitness_model=model, del_thr=c.del_threshold, ben_thr=c.ben_threshold,
+                   del_sigma=c.del_sigma, ben_sigma=c.ben_sigma, bits=c.differentia_bits,
+                   interval=c.ingest_interval)
+
+
+def gens_for(orc, kind, S, interval, want):
+    return min(want, orc.horizon_gen(kind, S, interval) + 1)
+
+
+def same_state(run, o):
+    for x, y in zip(run.agents(), o.agents()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(run.layout(), o.layout())
+    ob, oo = run.outbox(), o.outbox()
+    assert (ob is None) == (oo is None)
+    if ob is not None:
+        for x, y in zip(ob, oo):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("kind,S,bits,interval", SCHEMES)
+@pytest.mark.parametrize("model", ["int-neutral", "int-tournament", "float", "tag"])
+def test_runs_match_oracle(hs, orc, kind, S, bits, interval, model):
+    kw = {"int-neutral": dict(tournament_size=0), "int-tournament": dict(tournament_size=2),
+          "float": dict(fitness_model="float", tournament_size=5, del_threshold=1417339207,
+                        ben_threshold=128849010),
+          "tag": dict(fitness_model="tag", tournament_size=0)}[model]
+    c = cfg(hs, 7, 5, 16, kind, S, bits, interval, seed=kind + 3 * bits + interval, **kw)
+    G = gens_for(orc, kind, S, interval, 600)
+    run = hs.Run(c)
+    run.step(G)
+    o = oracle_for(orc, c)
+    o.step(G)
+    same_state(run, o)
+
+
+def test_every_generation_coarsened_bytes(hs, orc):
+    c = cfg(hs, 6, 6, 32, 0, 8, 8, 3, seed=5)
+    run = hs.Run(c)
+    o = oracle_for(orc, c)
+    for g in range(200):
+        run.step(1)
+        o.step(1)
+        assert np.array_equal(run.agents()[2], o.agents()[2]), g
+    same_state(run, o)
+
+
+@pytest.mark.parametrize("block,apt", [(64, 1), (128, 2), (256, 4), (1024, 2)])
+def test_launch_shapes(hs, orc, block, apt):
+    c = cfg(hs, 9, 7, 32, 2, 8, 8, 2, seed=8)
+    G = gens_for(orc, 2, 8, 2, 300)
+    run = hs.Run(c)
+    run.set_launch_shape(block, apt)
+    run.step(G)
+    o = oracle_for(orc, c)
+    o.step(G)
+    same_state(run, o)
+
+
+def test_chunked_schedule_with_interval(hs, orc):
+    """Chunks of the site schedule that start and end between ingests."""
+    c = cfg(hs, 4, 4, 16, 1, 32, 1, 5, seed=2)
+    run = hs.Run(c, max_gens_per_launch=7)
+    for n in (3, 1, 7, 11, 2, 13, 5):
+        run.step(n)
+    o = oracle_for(orc, c)
+    o.step(42)
+    same_state(run, o)
+
+
+@pytest.mark.parametrize("kind,S,bits,interval", SCHEMES)
+def test_mrca_and_tree_of_samples(hs, orc, kind, S, bits, interval):
+    c = cfg(hs, 16, 16, 32, kind, S, bits, interval, seed=11, tournament_size=0)
+    G = gens_for(orc, kind, S, interval, 900)
+    run = hs.Run(c)
+    run.step(G)
+    _, cnt, srf = run.sample(700)
+    cnt_h, srf_h = hs.as_u32(cnt), hs.as_u32(srf)
+    lb, ub = hs.mrca_bounds(KINDS[kind], S, cnt, srf, **c.scheme)
+    olb, oub = orc.mrca_allpairs(kind, S, cnt_h, srf_h, bits=bits, interval=interval)
+    assert np.array_equal(hs.as_u32(lb), olb) and np.array_equal(hs.as_u32(ub), oub)
+    got = hs.phylo_metrics(KINDS[kind], S, cnt, srf, **c.scheme)
+    sbl, pairs, root, internal, ed = orc.phylo_metrics(kind, S, cnt_h, srf_h, bits=bits,
+                                                       interval=interval)
+    assert got["status"] == 0
+    assert (got["sum_branch_length"], got["pair_sum"], got["root_time"],
+            got["internal_nodes"]) == (sbl, pairs, root, internal)
+
+
+@pytest.mark.parametrize("kind,S,bits,interval", [(0, 8, 8, 1), (1, 32, 1, 3), (2, 8, 8, 4)])
+def test_mixed_counters_route(hs, orc, kind, S, bits, interval):
+    rng = np.random.default_rng(S + interval)
+    n = 257
+    top = min(3000, orc.horizon_gen(kind, S, interval) + 1)
+    counters = rng.integers(0, top, size=n).astype(np.uint32)
+    counters[:6] = [0, 1, interval, interval + 1, 2 * interval, 1]
+    W = S * bits // 32
+    surf = rng.integers(0, 2**32, size=(n, W), dtype=np.uint64).astype(np.uint32)
+    lb, ub = hs.mrca_bounds(KINDS[kind], S, dev(counters), dev(surf), bits=bits,
+                            interval=interval)
+    olb, oub = orc.mrca_allpairs(kind, S, counters, surf, bits=bits, interval=interval)
+    assert np.array_equal(hs.as_u32(lb), olb) and np.array_equal(hs.as_u32(ub), oub)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 300, 1025])
+def test_many_way_trees_ragged(hs, orc, n):
+    """Byte differentiae drawn from a few values so that nodes split many
+    ways and identical annotations repeat."""
+    rng = np.random.default_rng(n)
+    counters = np.full(n, 8, np.uint32)        # steady, 8 byte sites, fill phase complete
+    vals = rng.integers(0, 3, size=(n, 8)).astype(np.uint32)
+    vals[: n // 4] = vals[0]
+    words = np.zeros((n, 2), np.uint32)
+    for k in range(8):
+        words[:, k // 4] |= vals[:, k] << (8 * (k % 4))
+    got = hs.phylo_metrics("steady", 8, dev(counters), dev(words), bits=8)
+    sbl, pairs, root, internal, _ = orc.phylo_metrics(0, 8, counters, words, bits=8)
+    assert (got["sum_branch_length"], got["pair_sum"], got["root_time"],
+            got["internal_nodes"]) == (sbl, pairs, root, internal)
+
+
+def test_hand_worked_many_way_tree(hs):
+    rows = [(1, 1, 1, 1), (1, 2, 1, 1), (1, 3, 5, 5), (1, 3, 5, 6), (7, 0, 0, 0)]
+    surf = np.array([[v[0] | v[1] << 8 | v[2] << 16 | v[3] << 24] for v in rows], np.uint32)
+    got = hs.phylo_metrics("steady", 4, dev(np.full(5, 4, np.uint32)), dev(surf), bits=8)
+    assert got["sum_branch_length"] == 15 and got["pair_sum"] == 32
+    assert got["root_time"] == 0 and got["internal_nodes"] == 3
+
+
+def test_horizon_in_generations(hs, orc):
+    for interval in (1, 3):
+        last = orc.horizon_gen(1, 4, interval)
+        run = hs.Run(cfg(hs, 2, 2, 4, 1, 4, 8, interval))
+        run.step(last + 1)
+        with pytest.raises(hs.HsgaError):
+            run.step(1)
+    # a counter past the horizon (in ingests) is refused by the query
+    past = 3 * 15 + 1
+    got = hs.phylo_metrics("tilted", 4, dev(np.full(3, past, np.uint32)),
+                           dev(np.zeros((3, 1), np.uint32)), bits=8, interval=3)
+    assert got["status"] == 2
+
+
+def test_invalid_schemes(hs):
+    for kw in (dict(differentia_bits=8), dict(differentia_bits=4),
+               dict(fitness_model="tag", tournament_size=2)):
+        with pytest.raises(hs.HsgaError):
+            hs.Run(hs.Config(2, 2, 4, 32, "steady", **kw))
+    with pytest.raises(hs.HsgaError):
+        hs.mrca_bounds("steady", 32, dev(np.zeros(2, np.uint32)),
+                       dev(np.zeros((2, 8), np.uint32)), bits=8)
+
+
+def test_batched_schemes_equal_alone(hs):
+    specs = [(cfg(hs, 8, 8, 32, 0, 8, 8, 1, seed=1), 300),
+             (cfg(hs, 5, 3, 17, 1, 32, 1, 3, seed=2), 410),
+             (cfg(hs, 7, 9, 16, 2, 8, 8, 4, seed=3, fitness_model="tag", tournament_size=0), 120),
+             (cfg(hs, 6, 6, 32, 2, 64, 1, 7, seed=4, fitness_model="float", tournament_size=5,
+                  del_threshold=1417339207, ben_threshold=12884901), 333),
+             (hs.Config(10, 10, 16, 64, "tilted", seed=5), 150)]
+    for use_graph in (False, True):
+        pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=50, use_graph=use_graph)
+        ids = {pool.admit(c, g): (c, g) for c, g in specs}
+        assert None not in ids
+        while pool.advance(50):
+            pass
+        for rid, (c, g) in ids.items():
+            alone = hs.Run(c)
+            alone.step(g)
+            for x, y in zip(pool.run(rid).agents(), alone.agents()):
+                assert np.array_equal(x, y)
+            assert np.array_equal(pool.run(rid).layout(), alone.layout())
+            alone.close()
+        pool.close()
+
+
+def test_clade_trial(hs):
+    """Clade trial (3x3 islands x 32, tilted 64, neutral, founder tags):
+    same-clade pairs get later MRCA bounds than different-clade pairs, and
+    the number of clades never grows with the duration."""
+    counts = []
+    for G in (25, 50, 100, 250):
+        c = hs.Config(3, 3, 32, 64, "tilted", tournament_size=0, seed=17, fitness_model="tag")
+        run = hs.Run(c)
+        run.step(G)
+        tags, cnt, srf = run.agents()
+        counts.append(len(np.unique(tags)))
+        lb, ub = hs.mrca_bounds("tilted", 64, dev(cnt), dev(srf))
+        ub = hs.as_u32(ub)
+        same = tags[:, None] == tags[None, :]
+        off = ~np.eye(len(tags), dtype=bool)
+        if (same & off).any() and (~same).any():
+            assert ub[same & off].mean() > ub[~same].mean()
+    assert counts == sorted(counts, reverse=True) and counts[-1] < counts[0]
