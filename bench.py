@@ -110,7 +110,7 @@ def main(argv=None) -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the run length (profiling only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair", "trial"),
+    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair", "trial", "clade"),
                     default="plain",
                     help="plain: the paper-scale run (default); batched / served: the run "
                          "sets of the batched and served workloads against sequential plain runs")
@@ -136,7 +136,13 @@ def main(argv=None) -> int:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         from paper_2404_10861_amd import benchmarks
-        if args.mode == "trial":
+        if args.mode == "clade":
+            t0 = time.perf_counter()
+            res = benchmarks.clade_trial([wl.clade(g) for g in (25, 50, 100, 250)], dev,
+                                         torch.cuda.current_stream(dev))
+            metric = "clade trial: founding clades and MRCA bounds within / between clades"
+            value = time.perf_counter() - t0
+        elif args.mode == "trial":
             gens = args.generations or 20000
             res = benchmarks.treatment_pair(
                 [wl.trial(False, generations=gens), wl.trial(True, generations=gens)], dev,
@@ -161,9 +167,11 @@ def main(argv=None) -> int:
                 progress=lambda text: print(text, file=sys.stderr, flush=True))
             metric = "agent-replications/sec and p50/p99 run latency (served)"
             value = res["served"]["replications_per_s"]
-        print(json.dumps({"metric": metric, "value": value, "unit": "agent-replications/s",
+        unit = "s (wall)" if args.mode == "clade" else "agent-replications/s"
+        print(json.dumps({"metric": metric, "value": value, "unit": unit,
                           "n_gpus": 1, "mode": args.mode,
                           "dtype": "u32,f32,f64" if args.mode == "trial" else "u32",
+                          "higher_is_better": args.mode != "clade",
                           "data": "synthetic",
                           "result": res}), flush=True)
         return 0

@@ -218,3 +218,36 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096, labels=None,
         out[label] = rec
         run.close()
     return out
+
+
+def clade_trial(specs, dev, stream) -> dict:
+    """The clade trial: for each duration, the founding clades still
+    present, the mean MRCA bounds of same-clade and different-clade pairs
+    over the whole population, and the tree of one agent sampled per
+    island (its clade labels listed in sample order)."""
+    out = {}
+    for s in specs:
+        cfg = hs.Config(**s.config_kwargs())
+        run = hs.Run(cfg, device=dev, stream=stream)
+        run.step(s.generations)
+        tags, cnt, srf = run.agents()
+        c_d = torch.from_numpy(cnt.view(np.int32)).to(dev)
+        s_d = torch.from_numpy(srf.view(np.int32)).to(dev)
+        lb, ub = hs.mrca_bounds(s.surface_kind, s.surface_sites, c_d, s_d, stream=stream)
+        ub_h = hs.as_u32(ub).astype(np.float64)
+        same = tags[:, None] == tags[None, :]
+        off = ~np.eye(len(tags), dtype=bool)
+        # one agent per island, as in the paper's reconstructions
+        pick = np.arange(cfg.islands) * cfg.pop_per_island
+        tree = hs.phylo_metrics(s.surface_kind, s.surface_sites, c_d[pick], s_d[pick],
+                                stream=stream)
+        out[str(s.generations)] = {
+            "clades_remaining": int(len(np.unique(tags))),
+            "mean_ub_same_clade": float(ub_h[same & off].mean()) if (same & off).any() else None,
+            "mean_ub_different_clades": float(ub_h[~same].mean()) if (~same).any() else None,
+            "per_island_sample_tags": [int(t) for t in tags[pick]],
+            "per_island_tree": {k: tree[k] for k in ("sum_branch_length", "root_time",
+                                                     "internal_nodes")},
+        }
+        run.close()
+    return out

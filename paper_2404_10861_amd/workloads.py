@@ -28,6 +28,10 @@ adding a uniform integer in [-8, 8], one migrant per island per generation.
   adaptation-enabled (additionally 0.3 % gain ben_sigma |Z|), scales 1.0;
   a 10,000-agent stratified sample is reconstructed into a tree.  The
   paper ran 1,000,000 generations; the default here is 20,000.
+* Clade trial (after the paper's Clade Reconstruction Trial): 3x3 islands
+  x 32 agents, 64-site tilted surface, neutral selection, founder tags;
+  durations 25, 50, 100 and 250 generations; one sampled agent per island
+  and the whole population are reconstructed.
 """
 from __future__ import annotations
 
@@ -107,6 +111,14 @@ def trial(adaptive: bool, side: int = 750, generations: int = 20000) -> RunSpec:
                    fitness_model="float", del_threshold=P_DELETERIOUS,
                    ben_threshold=P_BENEFICIAL if adaptive else 0,
                    name=f"float trial {name} {side}x{side}x32 tilted-64")
+
+
+def clade(generations: int, seed: int = 17) -> RunSpec:
+    """The clade trial (after the paper's Clade Reconstruction Trial): 3x3
+    islands x 32 agents, 64-site tilted surface, neutral selection, random
+    16-bit founder tags inherited without mutation."""
+    return RunSpec(3, 3, 32, 64, "tilted", 0, generations, seed=seed, fitness_model="tag",
+                   name=f"clade trial 3x3x32 tilted-64, {generations} generations")
 
 
 C4_GRIDS = ((16, 16), (32, 64), (64, 64), (128, 256))
