@@ -44,7 +44,8 @@ enum { ORC_STEADY = 0, ORC_TILTED = 1, ORC_HYBRID = 2 };
 /* purpose tags carried in the fourth Philox counter word */
 enum { ORC_BIRTH = 0, ORC_EMIGRATE = 1, ORC_IMMIGRATE = 2, ORC_SAMPLE = 3,
        ORC_BIRTH_B = 4 /* second block of a float-treatment birth */,
-       ORC_FOUNDER = 5 /* founder tags */ };
+       ORC_FOUNDER = 5 /* founder tags */,
+       ORC_ACTIVITY = 6 /* asynchronous runs: is an island active on a tick */ };
 /* fitness models */
 enum { ORC_INT_TRAIT = 0, ORC_FLOAT_FITNESS = 1, ORC_FOUNDER_TAG = 2 };
 /* torus directions */
@@ -357,6 +358,12 @@ typedef struct {
     /* annotation scheme: differentia width (1 or 8 bits per site) and the
      * ingest interval (one deposit every `interval` generations)          */
     uint32_t bits, interval;
+    /* asynchronous runs (orc_set_async): activity threshold (0: every
+     * island every step), the site of every ingest so far (tab, filled
+     * entries, capacity) and the layout after them (Ltab)                 */
+    uint32_t activity;
+    uint32_t *tab, tab_filled, tab_cap;
+    uint32_t Ltab[64];
     uint32_t I, A, SW;
     uint32_t g;                       /* generations elapsed                  */
     uint32_t *trait, *counter, *surf; /* A, A, A*SW (agent-major)             */
@@ -399,6 +406,7 @@ void orc_destroy(void *handle)
     free(r->trait); free(r->counter); free(r->surf); free(r->src);
     free(r->ob_dir); free(r->ob_trait); free(r->ob_counter); free(r->ob_surf);
     free(r->ob_src);
+    free(r->tab);
     free(r->ped_parent); free(r->ped_bit);
     free(r->q_trait); free(r->q_counter); free(r->q_surf); free(r->q_src);
     free(r->n_trait); free(r->n_counter); free(r->n_surf); free(r->n_src);
@@ -483,7 +491,7 @@ void *orc_create_ex(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kin
     for (uint32_t a = 0; a < r->A; a++)
         r->src[a] = a;
     for (uint32_t k = 0; k < 64; k++)
-        r->L[k] = ORC_EMPTY;
+        r->L[k] = r->Ltab[k] = ORC_EMPTY;
     r->g = 0;
     r->has_outbox = 0;
     return r;
@@ -543,6 +551,63 @@ int orc_set_fitness(void *handle, uint32_t model, uint32_t tournament,
         r->trait[a] = model == ORC_FOUNDER_TAG ? (w[0] & 0xffffu) : 0u;
     }
     return 0;
+}
+
+/* Selection, replication and mutation of the birth into slot j of island i
+ * at step g (the step index is the generation in synchronous runs and the
+ * tick in asynchronous ones), reading the island's members Q: the parent's
+ * index in Q, the child's trait word and the differentia drawn (the low
+ * `bits` bits of the drawn word).                                          */
+static void draw_birth(orc_run *r, uint32_t i, uint32_t j, uint32_t g, uint32_t *p_out,
+                       uint32_t *trait_out, uint32_t *val_out)
+{
+    const uint32_t N = r->N;
+    uint32_t w[4], p, child_trait, bit;
+    orc_philox(j, i, g, ORC_BIRTH, r->seed, w);
+    if (r->model == ORC_FOUNDER_TAG) {
+        /* neutral; the tag is inherited unchanged */
+        p = orc_mulhi(w[0], N);
+        child_trait = r->q_trait[p];
+        bit = w[3];
+    } else if (r->model == ORC_INT_TRAIT) {
+        p = orc_mulhi(w[0], N);
+        if (r->tournament == 2) {
+            uint32_t b = orc_mulhi(w[1], N);
+            if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])
+                p = b;
+        }
+        uint32_t delta = 0;
+        if (w[2] < r->mut_thr)
+            delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
+        child_trait = r->q_trait[p] + delta;
+        bit = w[3];
+    } else {
+        /* float treatments: candidates from words w0..w3, v0; the
+         * class of the mutation from v1; |Z| from v2 (radius) and
+         * v3 (angle); the differentia is the low bits of v3     */
+        uint32_t v[4];
+        orc_philox(j, i, g, ORC_BIRTH_B, r->seed, v);
+        uint32_t words[5] = {w[0], w[1], w[2], w[3], v[0]};
+        uint32_t k = r->tournament < 1 ? 1 : r->tournament;
+        p = orc_mulhi(words[0], N);
+        for (uint32_t c = 1; c < k; c++) {
+            uint32_t b = orc_mulhi(words[c], N);
+            if (f32_of(r->q_trait[b]) > f32_of(r->q_trait[p]))
+                p = b;
+        }
+        double f = (double)f32_of(r->q_trait[p]);
+        child_trait = r->q_trait[p];
+        if (v[1] < r->del_thr)
+            child_trait = f32_bits((float)(f - (double)r->del_sigma *
+                                                  orc_half_normal(v[2], v[3])));
+        else if ((uint64_t)v[1] + r->ben_thr >= (1ull << 32))
+            child_trait = f32_bits((float)(f + (double)r->ben_sigma *
+                                                  orc_half_normal(v[2], v[3])));
+        bit = v[3];
+    }
+    *p_out = p;
+    *trait_out = child_trait;
+    *val_out = bit & (r->bits == 8 ? 0xffu : 1u);
 }
 
 /* One generation, (P_g, O_g) -> (P_{g+1}, O_{g+1}), island by island, in the
@@ -611,50 +676,7 @@ static int step_one(orc_run *r)
         for (uint32_t j = 0; j < N; j++) {
             uint32_t a = i * N + j;
             uint32_t p, child_trait, bit;
-            orc_philox(j, i, g, ORC_BIRTH, r->seed, w);
-            if (r->model == ORC_FOUNDER_TAG) {
-                /* neutral; the tag is inherited unchanged */
-                p = orc_mulhi(w[0], N);
-                child_trait = r->q_trait[p];
-                bit = w[3];
-            } else if (r->model == ORC_INT_TRAIT) {
-                p = orc_mulhi(w[0], N);
-                if (r->tournament == 2) {
-                    uint32_t b = orc_mulhi(w[1], N);
-                    if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])
-                        p = b;
-                }
-                uint32_t delta = 0;
-                if (w[2] < r->mut_thr)
-                    delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
-                child_trait = r->q_trait[p] + delta;
-                bit = w[3];
-            } else {
-                /* float treatments: candidates from words w0..w3, v0; the
-                 * class of the mutation from v1; |Z| from v2 (radius) and
-                 * v3 (angle); the differentia is the low bits of v3     */
-                uint32_t v[4];
-                orc_philox(j, i, g, ORC_BIRTH_B, r->seed, v);
-                uint32_t words[5] = {w[0], w[1], w[2], w[3], v[0]};
-                uint32_t k = r->tournament < 1 ? 1 : r->tournament;
-                p = orc_mulhi(words[0], N);
-                for (uint32_t c = 1; c < k; c++) {
-                    uint32_t b = orc_mulhi(words[c], N);
-                    if (f32_of(r->q_trait[b]) > f32_of(r->q_trait[p]))
-                        p = b;
-                }
-                double f = (double)f32_of(r->q_trait[p]);
-                child_trait = r->q_trait[p];
-                if (v[1] < r->del_thr)
-                    child_trait = f32_bits((float)(f - (double)r->del_sigma *
-                                                          orc_half_normal(v[2], v[3])));
-                else if ((uint64_t)v[1] + r->ben_thr >= (1ull << 32))
-                    child_trait = f32_bits((float)(f + (double)r->ben_sigma *
-                                                          orc_half_normal(v[2], v[3])));
-                bit = v[3];
-            }
-            /* the differentia: the low `bits` bits of the drawn word */
-            bit &= r->bits == 8 ? 0xffu : 1u;
+            draw_birth(r, i, j, g, &p, &child_trait, &bit);
             uint32_t T = r->q_counter[p];
             if (T != g)
                 return -2;
@@ -707,6 +729,167 @@ static int step_one(orc_run *r)
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Asynchronous runs (Methods, Asynchronous Island-model Genetic Algorithm:
+ * processing elements run their own generation loops and exchange
+ * migrants without synchronising, so neighbours drift apart in generation
+ * count).  Reading: time advances in ticks; on tick k island i runs one
+ * generation iff the first word of Philox block (0, i, k, ACTIVITY) is below
+ * the activity threshold, else it stays as it is and posts no emigrant.  An
+ * active island reads the emigrants its neighbours posted on tick k-1, then
+ * breeds as in a synchronous generation, except that every agent carries its
+ * own counter: a birth from a parent with counter T deposits item T (in
+ * ingest units, when T is a multiple of the interval) at the site that the
+ * rule gives the T-th ingest.  That site depends on T alone, so a table of
+ * sites by ingest index makes the lookup O(1) per agent.                   */
+
+/* Site of ingest tau, extending the table by replaying placements.  Returns
+ * -1 beyond the horizon or on no memory.                                   */
+static int site_of(orc_run *r, uint32_t tau)
+{
+    while (r->tab_filled <= tau) {
+        if (r->tab_filled == r->tab_cap) {
+            uint32_t cap = r->tab_cap ? 2 * r->tab_cap : 1024;
+            uint32_t *t = (uint32_t *)realloc(r->tab, (size_t)cap * 4);
+            if (!t)
+                return -1;
+            r->tab = t;
+            r->tab_cap = cap;
+        }
+        uint32_t u = r->tab_filled;
+        if ((uint64_t)u > orc_horizon(r->kind, r->S))
+            return -1;
+        int site = orc_place(r->kind, r->S, r->Ltab, u);
+        if (site < 0)
+            return -1;
+        r->Ltab[site] = u;
+        r->tab[u] = (uint32_t)site;
+        r->tab_filled++;
+    }
+    return (int)r->tab[tau];
+}
+
+/* Switch a run to ticks with islands active with probability
+ * activity / 2^32 (0 switches back to synchronous generations).  Only
+ * before the first step.  Returns 0 or -1.                                  */
+int orc_set_async(void *handle, uint32_t activity)
+{
+    orc_run *r = (orc_run *)handle;
+    if (r->g != 0)
+        return -1;
+    r->activity = activity;
+    return 0;
+}
+
+static int step_async(orc_run *r)
+{
+    const uint32_t N = r->N, SW = r->SW, k = r->g;
+    uint32_t w[4];
+    if ((uint64_t)k > orc_horizon_gen(r->kind, r->S, r->interval))
+        return -1;
+    uint8_t *active = (uint8_t *)malloc(r->I);
+    if (!active)
+        return -2;
+    for (uint32_t i = 0; i < r->I; i++) {
+        orc_philox(0, i, k, ORC_ACTIVITY, r->seed, w);
+        active[i] = w[0] < r->activity;
+    }
+    for (uint32_t i = 0; i < r->I; i++) {
+        if (!active[i]) {
+            /* no generation: the same individuals on the next tick */
+            for (uint32_t j = 0; j < N; j++) {
+                uint32_t a = i * N + j;
+                r->n_trait[a] = r->trait[a];
+                r->n_counter[a] = r->counter[a];
+                for (uint32_t s = 0; s < SW; s++)
+                    r->n_surf[(size_t)a * SW + s] = r->surf[(size_t)a * SW + s];
+                if (k < r->ped_gens) {
+                    r->ped_parent[(size_t)k * r->A + a] = a;
+                    r->ped_bit[(size_t)k * r->A + a] = 0;
+                }
+            }
+            continue;
+        }
+        for (uint32_t j = 0; j < N; j++) {
+            uint32_t a = i * N + j;
+            r->q_trait[j] = r->trait[a];
+            r->q_counter[j] = r->counter[a];
+            for (uint32_t s = 0; s < SW; s++)
+                r->q_surf[j * SW + s] = r->surf[(size_t)a * SW + s];
+            r->q_src[j] = a;
+        }
+        /* immigrants posted on the previous tick toward this island */
+        if (r->migrants && r->has_outbox) {
+            orc_philox(0, i, k, ORC_IMMIGRATE, r->seed, w);
+            for (uint32_t d = 0; d < 4; d++) {
+                uint32_t nb = neighbour(r, i, d);
+                if (r->ob_dir[nb] == opposite(d)) {
+                    uint32_t slot = orc_mulhi(w[d], N);
+                    r->q_trait[slot] = r->ob_trait[nb];
+                    r->q_counter[slot] = r->ob_counter[nb];
+                    for (uint32_t s = 0; s < SW; s++)
+                        r->q_surf[slot * SW + s] = r->ob_surf[(size_t)nb * SW + s];
+                    r->q_src[slot] = r->ob_src[nb];
+                }
+            }
+        }
+        for (uint32_t j = 0; j < N; j++) {
+            uint32_t a = i * N + j;
+            uint32_t p, child_trait, bit;
+            draw_birth(r, i, j, k, &p, &child_trait, &bit);
+            uint32_t T = r->q_counter[p];
+            r->n_trait[a] = child_trait;
+            r->n_counter[a] = T + 1;
+            for (uint32_t s = 0; s < SW; s++)
+                r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];
+            if (T % r->interval == 0) {
+                int site = site_of(r, T / r->interval);
+                if (site < 0) {
+                    free(active);
+                    return -1;
+                }
+                uint32_t per_word = 32 / r->bits;
+                uint32_t shift = ((uint32_t)site % per_word) * r->bits;
+                uint32_t mask = (r->bits == 8 ? 0xffu : 1u) << shift;
+                uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / per_word];
+                *word = (*word & ~mask) | (bit << shift);
+            }
+            if (k < r->ped_gens) {
+                r->ped_parent[(size_t)k * r->A + a] = r->q_src[p];
+                r->ped_bit[(size_t)k * r->A + a] = (uint8_t)bit;
+            }
+        }
+    }
+    memcpy(r->trait, r->n_trait, (size_t)r->A * 4);
+    memcpy(r->counter, r->n_counter, (size_t)r->A * 4);
+    memcpy(r->surf, r->n_surf, (size_t)r->A * SW * 4);
+    /* emigration from active islands; inactive ones post nothing */
+    if (r->migrants) {
+        for (uint32_t i = 0; i < r->I; i++) {
+            if (!active[i]) {
+                r->ob_dir[i] = 4;   /* addressed to no neighbour */
+                r->ob_trait[i] = r->ob_counter[i] = r->ob_src[i] = 0;
+                for (uint32_t s = 0; s < SW; s++)
+                    r->ob_surf[(size_t)i * SW + s] = 0;
+                continue;
+            }
+            orc_philox(0, i, k, ORC_EMIGRATE, r->seed, w);
+            uint32_t e = orc_mulhi(w[0], N);
+            uint32_t a = i * N + e;
+            r->ob_dir[i] = w[1] >> 30;
+            r->ob_trait[i] = r->trait[a];
+            r->ob_counter[i] = r->counter[a];
+            for (uint32_t s = 0; s < SW; s++)
+                r->ob_surf[(size_t)i * SW + s] = r->surf[(size_t)a * SW + s];
+            r->ob_src[i] = a;
+        }
+        r->has_outbox = 1;
+    }
+    free(active);
+    r->g = k + 1;
+    return 0;
+}
+
 /* Advance n generations (the paper's main loop runs until a generation
  * count is reached).  Returns 0, -1 beyond the horizon, -2 on a broken
  * invariant, -3 if n would pass the end of the pedigree record.            */
@@ -716,7 +899,7 @@ int orc_step(void *handle, uint32_t n)
     if (r->ped_gens && (uint64_t)r->g + n > r->ped_gens)
         return -3;
     for (uint32_t k = 0; k < n; k++) {
-        int rc = step_one(r);
+        int rc = r->activity ? step_async(r) : step_one(r);
         if (rc)
             return rc;
     }
@@ -756,8 +939,18 @@ int orc_read_outbox(void *handle, uint32_t *dir, uint32_t *trait,
 void orc_read_layout(void *handle, uint32_t *L)
 {
     orc_run *r = (orc_run *)handle;
+    uint32_t Lr[64];
+    if (r->activity) {
+        /* asynchronous: the layout of an annotation whose counter is the
+         * number of ticks so far                                           */
+        if (orc_layout(r->kind, r->S, ingests_of(r->g, r->interval), Lr) != 0)
+            for (uint32_t k = 0; k < r->S; k++)
+                Lr[k] = ORC_EMPTY;
+    } else {
+        memcpy(Lr, r->L, sizeof Lr);
+    }
     for (uint32_t k = 0; k < r->S; k++)
-        L[k] = r->L[k] == ORC_EMPTY ? ORC_EMPTY : r->L[k] * r->interval;
+        L[k] = Lr[k] == ORC_EMPTY ? ORC_EMPTY : Lr[k] * r->interval;
 }
 
 /* Pedigree of generation gen (1..ped_gens): parent index in P_{gen-1} and

@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 EMPTY = 0xFFFFFFFF
 STEADY, TILTED, HYBRID = 0, 1, 2
 KINDS = {"steady": STEADY, "tilted": TILTED, "hybrid": HYBRID}
-BIRTH, EMIGRATE, IMMIGRATE, SAMPLE, BIRTH_B, FOUNDER = 0, 1, 2, 3, 4, 5
+BIRTH, EMIGRATE, IMMIGRATE, SAMPLE, BIRTH_B, FOUNDER, ACTIVITY = 0, 1, 2, 3, 4, 5, 6
 INT_TRAIT, FLOAT_FITNESS, FOUNDER_TAG = 0, 1, 2
 
 _lib = None
@@ -75,6 +75,8 @@ def load():
                                   [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
                                    ctypes.c_uint32, ctypes.c_uint32])
     lib.orc_create_ex.restype = ctypes.c_void_p
+    lib.orc_set_async.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    lib.orc_set_async.restype = ctypes.c_int
     lib.orc_horizon_gen.argtypes = [ctypes.c_uint32] * 3
     lib.orc_horizon_gen.restype = ctypes.c_uint64
     lib.orc_mrca_rows_x.argtypes = ([ctypes.c_uint32] * 5 + [u32p, u32p, ctypes.c_uint32, u32p,
@@ -197,7 +199,7 @@ class Run:
     def __init__(self, W, H, N, S, kind, tournament=2, mut_thr=42949672,
                  mut_lo=-8, mut_hi=8, migrants=1, seed=1, pedigree_gens=0,
                  fitness_model=INT_TRAIT, del_thr=0, ben_thr=0, del_sigma=1.0,
-                 ben_sigma=1.0, bits=1, interval=1):
+                 ben_sigma=1.0, bits=1, interval=1, activity=0):
         lib = load()
         h = lib.orc_create_ex(W, H, N, S, kind,
                               tournament if fitness_model == INT_TRAIT else 0,
@@ -210,6 +212,9 @@ class Run:
                                ben_sigma):
             self.close()
             raise ValueError("invalid oracle fitness configuration")
+        if lib.orc_set_async(h, activity):
+            self.close()
+            raise ValueError("invalid asynchronous configuration")
         self.W, self.H, self.N, self.S, self.kind = W, H, N, S, kind
         self.bits, self.interval = bits, interval
         self.I = W * H
