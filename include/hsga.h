@@ -70,9 +70,10 @@ typedef enum { GA_STEADY = 0, GA_TILTED = 1, GA_HYBRID = 2 } ga_surface_kind;
 typedef enum { GA_INT_TRAIT = 0, GA_FLOAT_FITNESS = 1, GA_FOUNDER_TAG = 2 } ga_fitness_model;
 
 typedef struct ga_config {
-    uint32_t struct_size;         /* sizeof(ga_config) = 80; 56 (a config
-                                     without the float fields) is accepted
-                                     and means GA_INT_TRAIT                   */
+    uint32_t struct_size;         /* sizeof(ga_config) = 88; 56 and 80 (the
+                                     layouts ending after seed and after
+                                     differentia_bits) are accepted, absent
+                                     fields read as 0                         */
     uint32_t grid_w, grid_h;      /* torus of islands; island i = y*w + x      */
     uint32_t pop_per_island;      /* N agents per island, 1..64                */
     uint32_t surface_sites;       /* S sites: 32 or 64 one-bit sites, or 4 or
@@ -99,6 +100,14 @@ typedef struct ga_config {
     float del_sigma, ben_sigma;   /* scales of |Z|, in [0, 2^20]               */
     /* any fitness model: */
     uint32_t differentia_bits;    /* 1 (0 means 1) or 8 bits per site          */
+    uint32_t async_activity;      /* 0: synchronous generations.  Otherwise
+                                     asynchronous ticks: on each tick an
+                                     island runs a generation with
+                                     probability async_activity / 2^32, agents
+                                     keep their own counters, and a run may
+                                     take at most max_gens_per_launch ticks
+                                     in total (its site table)                */
+    uint32_t reserved;            /* must be 0                                 */
 } ga_config;
 
 typedef struct ga_run ga_run;
@@ -125,11 +134,11 @@ size_t ga_footprint_bytes(const ga_config *cfg, uint32_t max_gens_per_launch);
  * aligned, arena_bytes >= ga_footprint_bytes) and enqueue the founders on
  * hip_stream: trait 0, counter 0, all sites 0, empty layout, no outboxes.
  * Founders carry no differentia; generation g's births deposit item g.
- * Errors: GA_EINVAL (struct_size not 56/80, S * differentia_bits not 32 or
+ * Errors: GA_EINVAL (struct_size not 56/80/88, S * differentia_bits not 32 or
  * 64, differentia_bits not 1/8, N = 0 or > 64, empty grid, mut_lo >
  * mut_hi, tournament not 0/2 (integer trait), above 5 (float fitness) or
  * not 0 (founder tags), migrants > 1, float thresholds summing above 2^32,
- * a scale outside [0, 2^20]), GA_ENOMEM
+ * a scale outside [0, 2^20], reserved != 0), GA_ENOMEM
  * (arena too small), GA_EDEVICE.  *out is owned by the caller until
  * ga_destroy.                                                              */
 int ga_create(const ga_config *cfg, void *dev_arena, size_t arena_bytes,
@@ -142,8 +151,15 @@ int ga_create(const ga_config *cfg, void *dev_arena, size_t arena_bytes,
  * neutral) parent, with trait mutation and one differentia written at the
  * site the surface policy picks for this generation; then a copy of a
  * random new member is posted to a random neighbour.  Returns at once.
- * Errors: GA_EHORIZON if generation T + n - 1 is past the site rule's
- * horizon (nothing is enqueued), GA_EDEVICE.                               */
+ * Asynchronous runs (async_activity != 0; Asynchronous Island-model GA:
+ * islands run their own loops and drift apart) advance n ticks instead: an
+ * island active on a tick takes the emigrants its neighbours posted on the
+ * previous tick and breeds, each birth depositing at the site its parent's
+ * own counter selects (an O(1) lookup in the run's site table); an idle
+ * island keeps its members and posts nothing.
+ * Errors: GA_EHORIZON if generation (tick) T + n - 1 is past the site
+ * rule's horizon (nothing is enqueued), GA_EINVAL if an asynchronous run
+ * would pass max_gens_per_launch ticks, GA_EDEVICE.                       */
 int ga_step(ga_run *run, uint32_t n);
 
 /* Block until all work enqueued for the run has finished. */

@@ -64,6 +64,8 @@ class ga_config(ctypes.Structure):
         ("del_sigma", ctypes.c_float),
         ("ben_sigma", ctypes.c_float),
         ("differentia_bits", ctypes.c_uint32),
+        ("async_activity", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -172,7 +174,10 @@ class Config:
     del_sigma / ben_sigma scales of the half-normal change); 'tag' gives
     founders random 16-bit tags, inherited unchanged (tournament_size 0).
     differentia_bits 1 (surface_sites 32 or 64) or 8 (surface_sites 4 or
-    8); ingest_interval n deposits every n-th generation only."""
+    8); ingest_interval n deposits every n-th generation only.
+    async_activity p * 2^32 (0: synchronous) runs asynchronous ticks: each
+    island runs a generation with probability p per tick, agents keep their
+    own counters (at most max_gens_per_launch ticks per run)."""
     grid_w: int
     grid_h: int
     pop_per_island: int = 32
@@ -191,6 +196,7 @@ class Config:
     ben_sigma: float = 1.0
     differentia_bits: int = 1
     ingest_interval: int = 1
+    async_activity: int = 0
 
     @property
     def kind(self) -> int:
@@ -232,6 +238,8 @@ class Config:
         c.del_sigma = self.del_sigma
         c.ben_sigma = self.ben_sigma
         c.differentia_bits = self.differentia_bits
+        c.async_activity = self.async_activity
+        c.reserved = 0
         return c
 
 

@@ -4,6 +4,7 @@
 // file only validates, carves memory and enqueues.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
@@ -47,7 +48,9 @@ Carve carve(uint32_t I, uint32_t N, uint32_t SW, uint32_t gens) {
 int validate(const ga_config* in, ga_config* out) {
     if (!in) return fail(GA_EINVAL, "config is NULL");
     constexpr uint32_t kIntOnlySize = offsetof(ga_config, fitness_model);
-    if (in->struct_size != sizeof(ga_config) && in->struct_size != kIntOnlySize)
+    constexpr uint32_t kSyncOnlySize = offsetof(ga_config, async_activity);
+    if (in->struct_size != sizeof(ga_config) && in->struct_size != kIntOnlySize &&
+        in->struct_size != kSyncOnlySize)
         return fail(GA_EINVAL, "config struct_size does not match this library");
     ga_config c;
     std::memset(&c, 0, sizeof c);
@@ -87,6 +90,7 @@ int validate(const ga_config* in, ga_config* out) {
             return fail(GA_EINVAL, "mutation scales must lie in [0, 2^20]");
     }
     if (cfg->migrants_per_island > 1) return fail(GA_EINVAL, "migrants_per_island must be 0 or 1");
+    if (cfg->reserved != 0) return fail(GA_EINVAL, "reserved must be 0");
     if (out) *out = c;
     return GA_OK;
 }
@@ -119,6 +123,7 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
     r->sites = reinterpret_cast<uint32_t*>(base + c.sites);
     r->gens = gens;
     r->T = 0;
+    r->tab_filled = 0;
     r->horizon = hsga::horizon_gen_of(cfg->surface_kind, r->S, cfg->ingest_interval);
     r->apt = default_agents_per_thread(r->N);
     r->block = r->apt == 4 ? 64u : 256u;   // small tiles: more workgroups in flight per CU
@@ -146,6 +151,9 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t tau0) {
     const uint32_t n = cfg.ingest_interval;
     p.site = g % n == 0 ? r->sites + (g / n - tau0) : nullptr;
     p.diff_log2 = cfg.differentia_bits == 8 ? 3u : 0u;
+    p.async_thr = cfg.async_activity;
+    p.site_tab = r->sites;
+    p.interval = n;
     p.W = cfg.grid_w;
     p.H = cfg.grid_h;
     p.N = r->N;
@@ -240,6 +248,44 @@ int ga_step(ga_run* r, uint32_t n) {
     const ga_config& cfg = r->cfg;
     const uint32_t model = birth_model(cfg);
     const bool mig = cfg.migrants_per_island != 0;
+    if (cfg.async_activity) {
+        // asynchronous ticks: extend the site table to every ingest a
+        // counter can reach by the last tick, then one launch per tick
+        const uint64_t need = hsga::ingests_of((uint32_t)std::min<uint64_t>(
+                                                   (uint64_t)r->T + n, 0xffffffffull),
+                                               cfg.ingest_interval);
+        if ((uint64_t)r->T + n > r->gens)
+            return fail(GA_EINVAL, "an asynchronous run is limited to " +
+                                       std::to_string(r->gens) +
+                                       " ticks (max_gens_per_launch)");
+        if (need > r->tab_filled) {
+            hipError_t e = hsga::launch_site_schedule(cfg.surface_kind, r->S, r->layout,
+                                                      r->sites + r->tab_filled, r->tab_filled,
+                                                      (uint32_t)need - r->tab_filled, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "site table launch");
+            r->tab_filled = (uint32_t)need;
+        }
+        ga_run::Span span{nullptr, nullptr, n};
+        if (r->timing) {
+            span.start = take_event(r);
+            span.stop = take_event(r);
+            if (!span.start || !span.stop) return fail(GA_EDEVICE, "hipEventCreate failed");
+            hipError_t e = hipEventRecord(span.start, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        }
+        for (uint32_t k = 0; k < n; ++k) {
+            const hsga::StepParams p = step_params(r, r->T + k, 0);
+            hipError_t e = hsga::launch_step(p, r->SW, model, mig, r->apt, r->block, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "step launch");
+        }
+        if (r->timing) {
+            hipError_t e = hipEventRecord(span.stop, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+            r->spans.push_back(span);
+        }
+        r->T += n;
+        return GA_OK;
+    }
     while (n > 0) {
         const uint32_t G = n < r->gens ? n : r->gens;
         const uint32_t tau0 = hsga::ingests_of(r->T, cfg.ingest_interval);

@@ -12,8 +12,9 @@ constexpr uint32_t kEmpty = 0xffffffffu;
 constexpr uint32_t kSteady = 0, kTilted = 1, kHybrid = 2;
 // Fourth Philox counter word: what the draw is for.
 constexpr uint32_t kBirth = 0, kEmigrate = 1, kImmigrate = 2, kSample = 3;
-// Second block of a float-treatment birth; founder tags.
-constexpr uint32_t kBirthB = 4, kFounder = 5;
+// Second block of a float-treatment birth; founder tags; whether an island
+// is active on a tick of an asynchronous run.
+constexpr uint32_t kBirthB = 4, kFounder = 5, kActivity = 6;
 // Outbox entry: dir, trait, counter, surface words (up to 2), padding.
 constexpr uint32_t kOutboxWords = 8;
 

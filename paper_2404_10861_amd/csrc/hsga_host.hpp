@@ -23,7 +23,8 @@ struct ga_run {
     uint32_t* layout;
     uint32_t* sites;
     uint32_t gens;       // site schedule capacity
-    uint32_t T;          // generations enqueued
+    uint32_t T;          // generations (ticks, when asynchronous) enqueued
+    uint32_t tab_filled; // asynchronous: ingests whose sites are in `sites`
     uint64_t horizon;
     uint32_t apt;        // agents per thread (1, 2, 4; divides N)
     uint32_t block;      // workgroup threads

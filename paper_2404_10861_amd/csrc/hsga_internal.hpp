@@ -44,6 +44,9 @@ struct StepParams {
     uint32_t tile_isl;         // islands per workgroup tile
     uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
     uint32_t diff_log2;        // log2 of the differentia width: 0 (bit) or 3 (byte)
+    uint32_t async_thr;        // asynchronous ticks: island activity threshold; 0: synchronous
+    const uint32_t* site_tab;  // asynchronous ticks: site of every ingest so far
+    uint32_t interval;         // asynchronous ticks: the ingest interval
     uint32_t tour;             // float model: tournament draws, 1..5
     uint32_t del_thr, ben_thr; // float model: mutation class thresholds
     float del_sigma, ben_sigma;

@@ -164,7 +164,7 @@ extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
 
 // One tile of one run.  Shared by the plain kernel (one run per launch) and
 // the batched kernel (many runs per launch).
-template <int SW, uint32_t BM, bool MIGR, int APT>
+template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC = false>
 __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     uint32_t* lds = g_step_lds;
     const uint32_t N = p.N, W = p.W;
@@ -192,16 +192,24 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
 #pragma unroll
         for (int w = 0; w < SW; ++w) sf[w] = load_lanes<APT>(p.in_surf + w * A + a0 + la0);
     }
-    if (MIGR) {
-        for (uint32_t b = t; b < 2 * nisl; b += blockDim.x) {
+    if (MIGR || ASYNC) {
+        // asynchronous ticks: an island runs a generation iff its activity
+        // draw is below the threshold (plan bit 31); an idle island takes no
+        // immigrants and posts no emigrant (direction 4)
+        const uint32_t passes = MIGR ? 2 * nisl : nisl;
+        for (uint32_t b = t; b < passes; b += blockDim.x) {
             const bool imm = b < nisl;
             const uint32_t il = imm ? b : b - nisl;
             const uint32_t isl = first_isl + il;
-            const uint4 w4 = philox4x32_10(make_uint4(0u, isl, p.g, imm ? kImmigrate : kEmigrate),
-                                           p.k0, p.k1);
+            bool act = true;
+            if constexpr (ASYNC)
+                act = philox4x32_10(make_uint4(0u, isl, p.g, kActivity), p.k0, p.k1).x <
+                      p.async_thr;
             if (imm) {
                 uint32_t plan = 0;
-                if (p.has_inbox) {
+                if (MIGR && act && p.has_inbox) {
+                    const uint4 w4 =
+                        philox4x32_10(make_uint4(0u, isl, p.g, kImmigrate), p.k0, p.k1);
                     const uint32_t x = isl % W;
                     // a neighbour delivers when its emigrant was sent our way
                     const uint32_t dn = p.ob_in[(size_t)neighbour_of(isl, x, 0, W, p.I) * kOutboxWords];
@@ -215,9 +223,11 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
                     plan |= word_below(w4.z, N) << 16;
                     plan |= word_below(w4.w, N) << 22;
                 }
+                if (ASYNC && act) plan |= 1u << 31;
                 l_plan[il] = plan;
             } else {
-                l_emig[il] = word_below(w4.x, N) | ((w4.y >> 30) << 8);
+                const uint4 w4 = philox4x32_10(make_uint4(0u, isl, p.g, kEmigrate), p.k0, p.k1);
+                l_emig[il] = word_below(w4.x, N) | ((act ? (w4.y >> 30) : 4u) << 8);
             }
         }
     }
@@ -280,65 +290,94 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         const uint32_t il = (la * p.div_magic) >> 20;   // la / N, exact for la < 4096
         const uint32_t j = la - il * N;
         const uint32_t isl = first_isl + il;
-        const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
-        const uint32_t base = il * N;
-        uint32_t par = base + word_below(r.x, N);
-        uint32_t bit;
-        if constexpr (BM == kBirthFloat) {
-            // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x), the
-            // first of maximal fitness winning; mutation class from v.y,
-            // |Z| from v.z and v.w, differentia the low bits of v.w
-            const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
-            float best = __uint_as_float(l_trait[par]);
-            const uint32_t words[4] = {r.y, r.z, r.w, v.x};
+        bool act = true;
+        if constexpr (ASYNC) act = (l_plan[il] >> 31) != 0u;
+        if (!act) {
+            // idle island: the same individual on the next tick
+            ctr.v[q] = l_trait[la];
+            ccn.v[q] = l_count[la];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if ((uint32_t)c + 1u < p.tour) {
-                    const uint32_t cb = base + word_below(words[c], N);
-                    const float fc = __uint_as_float(l_trait[cb]);
-                    if (fc > best) {
-                        best = fc;
-                        par = cb;
+            for (int w = 0; w < SW; ++w) csf[w].v[q] = l_surf[w * TA + la];
+        } else {
+            const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
+            const uint32_t base = il * N;
+            uint32_t par = base + word_below(r.x, N);
+            uint32_t bit;
+            if constexpr (BM == kBirthFloat) {
+                // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x),
+                // the first of maximal fitness winning; mutation class from
+                // v.y, |Z| from v.z and v.w, differentia the low bits of v.w
+                const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
+                float best = __uint_as_float(l_trait[par]);
+                const uint32_t words[4] = {r.y, r.z, r.w, v.x};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if ((uint32_t)c + 1u < p.tour) {
+                        const uint32_t cb = base + word_below(words[c], N);
+                        const float fc = __uint_as_float(l_trait[cb]);
+                        if (fc > best) {
+                            best = fc;
+                            par = cb;
+                        }
                     }
                 }
+                const bool del = v.y < p.del_thr;
+                const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
+                ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
+                                                                         p.ben_sigma, v.z, v.w))
+                                        : __float_as_uint(best);
+                bit = v.w & diff_mask;
+            } else {
+                uint32_t ptrait = l_trait[par];
+                if constexpr (BM == kBirthIntTournament) {
+                    const uint32_t pb = base + word_below(r.y, N);
+                    const uint32_t tb = l_trait[pb];
+                    if ((int32_t)tb > (int32_t)ptrait) {
+                        par = pb;
+                        ptrait = tb;
+                    }
+                }
+                const uint32_t delta =
+                    r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo)
+                                    : 0u;
+                ctr.v[q] = ptrait + delta;
+                bit = r.w & diff_mask;
             }
-            const bool del = v.y < p.del_thr;
-            const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
-            ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
-                                                                     p.ben_sigma, v.z, v.w))
-                                    : __float_as_uint(best);
-            bit = v.w & diff_mask;
-        } else {
-            uint32_t ptrait = l_trait[par];
-            if constexpr (BM == kBirthIntTournament) {
-                const uint32_t pb = base + word_below(r.y, N);
-                const uint32_t tb = l_trait[pb];
-                if ((int32_t)tb > (int32_t)ptrait) {
-                    par = pb;
-                    ptrait = tb;
+            const uint32_t T = l_count[par];
+            ccn.v[q] = T + 1u;
+            uint32_t dep_word = site_word, dep_shift = site_shift;
+            if constexpr (ASYNC) {
+                // the parent's own counter picks the item and, through the
+                // site table, its site
+                const uint32_t tau = p.interval == 1u ? T : T / p.interval;
+                dep_word = 0xffu;
+                if (tau * p.interval == T) {
+                    const uint32_t site = p.site_tab[tau];
+                    dep_word = site >> (5u - p.diff_log2);
+                    dep_shift = (site << p.diff_log2) & 31u;
                 }
             }
-            const uint32_t delta =
-                r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo) : 0u;
-            ctr.v[q] = ptrait + delta;
-            bit = r.w & diff_mask;
-        }
-        ccn.v[q] = l_count[par] + 1u;
 #pragma unroll
-        for (int w = 0; w < SW; ++w) {
-            const uint32_t word = l_surf[w * TA + par];
-            csf[w].v[q] = (uint32_t)w == site_word
-                              ? (word & ~(diff_mask << site_shift)) | (bit << site_shift)
-                              : word;
+            for (int w = 0; w < SW; ++w) {
+                const uint32_t word = l_surf[w * TA + par];
+                csf[w].v[q] = (uint32_t)w == dep_word
+                                  ? (word & ~(diff_mask << dep_shift)) | (bit << dep_shift)
+                                  : word;
+            }
         }
         if (MIGR) {
             const uint32_t em = l_emig[il];
             if (j == (em & 0xffu)) {
                 uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
-                *reinterpret_cast<uint4*>(o) =
-                    make_uint4((em >> 8) & 3u, ctr.v[q], ccn.v[q], csf[0].v[q]);
-                *reinterpret_cast<uint4*>(o + 4) =
-                    make_uint4(SW > 1 ? csf[SW - 1].v[q] : 0u, 0u, 0u, 0u);
+                const uint32_t dir = (em >> 8) & 7u;
+                if (dir < 4u) {
+                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, ctr.v[q], ccn.v[q], csf[0].v[q]);
+                    *reinterpret_cast<uint4*>(o + 4) =
+                        make_uint4(SW > 1 ? csf[SW - 1].v[q] : 0u, 0u, 0u, 0u);
+                } else {
+                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, 0u, 0u, 0u);
+                    *reinterpret_cast<uint4*>(o + 4) = make_uint4(0u, 0u, 0u, 0u);
+                }
             }
         }
     }
@@ -348,9 +387,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
 }
 
-template <int SW, uint32_t BM, bool MIGR, int APT>
+template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
 __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
-    step_tile<SW, BM, MIGR, APT>(p, xcd_local_block(blockIdx.x, gridDim.x));
+    step_tile<SW, BM, MIGR, APT, ASYNC>(p, xcd_local_block(blockIdx.x, gridDim.x));
 }
 
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
@@ -358,47 +397,57 @@ size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
     return ((2 + SW) * TA + 2 * (size_t)tile_isl) * 4;
 }
 
-template <int SW, uint32_t BM, bool MIGR, int APT>
+template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
 static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
     const uint32_t tiles = (p.I + p.tile_isl - 1) / p.tile_isl;
     const size_t lds = step_lds_bytes(p.tile_isl, p.N, SW);
-    hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT>), dim3(tiles), dim3(block_threads), lds,
-                       stream, p);
+    hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT, ASYNC>), dim3(tiles), dim3(block_threads),
+                       lds, stream, p);
     return hipGetLastError();
 }
 
-template <int SW, uint32_t BM, bool MIGR>
+template <int SW, uint32_t BM, bool MIGR, bool ASYNC>
 static hipError_t launch_step_apt(const StepParams& p, uint32_t apt, uint32_t block_threads,
                                   hipStream_t stream) {
-    if (apt == 4) return launch_step_t<SW, BM, MIGR, 4>(p, block_threads, stream);
-    if (apt == 2) return launch_step_t<SW, BM, MIGR, 2>(p, block_threads, stream);
-    return launch_step_t<SW, BM, MIGR, 1>(p, block_threads, stream);
+    if (apt == 4) return launch_step_t<SW, BM, MIGR, 4, ASYNC>(p, block_threads, stream);
+    if (apt == 2) return launch_step_t<SW, BM, MIGR, 2, ASYNC>(p, block_threads, stream);
+    return launch_step_t<SW, BM, MIGR, 1, ASYNC>(p, block_threads, stream);
 }
 
-template <int SW, uint32_t BM>
+template <int SW, uint32_t BM, bool ASYNC>
 static hipError_t launch_step_mig(const StepParams& p, bool migration, uint32_t apt,
                                   uint32_t block_threads, hipStream_t stream) {
-    return migration ? launch_step_apt<SW, BM, true>(p, apt, block_threads, stream)
-                     : launch_step_apt<SW, BM, false>(p, apt, block_threads, stream);
+    return migration ? launch_step_apt<SW, BM, true, ASYNC>(p, apt, block_threads, stream)
+                     : launch_step_apt<SW, BM, false, ASYNC>(p, apt, block_threads, stream);
 }
 
-template <int SW>
+template <int SW, bool ASYNC>
 static hipError_t launch_step_model(const StepParams& p, uint32_t birth_model, bool migration,
                                     uint32_t apt, uint32_t block_threads, hipStream_t stream) {
     if (birth_model == kBirthFloat)
-        return launch_step_mig<SW, kBirthFloat>(p, migration, apt, block_threads, stream);
+        return launch_step_mig<SW, kBirthFloat, ASYNC>(p, migration, apt, block_threads, stream);
     if (birth_model == kBirthIntTournament)
-        return launch_step_mig<SW, kBirthIntTournament>(p, migration, apt, block_threads, stream);
-    return launch_step_mig<SW, kBirthIntNeutral>(p, migration, apt, block_threads, stream);
+        return launch_step_mig<SW, kBirthIntTournament, ASYNC>(p, migration, apt, block_threads,
+                                                               stream);
+    return launch_step_mig<SW, kBirthIntNeutral, ASYNC>(p, migration, apt, block_threads, stream);
+}
+
+template <bool ASYNC>
+static hipError_t launch_step_sw(const StepParams& p, uint32_t SW, uint32_t birth_model,
+                                 bool migration, uint32_t apt, uint32_t block_threads,
+                                 hipStream_t stream) {
+    if (SW == 1)
+        return launch_step_model<1, ASYNC>(p, birth_model, migration, apt, block_threads, stream);
+    return launch_step_model<2, ASYNC>(p, birth_model, migration, apt, block_threads, stream);
 }
 
 hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream) {
-    if (SW == 1)
-        return launch_step_model<1>(p, birth_model, migration, agents_per_thread, block_threads,
-                                    stream);
-    return launch_step_model<2>(p, birth_model, migration, agents_per_thread, block_threads,
-                                stream);
+    if (p.async_thr)
+        return launch_step_sw<true>(p, SW, birth_model, migration, agents_per_thread,
+                                    block_threads, stream);
+    return launch_step_sw<false>(p, SW, birth_model, migration, agents_per_thread, block_threads,
+                                 stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -483,6 +532,9 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.has_inbox = (mig && g > 0) ? 1u : 0u;
     p.tile_isl = R.tile_isl;
     p.div_magic = R.div_magic;
+    p.async_thr = 0u;          // batched runs are synchronous
+    p.site_tab = nullptr;
+    p.interval = R.interval;
     p.tour = R.tour;
     p.del_thr = R.del_thr; p.ben_thr = R.ben_thr;
     p.del_sigma = R.del_sigma; p.ben_sigma = R.ben_sigma;

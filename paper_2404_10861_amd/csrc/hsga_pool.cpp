@@ -190,6 +190,8 @@ int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint3
     const ga_config* cfg = &cfg_copy;
     if (rc != GA_OK) return rc;
     if (n_generations == 0) return fail(GA_EINVAL, "a run needs at least one generation");
+    if (cfg->async_activity)
+        return fail(GA_EINVAL, "asynchronous runs use the plain API, not a pool");
     if ((uint64_t)n_generations - 1 >
         hsga::horizon_gen_of(cfg->surface_kind, cfg->surface_sites, cfg->ingest_interval))
         return fail(GA_EHORIZON, "generation count past the site rule's horizon");

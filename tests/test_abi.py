@@ -41,9 +41,10 @@ def test_binding_names_match_header():
 
 def test_config_struct_layout():
     import paper_2404_10861_amd.binding as b
-    # 12 uint32/int32 fields, a uint64 seed, then the six float-treatment
-    # words: 80 bytes, seed at offset 48, fitness_model at 56
-    assert ctypes.sizeof(b.ga_config) == 80
+    # 12 uint32/int32 fields, a uint64 seed, the six float-treatment and
+    # scheme words, the asynchronous activity and a reserved word: 88 bytes
+    assert ctypes.sizeof(b.ga_config) == 88
+    assert b.ga_config.async_activity.offset == 80
     assert b.ga_config.seed.offset == 48
     assert b.ga_config.fitness_model.offset == 56
     assert b.ga_config.del_sigma.offset == 68 and b.ga_config.differentia_bits.offset == 76
@@ -78,6 +79,10 @@ def test_config_versions_and_float_validation_without_gpu():
     assert full > 0
     c.struct_size = 56
     c.fitness_model = 7            # beyond a 56-byte config: never read
+    assert lib.ga_footprint_bytes(ctypes.byref(c), 0) == full
+    c.struct_size = 80
+    c.fitness_model = 0
+    c.async_activity = 9           # beyond an 80-byte config: never read
     assert lib.ga_footprint_bytes(ctypes.byref(c), 0) == full
     c.struct_size = 60
     assert lib.ga_footprint_bytes(ctypes.byref(c), 0) == 0
