@@ -110,7 +110,8 @@ def main(argv=None) -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the run length (profiling only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair", "trial", "clade"),
+    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair", "trial", "clade",
+                                       "async"),
                     default="plain",
                     help="plain: the paper-scale run (default); batched / served: the run "
                          "sets of the batched and served workloads against sequential plain runs")
@@ -136,7 +137,13 @@ def main(argv=None) -> int:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         from paper_2404_10861_amd import benchmarks
-        if args.mode == "clade":
+        if args.mode == "async":
+            spec = wl.c2()
+            spec.generations = args.generations or 2000
+            res = benchmarks.async_vs_sync(spec, 0.9, dev, torch.cuda.current_stream(dev))
+            metric = "agent-ticks/sec, asynchronous vs synchronous (paper-scale torus)"
+            value = res["asynchronous"]["agent_ticks_per_s"]
+        elif args.mode == "clade":
             t0 = time.perf_counter()
             res = benchmarks.clade_trial([wl.clade(g) for g in (25, 50, 100, 250)], dev,
                                          torch.cuda.current_stream(dev))
@@ -167,7 +174,8 @@ def main(argv=None) -> int:
                 progress=lambda text: print(text, file=sys.stderr, flush=True))
             metric = "agent-replications/sec and p50/p99 run latency (served)"
             value = res["served"]["replications_per_s"]
-        unit = "s (wall)" if args.mode == "clade" else "agent-replications/s"
+        unit = {"clade": "s (wall)", "async": "agent-ticks/s"}.get(args.mode,
+                                                                   "agent-replications/s")
         print(json.dumps({"metric": metric, "value": value, "unit": unit,
                           "n_gpus": 1, "mode": args.mode,
                           "dtype": "u32,f32,f64" if args.mode == "trial" else "u32",

@@ -251,3 +251,38 @@ def clade_trial(specs, dev, stream) -> dict:
         }
         run.close()
     return out
+
+
+def async_vs_sync(spec, activity: float, dev, stream) -> dict:
+    """The paper-scale torus run in asynchronous ticks (each island active
+    with probability `activity` per tick) against the same run in
+    synchronous generations: agent-ticks per second, the step kernel's
+    average time, and how far the islands drift apart."""
+    out = {}
+    for mode in ("synchronous", "asynchronous"):
+        kw = spec.config_kwargs()
+        if mode == "asynchronous":
+            kw["async_activity"] = int(activity * 2**32)
+        cfg = hs.Config(**kw)
+        run = hs.Run(cfg, max_gens_per_launch=spec.generations, device=dev, stream=stream)
+        run.set_kernel_timing(True)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        run.step(spec.generations)
+        run.sync()
+        wall = time.perf_counter() - t0
+        ms, launches = run.kernel_time()
+        counters = run.agents(0, min(cfg.agents, 1 << 20))[1]
+        out[mode] = {
+            "agent_ticks_per_s": cfg.agents * spec.generations / wall,
+            "expected_births_per_s": cfg.agents * spec.generations *
+                                     (activity if mode == "asynchronous" else 1.0) / wall,
+            "wall_s": wall,
+            "step_kernel_avg_us": ms * 1000.0 / max(launches, 1),
+            "counter_min": int(counters.min()), "counter_max": int(counters.max()),
+            "counter_mean": float(counters.mean()),
+        }
+        run.close()
+    out["activity"] = activity
+    out["ticks"] = spec.generations
+    return out
