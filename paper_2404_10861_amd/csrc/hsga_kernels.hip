@@ -908,104 +908,176 @@ __global__ __launch_bounds__(1024) void phylo_sort_kernel(uint32_t npad,
     }
 }
 
-struct PhyloScratch {
-    uint8_t* depth;        // n - 1 boundary depths
-    uint32_t* left;        // nearest strictly shallower boundary on the left
-    uint32_t* left_le;     // nearest not-deeper boundary on the left
-    uint32_t* right;       // nearest not-deeper boundary on the right (m if none)
-    uint32_t* rstrict;     // nearest strictly shallower boundary on the right
-    uint32_t* stack;
+// Boundary depths and the tree, in parallel.  tab[k][i] = the minimum depth
+// over boundaries [i, i + 2^k) (a sparse table); the nearest boundary to the
+// left or right of b shallower than a depth is found by binary lifting over
+// it, one thread per boundary.  Sums go to 64-bit accumulators.
+constexpr uint32_t kPhyloMaxLevels = 17;   // 2^16 > 65534 boundaries
+constexpr uint32_t kNoBoundary = 0xffffffffu;
+
+struct PhyloAcc {
+    unsigned long long sbl, pairs, internal, dmin;
 };
 
-__global__ __launch_bounds__(256) void phylo_metrics_kernel(uint32_t n, uint32_t diff_log2,
-                                                           const uint32_t* __restrict__ ws,
-                                                           const uint64_t* __restrict__ keys,
-                                                           PhyloScratch sc,
-                                                           uint64_t* __restrict__ out) {
-    const uint32_t status = ws[kWsStatus];
-    if (status != 0) {
-        if (threadIdx.x == 0) {
-            out[0] = out[1] = out[2] = out[3] = 0;
-            out[4] = status;
-            out[5] = n;
-        }
-        return;
+__device__ __forceinline__ uint64_t phylo_tau(const uint32_t* ws, uint32_t d) {
+    const uint32_t F = ws[kWsF];
+    return d < F ? (uint64_t)ws[kWsTimes + d] : (uint64_t)ws[kWsT];
+}
+
+__global__ __launch_bounds__(256) void phylo_depth_kernel(uint32_t n, uint32_t diff_log2,
+                                                         const uint32_t* __restrict__ ws,
+                                                         const uint64_t* __restrict__ keys,
+                                                         uint8_t* __restrict__ depth,
+                                                         PhyloAcc* __restrict__ acc) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t F = ws[kWsF];
+    if (i == 0) {
+        acc->sbl = 0;
+        acc->pairs = 0;
+        acc->internal = 0;
+        acc->dmin = F;
     }
-    const uint32_t T = ws[kWsT], F = ws[kWsF];
-    const uint32_t* times = ws + kWsTimes;
-    const uint32_t m = n - 1;                              // boundaries
-    uint8_t* depth = sc.depth;
-    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+    if (i + 1 < n) {
         const uint64_t x = keys[i] ^ keys[i + 1];
         const uint32_t d = x ? ((uint32_t)__clzll((long long)x) >> diff_log2) : 64u;
         depth[i] = (uint8_t)(d < F ? d : F);
     }
+}
+
+// Level k of the sparse table from level k - 1 (m boundaries per level).
+__global__ __launch_bounds__(256) void phylo_table_kernel(uint32_t m, uint32_t k,
+                                                         const uint32_t* __restrict__ ws,
+                                                         uint8_t* __restrict__ tab) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t half = 1u << (k - 1);
+    if (i + 2 * half > m) return;
+    const uint8_t* prev = tab + (size_t)(k - 1) * m;
+    const uint8_t a = prev[i], b = prev[i + half];
+    tab[(size_t)k * m + i] = a < b ? a : b;
+}
+
+// Nearest boundary i < b with depth[i] < d.
+__device__ __forceinline__ uint32_t phylo_left_below(const uint8_t* tab, uint32_t m,
+                                                     uint32_t levels, uint32_t b, uint32_t d) {
+    uint32_t pos = b;   // every boundary in [pos, b) is at depth >= d
+    for (uint32_t k = levels; k-- > 0;) {
+        const uint32_t len = 1u << k;
+        if (pos >= len && tab[(size_t)k * m + pos - len] >= d) pos -= len;
+    }
+    return pos == 0 ? kNoBoundary : pos - 1;
+}
+
+// Nearest boundary i > b with depth[i] < d.
+__device__ __forceinline__ uint32_t phylo_right_below(const uint8_t* tab, uint32_t m,
+                                                      uint32_t levels, uint32_t b, uint32_t d) {
+    uint32_t pos = b + 1;   // every boundary in (b, pos) is at depth >= d
+    for (uint32_t k = levels; k-- > 0;) {
+        const uint32_t len = 1u << k;
+        if (pos + len <= m && tab[(size_t)k * m + pos] >= d) pos += len;
+    }
+    return pos >= m ? kNoBoundary : pos;
+}
+
+__device__ __forceinline__ void phylo_add(PhyloAcc* acc, uint64_t sbl, uint64_t pairs,
+                                          uint64_t internal, uint32_t dmin) {
+    __shared__ unsigned long long s_sbl, s_pairs, s_internal;
+    __shared__ uint32_t s_dmin;
+    if (threadIdx.x == 0) {
+        s_sbl = 0;
+        s_pairs = 0;
+        s_internal = 0;
+        s_dmin = 0xffffffffu;
+    }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    auto tau = [&](uint32_t d) -> uint64_t { return d < F ? times[d] : T; };
-    constexpr uint32_t kNone = 0xffffffffu;
-    uint32_t* stack = sc.stack;
-    // nearest to the left: strictly shallower, and not deeper
-    uint32_t top = 0;
-    for (uint32_t b = 0; b < m; ++b) {
-        while (top && depth[stack[top - 1]] >= depth[b]) --top;
-        sc.left[b] = top ? stack[top - 1] : kNone;
-        stack[top++] = b;
+    if (sbl) atomicAdd(&s_sbl, (unsigned long long)sbl);
+    if (pairs) atomicAdd(&s_pairs, (unsigned long long)pairs);
+    if (internal) atomicAdd(&s_internal, (unsigned long long)internal);
+    if (dmin != 0xffffffffu) atomicMin(&s_dmin, dmin);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_sbl) atomicAdd(&acc->sbl, s_sbl);
+        if (s_pairs) atomicAdd(&acc->pairs, s_pairs);
+        if (s_internal) atomicAdd(&acc->internal, s_internal);
+        if (s_dmin != 0xffffffffu) atomicMin(&acc->dmin, (unsigned long long)s_dmin);
     }
-    top = 0;
-    for (uint32_t b = 0; b < m; ++b) {
-        while (top && depth[stack[top - 1]] > depth[b]) --top;
-        sc.left_le[b] = top ? stack[top - 1] : kNone;
-        stack[top++] = b;
-    }
-    // nearest to the right: strictly shallower, and not deeper
-    top = 0;
-    for (uint32_t b = m; b-- > 0;) {
-        while (top && depth[stack[top - 1]] >= depth[b]) --top;
-        sc.rstrict[b] = top ? stack[top - 1] : kNone;
-        stack[top++] = b;
-    }
-    top = 0;
-    for (uint32_t b = m; b-- > 0;) {
-        while (top && depth[stack[top - 1]] > depth[b]) --top;
-        sc.right[b] = top ? stack[top - 1] : m;
-        stack[top++] = b;
-    }
+}
+
+// One thread per boundary b (depth d):
+//   pairs meeting at b (b the rightmost shallowest boundary between them):
+//     (b - L) (Rq - b), L = nearest left shallower (-1 if none), Rq =
+//     nearest right not deeper (m if none), each adding T - tau(d);
+//   a tree node starts at b unless the nearest not-deeper boundary on its
+//   left has the same depth (one many-way node, or a run of identical
+//   annotations); the node hangs from the deeper of its nearest shallower
+//   boundaries (none on either side: the root).
+__global__ __launch_bounds__(256) void phylo_boundary_kernel(uint32_t m, uint32_t levels,
+                                                            const uint32_t* __restrict__ ws,
+                                                            const uint8_t* __restrict__ tab,
+                                                            PhyloAcc* __restrict__ acc) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t sbl = 0, pairs = 0, internal = 0;
-    uint32_t dmin = F;
-    for (uint32_t b = 0; b < m; ++b) {
+    uint32_t dmin = 0xffffffffu;
+    if (b < m) {
+        const uint8_t* depth = tab;
         const uint32_t d = depth[b];
-        dmin = d < dmin ? d : dmin;
-        // pairs meeting at b (b the rightmost shallowest boundary between them)
-        const uint32_t L = sc.left[b];
-        const uint64_t nl = (uint64_t)b - (L == kNone ? (uint64_t)-1 : L);
-        const uint64_t nr = (uint64_t)sc.right[b] - b;
-        pairs += (T - tau(d)) * nl * nr;
-        // a node starts here unless an equal-depth boundary of the same node
-        // lies to the left with nothing shallower between
-        const uint32_t Lq = sc.left_le[b];
-        if (Lq != kNone && depth[Lq] == d) continue;
-        ++internal;
-        const uint32_t R = sc.rstrict[b];
-        if (L == kNone && R == kNone) continue;   // the root
-        uint32_t pd;
-        if (L == kNone) pd = depth[R];
-        else if (R == kNone) pd = depth[L];
-        else pd = depth[L] > depth[R] ? depth[L] : depth[R];
-        sbl += tau(d) - tau(pd);
+        const uint64_t T = ws[kWsT];
+        const uint32_t L = phylo_left_below(tab, m, levels, b, d);
+        const uint32_t Lq = phylo_left_below(tab, m, levels, b, d + 1);
+        const uint32_t R = phylo_right_below(tab, m, levels, b, d);
+        const uint32_t Rq = phylo_right_below(tab, m, levels, b, d + 1);
+        const uint64_t nl = (uint64_t)b - (L == kNoBoundary ? (uint64_t)-1 : L);
+        const uint64_t nr = (uint64_t)(Rq == kNoBoundary ? m : Rq) - b;
+        pairs = (T - phylo_tau(ws, d)) * nl * nr;
+        dmin = d;
+        if (Lq == kNoBoundary || depth[Lq] < d) {
+            internal = 1;
+            if (L != kNoBoundary || R != kNoBoundary) {
+                uint32_t pd;
+                if (L == kNoBoundary) pd = depth[R];
+                else if (R == kNoBoundary) pd = depth[L];
+                else pd = depth[L] > depth[R] ? depth[L] : depth[R];
+                sbl = phylo_tau(ws, d) - phylo_tau(ws, pd);
+            }
+        }
     }
-    for (uint32_t i = 0; i < n; ++i) {
-        uint32_t pd = 0;
-        bool any = false;
-        if (i > 0) { pd = depth[i - 1]; any = true; }
-        if (i < m) { pd = any && pd > depth[i] ? pd : depth[i]; any = true; }
-        if (any) sbl += T - tau(pd);
+    phylo_add(acc, sbl, pairs, internal, dmin);
+}
+
+// One thread per leaf: its edge from the deeper adjacent boundary to T.
+__global__ __launch_bounds__(256) void phylo_leaf_kernel(uint32_t n,
+                                                        const uint32_t* __restrict__ ws,
+                                                        const uint8_t* __restrict__ depth,
+                                                        PhyloAcc* __restrict__ acc) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t sbl = 0;
+    if (i < n && n > 1) {
+        const uint32_t m = n - 1;
+        uint32_t pd = i > 0 ? depth[i - 1] : 0u;
+        if (i < m && (i == 0 || depth[i] > pd)) pd = depth[i];
+        sbl = (uint64_t)ws[kWsT] - phylo_tau(ws, pd);
     }
-    out[0] = sbl;
-    out[1] = pairs;
-    out[2] = n > 1 ? tau(dmin) : T;
-    out[3] = internal;
-    out[4] = 0;
+    phylo_add(acc, sbl, 0, 0, 0xffffffffu);
+}
+
+__global__ __launch_bounds__(64) void phylo_finish_kernel(uint32_t n,
+                                                         const uint32_t* __restrict__ ws,
+                                                         const PhyloAcc* __restrict__ acc,
+                                                         uint64_t* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    const uint32_t status = ws[kWsStatus];
+    if (status != 0) {
+        out[0] = out[1] = out[2] = out[3] = 0;
+    } else {
+        out[0] = acc->sbl;
+        out[1] = acc->pairs;
+        out[2] = n > 1 ? phylo_tau(ws, (uint32_t)acc->dmin) : ws[kWsT];
+        out[3] = acc->internal;
+    }
+    out[4] = status;
     out[5] = n;
 }
 
@@ -1013,7 +1085,7 @@ size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
     size_t npad = 1;
     while (npad < n) npad <<= 1;
     const size_t a = (MrcaWorkspace::bytes(S, n) + 255) & ~(size_t)255;
-    return a + npad * 8 + npad * 4 + (size_t)n * (1 + 5 * 4) + 1024;
+    return a + npad * 8 + npad * 4 + 256 + (size_t)kPhyloMaxLevels * n + 1024;
 }
 
 hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
@@ -1028,22 +1100,29 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
     size_t off = (MrcaWorkspace::bytes(scm.S, n) + 255) & ~(size_t)255;
     uint64_t* keys = reinterpret_cast<uint64_t*>(base + off);   off += npad * 8;
     uint32_t* idx = reinterpret_cast<uint32_t*>(base + off);    off += npad * 4;
-    PhyloScratch sc;
-    sc.left = reinterpret_cast<uint32_t*>(base + off);     off += (size_t)n * 4;
-    sc.left_le = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
-    sc.right = reinterpret_cast<uint32_t*>(base + off);    off += (size_t)n * 4;
-    sc.rstrict = reinterpret_cast<uint32_t*>(base + off);  off += (size_t)n * 4;
-    sc.stack = reinterpret_cast<uint32_t*>(base + off);    off += (size_t)n * 4;
-    sc.depth = base + off;
+    off = (off + 255) & ~(size_t)255;
+    PhyloAcc* acc = reinterpret_cast<PhyloAcc*>(base + off);    off += 256;
+    uint8_t* tab = base + off;                                  // levels x m bytes
+    const uint32_t m = n - 1;
+    uint32_t levels = 1;
+    while (levels < kPhyloMaxLevels && (2u << (levels - 1)) <= m) ++levels;
+    const uint32_t gn = (n + 255) / 256;
     hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
-    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, scm.S,
-                       diff_log2, n, surf, ws, ranked);
+    hipLaunchKernelGGL(mrca_rank_kernel, dim3(gn), dim3(256), 0, stream, scm.S, diff_log2, n,
+                       surf, ws, ranked);
     hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
                        stream, n, (uint32_t)npad, diff_log2, ranked, ws, keys, idx);
     hipLaunchKernelGGL(phylo_sort_kernel, dim3(1), dim3(1024), 0, stream, (uint32_t)npad, ws,
                        keys, idx);
-    hipLaunchKernelGGL(phylo_metrics_kernel, dim3(1), dim3(256), 0, stream, n, diff_log2, ws,
-                       keys, sc, out);
+    hipLaunchKernelGGL(phylo_depth_kernel, dim3(gn), dim3(256), 0, stream, n, diff_log2, ws, keys,
+                       tab, acc);
+    for (uint32_t k = 1; k < levels; ++k)
+        hipLaunchKernelGGL(phylo_table_kernel, dim3(gn), dim3(256), 0, stream, m, k, ws, tab);
+    if (m > 0)
+        hipLaunchKernelGGL(phylo_boundary_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, m,
+                           levels, ws, tab, acc);
+    hipLaunchKernelGGL(phylo_leaf_kernel, dim3(gn), dim3(256), 0, stream, n, ws, tab, acc);
+    hipLaunchKernelGGL(phylo_finish_kernel, dim3(1), dim3(64), 0, stream, n, ws, acc, out);
     return hipGetLastError();
 }
 
