@@ -271,7 +271,7 @@ def main(argv=None) -> int:
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": measured_traffic(spec),
-            "kernel": "step_kernel<2,true,true>",
+            "kernel": "step_kernel<2, kBirthIntTournament, migration, 4 agents per thread>",
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "attainable_copy_GBs": copy_gbs,
