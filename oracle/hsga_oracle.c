@@ -1263,10 +1263,28 @@ static void phylo_walk(orc_phylo_ctx *c, int v, uint32_t d, int has_parent,
     }
 }
 
-int orc_phylo_metrics_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
-                        uint32_t n, const uint32_t *counters, const uint32_t *surf,
-                        uint64_t out[4], double *ed)
+/* The trie of n annotations sharing a counter: retained deposit times in
+ * ascending order (times[F]), the trie, and the annotations at each depth-F
+ * node (leaf_next chains).  Returns 0, -1 if the counters differ or are past
+ * the horizon, -2 on no memory.                                             */
+typedef struct {
+    uint32_t T, F;
+    uint32_t times[64];
+    orc_trie trie;
+    int *leaf_next;
+} orc_built_trie;
+
+static void trie_free(orc_built_trie *b)
 {
+    free(b->leaf_next);
+    free(b->trie.nodes);
+}
+
+static int build_trie(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
+                      uint32_t n, const uint32_t *counters, const uint32_t *surf,
+                      orc_built_trie *b)
+{
+    memset(b, 0, sizeof *b);
     if (!scheme_ok(S, bits, interval))
         return -1;
     uint32_t SW = S * bits / 32;
@@ -1278,62 +1296,242 @@ int orc_phylo_metrics_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t inter
     if (orc_layout(kind, S, ingests_of(T, interval), L) != 0)
         return -1;
     /* retained sites in ascending deposit time */
-    uint32_t times[64], sites[64], F = 0;
+    uint32_t sites[64], F = 0;
     for (uint32_t k = 0; k < S; k++) {
         if (L[k] == ORC_EMPTY)
             continue;
         uint32_t q = F++;
-        while (q > 0 && times[q - 1] > L[k] * interval) {
-            times[q] = times[q - 1];
+        while (q > 0 && b->times[q - 1] > L[k] * interval) {
+            b->times[q] = b->times[q - 1];
             sites[q] = sites[q - 1];
             q--;
         }
-        times[q] = L[k] * interval;
+        b->times[q] = L[k] * interval;
         sites[q] = k;
     }
-    orc_trie trie = {0};
-    int *leaf_next = (int *)malloc((size_t)(n ? n : 1) * sizeof(int));
-    if (!leaf_next || trie_new(&trie, 0) < 0) {
-        free(leaf_next);
-        free(trie.nodes);
+    b->T = T;
+    b->F = F;
+    b->leaf_next = (int *)malloc((size_t)(n ? n : 1) * sizeof(int));
+    if (!b->leaf_next || trie_new(&b->trie, 0) < 0) {
+        trie_free(b);
         return -2;
     }
+    orc_trie *trie = &b->trie;
     for (uint32_t a = 0; a < n; a++) {
         int v = 0;
-        trie.nodes[v].nleaves++;
+        trie->nodes[v].nleaves++;
         for (uint32_t r = 0; r < F; r++) {
             uint32_t val = site_value(surf + (size_t)a * SW, sites[r], bits);
-            int w = trie.nodes[v].first_child;
-            while (w >= 0 && trie.nodes[w].value != val)
-                w = trie.nodes[w].next_sibling;
+            int w = trie->nodes[v].first_child;
+            while (w >= 0 && trie->nodes[w].value != val)
+                w = trie->nodes[w].next_sibling;
             if (w < 0) {
-                w = trie_new(&trie, val);
+                w = trie_new(trie, val);
                 if (w < 0) {
-                    free(leaf_next);
-                    free(trie.nodes);
+                    trie_free(b);
                     return -2;
                 }
-                trie.nodes[w].next_sibling = trie.nodes[v].first_child;
-                trie.nodes[v].first_child = w;
+                trie->nodes[w].next_sibling = trie->nodes[v].first_child;
+                trie->nodes[v].first_child = w;
             }
             v = w;
-            trie.nodes[v].nleaves++;
+            trie->nodes[v].nleaves++;
         }
-        leaf_next[a] = trie.nodes[v].leaf_first;
-        trie.nodes[v].leaf_first = (int)a;
+        b->leaf_next[a] = trie->nodes[v].leaf_first;
+        trie->nodes[v].leaf_first = (int)a;
     }
-    orc_phylo_ctx c = {times, F, T, &trie, leaf_next, 0, 0, 0, 0, 0, ed};
+    return 0;
+}
+
+int orc_phylo_metrics_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
+                        uint32_t n, const uint32_t *counters, const uint32_t *surf,
+                        uint64_t out[4], double *ed)
+{
+    orc_built_trie b;
+    int rc = build_trie(kind, S, bits, interval, n, counters, surf, &b);
+    if (rc)
+        return rc;
+    orc_phylo_ctx c = {b.times, b.F, b.T, &b.trie, b.leaf_next, 0, 0, 0, 0, 0, ed};
     if (n > 0)
         phylo_walk(&c, 0, 0, 0, 0, 0.0);
     if (!c.have_root)
-        c.root_time = T;
+        c.root_time = b.T;
     out[0] = c.sbl;
     out[1] = c.pair_sum;
     out[2] = c.root_time;
     out[3] = c.internal;
-    free(leaf_next);
-    free(trie.nodes);
+    trie_free(&b);
     return 0;
+}
+
+/* The reconstructed tree as canonical Newick text: leaves are annotation
+ * indices, branch lengths are generations, the children of every node are
+ * listed in the order of the smallest annotation index below them (and the
+ * leaves of a polytomy in ascending order), the root has no length.  A
+ * single annotation is "0;".                                                */
+typedef struct {
+    char *buf;
+    size_t cap, len;
+    int overflow;
+} orc_text;
+
+static void text_put(orc_text *t, const char *s)
+{
+    size_t k = strlen(s);
+    if (t->len + k + 1 > t->cap) {
+        t->overflow = 1;
+        return;
+    }
+    memcpy(t->buf + t->len, s, k + 1);
+    t->len += k;
+}
+
+static void text_uint(orc_text *t, uint64_t v)
+{
+    char tmp[24];
+    int k = 0;
+    do {
+        tmp[k++] = (char)('0' + v % 10);
+        v /= 10;
+    } while (v);
+    char out[24];
+    for (int i = 0; i < k; i++)
+        out[i] = tmp[k - 1 - i];
+    out[k] = 0;
+    text_put(t, out);
+}
+
+/* smallest annotation index below trie node v at depth d */
+static int trie_min_leaf(const orc_built_trie *b, int v, uint32_t d)
+{
+    const orc_trie_node *nd = &b->trie.nodes[v];
+    if (d == b->F) {
+        int m = -1;
+        for (int a = nd->leaf_first; a >= 0; a = b->leaf_next[a])
+            if (m < 0 || a < m)
+                m = a;
+        return m;
+    }
+    int m = -1;
+    for (int w = nd->first_child; w >= 0; w = b->trie.nodes[w].next_sibling) {
+        int x = trie_min_leaf(b, w, d + 1);
+        if (m < 0 || x < m)
+            m = x;
+    }
+    return m;
+}
+
+static int cmp_int(const void *x, const void *y)
+{
+    int a = *(const int *)x, c = *(const int *)y;
+    return (a > c) - (a < c);
+}
+
+static int newick_walk(const orc_built_trie *b, orc_text *t, int v, uint32_t d,
+                       int has_parent, uint32_t parent_t)
+{
+    /* collapse one-child chains */
+    while (d < b->F) {
+        const orc_trie_node *nd = &b->trie.nodes[v];
+        if (nd->first_child >= 0 && b->trie.nodes[nd->first_child].next_sibling >= 0)
+            break;
+        v = nd->first_child;
+        d++;
+    }
+    const orc_trie_node *nd = &b->trie.nodes[v];
+    if (d == b->F) {
+        int k = nd->nleaves;
+        int *leaves = (int *)malloc((size_t)k * sizeof(int));
+        if (!leaves)
+            return -2;
+        int i = 0;
+        for (int a = nd->leaf_first; a >= 0; a = b->leaf_next[a])
+            leaves[i++] = a;
+        qsort(leaves, (size_t)k, sizeof(int), cmp_int);
+        if (k == 1) {
+            text_uint(t, (uint64_t)leaves[0]);
+        } else {
+            text_put(t, "(");
+            for (i = 0; i < k; i++) {
+                if (i)
+                    text_put(t, ",");
+                text_uint(t, (uint64_t)leaves[i]);
+                text_put(t, ":0");
+            }
+            text_put(t, ")");
+        }
+        free(leaves);
+        if (has_parent) {
+            text_put(t, ":");
+            text_uint(t, (uint64_t)(b->T - parent_t));
+        }
+        return 0;
+    }
+    /* a branching node at t_d: children by their smallest annotation */
+    uint32_t here = b->times[d];
+    int nch = 0;
+    for (int w = nd->first_child; w >= 0; w = b->trie.nodes[w].next_sibling)
+        nch++;
+    int *ch = (int *)malloc((size_t)nch * 2 * sizeof(int));
+    if (!ch)
+        return -2;
+    int i = 0;
+    for (int w = nd->first_child; w >= 0; w = b->trie.nodes[w].next_sibling, i++) {
+        ch[2 * i] = trie_min_leaf(b, w, d + 1);
+        ch[2 * i + 1] = w;
+    }
+    /* sort pairs by smallest leaf (insertion sort: at most 256 children) */
+    for (int p = 1; p < nch; p++) {
+        int k0 = ch[2 * p], k1 = ch[2 * p + 1], q = p;
+        while (q > 0 && ch[2 * (q - 1)] > k0) {
+            ch[2 * q] = ch[2 * (q - 1)];
+            ch[2 * q + 1] = ch[2 * (q - 1) + 1];
+            q--;
+        }
+        ch[2 * q] = k0;
+        ch[2 * q + 1] = k1;
+    }
+    text_put(t, "(");
+    for (i = 0; i < nch; i++) {
+        if (i)
+            text_put(t, ",");
+        int rc = newick_walk(b, t, ch[2 * i + 1], d + 1, 1, here);
+        if (rc) {
+            free(ch);
+            return rc;
+        }
+    }
+    text_put(t, ")");
+    free(ch);
+    if (has_parent) {
+        text_put(t, ":");
+        text_uint(t, (uint64_t)(here - parent_t));
+    }
+    return 0;
+}
+
+/* Returns the text length, -1 if the counters differ or are past the
+ * horizon, -2 on no memory, -3 if cap is too small.                        */
+long orc_phylo_newick_x(uint32_t kind, uint32_t S, uint32_t bits, uint32_t interval,
+                        uint32_t n, const uint32_t *counters, const uint32_t *surf,
+                        char *buf, size_t cap)
+{
+    if (n == 0 || cap == 0)
+        return -3;
+    orc_built_trie b;
+    int rc = build_trie(kind, S, bits, interval, n, counters, surf, &b);
+    if (rc)
+        return rc;
+    orc_text t = {buf, cap, 0, 0};
+    buf[0] = 0;
+    rc = newick_walk(&b, &t, 0, 0, 0, 0);
+    text_put(&t, ";");
+    trie_free(&b);
+    if (rc)
+        return rc;
+    if (t.overflow)
+        return -3;
+    return (long)t.len;
 }
 
 int orc_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t *counters,

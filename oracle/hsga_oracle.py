@@ -88,6 +88,9 @@ def load():
                                         [u32p, u32p, ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.POINTER(ctypes.c_double)])
     lib.orc_phylo_metrics_x.restype = ctypes.c_int
+    lib.orc_phylo_newick_x.argtypes = ([ctypes.c_uint32] * 5 +
+                                       [u32p, u32p, ctypes.c_char_p, ctypes.c_size_t])
+    lib.orc_phylo_newick_x.restype = ctypes.c_long
     lib.orc_set_fitness.argtypes = [ctypes.c_void_p] + [ctypes.c_uint32] * 4 + [ctypes.c_float] * 2
     lib.orc_set_fitness.restype = ctypes.c_int
     lib.orc_half_normal.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
@@ -347,6 +350,21 @@ def phylo_metrics(kind: int, S: int, counters, surfaces, bits: int = 1, interval
     if rc:
         raise ValueError("counters differ, past the horizon, invalid scheme, or no memory")
     return int(out[0]), int(out[1]), int(out[2]), int(out[3]), ed[:n].copy()
+
+
+def phylo_newick(kind: int, S: int, counters, surfaces, bits: int = 1,
+                 interval: int = 1) -> str:
+    """The reconstructed tree as canonical Newick text (leaves = indices)."""
+    counters = np.ascontiguousarray(counters, np.uint32)
+    surfaces = np.ascontiguousarray(surfaces, np.uint32).reshape(-1)
+    n = counters.shape[0]
+    cap = 64 * max(n, 1) + 64
+    buf = ctypes.create_string_buffer(cap)
+    rc = load().orc_phylo_newick_x(kind, S, bits, interval, n, _p(counters), _p(surfaces),
+                                   buf, cap)
+    if rc < 0:
+        raise ValueError("counters differ, past the horizon, invalid scheme, or no memory")
+    return buf.value.decode()
 
 
 # --------------------------------------------------------------------------
