@@ -308,6 +308,23 @@ int hstrat_phylo_metrics_ex(const hstrat_scheme *scheme, uint32_t n,
                             uint64_t *out, void *workspace, size_t workspace_bytes,
                             void *hip_stream);
 
+/* The reconstructed tree itself (same reconstruction and the same six
+ * result words in out).  Tree nodes are named by boundary indices in
+ * [0, n-1): leaf_parent (device, n words): the node each annotation hangs
+ * from (0xFFFFFFFF: n = 1, the annotation is the whole tree);
+ * node_parent (device, n-1 words): for a boundary naming a node, its
+ * parent node (0xFFFFFFFF for the root), 0xFFFFFFFE for a boundary that
+ * names no node; node_time (device, n-1 words): the time of the boundary's
+ * node (the MRCA upper bound of the annotations it separates; T for a
+ * polytomy of identical annotations).  Leaves sit at T.  Contents are
+ * unspecified when out[4] (status) is not 0.  Errors as
+ * hstrat_phylo_metrics_ex.                                                  */
+int hstrat_phylo_tree_ex(const hstrat_scheme *scheme, uint32_t n,
+                         const uint32_t *counter, const uint32_t *surface_words,
+                         uint32_t *leaf_parent, uint32_t *node_parent, uint32_t *node_time,
+                         uint64_t *out, void *workspace, size_t workspace_bytes,
+                         void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batched and served runs: a pool of runs of any sizes, surfaces and
  * treatments sharing one caller-owned device arena and one stream.  An

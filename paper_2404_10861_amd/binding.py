@@ -33,7 +33,7 @@ EXPORTS = (
     "ga_pool_advance", "ga_pool_poll", "ga_pool_run", "ga_pool_release", "ga_pool_sync",
     "ga_pool_set_launch", "ga_pool_info", "ga_pool_destroy",
     "hstrat_phylo_workspace_bytes", "hstrat_phylo_metrics",
-    "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex",
+    "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
 )
 
 
@@ -136,6 +136,8 @@ def load_library():
         "hstrat_phylo_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
         "hstrat_phylo_metrics": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "hstrat_phylo_tree_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp,
+                                                _vp, _vp, ctypes.c_size_t, _vp]),
         "hstrat_mrca_bounds_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp,
                                                  ctypes.c_size_t, _vp]),
         "hstrat_phylo_metrics_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp,
@@ -570,6 +572,94 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
     res["mean_ed"] = res["sum_branch_length"] / n
     res["mean_pairwise_distance"] = 2.0 * res["pair_sum"] / npairs if npairs else 0.0
     return res
+
+
+PHYLO_ROOT, PHYLO_NOT_NODE = 0xFFFFFFFF, 0xFFFFFFFE
+
+
+def phylo_tree(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
+               stream=None, bits: int = 1, interval: int = 1) -> dict:
+    """The reconstructed tree on the device: {"leaf_parent", "node_parent",
+    "node_time"} numpy uint32 arrays (nodes named by boundary indices, see
+    hstrat_phylo_tree_ex) plus the metrics of phylo_metrics."""
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    n = counter.shape[0]
+    dev = counter.device
+    if counter.dtype != torch.int32 or surface_words.dtype != torch.int32:
+        raise ValueError("counter and surface_words must be int32 tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    lib = load_library()
+    with torch.cuda.stream(stream):
+        counter = counter.contiguous()
+        surface_words = surface_words.contiguous()
+        need = int(lib.hstrat_phylo_workspace_bytes(S, n))
+        buf, ptr = _aligned_bytes(need, dev)
+        out = torch.zeros(6, dtype=torch.int64, device=dev)
+        leaf = torch.empty(n, dtype=torch.int32, device=dev)
+        node_parent = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
+        node_time = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
+        sc = _scheme(kind, S, bits, interval)
+        _check(lib.hstrat_phylo_tree_ex(ctypes.byref(sc), n, _vp(counter.data_ptr()),
+                                        _vp(surface_words.data_ptr()), _vp(leaf.data_ptr()),
+                                        _vp(node_parent.data_ptr()), _vp(node_time.data_ptr()),
+                                        _vp(out.data_ptr()), _vp(ptr), need,
+                                        _vp(_stream_handle(stream))))
+        w = out.cpu().numpy().view(np.uint64)
+        res = {"leaf_parent": as_u32(leaf), "node_parent": as_u32(node_parent)[:n - 1],
+               "node_time": as_u32(node_time)[:n - 1]}
+        del buf
+    res.update({"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
+                "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5]),
+                "T": int(counter[0].item()) & 0xFFFFFFFF})
+    return res
+
+
+def newick(tree: dict) -> str:
+    """Canonical Newick text of a phylo_tree result: leaves are annotation
+    indices, branch lengths generations, children ordered by the smallest
+    annotation index below them, no length on the root."""
+    leaf_parent, node_parent, node_time = (tree["leaf_parent"], tree["node_parent"],
+                                           tree["node_time"])
+    T = tree["T"]
+    n = len(leaf_parent)
+    if n == 1:
+        return "0;"
+    children: dict[int, list] = {}
+    root = None
+    for b, p in enumerate(node_parent):
+        if p == PHYLO_NOT_NODE:
+            continue
+        if p == PHYLO_ROOT:
+            root = b
+        else:
+            children.setdefault(int(p), []).append(("node", b))
+    for a, p in enumerate(leaf_parent):
+        children.setdefault(int(p), []).append(("leaf", a))
+    smallest: dict[int, int] = {}
+
+    def least(kind_id):
+        kind, i = kind_id
+        if kind == "leaf":
+            return i
+        if i not in smallest:
+            smallest[i] = min(least(c) for c in children[i])
+        return smallest[i]
+
+    def text(kind_id, parent_time):
+        kind, i = kind_id
+        if kind == "leaf":
+            body, t = str(i), T
+        else:
+            kids = sorted(children[i], key=least)
+            t = int(node_time[i])
+            body = "(" + ",".join(text(c, t) for c in kids) + ")"
+        return body if parent_time is None else f"{body}:{t - parent_time}"
+
+    import sys
+    sys.setrecursionlimit(max(sys.getrecursionlimit(), 4 * n + 100))
+    return text(("node", root), None) + ";"
 
 
 def mrca_status(workspace: MrcaWorkspace, stream=None) -> int:

@@ -485,6 +485,27 @@ int hstrat_phylo_metrics_ex(const hstrat_scheme* scheme, uint32_t n, const uint3
     return GA_OK;
 }
 
+int hstrat_phylo_tree_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_t* counter,
+                         const uint32_t* surface_words, uint32_t* leaf_parent,
+                         uint32_t* node_parent, uint32_t* node_time, uint64_t* out,
+                         void* workspace, size_t workspace_bytes, void* hip_stream) {
+    hsga::Scheme sc;
+    int rc = check_scheme(scheme, &sc);
+    if (rc != GA_OK) return rc;
+    if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
+    if (!counter || !surface_words || !out || !workspace || !leaf_parent ||
+        (n > 1 && (!node_parent || !node_time)))
+        return fail(GA_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < hsga::phylo_workspace_bytes(sc.S, n))
+        return fail(GA_ENOMEM, "workspace too small");
+    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace,
+                                      static_cast<hipStream_t>(hip_stream), leaf_parent,
+                                      node_parent, node_time);
+    if (e != hipSuccess) return hip_fail(e, "phylo tree launch");
+    return GA_OK;
+}
+
 int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
                          const uint32_t* surface_words, uint64_t* out, void* workspace,
                          size_t workspace_bytes, void* hip_stream) {

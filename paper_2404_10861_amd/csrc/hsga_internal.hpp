@@ -126,8 +126,12 @@ struct MrcaWorkspace {
 };
 
 size_t phylo_workspace_bytes(uint32_t S, uint32_t n);
+// leaf_parent (n), node_parent and node_time (n - 1), all device: the tree
+// itself; NULL leaf_parent computes the metrics only.
 hipError_t launch_phylo(const Scheme& sc, uint32_t n, const uint32_t* counter,
-                        const uint32_t* surf, uint64_t* out, void* workspace, hipStream_t stream);
+                        const uint32_t* surf, uint64_t* out, void* workspace, hipStream_t stream,
+                        uint32_t* leaf_parent = nullptr, uint32_t* node_parent = nullptr,
+                        uint32_t* node_time = nullptr);
 
 hipError_t launch_mrca(const Scheme& sc, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,

@@ -1081,6 +1081,72 @@ __global__ __launch_bounds__(64) void phylo_finish_kernel(uint32_t n,
     out[5] = n;
 }
 
+// The tree itself.  A node is named by the first boundary of its run (the
+// first boundary after its nearest shallower left boundary L that is not
+// deeper than it).
+constexpr uint32_t kPhyloRoot = 0xffffffffu, kPhyloNotNode = 0xfffffffeu;
+
+__device__ __forceinline__ uint32_t phylo_node_of(const uint8_t* tab, uint32_t m,
+                                                  uint32_t levels, uint32_t b) {
+    const uint32_t d = tab[b];
+    const uint32_t L = phylo_left_below(tab, m, levels, b, d);
+    if (L == kNoBoundary) return tab[0] <= d ? 0u : phylo_right_below(tab, m, levels, 0, d + 1);
+    return phylo_right_below(tab, m, levels, L, d + 1);
+}
+
+// One thread per boundary: node_parent[b] = the parent node (kPhyloRoot for
+// the root) when b starts a node, kPhyloNotNode otherwise; node_time[b] =
+// the time of b's node.
+__global__ __launch_bounds__(256) void phylo_tree_kernel(uint32_t m, uint32_t levels,
+                                                        const uint32_t* __restrict__ ws,
+                                                        const uint8_t* __restrict__ tab,
+                                                        uint32_t* __restrict__ node_parent,
+                                                        uint32_t* __restrict__ node_time) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= m) return;
+    const uint32_t d = tab[b];
+    node_time[b] = (uint32_t)phylo_tau(ws, d);
+    const uint32_t Lq = phylo_left_below(tab, m, levels, b, d + 1);
+    if (Lq != kNoBoundary && tab[Lq] == d) {
+        node_parent[b] = kPhyloNotNode;
+        return;
+    }
+    const uint32_t L = phylo_left_below(tab, m, levels, b, d);
+    const uint32_t R = phylo_right_below(tab, m, levels, b, d);
+    if (L == kNoBoundary && R == kNoBoundary) {
+        node_parent[b] = kPhyloRoot;
+        return;
+    }
+    uint32_t p;
+    if (L == kNoBoundary) p = R;
+    else if (R == kNoBoundary) p = L;
+    else p = tab[L] >= tab[R] ? L : R;
+    node_parent[b] = phylo_node_of(tab, m, levels, p);
+}
+
+// One thread per sorted position i: the annotation idx[i] hangs from the
+// node of the deeper adjacent boundary.
+__global__ __launch_bounds__(256) void phylo_tree_leaf_kernel(uint32_t n, uint32_t levels,
+                                                             const uint32_t* __restrict__ ws,
+                                                             const uint8_t* __restrict__ tab,
+                                                             const uint32_t* __restrict__ idx,
+                                                             uint32_t* __restrict__ leaf_parent) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (n == 1) {
+        leaf_parent[idx[i]] = kPhyloRoot;
+        return;
+    }
+    const uint32_t m = n - 1;
+    uint32_t pb;
+    if (i == 0) pb = 0;
+    else if (i == m) pb = m - 1;
+    else pb = tab[i] > tab[i - 1] ? i : i - 1;
+    leaf_parent[idx[i]] = phylo_node_of(tab, m, levels, pb);
+}
+
 size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
     size_t npad = 1;
     while (npad < n) npad <<= 1;
@@ -1090,7 +1156,8 @@ size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
 
 hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
                         const uint32_t* surf, uint64_t* out, void* workspace,
-                        hipStream_t stream) {
+                        hipStream_t stream, uint32_t* leaf_parent, uint32_t* node_parent,
+                        uint32_t* node_time) {
     const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
     uint8_t* base = static_cast<uint8_t*>(workspace);
     uint32_t* ws = reinterpret_cast<uint32_t*>(base);
@@ -1123,6 +1190,13 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
                            levels, ws, tab, acc);
     hipLaunchKernelGGL(phylo_leaf_kernel, dim3(gn), dim3(256), 0, stream, n, ws, tab, acc);
     hipLaunchKernelGGL(phylo_finish_kernel, dim3(1), dim3(64), 0, stream, n, ws, acc, out);
+    if (leaf_parent) {
+        if (m > 0)
+            hipLaunchKernelGGL(phylo_tree_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, m,
+                               levels, ws, tab, node_parent, node_time);
+        hipLaunchKernelGGL(phylo_tree_leaf_kernel, dim3(gn), dim3(256), 0, stream, n, levels, ws,
+                           tab, idx, leaf_parent);
+    }
     return hipGetLastError();
 }
 

@@ -104,3 +104,49 @@ def test_selection_shortens_the_tree(hs):
         res[tour] = hs.phylo_metrics("hybrid", 64, cnt, srf)
     assert res[2]["sum_branch_length"] < res[0]["sum_branch_length"]
     assert res[2]["mean_pairwise_distance"] < res[0]["mean_pairwise_distance"]
+
+
+# --------------------------------------------------------------------------
+# The reconstructed tree itself: canonical Newick text from the device's
+# node and leaf parents equals the oracle's, character for character.
+
+@pytest.mark.parametrize("kind,S,bits,interval", [("steady", 32, 1, 1), ("tilted", 64, 1, 1),
+                                                  ("hybrid", 64, 1, 3), ("steady", 8, 8, 1),
+                                                  ("tilted", 8, 8, 2)])
+def test_tree_newick_matches_oracle(hs, orc, kind, S, bits, interval):
+    cfg = hs.Config(16, 16, 32, S, kind, tournament_size=0, seed=19, differentia_bits=bits,
+                    ingest_interval=interval)
+    G = min(800, orc.horizon_gen(KIND[kind], S, interval) + 1)
+    run = hs.Run(cfg)
+    run.step(G)
+    _, cnt, srf = run.sample(1500)
+    tree = hs.phylo_tree(kind, S, cnt, srf, bits=bits, interval=interval)
+    assert tree["status"] == 0
+    want = orc.phylo_newick(KIND[kind], S, hs.as_u32(cnt), hs.as_u32(srf), bits=bits,
+                            interval=interval)
+    assert hs.newick(tree) == want
+    nodes = tree["node_parent"] != hs.binding.PHYLO_NOT_NODE
+    assert int(nodes.sum()) == tree["internal_nodes"]
+    assert int((tree["node_parent"] == hs.binding.PHYLO_ROOT).sum()) == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 257, 1025])
+def test_tree_ragged_many_way_and_polytomies(hs, orc, n):
+    rng = np.random.default_rng(7 * n)
+    counters = np.full(n, 8, np.uint32)
+    vals = rng.integers(0, 3, size=(n, 8)).astype(np.uint32)
+    vals[: n // 4] = vals[0]
+    words = np.zeros((n, 2), np.uint32)
+    for k in range(8):
+        words[:, k // 4] |= vals[:, k] << (8 * (k % 4))
+    tree = hs.phylo_tree("steady", 8, dev(counters), dev(words), bits=8)
+    assert hs.newick(tree) == orc.phylo_newick(0, 8, counters, words, bits=8)
+
+
+def test_tree_of_a_large_sample(hs, orc):
+    cfg = hs.Config(64, 64, 32, 64, "hybrid", tournament_size=2, seed=77)
+    run = hs.Run(cfg)
+    run.step(3000)
+    _, cnt, srf = run.sample(65535)
+    tree = hs.phylo_tree("hybrid", 64, cnt, srf)
+    assert hs.newick(tree) == orc.phylo_newick(2, 64, hs.as_u32(cnt), hs.as_u32(srf))
