@@ -12,7 +12,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhsga.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("hsga_kernels.hip", "hsga_api.cpp", "hsga_pool.cpp")]
+SOURCES = [os.path.join(CSRC, f)
+           for f in ("hsga_kernels.hip", "hsga_query.hip", "hsga_api.cpp", "hsga_pool.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

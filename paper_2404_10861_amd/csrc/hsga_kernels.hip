@@ -1,5 +1,7 @@
 // hsga_kernels.hip -- gfx950 kernels of the island-model GA with
-// hereditary-stratigraphy surface annotations, and their launchers.
+// hereditary-stratigraphy surface annotations (founders, site schedule, the
+// generation step, its batched form), and their launchers.  The end-of-run
+// queries live in hsga_query.hip.
 //
 // Device state is structure-of-arrays: trait[A], counter[A] and the S/32
 // surface word planes [S/32][A], agent a = island * N + slot.  Consecutive
@@ -575,653 +577,6 @@ hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(probe_copy_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream,
                        static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Stratified end-of-run sample (Results, On-hardware Trial): agent k is
-// drawn uniformly from the k-th of n equal strata; every agent when A <= n.
-__global__ __launch_bounds__(256) void sample_kernel(const uint32_t* __restrict__ counter,
-                                                    const uint32_t* __restrict__ surf, uint32_t A,
-                                                    uint32_t SW, uint32_t n, uint32_t T,
-                                                    uint32_t k0, uint32_t k1,
-                                                    uint32_t* __restrict__ idx_out,
-                                                    uint32_t* __restrict__ counter_out,
-                                                    uint32_t* __restrict__ surf_out) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t taken = A <= n ? A : n;
-    if (k >= taken) return;
-    uint32_t a = k;
-    if (A > n) {
-        const uint32_t lo = (uint32_t)((uint64_t)k * A / n);
-        const uint32_t hi = (uint32_t)((uint64_t)(k + 1) * A / n);
-        const uint4 w = philox4x32_10(make_uint4(k, 0u, T, kSample), k0, k1);
-        a = lo + word_below(w.x, hi - lo);
-    }
-    idx_out[k] = a;
-    counter_out[k] = counter[a];
-    for (uint32_t w = 0; w < SW; ++w) surf_out[(size_t)k * SW + w] = surf[(size_t)w * A + a];
-}
-
-hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
-                         uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,
-                         uint32_t* counter_out, uint32_t* surf_out, hipStream_t stream) {
-    const uint32_t taken = A <= n ? A : n;
-    const uint32_t blocks = (taken + 255) / 256;
-    hipLaunchKernelGGL(sample_kernel, dim3(blocks ? blocks : 1), dim3(256), 0, stream, counter,
-                       surf, A, SW, n, T, k0, k1, idx_out, counter_out, surf_out);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// MRCA-generation bounds (Distributed Phylogenetic Tracking: mismatching
-// differentiae delimit common ancestry).
-//
-// Workspace header words.
-constexpr uint32_t kWsStatus = 0;  // 0 all counters equal, 1 mixed, 2 past horizon
-constexpr uint32_t kWsT = 1;
-constexpr uint32_t kWsF = 2;
-constexpr uint32_t kWsPerm = 64;    // site of each time rank (ascending time)
-constexpr uint32_t kWsTimes = 128;  // deposit time of each rank
-constexpr uint32_t kWsLbTab = 192;  // 65 entries: lb when the first mismatch is rank r (64: none)
-constexpr uint32_t kWsUbTab = 320;  // 65 entries: ub likewise
-constexpr uint32_t kWsStatusMixed = 1, kWsStatusHorizon = 2;
-
-// Rank of this lane's time among the S lanes (ascending; empty sites last,
-// ties by lane).  All 64 lanes call it.
-__device__ __forceinline__ uint32_t time_rank(uint32_t held, uint32_t lane, uint32_t S) {
-    uint32_t rank = 0;
-    for (uint32_t q = 0; q < S; ++q) {
-        const uint32_t tq = __shfl(held, (int)q);
-        rank += (tq < held || (tq == held && q < lane)) ? 1u : 0u;
-    }
-    return rank;
-}
-
-// Layout after T ingests, replayed in the wavefront (lane = site).
-__device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uint32_t T,
-                                                  uint32_t lane) {
-    uint32_t held = kEmpty, leave = 0;
-    place_items(kind, S, 0, T, held, leave, lane, [](uint32_t, int) {});
-    return held;
-}
-
-// One wavefront: classify the counters; when all are equal, replay the
-// shared layout once (in ingest units), order its sites by deposit time and
-// tabulate the bounds, in generations, for every possible first-mismatch
-// rank.
-__global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
-                                                         const uint32_t* __restrict__ counter,
-                                                         uint32_t* __restrict__ ws) {
-    const uint32_t lane = threadIdx.x;
-    const uint32_t S = sc.S;
-    const uint32_t T0 = counter[0];
-    const uint64_t hz = horizon_of(sc.kind, S);
-    bool same = true, past = false;
-    for (uint32_t k = lane; k < n; k += 64) {
-        const uint32_t c = counter[k];
-        const uint32_t ing = ingests_of(c, sc.interval);
-        same = same && c == T0;
-        past = past || ing > kMaxReplayGenerations || (ing > 0 && (uint64_t)(ing - 1) > hz);
-    }
-    const bool any_past = __ballot(past) != 0;
-    const bool all_same = __ballot(!same) == 0;
-    if (any_past || !all_same) {
-        if (lane == 0) {
-            ws[kWsStatus] = any_past ? kWsStatusHorizon : kWsStatusMixed;
-            ws[kWsT] = T0;
-        }
-        return;
-    }
-    const uint32_t held = replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
-    const uint32_t rank = time_rank(held, lane, S);
-    const uint32_t F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
-    __shared__ uint32_t times[64];
-    if (lane < S) {
-        const uint32_t gen = held == kEmpty ? kEmpty : held * sc.interval;   // deposit generation
-        times[rank] = gen;
-        ws[kWsPerm + rank] = lane;
-        ws[kWsTimes + rank] = gen;
-    }
-    __syncthreads();
-    // first mismatch at rank r: ub = times[r], lb = times[r-1] + 1 (0 if r = 0);
-    // no mismatch (entry 64): ub = T, lb = times[F-1] + 1 (0 if F = 0)
-    ws[kWsLbTab + lane] = lane == 0 ? 0u : (lane < S ? times[lane - 1] + 1u : 0u);
-    ws[kWsUbTab + lane] = lane < S ? times[lane] : 0u;
-    if (lane == 0) {
-        ws[kWsLbTab + 64] = F > 0 ? times[F - 1] + 1u : 0u;
-        ws[kWsUbTab + 64] = T0;
-        ws[kWsT] = T0;
-        ws[kWsF] = F;
-        ws[kWsStatus] = 0;
-    }
-}
-
-// The annotation's surface words as one 64-bit value.
-__device__ __forceinline__ uint64_t surface64(const uint32_t* __restrict__ surf, uint32_t SW,
-                                              uint32_t a) {
-    return SW == 2 ? ((uint64_t)surf[(size_t)a * 2 + 1] << 32) | surf[(size_t)a * 2]
-                   : (uint64_t)surf[a];
-}
-
-// Fast route: each annotation's differentiae in ascending-time order, packed
-// in 64 bits (rank r at bit r for one-bit differentiae, at byte r for bytes).
-__global__ __launch_bounds__(256) void mrca_rank_kernel(uint32_t S, uint32_t diff_log2,
-                                                       uint32_t n,
-                                                       const uint32_t* __restrict__ surf,
-                                                       const uint32_t* __restrict__ ws,
-                                                       uint64_t* __restrict__ ranked) {
-    if (ws[kWsStatus] != 0) return;
-    __shared__ uint32_t perm[64];
-    if (threadIdx.x < 64) perm[threadIdx.x] = ws[kWsPerm + threadIdx.x];
-    __syncthreads();
-    const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n) return;
-    const uint32_t F = ws[kWsF];
-    const uint64_t s = surface64(surf, (S << diff_log2) >> 5, a);
-    const uint64_t mask = diff_log2 ? 0xffull : 1ull;
-    uint64_t packed = 0;
-    for (uint32_t r = 0; r < F; ++r)
-        packed |= ((s >> (perm[r] << diff_log2)) & mask) << (r << diff_log2);
-    ranked[a] = packed;
-}
-
-// Fast route, all ordered pairs: x = P_a xor P_b; the first set bit gives
-// the rank of the first mismatch (its bit index, or its byte index).  Each thread owns 4 adjacent columns of 4
-// rows, so stores are 16-byte and a wavefront writes 1 KiB contiguously.
-constexpr uint32_t kPairRows = 4;
-__global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n, uint32_t diff_log2,
-                                                           const uint64_t* __restrict__ ranked,
-                                                           const uint32_t* __restrict__ ws,
-                                                           uint32_t* __restrict__ lb,
-                                                           uint32_t* __restrict__ ub) {
-    if (ws[kWsStatus] != 0) return;
-    __shared__ uint32_t lbt[65], ubt[65];
-    if (threadIdx.x < 65) {
-        lbt[threadIdx.x] = ws[kWsLbTab + threadIdx.x];
-        ubt[threadIdx.x] = ws[kWsUbTab + threadIdx.x];
-    }
-    __syncthreads();
-    const uint32_t c0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4u;
-    if (c0 >= n) return;
-    const uint32_t a0 = blockIdx.y * kPairRows;
-    uint64_t pb[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) pb[q] = c0 + q < n ? ranked[c0 + q] : 0ull;
-    const bool vec = (n & 3u) == 0;
-    for (uint32_t rr = 0; rr < kPairRows; ++rr) {
-        const uint32_t a = a0 + rr;
-        if (a >= n) break;
-        const uint64_t pa = ranked[a];
-        uint32_t l[4], u[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint64_t x = pa ^ pb[q];
-            const uint32_t idx =
-                x ? ((uint32_t)(__ffsll((long long)x) - 1) >> diff_log2) : 64u;
-            l[q] = lbt[idx];
-            u[q] = ubt[idx];
-        }
-        const size_t off = (size_t)a * n + c0;
-        if (vec) {
-            *reinterpret_cast<uint4*>(lb + off) = make_uint4(l[0], l[1], l[2], l[3]);
-            *reinterpret_cast<uint4*>(ub + off) = make_uint4(u[0], u[1], u[2], u[3]);
-        } else {
-            for (uint32_t q = 0; q < 4 && c0 + q < n; ++q) {
-                lb[off + q] = l[q];
-                ub[off + q] = u[q];
-            }
-        }
-    }
-}
-
-// General route (counters differ): one wavefront per annotation replays its
-// own layout and stores its retained deposit generations in ascending order
-// with their sites.
-__global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc, uint32_t n,
-                                                         const uint32_t* __restrict__ counter,
-                                                         const uint32_t* __restrict__ ws,
-                                                         uint32_t* __restrict__ times,
-                                                         uint8_t* __restrict__ sites) {
-    if (ws[kWsStatus] != kWsStatusMixed) return;
-    const uint32_t a = blockIdx.x;
-    const uint32_t lane = threadIdx.x;
-    const uint32_t S = sc.S;
-    const uint32_t held = replay_layout(sc.kind, S, ingests_of(counter[a], sc.interval), lane);
-    const uint32_t rank = time_rank(held, lane, S);
-    if (lane < S) {
-        times[(size_t)a * S + rank] = held == kEmpty ? kEmpty : held * sc.interval;
-        sites[(size_t)a * S + rank] = (uint8_t)lane;
-    }
-}
-
-// General route, all ordered pairs: merge the two ascending time lists,
-// comparing differentiae on common times until the first mismatch.
-__global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
-    uint32_t S, uint32_t diff_log2, uint32_t n, const uint32_t* __restrict__ counter,
-    const uint32_t* __restrict__ surf, const uint32_t* __restrict__ times,
-    const uint8_t* __restrict__ sites, const uint32_t* __restrict__ ws, uint32_t* __restrict__ lb,
-    uint32_t* __restrict__ ub) {
-    if (ws[kWsStatus] != kWsStatusMixed) return;
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t a = blockIdx.y;
-    if (b >= n) return;
-    const uint32_t SW = (S << diff_log2) >> 5;
-    const uint64_t sa = surface64(surf, SW, a);
-    const uint64_t sb = surface64(surf, SW, b);
-    const uint64_t mask = diff_log2 ? 0xffull : 1ull;
-    const uint32_t* ta = times + (size_t)a * S;
-    const uint32_t* tb = times + (size_t)b * S;
-    const uint8_t* ka = sites + (size_t)a * S;
-    const uint8_t* kb = sites + (size_t)b * S;
-    uint32_t i = 0, k = 0;
-    bool have_last = false, mismatch = false;
-    uint32_t last = 0, tstar = 0;
-    while (i < S && k < S) {
-        const uint32_t x = ta[i], y = tb[k];
-        if (x == kEmpty || y == kEmpty) break;
-        if (x == y) {
-            if (((sa >> ((uint32_t)ka[i] << diff_log2)) & mask) !=
-                ((sb >> ((uint32_t)kb[k] << diff_log2)) & mask)) {
-                mismatch = true;
-                tstar = x;
-                break;
-            }
-            have_last = true;
-            last = x;
-            ++i;
-            ++k;
-        } else if (x < y) {
-            ++i;
-        } else {
-            ++k;
-        }
-    }
-    const uint32_t Ta = counter[a], Tb = counter[b];
-    const size_t off = (size_t)a * n + b;
-    ub[off] = mismatch ? tstar : (Ta < Tb ? Ta : Tb);
-    lb[off] = have_last ? last + 1u : 0u;
-}
-
-// ---------------------------------------------------------------------------
-// Trie reconstruction and phylometrics of annotations sharing a counter
-// (Distributed Phylogenetic Tracking: reconstruction is a trie over the
-// record of differentiae; Results, On-hardware Trial: sum branch length and
-// mean evolutionary distinctiveness).  Annotations read as their
-// differentiae in ascending deposit time are sorted lexicographically;
-// neighbours in that order share a prefix of d_i = LCP(i, i+1) retained
-// items, and the trie's branching nodes are exactly these boundaries.  A
-// node at depth d sits at time tau(d) = t_d (the MRCA upper bound of the
-// pairs it separates), tau(F) = T (identical annotations).
-//   boundaries of one node: equal depth d with nothing shallower between
-//     (a many-way split, or a run of identical annotations); the node
-//     starts at the boundary whose nearest not-deeper left neighbour is
-//     strictly shallower;
-//   leaf i hangs from the deeper of boundaries i-1, i;
-//   a node hangs from the deeper of its nearest strictly shallower
-//   boundaries on either side (none: the root);
-//   pairs (a, b) meet at the shallowest boundary between them, so the sum
-//   over pairs of T - tau(MRCA) is a sum over all boundary ranges of their
-//   minimum, counted by nearest-smaller spans.
-constexpr uint32_t kPhyloOutWords = 6;   // sbl, pair sum, root, internal, status, n
-
-// Sort keys: rank 0 most significant (bit-reversed for one-bit
-// differentiae, byte-reversed for bytes).
-__global__ __launch_bounds__(256) void phylo_keys_kernel(uint32_t n, uint32_t npad,
-                                                        uint32_t diff_log2,
-                                                        const uint64_t* __restrict__ ranked,
-                                                        const uint32_t* __restrict__ ws,
-                                                        uint64_t* __restrict__ keys,
-                                                        uint32_t* __restrict__ idx) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npad) return;
-    uint64_t key = ~0ull;
-    if (i < n) key = diff_log2 ? __builtin_bswap64(ranked[i]) : __brevll(ranked[i]);
-    keys[i] = key;
-    idx[i] = i < n ? i : 0xffffffffu;
-}
-
-// One workgroup: bitonic sort of (key, index) over npad (a power of two)
-// entries held in global memory.
-__global__ __launch_bounds__(1024) void phylo_sort_kernel(uint32_t npad,
-                                                         const uint32_t* __restrict__ ws,
-                                                         uint64_t* __restrict__ keys,
-                                                         uint32_t* __restrict__ idx) {
-    if (ws[kWsStatus] != 0) return;
-    for (uint32_t k = 2; k <= npad; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = threadIdx.x; t < npad / 2; t += blockDim.x) {
-                const uint32_t i = (t / j) * 2 * j + (t % j);
-                const uint32_t l = i + j;
-                const bool up = (i & k) == 0;
-                const uint64_t ki = keys[i], kl = keys[l];
-                const uint32_t ii = idx[i], il = idx[l];
-                const bool greater = ki > kl || (ki == kl && ii > il);
-                if (greater == up) {
-                    keys[i] = kl; keys[l] = ki;
-                    idx[i] = il; idx[l] = ii;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// Boundary depths and the tree, in parallel.  tab[k][i] = the minimum depth
-// over boundaries [i, i + 2^k) (a sparse table); the nearest boundary to the
-// left or right of b shallower than a depth is found by binary lifting over
-// it, one thread per boundary.  Sums go to 64-bit accumulators.
-constexpr uint32_t kPhyloMaxLevels = 17;   // 2^16 > 65534 boundaries
-constexpr uint32_t kNoBoundary = 0xffffffffu;
-
-struct PhyloAcc {
-    unsigned long long sbl, pairs, internal, dmin;
-};
-
-__device__ __forceinline__ uint64_t phylo_tau(const uint32_t* ws, uint32_t d) {
-    const uint32_t F = ws[kWsF];
-    return d < F ? (uint64_t)ws[kWsTimes + d] : (uint64_t)ws[kWsT];
-}
-
-__global__ __launch_bounds__(256) void phylo_depth_kernel(uint32_t n, uint32_t diff_log2,
-                                                         const uint32_t* __restrict__ ws,
-                                                         const uint64_t* __restrict__ keys,
-                                                         uint8_t* __restrict__ depth,
-                                                         PhyloAcc* __restrict__ acc) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t F = ws[kWsF];
-    if (i == 0) {
-        acc->sbl = 0;
-        acc->pairs = 0;
-        acc->internal = 0;
-        acc->dmin = F;
-    }
-    if (i + 1 < n) {
-        const uint64_t x = keys[i] ^ keys[i + 1];
-        const uint32_t d = x ? ((uint32_t)__clzll((long long)x) >> diff_log2) : 64u;
-        depth[i] = (uint8_t)(d < F ? d : F);
-    }
-}
-
-// Level k of the sparse table from level k - 1 (m boundaries per level).
-__global__ __launch_bounds__(256) void phylo_table_kernel(uint32_t m, uint32_t k,
-                                                         const uint32_t* __restrict__ ws,
-                                                         uint8_t* __restrict__ tab) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t half = 1u << (k - 1);
-    if (i + 2 * half > m) return;
-    const uint8_t* prev = tab + (size_t)(k - 1) * m;
-    const uint8_t a = prev[i], b = prev[i + half];
-    tab[(size_t)k * m + i] = a < b ? a : b;
-}
-
-// Nearest boundary i < b with depth[i] < d.
-__device__ __forceinline__ uint32_t phylo_left_below(const uint8_t* tab, uint32_t m,
-                                                     uint32_t levels, uint32_t b, uint32_t d) {
-    uint32_t pos = b;   // every boundary in [pos, b) is at depth >= d
-    for (uint32_t k = levels; k-- > 0;) {
-        const uint32_t len = 1u << k;
-        if (pos >= len && tab[(size_t)k * m + pos - len] >= d) pos -= len;
-    }
-    return pos == 0 ? kNoBoundary : pos - 1;
-}
-
-// Nearest boundary i > b with depth[i] < d.
-__device__ __forceinline__ uint32_t phylo_right_below(const uint8_t* tab, uint32_t m,
-                                                      uint32_t levels, uint32_t b, uint32_t d) {
-    uint32_t pos = b + 1;   // every boundary in (b, pos) is at depth >= d
-    for (uint32_t k = levels; k-- > 0;) {
-        const uint32_t len = 1u << k;
-        if (pos + len <= m && tab[(size_t)k * m + pos] >= d) pos += len;
-    }
-    return pos >= m ? kNoBoundary : pos;
-}
-
-__device__ __forceinline__ void phylo_add(PhyloAcc* acc, uint64_t sbl, uint64_t pairs,
-                                          uint64_t internal, uint32_t dmin) {
-    __shared__ unsigned long long s_sbl, s_pairs, s_internal;
-    __shared__ uint32_t s_dmin;
-    if (threadIdx.x == 0) {
-        s_sbl = 0;
-        s_pairs = 0;
-        s_internal = 0;
-        s_dmin = 0xffffffffu;
-    }
-    __syncthreads();
-    if (sbl) atomicAdd(&s_sbl, (unsigned long long)sbl);
-    if (pairs) atomicAdd(&s_pairs, (unsigned long long)pairs);
-    if (internal) atomicAdd(&s_internal, (unsigned long long)internal);
-    if (dmin != 0xffffffffu) atomicMin(&s_dmin, dmin);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_sbl) atomicAdd(&acc->sbl, s_sbl);
-        if (s_pairs) atomicAdd(&acc->pairs, s_pairs);
-        if (s_internal) atomicAdd(&acc->internal, s_internal);
-        if (s_dmin != 0xffffffffu) atomicMin(&acc->dmin, (unsigned long long)s_dmin);
-    }
-}
-
-// One thread per boundary b (depth d):
-//   pairs meeting at b (b the rightmost shallowest boundary between them):
-//     (b - L) (Rq - b), L = nearest left shallower (-1 if none), Rq =
-//     nearest right not deeper (m if none), each adding T - tau(d);
-//   a tree node starts at b unless the nearest not-deeper boundary on its
-//   left has the same depth (one many-way node, or a run of identical
-//   annotations); the node hangs from the deeper of its nearest shallower
-//   boundaries (none on either side: the root).
-__global__ __launch_bounds__(256) void phylo_boundary_kernel(uint32_t m, uint32_t levels,
-                                                            const uint32_t* __restrict__ ws,
-                                                            const uint8_t* __restrict__ tab,
-                                                            PhyloAcc* __restrict__ acc) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t sbl = 0, pairs = 0, internal = 0;
-    uint32_t dmin = 0xffffffffu;
-    if (b < m) {
-        const uint8_t* depth = tab;
-        const uint32_t d = depth[b];
-        const uint64_t T = ws[kWsT];
-        const uint32_t L = phylo_left_below(tab, m, levels, b, d);
-        const uint32_t Lq = phylo_left_below(tab, m, levels, b, d + 1);
-        const uint32_t R = phylo_right_below(tab, m, levels, b, d);
-        const uint32_t Rq = phylo_right_below(tab, m, levels, b, d + 1);
-        const uint64_t nl = (uint64_t)b - (L == kNoBoundary ? (uint64_t)-1 : L);
-        const uint64_t nr = (uint64_t)(Rq == kNoBoundary ? m : Rq) - b;
-        pairs = (T - phylo_tau(ws, d)) * nl * nr;
-        dmin = d;
-        if (Lq == kNoBoundary || depth[Lq] < d) {
-            internal = 1;
-            if (L != kNoBoundary || R != kNoBoundary) {
-                uint32_t pd;
-                if (L == kNoBoundary) pd = depth[R];
-                else if (R == kNoBoundary) pd = depth[L];
-                else pd = depth[L] > depth[R] ? depth[L] : depth[R];
-                sbl = phylo_tau(ws, d) - phylo_tau(ws, pd);
-            }
-        }
-    }
-    phylo_add(acc, sbl, pairs, internal, dmin);
-}
-
-// One thread per leaf: its edge from the deeper adjacent boundary to T.
-__global__ __launch_bounds__(256) void phylo_leaf_kernel(uint32_t n,
-                                                        const uint32_t* __restrict__ ws,
-                                                        const uint8_t* __restrict__ depth,
-                                                        PhyloAcc* __restrict__ acc) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t sbl = 0;
-    if (i < n && n > 1) {
-        const uint32_t m = n - 1;
-        uint32_t pd = i > 0 ? depth[i - 1] : 0u;
-        if (i < m && (i == 0 || depth[i] > pd)) pd = depth[i];
-        sbl = (uint64_t)ws[kWsT] - phylo_tau(ws, pd);
-    }
-    phylo_add(acc, sbl, 0, 0, 0xffffffffu);
-}
-
-__global__ __launch_bounds__(64) void phylo_finish_kernel(uint32_t n,
-                                                         const uint32_t* __restrict__ ws,
-                                                         const PhyloAcc* __restrict__ acc,
-                                                         uint64_t* __restrict__ out) {
-    if (threadIdx.x != 0) return;
-    const uint32_t status = ws[kWsStatus];
-    if (status != 0) {
-        out[0] = out[1] = out[2] = out[3] = 0;
-    } else {
-        out[0] = acc->sbl;
-        out[1] = acc->pairs;
-        out[2] = n > 1 ? phylo_tau(ws, (uint32_t)acc->dmin) : ws[kWsT];
-        out[3] = acc->internal;
-    }
-    out[4] = status;
-    out[5] = n;
-}
-
-// The tree itself.  A node is named by the first boundary of its run (the
-// first boundary after its nearest shallower left boundary L that is not
-// deeper than it).
-constexpr uint32_t kPhyloRoot = 0xffffffffu, kPhyloNotNode = 0xfffffffeu;
-
-__device__ __forceinline__ uint32_t phylo_node_of(const uint8_t* tab, uint32_t m,
-                                                  uint32_t levels, uint32_t b) {
-    const uint32_t d = tab[b];
-    const uint32_t L = phylo_left_below(tab, m, levels, b, d);
-    if (L == kNoBoundary) return tab[0] <= d ? 0u : phylo_right_below(tab, m, levels, 0, d + 1);
-    return phylo_right_below(tab, m, levels, L, d + 1);
-}
-
-// One thread per boundary: node_parent[b] = the parent node (kPhyloRoot for
-// the root) when b starts a node, kPhyloNotNode otherwise; node_time[b] =
-// the time of b's node.
-__global__ __launch_bounds__(256) void phylo_tree_kernel(uint32_t m, uint32_t levels,
-                                                        const uint32_t* __restrict__ ws,
-                                                        const uint8_t* __restrict__ tab,
-                                                        uint32_t* __restrict__ node_parent,
-                                                        uint32_t* __restrict__ node_time) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= m) return;
-    const uint32_t d = tab[b];
-    node_time[b] = (uint32_t)phylo_tau(ws, d);
-    const uint32_t Lq = phylo_left_below(tab, m, levels, b, d + 1);
-    if (Lq != kNoBoundary && tab[Lq] == d) {
-        node_parent[b] = kPhyloNotNode;
-        return;
-    }
-    const uint32_t L = phylo_left_below(tab, m, levels, b, d);
-    const uint32_t R = phylo_right_below(tab, m, levels, b, d);
-    if (L == kNoBoundary && R == kNoBoundary) {
-        node_parent[b] = kPhyloRoot;
-        return;
-    }
-    uint32_t p;
-    if (L == kNoBoundary) p = R;
-    else if (R == kNoBoundary) p = L;
-    else p = tab[L] >= tab[R] ? L : R;
-    node_parent[b] = phylo_node_of(tab, m, levels, p);
-}
-
-// One thread per sorted position i: the annotation idx[i] hangs from the
-// node of the deeper adjacent boundary.
-__global__ __launch_bounds__(256) void phylo_tree_leaf_kernel(uint32_t n, uint32_t levels,
-                                                             const uint32_t* __restrict__ ws,
-                                                             const uint8_t* __restrict__ tab,
-                                                             const uint32_t* __restrict__ idx,
-                                                             uint32_t* __restrict__ leaf_parent) {
-    if (ws[kWsStatus] != 0) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (n == 1) {
-        leaf_parent[idx[i]] = kPhyloRoot;
-        return;
-    }
-    const uint32_t m = n - 1;
-    uint32_t pb;
-    if (i == 0) pb = 0;
-    else if (i == m) pb = m - 1;
-    else pb = tab[i] > tab[i - 1] ? i : i - 1;
-    leaf_parent[idx[i]] = phylo_node_of(tab, m, levels, pb);
-}
-
-size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
-    size_t npad = 1;
-    while (npad < n) npad <<= 1;
-    const size_t a = (MrcaWorkspace::bytes(S, n) + 255) & ~(size_t)255;
-    return a + npad * 8 + npad * 4 + 256 + (size_t)kPhyloMaxLevels * n + 1024;
-}
-
-hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
-                        const uint32_t* surf, uint64_t* out, void* workspace,
-                        hipStream_t stream, uint32_t* leaf_parent, uint32_t* node_parent,
-                        uint32_t* node_time) {
-    const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
-    uint8_t* base = static_cast<uint8_t*>(workspace);
-    uint32_t* ws = reinterpret_cast<uint32_t*>(base);
-    uint64_t* ranked = reinterpret_cast<uint64_t*>(base + MrcaWorkspace::kHeader);
-    size_t npad = 1;
-    while (npad < n) npad <<= 1;
-    size_t off = (MrcaWorkspace::bytes(scm.S, n) + 255) & ~(size_t)255;
-    uint64_t* keys = reinterpret_cast<uint64_t*>(base + off);   off += npad * 8;
-    uint32_t* idx = reinterpret_cast<uint32_t*>(base + off);    off += npad * 4;
-    off = (off + 255) & ~(size_t)255;
-    PhyloAcc* acc = reinterpret_cast<PhyloAcc*>(base + off);    off += 256;
-    uint8_t* tab = base + off;                                  // levels x m bytes
-    const uint32_t m = n - 1;
-    uint32_t levels = 1;
-    while (levels < kPhyloMaxLevels && (2u << (levels - 1)) <= m) ++levels;
-    const uint32_t gn = (n + 255) / 256;
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
-    hipLaunchKernelGGL(mrca_rank_kernel, dim3(gn), dim3(256), 0, stream, scm.S, diff_log2, n,
-                       surf, ws, ranked);
-    hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
-                       stream, n, (uint32_t)npad, diff_log2, ranked, ws, keys, idx);
-    hipLaunchKernelGGL(phylo_sort_kernel, dim3(1), dim3(1024), 0, stream, (uint32_t)npad, ws,
-                       keys, idx);
-    hipLaunchKernelGGL(phylo_depth_kernel, dim3(gn), dim3(256), 0, stream, n, diff_log2, ws, keys,
-                       tab, acc);
-    for (uint32_t k = 1; k < levels; ++k)
-        hipLaunchKernelGGL(phylo_table_kernel, dim3(gn), dim3(256), 0, stream, m, k, ws, tab);
-    if (m > 0)
-        hipLaunchKernelGGL(phylo_boundary_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, m,
-                           levels, ws, tab, acc);
-    hipLaunchKernelGGL(phylo_leaf_kernel, dim3(gn), dim3(256), 0, stream, n, ws, tab, acc);
-    hipLaunchKernelGGL(phylo_finish_kernel, dim3(1), dim3(64), 0, stream, n, ws, acc, out);
-    if (leaf_parent) {
-        if (m > 0)
-            hipLaunchKernelGGL(phylo_tree_kernel, dim3((m + 255) / 256), dim3(256), 0, stream, m,
-                               levels, ws, tab, node_parent, node_time);
-        hipLaunchKernelGGL(phylo_tree_leaf_kernel, dim3(gn), dim3(256), 0, stream, n, levels, ws,
-                           tab, idx, leaf_parent);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
-                       const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
-                       hipStream_t stream) {
-    const uint32_t S = scm.S;
-    const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
-    uint8_t* base = static_cast<uint8_t*>(workspace);
-    uint32_t* ws = reinterpret_cast<uint32_t*>(base);
-    uint64_t* ranked = reinterpret_cast<uint64_t*>(base + MrcaWorkspace::kHeader);
-    const size_t ranked_bytes = ((size_t)n * 8 + 255) & ~(size_t)255;
-    uint32_t* times = reinterpret_cast<uint32_t*>(base + MrcaWorkspace::kHeader + ranked_bytes);
-    const size_t times_bytes = ((size_t)n * S * 4 + 255) & ~(size_t)255;
-    uint8_t* sites = base + MrcaWorkspace::kHeader + ranked_bytes + times_bytes;
-
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
-    hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S,
-                       diff_log2, n, surf, ws, ranked);
-    hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
-                       dim3(256), 0, stream, n, diff_log2, ranked, ws, lb, ub);
-    hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, scm, n, counter, ws,
-                       times, sites);
-    hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, n), dim3(256), 0, stream,
-                       S, diff_log2, n, counter, surf, times, sites, ws, lb, ub);
     return hipGetLastError();
 }
 
