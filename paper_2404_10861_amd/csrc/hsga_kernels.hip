@@ -164,6 +164,133 @@ __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint3
 
 extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
 
+// Births of this thread's APT agents.  APT divides N, so they share one
+// island: its index and the first slot come from one division.
+template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC, bool POW2>
+__device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_isl,
+                                            uint32_t la0, uint32_t site_word,
+                                            uint32_t site_shift, uint32_t diff_mask,
+                                            uint32_t n_shift) {
+    uint32_t* lds = g_step_lds;
+    const uint32_t N = p.N;
+    const uint32_t TA = (p.tile_isl * N + 3u) & ~3u;
+    const uint32_t* l_trait = lds;
+    const uint32_t* l_count = lds + TA;
+    const uint32_t* l_surf = lds + 2 * TA;
+    const uint32_t* l_plan = lds + (2 + SW) * TA;
+    const uint32_t* l_emig = l_plan + p.tile_isl;
+    const size_t a0 = (size_t)first_isl * N;
+    const size_t A = p.A;
+    auto pick = [&](uint32_t w) -> uint32_t {
+        if constexpr (POW2) return w >> n_shift;   // = mulhi(w, N) for N = 2^(32 - n_shift)
+        else return word_below(w, N);
+    };
+    const uint32_t il = (la0 * p.div_magic) >> 20;      // la0 / N, exact for la0 < 4096
+    const uint32_t j0 = la0 - il * N;
+    const uint32_t isl = first_isl + il;
+    const uint32_t base = il * N;
+    Lanes<APT> ctr, ccn, csf[SW];
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        const uint32_t la = la0 + q;
+        const uint32_t j = j0 + q;
+        bool act = true;
+        if constexpr (ASYNC) act = (l_plan[il] >> 31) != 0u;
+        if (!act) {
+            // idle island: the same individual on the next tick
+            ctr.v[q] = l_trait[la];
+            ccn.v[q] = l_count[la];
+#pragma unroll
+            for (int w = 0; w < SW; ++w) csf[w].v[q] = l_surf[w * TA + la];
+        } else {
+            const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
+            uint32_t par = base + pick(r.x);
+            uint32_t bit;
+            if constexpr (BM == kBirthFloat) {
+                // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x),
+                // the first of maximal fitness winning; mutation class from
+                // v.y, |Z| from v.z and v.w, differentia the low bits of v.w
+                const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
+                float best = __uint_as_float(l_trait[par]);
+                const uint32_t words[4] = {r.y, r.z, r.w, v.x};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if ((uint32_t)c + 1u < p.tour) {
+                        const uint32_t cb = base + pick(words[c]);
+                        const float fc = __uint_as_float(l_trait[cb]);
+                        if (fc > best) {
+                            best = fc;
+                            par = cb;
+                        }
+                    }
+                }
+                const bool del = v.y < p.del_thr;
+                const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
+                ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
+                                                                         p.ben_sigma, v.z, v.w))
+                                        : __float_as_uint(best);
+                bit = v.w & diff_mask;
+            } else {
+                uint32_t ptrait = l_trait[par];
+                if constexpr (BM == kBirthIntTournament) {
+                    const uint32_t pb = base + pick(r.y);
+                    const uint32_t tb = l_trait[pb];
+                    if ((int32_t)tb > (int32_t)ptrait) {
+                        par = pb;
+                        ptrait = tb;
+                    }
+                }
+                const uint32_t delta =
+                    r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo)
+                                    : 0u;
+                ctr.v[q] = ptrait + delta;
+                bit = r.w & diff_mask;
+            }
+            const uint32_t T = l_count[par];
+            ccn.v[q] = T + 1u;
+            uint32_t dep_word = site_word, dep_shift = site_shift;
+            if constexpr (ASYNC) {
+                // the parent's own counter picks the item and, through the
+                // site table, its site
+                const uint32_t tau = p.interval == 1u ? T : T / p.interval;
+                dep_word = 0xffu;
+                if (tau * p.interval == T) {
+                    const uint32_t site = p.site_tab[tau];
+                    dep_word = site >> (5u - p.diff_log2);
+                    dep_shift = (site << p.diff_log2) & 31u;
+                }
+            }
+#pragma unroll
+            for (int w = 0; w < SW; ++w) {
+                const uint32_t word = l_surf[w * TA + par];
+                csf[w].v[q] = (uint32_t)w == dep_word
+                                  ? (word & ~(diff_mask << dep_shift)) | (bit << dep_shift)
+                                  : word;
+            }
+        }
+        if (MIGR) {
+            const uint32_t em = l_emig[il];
+            if (j == (em & 0xffu)) {
+                uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
+                const uint32_t dir = (em >> 8) & 7u;
+                if (dir < 4u) {
+                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, ctr.v[q], ccn.v[q], csf[0].v[q]);
+                    *reinterpret_cast<uint4*>(o + 4) =
+                        make_uint4(SW > 1 ? csf[SW - 1].v[q] : 0u, 0u, 0u, 0u);
+                } else {
+                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, 0u, 0u, 0u);
+                    *reinterpret_cast<uint4*>(o + 4) = make_uint4(0u, 0u, 0u, 0u);
+                }
+            }
+        }
+    }
+    store_lanes<APT>(p.out_trait + a0 + la0, ctr);
+    store_lanes<APT>(p.out_counter + a0 + la0, ccn);
+#pragma unroll
+    for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
+}
+
+
 // One tile of one run.  Shared by the plain kernel (one run per launch) and
 // the batched kernel (many runs per launch).
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC = false>
@@ -285,108 +412,15 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     }
     const uint32_t diff_mask = p.diff_log2 ? 0xffu : 1u;
     if (!mine) return;
-    Lanes<APT> ctr, ccn, csf[SW];
-#pragma unroll
-    for (int q = 0; q < APT; ++q) {
-        const uint32_t la = la0 + q;
-        const uint32_t il = (la * p.div_magic) >> 20;   // la / N, exact for la < 4096
-        const uint32_t j = la - il * N;
-        const uint32_t isl = first_isl + il;
-        bool act = true;
-        if constexpr (ASYNC) act = (l_plan[il] >> 31) != 0u;
-        if (!act) {
-            // idle island: the same individual on the next tick
-            ctr.v[q] = l_trait[la];
-            ccn.v[q] = l_count[la];
-#pragma unroll
-            for (int w = 0; w < SW; ++w) csf[w].v[q] = l_surf[w * TA + la];
-        } else {
-            const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
-            const uint32_t base = il * N;
-            uint32_t par = base + word_below(r.x, N);
-            uint32_t bit;
-            if constexpr (BM == kBirthFloat) {
-                // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x),
-                // the first of maximal fitness winning; mutation class from
-                // v.y, |Z| from v.z and v.w, differentia the low bits of v.w
-                const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
-                float best = __uint_as_float(l_trait[par]);
-                const uint32_t words[4] = {r.y, r.z, r.w, v.x};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if ((uint32_t)c + 1u < p.tour) {
-                        const uint32_t cb = base + word_below(words[c], N);
-                        const float fc = __uint_as_float(l_trait[cb]);
-                        if (fc > best) {
-                            best = fc;
-                            par = cb;
-                        }
-                    }
-                }
-                const bool del = v.y < p.del_thr;
-                const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
-                ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
-                                                                         p.ben_sigma, v.z, v.w))
-                                        : __float_as_uint(best);
-                bit = v.w & diff_mask;
-            } else {
-                uint32_t ptrait = l_trait[par];
-                if constexpr (BM == kBirthIntTournament) {
-                    const uint32_t pb = base + word_below(r.y, N);
-                    const uint32_t tb = l_trait[pb];
-                    if ((int32_t)tb > (int32_t)ptrait) {
-                        par = pb;
-                        ptrait = tb;
-                    }
-                }
-                const uint32_t delta =
-                    r.z < p.mut_thr ? (uint32_t)((int32_t)word_below(r.w, p.mut_span) + p.mut_lo)
-                                    : 0u;
-                ctr.v[q] = ptrait + delta;
-                bit = r.w & diff_mask;
-            }
-            const uint32_t T = l_count[par];
-            ccn.v[q] = T + 1u;
-            uint32_t dep_word = site_word, dep_shift = site_shift;
-            if constexpr (ASYNC) {
-                // the parent's own counter picks the item and, through the
-                // site table, its site
-                const uint32_t tau = p.interval == 1u ? T : T / p.interval;
-                dep_word = 0xffu;
-                if (tau * p.interval == T) {
-                    const uint32_t site = p.site_tab[tau];
-                    dep_word = site >> (5u - p.diff_log2);
-                    dep_shift = (site << p.diff_log2) & 31u;
-                }
-            }
-#pragma unroll
-            for (int w = 0; w < SW; ++w) {
-                const uint32_t word = l_surf[w * TA + par];
-                csf[w].v[q] = (uint32_t)w == dep_word
-                                  ? (word & ~(diff_mask << dep_shift)) | (bit << dep_shift)
-                                  : word;
-            }
-        }
-        if (MIGR) {
-            const uint32_t em = l_emig[il];
-            if (j == (em & 0xffu)) {
-                uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
-                const uint32_t dir = (em >> 8) & 7u;
-                if (dir < 4u) {
-                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, ctr.v[q], ccn.v[q], csf[0].v[q]);
-                    *reinterpret_cast<uint4*>(o + 4) =
-                        make_uint4(SW > 1 ? csf[SW - 1].v[q] : 0u, 0u, 0u, 0u);
-                } else {
-                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, 0u, 0u, 0u);
-                    *reinterpret_cast<uint4*>(o + 4) = make_uint4(0u, 0u, 0u, 0u);
-                }
-            }
-        }
-    }
-    store_lanes<APT>(p.out_trait + a0 + la0, ctr);
-    store_lanes<APT>(p.out_counter + a0 + la0, ccn);
-#pragma unroll
-    for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
+    // draws onto [0, N): a shift when N is a power of two above 1 (a
+    // wave-uniform choice between two copies of the births)
+    const uint32_t n_shift = (N > 1u && (N & (N - 1u)) == 0u) ? 32u - __builtin_ctz(N) : 0u;
+    if (n_shift)
+        step_births<SW, BM, MIGR, APT, ASYNC, true>(p, first_isl, la0, site_word, site_shift,
+                                                    diff_mask, n_shift);
+    else
+        step_births<SW, BM, MIGR, APT, ASYNC, false>(p, first_isl, la0, site_word, site_shift,
+                                                     diff_mask, n_shift);
 }
 
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
