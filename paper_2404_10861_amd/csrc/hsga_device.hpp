@@ -43,6 +43,25 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
     return c;
 }
 
+// K independent Philox4x32-10 blocks under one key, advanced round by
+// round together so that their multiply chains overlap in the pipeline.
+template <int K>
+__device__ __forceinline__ void philox4x32_10_multi(uint4 (&c)[K], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const uint64_t prod0 = (uint64_t)c[q].x * 0xD2511F53u;
+            const uint64_t prod1 = (uint64_t)c[q].z * 0xCD9E8D57u;
+            const uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+            const uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+            c[q] = make_uint4(xor3(hi1, c[q].y, k0), lo1, xor3(hi0, c[q].w, k1), lo0);
+        }
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
 // A uniform 32-bit word mapped onto [0, n).
 __device__ __forceinline__ uint32_t word_below(uint32_t w, uint32_t n) {
     return __umulhi(w, n);

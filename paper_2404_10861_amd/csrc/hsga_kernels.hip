@@ -189,6 +189,16 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
     const uint32_t j0 = la0 - il * N;
     const uint32_t isl = first_isl + il;
     const uint32_t base = il * N;
+    // the birth blocks of all APT agents (and the second blocks of float
+    // births), computed together
+    constexpr int NB = BM == kBirthFloat ? 2 * APT : APT;
+    uint4 blk[NB];
+#pragma unroll
+    for (int q = 0; q < APT; ++q) {
+        blk[q] = make_uint4(j0 + q, isl, p.g, kBirth);
+        if constexpr (BM == kBirthFloat) blk[APT + q] = make_uint4(j0 + q, isl, p.g, kBirthB);
+    }
+    philox4x32_10_multi<NB>(blk, p.k0, p.k1);
     Lanes<APT> ctr, ccn, csf[SW];
 #pragma unroll
     for (int q = 0; q < APT; ++q) {
@@ -203,14 +213,14 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
 #pragma unroll
             for (int w = 0; w < SW; ++w) csf[w].v[q] = l_surf[w * TA + la];
         } else {
-            const uint4 r = philox4x32_10(make_uint4(j, isl, p.g, kBirth), p.k0, p.k1);
+            const uint4 r = blk[q];
             uint32_t par = base + pick(r.x);
             uint32_t bit;
             if constexpr (BM == kBirthFloat) {
                 // tournament of p.tour draws (words r.x, r.y, r.z, r.w, v.x),
                 // the first of maximal fitness winning; mutation class from
                 // v.y, |Z| from v.z and v.w, differentia the low bits of v.w
-                const uint4 v = philox4x32_10(make_uint4(j, isl, p.g, kBirthB), p.k0, p.k1);
+                const uint4 v = blk[APT + q];
                 float best = __uint_as_float(l_trait[par]);
                 const uint32_t words[4] = {r.y, r.z, r.w, v.x};
 #pragma unroll
@@ -321,47 +331,60 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
 #pragma unroll
         for (int w = 0; w < SW; ++w) sf[w] = load_lanes<APT>(p.in_surf + w * A + a0 + la0);
     }
+    // Island pass: thread t takes island t for immigration (and the activity
+    // draw) and thread blockDim-1-t takes island t for emigration; the host
+    // keeps tile_isl <= blockDim.  Each neighbour's whole outbox entry is
+    // read together with the tile (the record shares the direction word's
+    // cache line), so the immigrants need no second round trip.
+    uint4 in_lo[4], in_hi[4];
+    uint32_t arrivals = 0;
     if (MIGR || ASYNC) {
         // asynchronous ticks: an island runs a generation iff its activity
         // draw is below the threshold (plan bit 31); an idle island takes no
         // immigrants and posts no emigrant (direction 4)
-        const uint32_t passes = MIGR ? 2 * nisl : nisl;
-        for (uint32_t b = t; b < passes; b += blockDim.x) {
-            const bool imm = b < nisl;
-            const uint32_t il = imm ? b : b - nisl;
-            const uint32_t isl = first_isl + il;
+        if (t < nisl) {
+            const uint32_t isl = first_isl + t;
             bool act = true;
             if constexpr (ASYNC)
                 act = philox4x32_10(make_uint4(0u, isl, p.g, kActivity), p.k0, p.k1).x <
                       p.async_thr;
-            if (imm) {
-                uint32_t plan = 0;
-                if (MIGR && act && p.has_inbox) {
-                    const uint4 w4 =
-                        philox4x32_10(make_uint4(0u, isl, p.g, kImmigrate), p.k0, p.k1);
-                    const uint32_t x = isl % W;
-                    // a neighbour delivers when its emigrant was sent our way
-                    const uint32_t dn = p.ob_in[(size_t)neighbour_of(isl, x, 0, W, p.I) * kOutboxWords];
-                    const uint32_t ds = p.ob_in[(size_t)neighbour_of(isl, x, 1, W, p.I) * kOutboxWords];
-                    const uint32_t dw = p.ob_in[(size_t)neighbour_of(isl, x, 2, W, p.I) * kOutboxWords];
-                    const uint32_t de = p.ob_in[(size_t)neighbour_of(isl, x, 3, W, p.I) * kOutboxWords];
-                    plan = (dn == 1u ? 1u : 0u) | (ds == 0u ? 2u : 0u) | (dw == 3u ? 4u : 0u) |
-                           (de == 2u ? 8u : 0u);
-                    plan |= word_below(w4.x, N) << 4;
-                    plan |= word_below(w4.y, N) << 10;
-                    plan |= word_below(w4.z, N) << 16;
-                    plan |= word_below(w4.w, N) << 22;
+            uint32_t plan = 0;
+            if (MIGR && act && p.has_inbox) {
+                const uint4 w4 = philox4x32_10(make_uint4(0u, isl, p.g, kImmigrate), p.k0, p.k1);
+                const uint32_t x = isl % W;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t* e =
+                        p.ob_in + (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * kOutboxWords;
+                    in_lo[d] = *reinterpret_cast<const uint4*>(e);
+                    if (SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(e + 4);
                 }
-                if (ASYNC && act) plan |= 1u << 31;
-                l_plan[il] = plan;
-            } else {
+                // a neighbour delivers when its emigrant was sent our way
+                arrivals = (in_lo[0].x == 1u ? 1u : 0u) | (in_lo[1].x == 0u ? 2u : 0u) |
+                           (in_lo[2].x == 3u ? 4u : 0u) | (in_lo[3].x == 2u ? 8u : 0u);
+                plan = word_below(w4.x, N) | (word_below(w4.y, N) << 6) |
+                       (word_below(w4.z, N) << 12) | (word_below(w4.w, N) << 18);
+            }
+            if (ASYNC && act) plan |= 1u << 31;
+            arrivals |= plan << 4;     // slots of the four directions above the arrival bits
+            l_plan[t] = plan;
+        }
+        if (MIGR) {
+            const uint32_t il = blockDim.x - 1u - t;
+            if (il < nisl) {
+                const uint32_t isl = first_isl + il;
+                bool act = true;
+                if constexpr (ASYNC)
+                    act = philox4x32_10(make_uint4(0u, isl, p.g, kActivity), p.k0, p.k1).x <
+                          p.async_thr;
                 const uint4 w4 = philox4x32_10(make_uint4(0u, isl, p.g, kEmigrate), p.k0, p.k1);
                 l_emig[il] = word_below(w4.x, N) | ((act ? (w4.y >> 30) : 4u) << 8);
             }
         }
     }
 
-    // 2. stage the tile in LDS, then overwrite immigrant slots
+    // 2. stage the tile in LDS, then overwrite immigrant slots (north,
+    // south, west, east: a later direction overwrites an earlier one)
     if (mine) {
         lds_store_lanes<APT>(l_trait + la0, tr);
         lds_store_lanes<APT>(l_count + la0, ct);
@@ -370,31 +393,15 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     }
     __syncthreads();
     if (MIGR) {
-        if (p.has_inbox) {
-            for (uint32_t il = t; il < nisl; il += blockDim.x) {
-                const uint32_t plan = l_plan[il];
-                if ((plan & 15u) == 0) continue;
-                const uint32_t isl = first_isl + il;
-                const uint32_t x = isl % W;
-                uint4 lo[4], hi[4];
+        if (arrivals & 15u) {
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    if ((plan >> d) & 1u) {
-                        const uint32_t* e =
-                            p.ob_in + (size_t)neighbour_of(isl, x, d, W, p.I) * kOutboxWords;
-                        lo[d] = *reinterpret_cast<const uint4*>(e);
-                        if (SW > 1) hi[d] = *reinterpret_cast<const uint4*>(e + 4);
-                    }
-                }
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    if ((plan >> d) & 1u) {
-                        const uint32_t la = il * N + ((plan >> (4 + 6 * d)) & 63u);
-                        l_trait[la] = lo[d].y;
-                        l_count[la] = lo[d].z;
-                        l_surf[la] = lo[d].w;
-                        if (SW > 1) l_surf[TA + la] = hi[d].x;
-                    }
+            for (int d = 0; d < 4; ++d) {
+                if ((arrivals >> d) & 1u) {
+                    const uint32_t la = t * N + ((arrivals >> (4 + 6 * d)) & 63u);
+                    l_trait[la] = in_lo[d].y;
+                    l_count[la] = in_lo[d].z;
+                    l_surf[la] = in_lo[d].w;
+                    if (SW > 1) l_surf[TA + la] = in_hi[d].x;
                 }
             }
         }
@@ -435,6 +442,7 @@ size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
 
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
 static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
+    if (p.tile_isl == 0 || p.tile_isl > block_threads) return hipErrorInvalidValue;
     const uint32_t tiles = (p.I + p.tile_isl - 1) / p.tile_isl;
     const size_t lds = step_lds_bytes(p.tile_isl, p.N, SW);
     hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT, ASYNC>), dim3(tiles), dim3(block_threads),
