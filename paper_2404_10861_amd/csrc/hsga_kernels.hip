@@ -164,13 +164,31 @@ __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint3
 
 extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
 
+// The Philox blocks of a thread's APT births (and the second blocks of
+// float births), computed as interleaved chains.  They depend only on the
+// counters, so the tile computes them while its loads are in flight.
+template <uint32_t BM, int APT>
+struct BirthDraws {
+    static constexpr int NB = BM == kBirthFloat ? 2 * APT : APT;
+    uint4 blk[NB];
+    __device__ __forceinline__ void compute(const StepParams& p, uint32_t j0, uint32_t isl) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            blk[q] = make_uint4(j0 + q, isl, p.g, kBirth);
+            if constexpr (BM == kBirthFloat) blk[APT + q] = make_uint4(j0 + q, isl, p.g, kBirthB);
+        }
+        philox4x32_10_multi<NB>(blk, p.k0, p.k1);
+    }
+};
+
 // Births of this thread's APT agents.  APT divides N, so they share one
-// island: its index and the first slot come from one division.
+// island (il of the tile, slots j0 .. j0+APT-1).
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC, bool POW2>
 __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_isl,
-                                            uint32_t la0, uint32_t site_word,
-                                            uint32_t site_shift, uint32_t diff_mask,
-                                            uint32_t n_shift) {
+                                            uint32_t la0, uint32_t il, uint32_t j0,
+                                            const BirthDraws<BM, APT>& draws,
+                                            uint32_t site_word, uint32_t site_shift,
+                                            uint32_t diff_mask, uint32_t n_shift) {
     uint32_t* lds = g_step_lds;
     const uint32_t N = p.N;
     const uint32_t TA = (p.tile_isl * N + 3u) & ~3u;
@@ -185,25 +203,13 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
         if constexpr (POW2) return w >> n_shift;   // = mulhi(w, N) for N = 2^(32 - n_shift)
         else return word_below(w, N);
     };
-    const uint32_t il = (la0 * p.div_magic) >> 20;      // la0 / N, exact for la0 < 4096
-    const uint32_t j0 = la0 - il * N;
     const uint32_t isl = first_isl + il;
     const uint32_t base = il * N;
-    // the birth blocks of all APT agents (and the second blocks of float
-    // births), computed together
-    constexpr int NB = BM == kBirthFloat ? 2 * APT : APT;
-    uint4 blk[NB];
-#pragma unroll
-    for (int q = 0; q < APT; ++q) {
-        blk[q] = make_uint4(j0 + q, isl, p.g, kBirth);
-        if constexpr (BM == kBirthFloat) blk[APT + q] = make_uint4(j0 + q, isl, p.g, kBirthB);
-    }
-    philox4x32_10_multi<NB>(blk, p.k0, p.k1);
+    const uint4* blk = draws.blk;
     Lanes<APT> ctr, ccn, csf[SW];
 #pragma unroll
     for (int q = 0; q < APT; ++q) {
         const uint32_t la = la0 + q;
-        const uint32_t j = j0 + q;
         bool act = true;
         if constexpr (ASYNC) act = (l_plan[il] >> 31) != 0u;
         if (!act) {
@@ -278,19 +284,33 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                                   : word;
             }
         }
-        if (MIGR) {
-            const uint32_t em = l_emig[il];
-            if (j == (em & 0xffu)) {
-                uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
-                const uint32_t dir = (em >> 8) & 7u;
-                if (dir < 4u) {
-                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, ctr.v[q], ccn.v[q], csf[0].v[q]);
-                    *reinterpret_cast<uint4*>(o + 4) =
-                        make_uint4(SW > 1 ? csf[SW - 1].v[q] : 0u, 0u, 0u, 0u);
-                } else {
-                    *reinterpret_cast<uint4*>(o) = make_uint4(dir, 0u, 0u, 0u);
-                    *reinterpret_cast<uint4*>(o + 4) = make_uint4(0u, 0u, 0u, 0u);
+    }
+    if (MIGR) {
+        // the island's emigrant, if it is one of this thread's agents (after
+        // the loop, so that the loop body has no branch and the agents' LDS
+        // reads overlap)
+        const uint32_t em = l_emig[il];
+        const uint32_t qe = (em & 0xffu) - j0;          // >= APT: another thread's
+        if (qe < (uint32_t)APT) {
+            uint32_t e_tr = ctr.v[0], e_cn = ccn.v[0], e_s0 = csf[0].v[0],
+                     e_s1 = csf[SW - 1].v[0];
+#pragma unroll
+            for (int q = 1; q < APT; ++q) {
+                if (qe == (uint32_t)q) {
+                    e_tr = ctr.v[q];
+                    e_cn = ccn.v[q];
+                    e_s0 = csf[0].v[q];
+                    e_s1 = csf[SW - 1].v[q];
                 }
+            }
+            uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
+            const uint32_t dir = (em >> 8) & 7u;
+            if (dir < 4u) {
+                *reinterpret_cast<uint4*>(o) = make_uint4(dir, e_tr, e_cn, e_s0);
+                *reinterpret_cast<uint4*>(o + 4) = make_uint4(SW > 1 ? e_s1 : 0u, 0u, 0u, 0u);
+            } else {
+                *reinterpret_cast<uint4*>(o) = make_uint4(dir, 0u, 0u, 0u);
+                *reinterpret_cast<uint4*>(o + 4) = make_uint4(0u, 0u, 0u, 0u);
             }
         }
     }
@@ -323,6 +343,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     const uint32_t la0 = t * APT;
     const bool mine = la0 < nag;
 
+    // this generation's deposit: word and bit offset of the site, none
+    // (no word matches) between ingests
+    uint32_t site_word = 0xffu, site_shift = 0u;
+    if (p.site) {
+        const uint32_t site = *p.site;
+        site_word = site >> (5u - p.diff_log2);
+        site_shift = (site << p.diff_log2) & 31u;
+    }
     // 1. this thread's agents, every plane
     Lanes<APT> tr, ct, sf[SW];
     if (mine) {
@@ -335,9 +363,25 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     // draw) and thread blockDim-1-t takes island t for emigration; the host
     // keeps tile_isl <= blockDim.  Each neighbour's whole outbox entry is
     // read together with the tile (the record shares the direction word's
-    // cache line), so the immigrants need no second round trip.
+    // cache line), so the immigrants need no second round trip; the loads
+    // are issued outside any branch (lanes without an island read entry 0;
+    // before the first generation the entries are read but not used) so
+    // that nothing waits for them before the birth draws.
     uint4 in_lo[4], in_hi[4];
-    uint32_t arrivals = 0;
+    uint32_t imm_slots = 0;        // the four directions' slots, 6 bits each
+    bool imm_take = false;         // this lane's island takes immigrants
+    if (MIGR) {
+        const bool lane_isl = t < nisl;
+        const uint32_t isl = first_isl + (lane_isl ? t : 0u);
+        const uint32_t x = isl % W;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const size_t e =
+                lane_isl ? (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * kOutboxWords : 0;
+            in_lo[d] = *reinterpret_cast<const uint4*>(p.ob_in + e);
+            if (SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(p.ob_in + e + 4);
+        }
+    }
     if (MIGR || ASYNC) {
         // asynchronous ticks: an island runs a generation iff its activity
         // draw is below the threshold (plan bit 31); an idle island takes no
@@ -348,26 +392,13 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
             if constexpr (ASYNC)
                 act = philox4x32_10(make_uint4(0u, isl, p.g, kActivity), p.k0, p.k1).x <
                       p.async_thr;
-            uint32_t plan = 0;
             if (MIGR && act && p.has_inbox) {
                 const uint4 w4 = philox4x32_10(make_uint4(0u, isl, p.g, kImmigrate), p.k0, p.k1);
-                const uint32_t x = isl % W;
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const uint32_t* e =
-                        p.ob_in + (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * kOutboxWords;
-                    in_lo[d] = *reinterpret_cast<const uint4*>(e);
-                    if (SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(e + 4);
-                }
-                // a neighbour delivers when its emigrant was sent our way
-                arrivals = (in_lo[0].x == 1u ? 1u : 0u) | (in_lo[1].x == 0u ? 2u : 0u) |
-                           (in_lo[2].x == 3u ? 4u : 0u) | (in_lo[3].x == 2u ? 8u : 0u);
-                plan = word_below(w4.x, N) | (word_below(w4.y, N) << 6) |
-                       (word_below(w4.z, N) << 12) | (word_below(w4.w, N) << 18);
+                imm_slots = word_below(w4.x, N) | (word_below(w4.y, N) << 6) |
+                            (word_below(w4.z, N) << 12) | (word_below(w4.w, N) << 18);
+                imm_take = true;
             }
-            if (ASYNC && act) plan |= 1u << 31;
-            arrivals |= plan << 4;     // slots of the four directions above the arrival bits
-            l_plan[t] = plan;
+            if constexpr (ASYNC) l_plan[t] = act ? 1u << 31 : 0u;
         }
         if (MIGR) {
             const uint32_t il = blockDim.x - 1u - t;
@@ -383,6 +414,16 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         }
     }
 
+    // this thread's island and first slot (one division: la0 < 4096), and
+    // its birth draws while the loads are in flight (integer births; the
+    // float births' two blocks per agent would cost a wave per SIMD, so
+    // they are drawn after the staging)
+    const uint32_t il = (la0 * p.div_magic) >> 20;
+    const uint32_t j0 = la0 - il * N;
+    BirthDraws<BM, APT> draws;
+    if constexpr (BM != kBirthFloat)
+        if (mine) draws.compute(p, j0, first_isl + il);
+
     // 2. stage the tile in LDS, then overwrite immigrant slots (north,
     // south, west, east: a later direction overwrites an earlier one)
     if (mine) {
@@ -393,11 +434,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     }
     __syncthreads();
     if (MIGR) {
-        if (arrivals & 15u) {
+        if (imm_take) {
+            // a neighbour delivers when its emigrant was sent our way
+            const uint32_t arrivals = (in_lo[0].x == 1u ? 1u : 0u) | (in_lo[1].x == 0u ? 2u : 0u) |
+                                      (in_lo[2].x == 3u ? 4u : 0u) | (in_lo[3].x == 2u ? 8u : 0u);
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 if ((arrivals >> d) & 1u) {
-                    const uint32_t la = t * N + ((arrivals >> (4 + 6 * d)) & 63u);
+                    const uint32_t la = t * N + ((imm_slots >> (6 * d)) & 63u);
                     l_trait[la] = in_lo[d].y;
                     l_count[la] = in_lo[d].z;
                     l_surf[la] = in_lo[d].w;
@@ -409,25 +453,18 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     }
 
     // 3. births
-    // this generation's deposit: word and bit offset of the site, none
-    // (no word matches) between ingests
-    uint32_t site_word = 0xffu, site_shift = 0u;
-    if (p.site) {
-        const uint32_t site = *p.site;
-        site_word = site >> (5u - p.diff_log2);
-        site_shift = (site << p.diff_log2) & 31u;
-    }
     const uint32_t diff_mask = p.diff_log2 ? 0xffu : 1u;
     if (!mine) return;
+    if constexpr (BM == kBirthFloat) draws.compute(p, j0, first_isl + il);
     // draws onto [0, N): a shift when N is a power of two above 1 (a
     // wave-uniform choice between two copies of the births)
     const uint32_t n_shift = (N > 1u && (N & (N - 1u)) == 0u) ? 32u - __builtin_ctz(N) : 0u;
     if (n_shift)
-        step_births<SW, BM, MIGR, APT, ASYNC, true>(p, first_isl, la0, site_word, site_shift,
-                                                    diff_mask, n_shift);
+        step_births<SW, BM, MIGR, APT, ASYNC, true>(p, first_isl, la0, il, j0, draws, site_word,
+                                                    site_shift, diff_mask, n_shift);
     else
-        step_births<SW, BM, MIGR, APT, ASYNC, false>(p, first_isl, la0, site_word, site_shift,
-                                                     diff_mask, n_shift);
+        step_births<SW, BM, MIGR, APT, ASYNC, false>(p, first_isl, la0, il, j0, draws, site_word,
+                                                     site_shift, diff_mask, n_shift);
 }
 
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
