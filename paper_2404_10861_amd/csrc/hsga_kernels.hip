@@ -262,7 +262,8 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                 ctr.v[q] = ptrait + delta;
                 bit = r.w & diff_mask;
             }
-            const uint32_t T = l_count[par];
+            // synchronous generations: every member's counter is g
+            const uint32_t T = ASYNC ? l_count[par] : p.g;
             ccn.v[q] = T + 1u;
             uint32_t dep_word = site_word, dep_shift = site_shift;
             if constexpr (ASYNC) {
@@ -355,7 +356,11 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     Lanes<APT> tr, ct, sf[SW];
     if (mine) {
         tr = load_lanes<APT>(p.in_trait + a0 + la0);
-        ct = load_lanes<APT>(p.in_counter + a0 + la0);
+        // the counter plane is read only by asynchronous ticks: in
+        // synchronous generations every agent's counter is the generation
+        // number (founders 0, each birth one above a parent of the same
+        // generation), so the step needs no copy of it
+        if (ASYNC) ct = load_lanes<APT>(p.in_counter + a0 + la0);
 #pragma unroll
         for (int w = 0; w < SW; ++w) sf[w] = load_lanes<APT>(p.in_surf + w * A + a0 + la0);
     }
@@ -428,7 +433,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     // south, west, east: a later direction overwrites an earlier one)
     if (mine) {
         lds_store_lanes<APT>(l_trait + la0, tr);
-        lds_store_lanes<APT>(l_count + la0, ct);
+        if (ASYNC) lds_store_lanes<APT>(l_count + la0, ct);
 #pragma unroll
         for (int w = 0; w < SW; ++w) lds_store_lanes<APT>(l_surf + w * TA + la0, sf[w]);
     }
@@ -443,7 +448,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
                 if ((arrivals >> d) & 1u) {
                     const uint32_t la = t * N + ((imm_slots >> (6 * d)) & 63u);
                     l_trait[la] = in_lo[d].y;
-                    l_count[la] = in_lo[d].z;
+                    if (ASYNC) l_count[la] = in_lo[d].z;
                     l_surf[la] = in_lo[d].w;
                     if (SW > 1) l_surf[TA + la] = in_hi[d].x;
                 }
