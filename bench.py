@@ -240,6 +240,7 @@ def main(argv=None) -> int:
     bytes_per_launch = algorithmic_bytes_per_generation(spec)
     avg_launch_s = kern_ms / 1000.0 / max(launches, 1)
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic(spec)
     line = {
         "metric": "agent-replications/sec",
         "value": value,
@@ -270,12 +271,18 @@ def main(argv=None) -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": measured_traffic(spec),
+            "traffic": traffic,
             "kernel": "step_kernel<2, kBirthIntTournament, migration, 4 agents per thread>",
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "attainable_copy_GBs": copy_gbs,
             "frac_of_attainable": achieved_gbs / copy_gbs,
+            # measured HBM bytes over the same launch time: synchronous
+            # steps read no counter plane (every counter is the generation
+            # number), so the traffic is below the algorithmic bytes
+            "traffic_GBs": traffic / avg_launch_s / 1e9 if traffic else None,
+            "traffic_frac_of_attainable":
+                traffic / avg_launch_s / 1e9 / copy_gbs if traffic else None,
         },
         "context": {
             "paper_cs2_replications_per_s": 3.18e11,
