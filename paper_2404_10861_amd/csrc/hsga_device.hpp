@@ -233,53 +233,54 @@ __host__ __device__ inline uint32_t leave_time(uint32_t policy, uint32_t m, uint
     return kNever;   // stays until past the horizon
 }
 
-// One placement across the wavefront: lane k holds the deposit time of
-// site k (global time, kEmpty if unfilled) and the local time its item
-// leaves the target (0 if unfilled).  Item T goes to its own local slot
-// while its sub-surface fills, otherwise to the lowest site of the
-// sub-surface whose item has left the target (ballot + bit scan); -1 if
-// none (past the horizon).  The chosen lane takes (T, new_leave), the leave
-// time of item T.  Must be called by all 64 lanes with uniform arguments.
-__device__ __forceinline__ int place_in_wave(uint32_t kind, uint32_t S, uint32_t T,
-                                             uint32_t new_leave, uint32_t& lane_time,
-                                             uint32_t& lane_leave, uint32_t lane) {
-    const SubSurface s = sub_surface(kind, S, T);
-    int site;
-    if (s.u < s.m) {
-        site = (int)(s.offset + s.u);
-    } else {
-        const bool evictable = lane >= s.offset && lane < s.offset + s.m && s.u >= lane_leave;
-        const uint64_t mask = __ballot(evictable);
-        site = mask ? (int)(__ffsll((long long)mask) - 1) : -1;
-    }
-    if ((int)lane == site) {
-        lane_time = T;
-        lane_leave = new_leave;
-    }
-    return site;
-}
-
-// Leave time of item T in its own sub-surface.
-__device__ __forceinline__ uint32_t item_leave_time(uint32_t kind, uint32_t S, uint32_t T) {
-    const SubSurface s = sub_surface(kind, S, T);
-    return leave_time(s.policy, s.m, s.u);
-}
-
-// Places items T0 .. T0+G-1 in blocks of 64: each lane first computes the
-// leave time of one item of the block (in parallel), then the 64 serial
-// placements read it with readlane.  site_out(k, site) is called by lane
-// k % 64 once per item.  Must be called by all 64 lanes.
+// Places items T0 .. T0+G-1 across the wavefront.  Lane k holds the deposit
+// time of site k (global time, kEmpty if unfilled) and the local time its
+// item leaves the target (0 if unfilled).  Item T goes to its own local
+// slot while its sub-surface fills, otherwise to the lowest site of the
+// sub-surface whose item has left the target; -1 if none (past the
+// horizon).  The chosen lane takes (T, the leave time of item T).
+// Items go in blocks of 64: each lane first works out one item of the
+// block (sub-surface, local time, leave time) in parallel; the serial
+// placements then read them with readlane and reduce to a compare, a
+// ballot, a bit scan and two selects.  site_out(k, site) is called by
+// lane k % 64 once per item.  Must be called by all 64 lanes with uniform
+// arguments.
 template <typename SiteOut>
 __device__ __forceinline__ void place_items(uint32_t kind, uint32_t S, uint32_t T0, uint32_t G,
                                             uint32_t& lane_time, uint32_t& lane_leave,
                                             uint32_t lane, SiteOut site_out) {
+    // sites of the sub-surfaces: the whole surface, or the halves of a
+    // hybrid one (steady below, tilted above)
+    const uint32_t half = S >> 1;
+    const uint64_t all = S >= 64 ? ~0ull : (1ull << S) - 1;
+    const uint64_t lower = kind == kHybrid ? (1ull << half) - 1 : all;
+    const uint64_t upper = ((1ull << half) - 1) << half;
     for (uint32_t base = 0; base < G; base += 64) {
         const uint32_t n = G - base < 64 ? G - base : 64;
-        const uint32_t mine = lane < n ? item_leave_time(kind, S, T0 + base + lane) : 0u;
+        // item T0+base+lane: local time, leave time, and a word holding its
+        // fill-phase site (bits 0-7), "still filling" (bit 8) and "upper
+        // half" (bit 9)
+        uint32_t my_u = 0, my_leave = 0, my_info = 0;
+        if (lane < n) {
+            const SubSurface sb = sub_surface(kind, S, T0 + base + lane);
+            my_u = sb.u;
+            my_leave = leave_time(sb.policy, sb.m, sb.u);
+            my_info = (sb.u < sb.m ? ((sb.offset + sb.u) | 0x100u) : 0u) |
+                      (sb.offset != 0 ? 0x200u : 0u);
+        }
         int my_site = -1;
         for (uint32_t j = 0; j < n; ++j) {
-            const uint32_t nl = (uint32_t)__builtin_amdgcn_readlane((int)mine, (int)j);
-            const int site = place_in_wave(kind, S, T0 + base + j, nl, lane_time, lane_leave, lane);
+            const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)my_u, (int)j);
+            const uint32_t nl = (uint32_t)__builtin_amdgcn_readlane((int)my_leave, (int)j);
+            const uint32_t info = (uint32_t)__builtin_amdgcn_readlane((int)my_info, (int)j);
+            const uint64_t range = (info & 0x200u) ? upper : lower;
+            const uint64_t left = __ballot(u >= lane_leave) & range;
+            const int site = (info & 0x100u) ? (int)(info & 0xffu)
+                                              : (left ? (int)__builtin_ctzll(left) : -1);
+            if ((int)lane == site) {
+                lane_time = T0 + base + j;
+                lane_leave = nl;
+            }
             if (lane == j) my_site = site;
         }
         if (lane < n) site_out(base + lane, my_site);
