@@ -118,7 +118,9 @@ typedef struct ga_run ga_run;
  * Device state of a run, carved from the caller's arena:
  *   - two ping-pong populations, structure of arrays: trait[A],
  *     counter[A], surface word planes [S/32][A] (A = w*h*N agents);
- *   - two ping-pong outboxes, one 32-byte entry per island;
+ *   - two ping-pong outboxes, 32 bytes reserved per island (a synchronous
+ *     run's entry uses 16: direction, trait, surface words, since every
+ *     emigrant's counter is the generation count);
  *   - the run's surface layout (deposit time of each site) and a site
  *     schedule of max_gens_per_launch words.
  * An agent record is (uint32 trait, uint32 generation counter, S one-bit

@@ -366,17 +366,23 @@ int ga_read_outbox(ga_run* r, uint32_t first, uint32_t count, uint32_t* dir, uin
     if (!*valid || count == 0) return GA_OK;
     hipError_t e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    std::vector<uint32_t> entries((size_t)count * hsga::kOutboxWords);
-    e = hipMemcpy(entries.data(), r->outbox[r->T & 1] + (size_t)first * hsga::kOutboxWords,
+    // asynchronous entries: dir, trait, counter, surface; synchronous ones
+    // leave the counter out (every emigrant's counter is T)
+    const bool async = r->cfg.async_activity != 0;
+    const uint32_t words = async ? hsga::kOutboxWords : hsga::kSyncOutboxWords;
+    const uint32_t surf0 = async ? 3 : 2;
+    std::vector<uint32_t> entries((size_t)count * words);
+    e = hipMemcpy(entries.data(), r->outbox[r->T & 1] + (size_t)first * words,
                   entries.size() * 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy outbox");
     for (uint32_t k = 0; k < count; ++k) {
-        const uint32_t* en = &entries[(size_t)k * hsga::kOutboxWords];
+        const uint32_t* en = &entries[(size_t)k * words];
         if (dir) dir[k] = en[0];
         if (trait) trait[k] = en[1];
-        if (counter) counter[k] = en[2];
+        if (counter) counter[k] = async ? en[2] : r->T;
         if (surface_words)
-            for (uint32_t w = 0; w < r->SW; ++w) surface_words[(size_t)k * r->SW + w] = en[3 + w];
+            for (uint32_t w = 0; w < r->SW; ++w)
+                surface_words[(size_t)k * r->SW + w] = en[surf0 + w];
     }
     return GA_OK;
 }

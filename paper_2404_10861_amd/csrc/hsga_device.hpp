@@ -15,8 +15,12 @@ constexpr uint32_t kBirth = 0, kEmigrate = 1, kImmigrate = 2, kSample = 3;
 // Second block of a float-treatment birth; founder tags; whether an island
 // is active on a tick of an asynchronous run.
 constexpr uint32_t kBirthB = 4, kFounder = 5, kActivity = 6;
-// Outbox entry: dir, trait, counter, surface words (up to 2), padding.
+// Outbox entry of an asynchronous run: dir, trait, counter, surface words
+// (up to 2), padding.  A synchronous run's emigrant carries counter T, the
+// generation count, so its entry is dir, trait, surface words (up to 2):
+// 16 bytes.  The arena reserves the larger size.
 constexpr uint32_t kOutboxWords = 8;
+constexpr uint32_t kSyncOutboxWords = 4;
 
 // Philox4x32-10 (Salmon et al., SC'11).  Counter (c.x, c.y, c.z, c.w), key
 // (k0, k1).  Each round forms the two 32x32->64 products of counter words

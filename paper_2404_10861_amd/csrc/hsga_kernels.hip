@@ -292,6 +292,7 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
         // reads overlap)
         const uint32_t em = l_emig[il];
         const uint32_t qe = (em & 0xffu) - j0;          // >= APT: another thread's
+        constexpr uint32_t OBW = ASYNC ? kOutboxWords : kSyncOutboxWords;
         if (qe < (uint32_t)APT) {
             uint32_t e_tr = ctr.v[0], e_cn = ccn.v[0], e_s0 = csf[0].v[0],
                      e_s1 = csf[SW - 1].v[0];
@@ -304,9 +305,12 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                     e_s1 = csf[SW - 1].v[q];
                 }
             }
-            uint32_t* o = p.ob_out + (size_t)isl * kOutboxWords;
+            uint32_t* o = p.ob_out + (size_t)isl * OBW;
             const uint32_t dir = (em >> 8) & 7u;
-            if (dir < 4u) {
+            if constexpr (!ASYNC) {
+                // synchronous: always a direction below 4, counter implied
+                *reinterpret_cast<uint4*>(o) = make_uint4(dir, e_tr, e_s0, SW > 1 ? e_s1 : 0u);
+            } else if (dir < 4u) {
                 *reinterpret_cast<uint4*>(o) = make_uint4(dir, e_tr, e_cn, e_s0);
                 *reinterpret_cast<uint4*>(o + 4) = make_uint4(SW > 1 ? e_s1 : 0u, 0u, 0u, 0u);
             } else {
@@ -372,6 +376,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     // are issued outside any branch (lanes without an island read entry 0;
     // before the first generation the entries are read but not used) so
     // that nothing waits for them before the birth draws.
+    constexpr uint32_t OBW = ASYNC ? kOutboxWords : kSyncOutboxWords;
     uint4 in_lo[4], in_hi[4];
     uint32_t imm_slots = 0;        // the four directions' slots, 6 bits each
     bool imm_take = false;         // this lane's island takes immigrants
@@ -382,9 +387,9 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const size_t e =
-                lane_isl ? (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * kOutboxWords : 0;
+                lane_isl ? (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * OBW : 0;
             in_lo[d] = *reinterpret_cast<const uint4*>(p.ob_in + e);
-            if (SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(p.ob_in + e + 4);
+            if (ASYNC && SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(p.ob_in + e + 4);
         }
     }
     if (MIGR || ASYNC) {
@@ -448,9 +453,14 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
                 if ((arrivals >> d) & 1u) {
                     const uint32_t la = t * N + ((imm_slots >> (6 * d)) & 63u);
                     l_trait[la] = in_lo[d].y;
-                    if (ASYNC) l_count[la] = in_lo[d].z;
-                    l_surf[la] = in_lo[d].w;
-                    if (SW > 1) l_surf[TA + la] = in_hi[d].x;
+                    if constexpr (ASYNC) {
+                        l_count[la] = in_lo[d].z;
+                        l_surf[la] = in_lo[d].w;
+                        if (SW > 1) l_surf[TA + la] = in_hi[d].x;
+                    } else {
+                        l_surf[la] = in_lo[d].z;
+                        if (SW > 1) l_surf[TA + la] = in_lo[d].w;
+                    }
                 }
             }
         }
