@@ -410,8 +410,8 @@ int ga_set_kernel_timing(ga_run *run, int enable);
 int ga_kernel_time(ga_run *run, double *ms, uint64_t *launches, int reset);
 
 /* A plain device-to-device copy of `bytes` bytes (multiple of 16; both
- * pointers 16-byte aligned), one 16-byte load and store per lane, no cache
- * hints.  Not part of the method: it measures the attainable HBM bandwidth
+ * pointers 16-byte aligned), one 16-byte load and store per thread, with
+ * the non-temporal hint.  Not part of the method: it measures the attainable HBM bandwidth
  * next to the step kernel and calibrates hardware byte counters against a
  * kernel of known traffic.  Enqueued on hip_stream.  Errors: GA_EINVAL.   */
 int ga_probe_copy(const void *src, void *dst, size_t bytes, void *hip_stream);

@@ -655,22 +655,23 @@ hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32
 }
 
 // ---------------------------------------------------------------------------
-// Plain streaming copy (instrumentation): one 16-byte load and store per
-// lane per iteration, grid-stride.
-__global__ __launch_bounds__(256) void probe_copy_kernel(const uint4* __restrict__ src,
-                                                        uint4* __restrict__ dst, size_t n16) {
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
-        dst[i] = src[i];
+// Plain streaming copy (instrumentation): one 16-byte non-temporal load
+// and store per thread over a grid that covers the buffer (the fastest of
+// the simple copy forms on this chip, so the attainable-bandwidth figure
+// is not understated).
+__global__ __launch_bounds__(256) void probe_copy_kernel(const u32x4* __restrict__ src,
+                                                        u32x4* __restrict__ dst, size_t n16) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream_t stream) {
     const size_t n16 = bytes / 16;
-    size_t blocks = (n16 + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    const size_t blocks = (n16 + 255) / 256;
     if (blocks == 0) return hipSuccess;
+    if (blocks > 0xffffffffull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(probe_copy_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+                       static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n16);
     return hipGetLastError();
 }
 

@@ -182,3 +182,20 @@ def test_site_schedule_past_2_16(hs, orc, kind, S):
         done += chunk
         assert np.array_equal(g.layout(), orc.layout(KIND[kind], S, done)), done
     assert done == 70000
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, (1 << 20) + 48])
+def test_probe_copy_is_exact(hs, nbytes):
+    """The instrumentation copy moves exactly the requested 16-byte multiple
+    (ragged last workgroup included) and nothing beyond it."""
+    import torch
+    rng = np.random.default_rng(nbytes)
+    src_h = rng.integers(0, 256, size=nbytes + 64, dtype=np.uint8)
+    src = torch.from_numpy(src_h).cuda()
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    moved = hs.probe_copy(src[:nbytes], dst)
+    torch.cuda.synchronize()
+    out = dst.cpu().numpy()
+    assert moved == nbytes
+    assert np.array_equal(out[:nbytes], src_h[:nbytes])
+    assert not out[nbytes:].any()
