@@ -7,10 +7,15 @@ FETCH_SIZE or WRITE_SIZE runs) and writes short text summaries:
   python -m paper_2404_10861_amd.profiling traffic --fetch DIR --write DIR
         --copy-bytes B --kernel step_kernel --bytes-per-launch X
         --out FILE.json --md FILE.md --cmd "..." --cmd "..."
+  python -m paper_2404_10861_amd.profiling counters --fetch DIR --write DIR
+        --kernel NAME --bytes-per-launch X --md FILE.md --cmd "..."
 
 The traffic summary scales each counter by what the same counter reads for
 the plain copy kernel of known size (bytes read, bytes written), giving HBM
-bytes per launch of the step kernel.
+bytes per launch of the step kernel.  The counters summary reports the raw
+per-dispatch medians of one kernel (KiB) next to its algorithmic bytes, for
+runs without the copy kernel (WRITE_SIZE reads 1.000 of the copy kernel's
+written bytes, FETCH_SIZE 0.5000 of its read bytes, on MI355X).
 """
 from __future__ import annotations
 
@@ -28,9 +33,14 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2404_10861_amd", "csrc", f)
                   for f in ("hsga_kernels.hip", "hsga_device.hpp")]
 
 
-def kernel_hash() -> str:
+QUERY_SOURCES = [os.path.join(ROOT, "paper_2404_10861_amd", "csrc", f)
+                 for f in ("hsga_query.hip", "hsga_device.hpp")]
+
+
+def kernel_hash(sources=None) -> str:
+    """Hash of the step kernel's sources (or of the given files)."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -146,6 +156,27 @@ def cmd_traffic(a):
     print("\n".join(lines))
 
 
+def cmd_counters(a):
+    fetch = counter_values(a.fetch, "FETCH_SIZE")
+    write = counter_values(a.write, "WRITE_SIZE")
+    names, sf = _pick(fetch, a.kernel)
+    _, sw = _pick(write, a.kernel)
+    f_kib, w_kib = statistics.median(sf), statistics.median(sw)
+    lines = [f"# HBM counters of `{a.kernel}`: {a.title}", "", "Commands:", ""]
+    for c in a.cmd:
+        lines.append(f"    {c}")
+    lines += ["",
+              f"- dispatches: {len(sf)} ({', '.join(n[:60] for n in names)})",
+              f"- FETCH_SIZE median {f_kib:.1f} KiB per dispatch, WRITE_SIZE median "
+              f"{w_kib:.1f} KiB per dispatch",
+              f"- algorithmic bytes per dispatch: {a.bytes_per_launch / 1e6:.1f} MB; "
+              f"WRITE_SIZE bytes / algorithmic = {w_kib * 1024 / a.bytes_per_launch:.3f}",
+              f"- query kernel source hash: {kernel_hash(QUERY_SOURCES)}", ""]
+    with open(a.md, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -164,9 +195,19 @@ def main(argv=None):
     t.add_argument("--md", required=True)
     t.add_argument("--title", default="")
     t.add_argument("--cmd", action="append", default=[])
+    c = sub.add_parser("counters")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--kernel", required=True, help="a query kernel (hsga_query.hip)")
+    c.add_argument("--bytes-per-launch", type=float, required=True)
+    c.add_argument("--md", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--cmd", action="append", default=[])
     a = ap.parse_args(argv)
     if a.what == "stats":
         cmd_stats(a)
+    elif a.what == "counters":
+        cmd_counters(a)
     else:
         cmd_traffic(a)
 
