@@ -87,22 +87,26 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 //
 // One workgroup per tile of whole islands; the tile's population is staged
 // in LDS as structure-of-arrays planes.
-//  1. Each thread loads APT consecutive agents of every plane with one
-//     16-byte (APT = 4) load per plane; meanwhile the island pass draws one
-//     immigration and one emigration Philox block per island and reads the
-//     four neighbours' outbox directions.
-//  2. Records go to LDS; after a barrier, one thread per island copies the
-//     neighbours' emigrants that were addressed to it over the chosen slots,
+//  1. Each thread issues one 16-byte (APT = 4) non-temporal load per plane
+//     for its APT consecutive agents: traits and surface words, counters
+//     only for asynchronous ticks (in a synchronous run every counter is the
+//     generation number).  In the same round thread t issues the loads of
+//     island t's four neighbour outbox entries (direction word and record
+//     together), the island pass draws the immigration and emigration
+//     Philox blocks, and, while the loads are in flight, each thread draws
+//     the Philox blocks of its births.
+//  2. Records go to LDS; after a barrier, the thread of each island copies
+//     the neighbours' emigrants addressed to it over the drawn slots,
 //     north, south, west, east (a later one wins).
-//  3. After a second barrier each thread gives birth to its APT agents: one
-//     Philox block each, a tournament of two read from the island's LDS
-//     traits, the parent record copied from LDS, trait mutation, counter
-//     increment and the differentia bit written at this generation's site.
-//     The thread holding the chosen emigrant posts its copy to the outbox
-//     for g + 1.  Children leave with one 16-byte store per plane.
-// Immigration plan word: bits 0..3 = direction d delivers, bits 4+6d ..
-// 9+6d = slot for direction d.  Emigration word: bits 0..7 = slot, 8..9 =
-// direction.
+//  3. After a second barrier each thread gives birth to its APT agents: a
+//     tournament of two over the island's LDS traits, the parent record
+//     copied from LDS, trait mutation, counter + 1 and the differentia bit
+//     written at this generation's site.  After the loop the thread holding
+//     the island's emigrant posts its copy to the outbox for g + 1.
+//     Children leave with one 16-byte store per plane, counters included.
+// Immigration slots: bits 6d .. 6d+5 = slot for direction d.  Emigration
+// word: bits 0..7 = slot, 8..10 = direction (4: none, an idle island).
+// Plan word (asynchronous ticks): bit 31 = the island is active.
 template <int APT>
 struct Lanes {
     uint32_t v[APT];

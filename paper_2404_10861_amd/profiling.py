@@ -25,6 +25,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 
@@ -37,12 +38,22 @@ QUERY_SOURCES = [os.path.join(ROOT, "paper_2404_10861_amd", "csrc", f)
                  for f in ("hsga_query.hip", "hsga_device.hpp")]
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace collapsed, so that a
+    comment edit does not mark a profile stale (string literals in these
+    files hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_hash(sources=None) -> str:
-    """Hash of the step kernel's sources (or of the given files)."""
+    """Hash of the code (comments and layout aside) of the step kernel's
+    sources, or of the given files."""
     h = hashlib.sha256()
     for p in sources or KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
