@@ -10,7 +10,9 @@ are generated on the device; the paper's workloads are synthetic too).
 Prints one JSON line:
   value     agent-replications/s over the timed steps (births only)
   roofline  the step kernel's algorithmic HBM bytes per launch over its
-            average launch duration (HIP events on the run's stream)
+            average launch duration (HIP events on the run's stream);
+            traffic: the HBM bytes per launch that rocprofv3 counted for
+            the same code (profiles/), null once the code has changed
   cpu_baseline  the plain C oracle on a bounded sample of the same
             workload (the first generations from the founders).
 
