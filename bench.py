@@ -104,6 +104,31 @@ def cpu_baseline(spec, budget_s: float = 12.0):
     }
 
 
+def cpu_baseline_query(spec, counters, surfaces, rows: int = 1024):
+    """The oracle's all-pairs MRCA bounds, single-threaded, on the first
+    rows of the GPU run's sample (every column), as ordered pairs per
+    second."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import hsga_oracle as orc
+    if not os.path.exists(orc.LIB):
+        orc.build()
+    import numpy as np
+    n = len(counters)
+    rows = min(rows, n)
+    t0 = time.perf_counter()
+    orc.mrca_rows(orc.KINDS[spec.surface_kind], spec.surface_sites, counters, surfaces,
+                  np.arange(rows, dtype=np.uint32))
+    el = time.perf_counter() - t0
+    return {
+        "value": rows * n / el,
+        "unit": "MRCA ordered pairs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"rows 0..{rows - 1} of the {n:,}-agent sample of {spec.name} "
+                   f"({rows * n:,} ordered pairs in {el:.1f} s), plain C oracle, one thread"),
+    }
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,8 +186,16 @@ def main(argv=None) -> int:
             metric = "agent-replications/sec (float trial) and phylometrics"
             value = res["purifying"]["replications_per_s"]
         elif args.mode == "pair":
-            res = benchmarks.treatment_pair([wl.c3(True), wl.c3(False)], dev,
-                                            torch.cuda.current_stream(dev))
+            spec_sel = wl.c3(True)
+            res = benchmarks.treatment_pair([spec_sel, wl.c3(False)], dev,
+                                            torch.cuda.current_stream(dev),
+                                            keep_samples=not args.no_cpu_baseline)
+            samples = res.pop("_samples", None)
+            for label in ("selection", "neutral"):
+                r = res[label]
+                r["mrca_pairs_per_s"] = r["mrca_pairs"] / (r["mrca_query_ms"] / 1000.0)
+            if samples is not None:
+                res["cpu_baseline_query"] = cpu_baseline_query(spec_sel, *samples["selection"])
             metric = "agent-replications/sec (treatment pair) and MRCA query time"
             value = res["selection"]["replications_per_s"]
         elif args.mode == "batched":

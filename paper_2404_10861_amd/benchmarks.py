@@ -154,7 +154,7 @@ def served_vs_plain(reqs, dev, chunk_gens: int = 256, time_scale: float = 1.0,
 
 
 def treatment_pair(specs, dev, stream, n_sample: int = 4096, labels=None,
-                   allpairs: bool = True, progress=None) -> dict:
+                   allpairs: bool = True, progress=None, keep_samples: bool = False) -> dict:
     """A treatment pair: each run, its stratified sample, all-pairs MRCA
     bounds (if allpairs) and the reconstructed tree's phylometrics (sum
     branch length, mean evolutionary distinctiveness, mean pairwise
@@ -192,6 +192,9 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096, labels=None,
         wall = time.perf_counter() - t0
         ms, launches = run.kernel_time()
         trait = run.agents(0, 65536)[0]
+        if keep_samples:
+            # host copies of the sample, under a key the caller removes
+            out.setdefault("_samples", {})[label] = (hs.as_u32(cnt), hs.as_u32(srf))
         rec = {
             "workload": s.name,
             "replications_per_s": s.replications / wall,
