@@ -169,8 +169,9 @@ __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint3
 extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
 
 // The Philox blocks of a thread's APT births (and the second blocks of
-// float births), computed as interleaved chains.  They depend only on the
-// counters, so the tile computes them while its loads are in flight.
+// float births), computed as interleaved chains.  Their counter words
+// (slot, island, generation, purpose) need no population data, so the tile
+// computes them while its loads are in flight.
 template <uint32_t BM, int APT>
 struct BirthDraws {
     static constexpr int NB = BM == kBirthFloat ? 2 * APT : APT;
