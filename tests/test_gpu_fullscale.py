@@ -1,10 +1,12 @@
 """Full-size GPU parity over many generations (opt-in: set
 HSGA_FULL_PARITY=1; the oracle needs minutes of host time): the
 paper-scale workload (512x1024 islands x 32, hybrid-64, tournament of two)
-for 300 generations and the treatment pair's torus (256x256 x 64,
-tilted-32) for 2,000 generations of each treatment, every agent word, the
+for 300 generations, the treatment pair's torus (256x256 x 64, tilted-32)
+for 2,000 generations of each treatment, the float trial (750x750 x 32,
+tilted-64, adaptation-enabled) for 100 generations, and asynchronous ticks on
+the paper-scale torus (activity 0.9) for 200 ticks: every agent word, the
 layout and every outbox entry against the oracle, in the launch
-configuration the benchmark uses."""
+configuration the benchmarks use."""
 import os
 import sys
 import time
@@ -52,6 +54,43 @@ def test_full_size_runs_match_oracle(hs, orc, W, H, N, S, kind, tour, G):
     run.sync()
     o = orc.Run(W, H, N, S, kinds[kind], tournament=tour, seed=1)
     oracle_steps(o, G, f"{W}x{H}x{N} {kind}-{S} tournament {tour}")
+    for name, x, y in zip(("trait", "counter", "surface"), run.agents(), o.agents()):
+        assert np.array_equal(x, y), name
+    assert np.array_equal(run.layout(), o.layout())
+    for x, y in zip(run.outbox(), o.outbox()):
+        assert np.array_equal(x, y)
+    o.close()
+
+
+def test_full_size_float_trial_matches_oracle(hs, orc):
+    """The adaptation-enabled treatment (deleterious and beneficial
+    mutations both occur)."""
+    G, ben = 100, 12884901
+    cfg = hs.Config(750, 750, 32, 64, "tilted", tournament_size=5, seed=1,
+                    fitness_model="float", del_threshold=1417339207, ben_threshold=ben)
+    run = hs.Run(cfg)
+    run.step(G)
+    run.sync()
+    o = orc.Run(750, 750, 32, 64, 1, tournament=5, seed=1, fitness_model=orc.FLOAT_FITNESS,
+                del_thr=1417339207, ben_thr=ben)
+    oracle_steps(o, G, f"float trial, beneficial threshold {ben}")
+    for name, x, y in zip(("fitness", "counter", "surface"), run.agents(), o.agents()):
+        assert np.array_equal(x, y), name
+    assert np.array_equal(run.layout(), o.layout())
+    for x, y in zip(run.outbox(), o.outbox()):
+        assert np.array_equal(x, y)
+    o.close()
+
+
+def test_full_size_asynchronous_ticks_match_oracle(hs, orc):
+    G = 200
+    act = int(0.9 * 2**32)
+    cfg = hs.Config(512, 1024, 32, 64, "hybrid", tournament_size=2, seed=1, async_activity=act)
+    run = hs.Run(cfg, max_gens_per_launch=G)
+    run.step(G)
+    run.sync()
+    o = orc.Run(512, 1024, 32, 64, 2, tournament=2, seed=1, activity=act)
+    oracle_steps(o, G, "asynchronous ticks")
     for name, x, y in zip(("trait", "counter", "surface"), run.agents(), o.agents()):
         assert np.array_equal(x, y), name
     assert np.array_equal(run.layout(), o.layout())
