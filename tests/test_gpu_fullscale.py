@@ -6,7 +6,8 @@ for 2,000 generations of each treatment, the float trial (750x750 x 32,
 tilted-64, adaptation-enabled) for 100 generations, and asynchronous ticks on
 the paper-scale torus (activity 0.9) for 200 ticks: every agent word, the
 layout and every outbox entry against the oracle, in the launch
-configuration the benchmarks use."""
+configuration the benchmarks use; for the integer runs also every pair of
+the benchmark's 4,096-agent MRCA query and its reconstructed tree."""
 import os
 import sys
 import time
@@ -60,6 +61,17 @@ def test_full_size_runs_match_oracle(hs, orc, W, H, N, S, kind, tour, G):
     for x, y in zip(run.outbox(), o.outbox()):
         assert np.array_equal(x, y)
     o.close()
+    # the benchmark's query on the evolved population: a 4,096-agent sample,
+    # every one of its 16,777,216 ordered pairs, and the reconstructed tree
+    _, cnt, srf = run.sample(4096)
+    cnt_h, srf_h = hs.as_u32(cnt), hs.as_u32(srf)
+    lb, ub = hs.mrca_bounds(kind, S, cnt, srf)
+    olb, oub = orc.mrca_allpairs(kinds[kind], S, cnt_h, srf_h)
+    assert np.array_equal(hs.as_u32(lb), olb) and np.array_equal(hs.as_u32(ub), oub)
+    got = hs.phylo_metrics(kind, S, cnt, srf)
+    sbl, pairs, root, internal, ed = orc.phylo_metrics(kinds[kind], S, cnt_h, srf_h)
+    assert (got["sum_branch_length"], got["pair_sum"], got["root_time"],
+            got["internal_nodes"]) == (sbl, pairs, root, internal)
 
 
 def test_full_size_float_trial_matches_oracle(hs, orc):
