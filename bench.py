@@ -16,8 +16,14 @@ Prints one JSON line:
   cpu_baseline  the plain C oracle on a bounded sample of the same
             workload (the first generations from the founders).
 
+  batched_vs_plain  the rest of the metric, measured after the timed
+            steps: the 64-run batched workload against the same runs one
+            at a time, and a window of the served workload's arrivals
+            against a one-at-a-time server, with p50/p99 run latency
+            (skipped with --no-pools or when --generations is given).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       [--generations G] [--no-cpu-baseline]
+       [--generations G] [--no-cpu-baseline] [--no-pools]
 """
 from __future__ import annotations
 
@@ -148,6 +154,10 @@ def main(argv=None) -> int:
                     help="served mode: skip the plain one-at-a-time server")
     ap.add_argument("--duration", type=float, default=120.0,
                     help="served mode: seconds of arrivals (before time scaling)")
+    ap.add_argument("--no-pools", action="store_true",
+                    help="plain mode: skip the batched and served summaries")
+    ap.add_argument("--served-window", type=float, default=20.0,
+                    help="plain mode: seconds of served-workload arrivals in the summary")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -324,10 +334,47 @@ def main(argv=None) -> int:
             "paper_note": "Cerebras CS-2, 750x750 PEs x 32 agents, float genome, tournament 5",
         },
     }
+    if not args.generations and not args.no_pools:
+        # the rest of the metric, on the batched and served workloads
+        del arena, arena_view, ws, lb, ub
+        torch.cuda.synchronize(dev)
+        torch.cuda.empty_cache()
+        line["batched_vs_plain"] = pool_summary(torch, dev, stream, args.served_window)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def pool_summary(torch, dev, stream, window_s: float) -> dict:
+    """Batched and served against plain: the 64-run batched workload against
+    the same runs one at a time, and a window of the served workload's
+    arrivals (Poisson, 20/s, in real time) against a one-at-a-time server of
+    the same requests, with p50/p99 run latency."""
+    from paper_2404_10861_amd import benchmarks
+    from paper_2404_10861_amd import workloads as wl
+    b = benchmarks.batched_vs_plain(wl.c4(), dev, stream)
+    reqs = wl.c5(duration=window_s)
+    v = benchmarks.served_vs_plain(
+        reqs, dev, progress=lambda text: print(text, file=sys.stderr, flush=True))
+    return {
+        "batched": {
+            "workload": b["workload"],
+            "replications_per_s": b["batched_replications_per_s"],
+            "plain_sequential_replications_per_s": b["plain_sequential_replications_per_s"],
+            "batched_over_plain": b["batched_over_plain"],
+        },
+        "served": {
+            "workload": f"{len(reqs)} requests arriving over {window_s:g} s (the served "
+                        "workload's first arrivals)",
+            "replications_per_s": v["served"]["replications_per_s"],
+            "latency_p50_s": v["served"]["latency_p50_s"],
+            "latency_p99_s": v["served"]["latency_p99_s"],
+            "plain_latency_p50_s": v["plain_fifo"]["latency_p50_s"],
+            "plain_latency_p99_s": v["plain_fifo"]["latency_p99_s"],
+            "served_over_plain_throughput": v["served_over_plain_throughput"],
+        },
+    }
 
 
 if __name__ == "__main__":
