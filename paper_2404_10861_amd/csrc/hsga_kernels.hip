@@ -361,6 +361,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         site_word = site >> (5u - p.diff_log2);
         site_shift = (site << p.diff_log2) & 31u;
     }
+    // A wave issues its loads at the highest priority and then drops back:
+    // when a fresh wave arrives, its loads go out ahead of the arithmetic of
+    // waves already holding data, which keeps more bytes in flight.
+    __builtin_amdgcn_s_setprio(3);
     // 1. this thread's agents, every plane
     Lanes<APT> tr, ct, sf[SW];
     if (mine) {
@@ -397,6 +401,7 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
             if (ASYNC && SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(p.ob_in + e + 4);
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     if (MIGR || ASYNC) {
         // asynchronous ticks: an island runs a generation iff its activity
         // draw is below the threshold (plan bit 31); an idle island takes no
