@@ -9,13 +9,19 @@ FETCH_SIZE or WRITE_SIZE runs) and writes short text summaries:
         --out FILE.json --md FILE.md --cmd "..." --cmd "..."
   python -m paper_2404_10861_amd.profiling counters --fetch DIR --write DIR
         --kernel NAME --bytes-per-launch X --md FILE.md --cmd "..."
+  python -m paper_2404_10861_amd.profiling sq DIR1 DIR2 --kernel NAME
+        --md FILE.md --cmd "..."
 
 The traffic summary scales each counter by what the same counter reads for
 the plain copy kernel of known size (bytes read, bytes written), giving HBM
 bytes per launch of the step kernel.  The counters summary reports the raw
 per-dispatch medians of one kernel (KiB) next to its algorithmic bytes, for
 runs without the copy kernel (WRITE_SIZE reads 1.000 of the copy kernel's
-written bytes, FETCH_SIZE 0.5000 of its read bytes, on MI355X).
+written bytes, FETCH_SIZE 0.5000 of its read bytes, on MI355X).  The sq
+summary derives, from SQ and GRBM counters of two passes, the VALU busy
+fraction, the mean resident waves per SIMD and the share of wave time spent
+waiting (SQ_* cycle counters count 4-cycle units; GRBM_GUI_ACTIVE sums the
+8 XCDs; 1,024 SIMDs).
 """
 from __future__ import annotations
 
@@ -188,6 +194,43 @@ def cmd_counters(a):
     print("\n".join(lines))
 
 
+def cmd_sq(a):
+    vals = {}
+    names = []
+    for d in a.dirs:
+        with open(_find(d, "counter_collection.csv")) as f:
+            per = {}
+            for r in csv.DictReader(f):
+                if a.kernel not in r["Kernel_Name"]:
+                    continue
+                if r["Kernel_Name"] not in names:
+                    names.append(r["Kernel_Name"])
+                per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for k, v in per.items():
+            vals[k] = statistics.median(v)
+    cycles = vals["GRBM_GUI_ACTIVE"] / 8            # per XCD
+    simds = 1024
+    valu = vals["SQ_ACTIVE_INST_VALU"] * 4 / (simds * cycles)
+    waves = vals["SQ_WAVE_CYCLES"] * 4 / (simds * cycles)
+    wait = vals["SQ_WAIT_INST_ANY"] / vals["SQ_WAVE_CYCLES"]
+    per_wave = vals["SQ_INSTS_VALU"] / vals["SQ_WAVES"]
+    lines = [f"# SQ counters of `{a.kernel}`: {a.title}", "", "Commands:", ""]
+    for c in a.cmd:
+        lines.append(f"    {c}")
+    lines += ["", f"- kernel: {names[0][:90] if names else a.kernel}",
+              "- medians per dispatch: " + ", ".join(f"{k} {v:.0f}" for k, v in sorted(vals.items())),
+              f"- duration: {cycles:.0f} cycles per XCD ({cycles / 2.4e3:.1f} us at 2.4 GHz, "
+              "counters on)",
+              f"- VALU busy: {100 * valu:.0f} % of SIMD cycles; VALU instructions per wave: "
+              f"{per_wave:.0f}",
+              f"- resident waves per SIMD (mean): {waves:.1f}",
+              f"- wave time spent waiting (s_waitcnt): {100 * wait:.0f} %",
+              f"- kernel source hash: {kernel_hash()}", ""]
+    with open(a.md, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -214,7 +257,16 @@ def main(argv=None):
     c.add_argument("--md", required=True)
     c.add_argument("--title", default="")
     c.add_argument("--cmd", action="append", default=[])
+    q = sub.add_parser("sq")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--md", required=True)
+    q.add_argument("--title", default="")
+    q.add_argument("--cmd", action="append", default=[])
     a = ap.parse_args(argv)
+    if a.what == "sq":
+        cmd_sq(a)
+        return
     if a.what == "stats":
         cmd_stats(a)
     elif a.what == "counters":
