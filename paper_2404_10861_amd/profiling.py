@@ -18,8 +18,8 @@ bytes per launch of the step kernel.  The counters summary reports the raw
 per-dispatch medians of one kernel (KiB) next to its algorithmic bytes, for
 runs without the copy kernel (WRITE_SIZE reads 1.000 of the copy kernel's
 written bytes, FETCH_SIZE 0.5000 of its read bytes, on MI355X).  The sq
-summary derives, from SQ and GRBM counters of two passes, the VALU busy
-fraction, the mean resident waves per SIMD and the share of wave time spent
+summary derives, from SQ and GRBM counters of two passes, an estimate of
+the VALU issue fraction, the mean resident waves per SIMD and the share of wave time spent
 waiting (SQ_* cycle counters count 4-cycle units; GRBM_GUI_ACTIVE sums the
 8 XCDs; 1,024 SIMDs).
 """
@@ -221,8 +221,9 @@ def cmd_sq(a):
               "- medians per dispatch: " + ", ".join(f"{k} {v:.0f}" for k, v in sorted(vals.items())),
               f"- duration: {cycles:.0f} cycles per XCD ({cycles / 2.4e3:.1f} us at 2.4 GHz, "
               "counters on)",
-              f"- VALU busy: {100 * valu:.0f} % of SIMD cycles; VALU instructions per wave: "
-              f"{per_wave:.0f}",
+              f"- VALU issue estimate: {100 * valu:.0f} % of SIMD cycles (SQ_ACTIVE_INST_VALU "
+              "x 4 cycles; an upper estimate, since some wave64 VALU instructions issue in "
+              f"fewer cycles); VALU instructions per wave: {per_wave:.0f}",
               f"- resident waves per SIMD (mean): {waves:.1f}",
               f"- wave time spent waiting (s_waitcnt): {100 * wait:.0f} %",
               f"- kernel source hash: {kernel_hash()}", ""]
