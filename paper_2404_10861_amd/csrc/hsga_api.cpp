@@ -580,7 +580,8 @@ int ga_set_launch_shape(ga_run* r, uint32_t block_threads, uint32_t agents_per_t
         return fail(GA_EINVAL, "block_threads must be a multiple of 64 in 64..1024");
     if ((apt != 1 && apt != 2 && apt != 4) || r->N % apt)
         return fail(GA_EINVAL, "agents_per_thread must be 1, 2 or 4 and divide pop_per_island");
-    if (hsga::step_lds_bytes(tile_islands(block, apt, r->N), r->N, r->SW) > kMaxStepLds)
+    if (hsga::step_lds_bytes(tile_islands(block, apt, r->N), r->N, r->SW,
+                             birth_model(r->cfg) == hsga::kBirthFloat, block, apt) > kMaxStepLds)
         return fail(GA_EINVAL, "tile needs more than 64 KiB of LDS");
     r->block = block;
     r->apt = apt;

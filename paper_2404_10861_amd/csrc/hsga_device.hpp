@@ -91,8 +91,25 @@ __device__ __forceinline__ double exact_pow2(int k) {   // 2^k, |k| < 1023
     return __longlong_as_double((long long)(1023 + k) << 52);
 }
 
+// The series coefficients of the half-normal evaluation, read through
+// scalar loads (so that a loop over draws keeps them in scalar registers):
+// atanh 1/(2k+1) for k = 10 .. 0, then sine 1/(2k+1)! with alternating
+// signs for k = 9 .. 0, then cosine 1/(2k)! for k = 10 .. 1 (the last
+// cosine term, 1, is written out).
+__constant__ double kHalfNormalSeries[31] = {
+    1.0 / 21.0, 1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
+    1.0 / 9.0, 1.0 / 7.0, 1.0 / 5.0, 1.0 / 3.0, 1.0,
+    -1.0 / 121645100408832000.0, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0,
+    1.0 / 6227020800.0, -1.0 / 39916800.0, 1.0 / 362880.0, -1.0 / 5040.0, 1.0 / 120.0,
+    -1.0 / 6.0, 1.0,
+    -1.0 / 6402373705728000.0, 1.0 / 20922789888000.0, -1.0 / 87178291200.0,
+    1.0 / 479001600.0, -1.0 / 3628800.0, 1.0 / 40320.0, -1.0 / 720.0, 1.0 / 24.0,
+    -1.0 / 2.0, 1.0,
+};
+
 __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
 #pragma clang fp contract(off)
+    const double* K = kHalfNormalSeries;
     // ln U1
     const uint64_t v = 2ull * w_radius + 1ull;
     int e = 63 - __clzll((long long)v);
@@ -107,17 +124,9 @@ __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
     for (int k = 0; k < 5; ++k) r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
     const double sv = (m - 1.0) * r;
     const double z = sv * sv;
-    double p = 1.0 / 21.0;
-    p = __builtin_fma(p, z, 1.0 / 19.0);
-    p = __builtin_fma(p, z, 1.0 / 17.0);
-    p = __builtin_fma(p, z, 1.0 / 15.0);
-    p = __builtin_fma(p, z, 1.0 / 13.0);
-    p = __builtin_fma(p, z, 1.0 / 11.0);
-    p = __builtin_fma(p, z, 1.0 / 9.0);
-    p = __builtin_fma(p, z, 1.0 / 7.0);
-    p = __builtin_fma(p, z, 1.0 / 5.0);
-    p = __builtin_fma(p, z, 1.0 / 3.0);
-    p = __builtin_fma(p, z, 1.0);
+    double p = K[0];
+#pragma unroll
+    for (int k = 1; k < 11; ++k) p = __builtin_fma(p, z, K[k]);
     const double ln_u = __builtin_fma((double)e - 33.0, 0.6931471805599453, (sv + sv) * p);
     // sqrt(-2 ln U1)
     const double y = -2.0 * ln_u;
@@ -139,42 +148,30 @@ __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
     const double x2 = x * x;
     double c;
     if (use_sin) {
-        c = -1.0 / 121645100408832000.0;
-        c = __builtin_fma(c, x2, 1.0 / 355687428096000.0);
-        c = __builtin_fma(c, x2, -1.0 / 1307674368000.0);
-        c = __builtin_fma(c, x2, 1.0 / 6227020800.0);
-        c = __builtin_fma(c, x2, -1.0 / 39916800.0);
-        c = __builtin_fma(c, x2, 1.0 / 362880.0);
-        c = __builtin_fma(c, x2, -1.0 / 5040.0);
-        c = __builtin_fma(c, x2, 1.0 / 120.0);
-        c = __builtin_fma(c, x2, -1.0 / 6.0);
-        c = __builtin_fma(c, x2, 1.0);
+        c = K[11];
+#pragma unroll
+        for (int k = 12; k < 21; ++k) c = __builtin_fma(c, x2, K[k]);
         c = x * c;
     } else {
-        c = -1.0 / 6402373705728000.0;
-        c = __builtin_fma(c, x2, 1.0 / 20922789888000.0);
-        c = __builtin_fma(c, x2, -1.0 / 87178291200.0);
-        c = __builtin_fma(c, x2, 1.0 / 479001600.0);
-        c = __builtin_fma(c, x2, -1.0 / 3628800.0);
-        c = __builtin_fma(c, x2, 1.0 / 40320.0);
-        c = __builtin_fma(c, x2, -1.0 / 720.0);
-        c = __builtin_fma(c, x2, 1.0 / 24.0);
-        c = __builtin_fma(c, x2, -1.0 / 2.0);
-        c = __builtin_fma(c, x2, 1.0);
+        c = K[21];
+#pragma unroll
+        for (int k = 22; k < 31; ++k) c = __builtin_fma(c, x2, K[k]);
     }
     return radius * c;
 }
 
-// Fitness of a float-treatment child: the parent's, moved down by
-// del_sigma |Z| (deleterious) or up by ben_sigma |Z| (beneficial), in
-// binary64, rounded once to binary32.
+__device__ __forceinline__ float apply_half_normal(float f, bool deleterious, float del_sigma,
+                                                   float ben_sigma, double z) {
+#pragma clang fp contract(off)
+    const double fd = (double)f;
+    return deleterious ? (float)(fd - (double)del_sigma * z) : (float)(fd + (double)ben_sigma * z);
+}
+
 __device__ __forceinline__ float mutate_fitness(float f, bool deleterious, float del_sigma,
                                                 float ben_sigma, uint32_t w_radius,
                                                 uint32_t w_angle) {
-#pragma clang fp contract(off)
-    const double z = half_normal(w_radius, w_angle);
-    const double fd = (double)f;
-    return deleterious ? (float)(fd - (double)del_sigma * z) : (float)(fd + (double)ben_sigma * z);
+    return apply_half_normal(f, deleterious, del_sigma, ben_sigma,
+                             half_normal(w_radius, w_angle));
 }
 
 // Number of significant bits.

@@ -84,6 +84,10 @@ constexpr uint32_t kMaxBatchRuns = 256;
 
 // LDS bytes of one step workgroup.
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW);
+// ... and with the float births' draw queues (8 bytes per agent slot of the
+// workgroup, block_threads * apt).
+size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW, bool float_births,
+                      uint32_t block_threads, uint32_t apt);
 
 // tags: founders' trait words are random 16-bit founder tags (key k0, k1).
 hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,

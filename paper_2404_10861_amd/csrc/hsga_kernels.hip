@@ -166,6 +166,11 @@ __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint3
     return x + 1 < W ? isl + 1 : isl + 1 - W;
 }
 
+// Set bits of a wave mask on lanes below this one.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 extern __shared__ __attribute__((aligned(16))) uint32_t g_step_lds[];
 
 // The Philox blocks of a thread's APT births (and the second blocks of
@@ -212,6 +217,17 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
     const uint32_t base = il * N;
     const uint4* blk = draws.blk;
     Lanes<APT> ctr, ccn, csf[SW];
+    // Float births: the half-normal draws of the mutating births are queued
+    // in the wave's LDS area (cosine cases from the front, sine cases from
+    // the back) and evaluated after the loop in rounds of the wave's lanes,
+    // so the draw runs once per mutating birth rather than once per birth
+    // for the whole wave, and no round mixes the two series.
+    constexpr uint32_t QC = 64u * APT;                  // queue capacity of a wave
+    uint2* wq = nullptr;
+    uint32_t fneed = 0, fdel = 0, fslot = 0, ncos = 0, nsin = 0;
+    if constexpr (BM == kBirthFloat)
+        wq = reinterpret_cast<uint2*>(lds + ((((2 + SW) * TA + 2 * p.tile_isl) + 3u) & ~3u)) +
+             (threadIdx.x >> 6) * QC;
 #pragma unroll
     for (int q = 0; q < APT; ++q) {
         const uint32_t la = la0 + q;
@@ -247,9 +263,9 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                 }
                 const bool del = v.y < p.del_thr;
                 const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
-                ctr.v[q] = (del || ben) ? __float_as_uint(mutate_fitness(best, del, p.del_sigma,
-                                                                         p.ben_sigma, v.z, v.w))
-                                        : __float_as_uint(best);
+                ctr.v[q] = __float_as_uint(best);        // the draw is applied after the loop
+                fneed |= (del || ben ? 1u : 0u) << q;
+                fdel |= (del ? 1u : 0u) << q;
                 bit = v.w & diff_mask;
             } else {
                 uint32_t ptrait = l_trait[par];
@@ -288,6 +304,55 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                 csf[w].v[q] = (uint32_t)w == dep_word
                                   ? (word & ~(diff_mask << dep_shift)) | (bit << dep_shift)
                                   : word;
+            }
+        }
+        if constexpr (BM == kBirthFloat) {
+            const uint4 vq = blk[APT + q];
+            const bool nd = (fneed >> q) & 1u;
+            const bool sn = vq.w >= 0x80000000u;          // the draw's sine case
+            const uint64_t mc = __ballot(nd && !sn);
+            const uint64_t ms = __ballot(nd && sn);
+            if (nd) {
+                const uint32_t slot = sn ? QC - 1u - (nsin + lanes_below(ms))
+                                         : ncos + lanes_below(mc);
+                wq[slot] = make_uint2(vq.z, vq.w);
+                fslot |= slot << (8 * q);
+            }
+            ncos += (uint32_t)__popcll(mc);
+            nsin += (uint32_t)__popcll(ms);
+        }
+    }
+    if constexpr (BM == kBirthFloat) {
+        // the queued draws in rounds of the active lanes (one wavefront: its
+        // LDS writes land before its later reads), then each birth's fitness
+        const uint64_t ex = __ballot(true);
+        const uint32_t me = lanes_below(ex), na = (uint32_t)__popcll(ex);
+        for (uint32_t b0 = 0; b0 < ncos; b0 += na) {
+            if (b0 + me < ncos) {
+                const uint2 e = wq[b0 + me];
+                const double z = half_normal(e.x, e.y);
+                const uint64_t zb = (uint64_t)__double_as_longlong(z);
+                wq[b0 + me] = make_uint2((uint32_t)zb, (uint32_t)(zb >> 32));
+            }
+        }
+        for (uint32_t b0 = 0; b0 < nsin; b0 += na) {
+            if (b0 + me < nsin) {
+                const uint32_t i = QC - 1u - (b0 + me);
+                const uint2 e = wq[i];
+                const double z = half_normal(e.x, e.y);
+                const uint64_t zb = (uint64_t)__double_as_longlong(z);
+                wq[i] = make_uint2((uint32_t)zb, (uint32_t)(zb >> 32));
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+            if ((fneed >> q) & 1u) {
+                const uint2 e = wq[(fslot >> (8 * q)) & 0xffu];
+                const double z =
+                    __longlong_as_double((long long)(((uint64_t)e.y << 32) | e.x));
+                ctr.v[q] = __float_as_uint(apply_half_normal(__uint_as_float(ctr.v[q]),
+                                                             (fdel >> q) & 1u, p.del_sigma,
+                                                             p.ben_sigma, z));
             }
         }
     }
@@ -502,11 +567,19 @@ size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
     return ((2 + SW) * TA + 2 * (size_t)tile_isl) * 4;
 }
 
+size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW, bool float_births,
+                      uint32_t block_threads, uint32_t apt) {
+    const size_t b = step_lds_bytes(tile_isl, N, SW);
+    if (!float_births) return b;
+    return ((b + 15) & ~(size_t)15) + (size_t)block_threads * apt * 8;   // the draw queues
+}
+
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
 static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
     if (p.tile_isl == 0 || p.tile_isl > block_threads) return hipErrorInvalidValue;
     const uint32_t tiles = (p.I + p.tile_isl - 1) / p.tile_isl;
-    const size_t lds = step_lds_bytes(p.tile_isl, p.N, SW);
+    const size_t lds =
+        step_lds_bytes(p.tile_isl, p.N, SW, BM == kBirthFloat, block_threads, APT);
     hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT, ASYNC>), dim3(tiles), dim3(block_threads),
                        lds, stream, p);
     return hipGetLastError();

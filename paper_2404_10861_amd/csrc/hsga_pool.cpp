@@ -279,8 +279,11 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         const uint32_t rt = (r.I + sp.tile_isl - 1) / sp.tile_isl;
         tiles += rt;
         gens = std::max(gens, g);
-        lds = std::max(lds, hsga::step_lds_bytes(sp.tile_isl, r.N, r.SW));
+        lds = std::max(lds, hsga::step_lds_bytes(sp.tile_isl, r.N, r.SW,
+                                                 birth_model(r.cfg) == hsga::kBirthFloat,
+                                                 p->block, r.apt));
     }
+    if (lds > kMaxStepLds) return fail(GA_EINVAL, "batched tiles need more than 64 KiB of LDS");
     p->h_tile0[nruns] = tiles;
     hipError_t e = hipMemcpyAsync(p->d_table, p->h_table, sizeof(hsga::BatchRun) * nruns,
                                   hipMemcpyHostToDevice, p->stream);
