@@ -203,6 +203,47 @@ int ga_read_layout(ga_run *run, uint32_t *layout);
 int ga_sample(ga_run *run, uint32_t n, uint32_t *dev_idx, uint32_t *dev_counter,
               uint32_t *dev_surface_words, uint32_t *n_taken);
 
+/* ------------------------------------------------------------------------
+ * Checkpoint and resume.  A run's state at generation (tick) T is its
+ * current population and the outbox that generation T reads (Methods,
+ * Asynchronous Island-model Genetic Algorithm); the layout and site table
+ * follow from T and the site rule, and every random draw is a Philox block
+ * of the seed and of counters the state holds.  A run resumed from an
+ * exported state therefore continues exactly as the uninterrupted run.
+ *
+ * The state is one host blob of uint32 words (native byte order):
+ *   [0] 0x53475348, [1] format version 1, [2] sizeof(ga_config), [3] T,
+ *   then the run's validated ga_config (its struct_size bytes),
+ *   trait[A], counter[A], the surface word planes [W][A] (plane-major),
+ *   and the outbox entries [I][E] as the device holds them: E = 4 words
+ *   (direction, trait, surface words, zero-padded) for a synchronous run,
+ *   E = 8 (direction, trait, counter, surface words, zero-padded) for an
+ *   asynchronous one; all zero when no outbox exists yet.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the run's exported state; 0 if run is NULL. */
+size_t ga_state_bytes(const ga_run *run);
+
+/* Blocking: wait for the run's stream, then write its state at the
+ * generation enqueued so far into host buffer (4-byte aligned, bytes >=
+ * ga_state_bytes).  Works on runs of a pool too.
+ * Errors: GA_EINVAL (NULL, short or misaligned buffer), GA_EDEVICE.        */
+int ga_export_state(ga_run *run, void *host, size_t bytes);
+
+/* Blocking: replace the state of run, which must have been created with
+ * the configuration the state was exported under (compared byte for byte
+ * after validation; max_gens_per_launch may differ), by the state in host.
+ * The layout and, for asynchronous runs, the site table are rebuilt by
+ * replaying the site rule up to T.  The state is checked before anything
+ * is written: every counter must equal T (synchronous) or be at most T
+ * (asynchronous), every outbox direction must be 0..4 and every
+ * asynchronous outbox counter at most T.
+ * Errors: GA_EINVAL (NULL or misaligned buffer, size, format or
+ * configuration mismatch, a counter or direction outside those ranges, an
+ * asynchronous T above the run's max_gens_per_launch, a run of a pool),
+ * GA_EHORIZON (T past the site rule's horizon + 1), GA_EDEVICE.             */
+int ga_import_state(ga_run *run, const void *host, size_t bytes);
+
 /* Release the host handle.  Does not free (or touch) the arena; work still
  * enqueued on the stream keeps using it, so sync first when reusing it.    */
 void ga_destroy(ga_run *run);

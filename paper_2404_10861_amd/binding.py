@@ -26,6 +26,7 @@ EMPTY_SITE = 0xFFFFFFFF
 EXPORTS = (
     "ga_footprint_bytes", "ga_create", "ga_step", "ga_sync", "ga_generation",
     "ga_read_agents", "ga_read_outbox", "ga_read_layout", "ga_sample",
+    "ga_state_bytes", "ga_export_state", "ga_import_state",
     "ga_destroy", "ga_last_error", "hstrat_mrca_workspace_bytes",
     "hstrat_mrca_bounds", "hstrat_mrca_status", "ga_set_kernel_timing",
     "ga_kernel_time", "ga_set_launch_shape", "ga_probe_copy",
@@ -108,6 +109,9 @@ def load_library():
                                           _vp, ctypes.POINTER(ctypes.c_int)]),
         "ga_read_layout": (ctypes.c_int, [_vp, _vp]),
         "ga_sample": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _u32p]),
+        "ga_state_bytes": (ctypes.c_size_t, [_vp]),
+        "ga_export_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+        "ga_import_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
         "ga_destroy": (None, [_vp]),
         "ga_last_error": (ctypes.c_char_p, []),
         "hstrat_mrca_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32]),
@@ -307,6 +311,15 @@ class RunHandle:
         _check(load_library().ga_read_layout(self._h, _ptr(L)))
         return L
 
+    def export_state(self) -> np.ndarray:
+        """The run's state at the generation enqueued so far, as a uint8
+        host array (blocking); ``Run.import_state`` resumes from it."""
+        lib = load_library()
+        nbytes = lib.ga_state_bytes(self._h)
+        words = np.zeros(nbytes // 4, np.uint32)
+        _check(lib.ga_export_state(self._h, _ptr(words), nbytes))
+        return words.view(np.uint8)
+
     def sample(self, n: int, out=None):
         """Stratified sample on the device: (idx, counter, surface[n, S/32])
         as int32 CUDA tensors holding the uint32 bit patterns."""
@@ -376,6 +389,16 @@ class Run(RunHandle):
 
     def set_launch_shape(self, block_threads: int = 0, agents_per_thread: int = 0):
         _check(load_library().ga_set_launch_shape(self._h, block_threads, agents_per_thread))
+
+    def import_state(self, state):
+        """Replace this run's state by one exported from a run of the same
+        configuration (a uint8 array or bytes); the run continues from
+        there exactly as the exporting run would (blocking)."""
+        raw = np.frombuffer(bytes(state), np.uint8) if not isinstance(state, np.ndarray) \
+            else np.ascontiguousarray(state).reshape(-1).view(np.uint8)
+        words = np.zeros((raw.size + 3) // 4, np.uint32)      # a 4-byte aligned copy
+        words.view(np.uint8)[: raw.size] = raw
+        _check(load_library().ga_import_state(self._h, _ptr(words), raw.size))
 
 
 class PoolRun(RunHandle):

@@ -189,6 +189,19 @@ using namespace hsga_host;
 
 namespace {
 
+// Exported state: header words (magic "HSGS", version, sizeof(ga_config), T).
+constexpr uint32_t kStateMagic = 0x53475348u;
+constexpr uint32_t kStateVersion = 1;
+constexpr size_t kStateHeaderWords = 4;
+static_assert(sizeof(ga_config) % 4 == 0, "the state holds the config as whole words");
+
+// Words of one outbox entry as the device holds it.
+uint32_t entry_words(const ga_run* r) {
+    return r->cfg.async_activity ? hsga::kOutboxWords : hsga::kSyncOutboxWords;
+}
+
+bool has_outbox(const ga_run* r) { return r->cfg.migrants_per_island != 0 && r->T > 0; }
+
 hipEvent_t take_event(ga_run* r) {
     if (!r->spare.empty()) {
         hipEvent_t e = r->spare.back();
@@ -410,6 +423,117 @@ int ga_sample(ga_run* r, uint32_t n, uint32_t* dev_idx, uint32_t* dev_counter,
                                        dev_idx, dev_counter, dev_surface_words, r->stream);
     if (e != hipSuccess) return hip_fail(e, "sample launch");
     *n_taken = r->A <= n ? r->A : n;
+    return GA_OK;
+}
+
+size_t ga_state_bytes(const ga_run* r) {
+    if (!r) return 0;
+    return 4 * (kStateHeaderWords + sizeof(ga_config) / 4 + (size_t)r->A * (2 + r->SW) +
+                (size_t)r->I * entry_words(r));
+}
+
+int ga_export_state(ga_run* r, void* host, size_t bytes) {
+    if (!r || !host) return fail(GA_EINVAL, "NULL argument");
+    if ((uintptr_t)host % 4) return fail(GA_EINVAL, "state buffer not 4-byte aligned");
+    const size_t need = ga_state_bytes(r);
+    if (bytes < need)
+        return fail(GA_EINVAL, "state buffer of " + std::to_string(bytes) + " bytes, need " +
+                                   std::to_string(need));
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t* w = static_cast<uint32_t*>(host);
+    w[0] = kStateMagic;
+    w[1] = kStateVersion;
+    w[2] = sizeof(ga_config);
+    w[3] = r->T;
+    std::memcpy(w + kStateHeaderWords, &r->cfg, sizeof(ga_config));
+    uint32_t* at = w + kStateHeaderWords + sizeof(ga_config) / 4;
+    const int cur = r->T & 1;
+    const size_t A = r->A;
+    const struct { const uint32_t* src; size_t words; } planes[] = {
+        {r->trait[cur], A}, {r->counter[cur], A}, {r->surf[cur], r->SW * A}};
+    for (const auto& pl : planes) {
+        e = hipMemcpy(at, pl.src, pl.words * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy state");
+        at += pl.words;
+    }
+    const size_t ob = (size_t)r->I * entry_words(r);
+    if (has_outbox(r)) {
+        e = hipMemcpy(at, r->outbox[cur], ob * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy outbox");
+    } else {
+        std::memset(at, 0, ob * 4);
+    }
+    return GA_OK;
+}
+
+int ga_import_state(ga_run* r, const void* host, size_t bytes) {
+    if (!r || !host) return fail(GA_EINVAL, "NULL argument");
+    if (r->pooled) return fail(GA_EINVAL, "a run of a pool cannot import a state");
+    if ((uintptr_t)host % 4) return fail(GA_EINVAL, "state buffer not 4-byte aligned");
+    if (bytes != ga_state_bytes(r))
+        return fail(GA_EINVAL, "state of " + std::to_string(bytes) + " bytes; this run's has " +
+                                   std::to_string(ga_state_bytes(r)));
+    const uint32_t* w = static_cast<const uint32_t*>(host);
+    if (w[0] != kStateMagic || w[1] != kStateVersion || w[2] != sizeof(ga_config))
+        return fail(GA_EINVAL, "not a run state of this format version");
+    if (std::memcmp(w + kStateHeaderWords, &r->cfg, sizeof(ga_config)) != 0)
+        return fail(GA_EINVAL, "state exported under another configuration");
+    const uint32_t T = w[3];
+    const bool async = r->cfg.async_activity != 0;
+    if ((uint64_t)T > r->horizon + 1)
+        return fail(GA_EHORIZON, "state generation " + std::to_string(T) +
+                                     " is past the site rule's horizon");
+    if (async && T > r->gens)
+        return fail(GA_EINVAL, "an asynchronous state at tick " + std::to_string(T) +
+                                   " needs max_gens_per_launch >= " + std::to_string(T));
+    const size_t A = r->A;
+    const uint32_t* trait = w + kStateHeaderWords + sizeof(ga_config) / 4;
+    const uint32_t* counter = trait + A;
+    const uint32_t* surf = counter + A;
+    const uint32_t* ob = surf + r->SW * A;
+    // every later launch indexes the site table by counters: check them
+    for (size_t a = 0; a < A; ++a)
+        if (async ? counter[a] > T : counter[a] != T)
+            return fail(GA_EINVAL, "agent " + std::to_string(a) + " has counter " +
+                                       std::to_string(counter[a]) + " at generation " +
+                                       std::to_string(T));
+    const uint32_t E = entry_words(r);
+    const bool outbox = r->cfg.migrants_per_island != 0 && T > 0;
+    if (outbox)
+        for (uint32_t i = 0; i < r->I; ++i) {
+            const uint32_t* en = ob + (size_t)i * E;
+            if (en[0] > 4 || (async && en[2] > T))
+                return fail(GA_EINVAL, "outbox entry " + std::to_string(i) + " out of range");
+        }
+    hipError_t e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    const int cur = T & 1;
+    const struct { uint32_t* dst; const uint32_t* src; size_t words; } planes[] = {
+        {r->trait[cur], trait, A}, {r->counter[cur], counter, A}, {r->surf[cur], surf, r->SW * A},
+        {r->outbox[cur], ob, outbox ? (size_t)r->I * E : 0}};
+    for (const auto& pl : planes) {
+        if (pl.words == 0) continue;
+        e = hipMemcpy(pl.dst, pl.src, pl.words * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy state");
+    }
+    // rebuild the layout after ingests_of(T) ingests by replaying the site
+    // rule from the empty layout (in pieces of the site table's capacity;
+    // an asynchronous run keeps the whole table, T <= gens)
+    const std::vector<uint32_t> empty(r->S, GA_EMPTY_SITE);
+    e = hipMemcpy(r->layout, empty.data(), (size_t)r->S * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy layout");
+    const uint32_t tau = hsga::ingests_of(T, r->cfg.ingest_interval);
+    for (uint32_t t0 = 0; t0 < tau; t0 += r->gens) {
+        const uint32_t count = std::min(r->gens, tau - t0);
+        e = hsga::launch_site_schedule(r->cfg.surface_kind, r->S, r->layout,
+                                       r->sites + (async ? t0 : 0), t0, count, r->stream);
+        if (e != hipSuccess) return hip_fail(e, "site schedule launch");
+    }
+    e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    r->tab_filled = async ? tau : 0;
+    r->T = T;
     return GA_OK;
 }
 

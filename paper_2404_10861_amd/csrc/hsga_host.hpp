@@ -29,6 +29,7 @@ struct ga_run {
     uint32_t apt;        // agents per thread (1, 2, 4; divides N)
     uint32_t block;      // workgroup threads
     bool timing;
+    bool pooled = false; // a slot of a pool (its generation targets live there)
     struct Span { hipEvent_t start, stop; uint32_t launches; };
     std::vector<Span> spans;
     std::vector<hipEvent_t> spare;

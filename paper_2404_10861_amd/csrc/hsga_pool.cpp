@@ -213,6 +213,7 @@ int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint3
         return rc;
     }
     s.run.block = p->block;
+    s.run.pooled = true;
     s.used = true;
     s.reported = false;
     s.target = n_generations;

@@ -1,0 +1,242 @@
+"""GPU checkpoint and resume (zero tolerance): a run exported at generation
+(tick) T, destroyed, and imported into a fresh run of the same
+configuration continues exactly as the uninterrupted run, for every birth
+model, annotation scheme, migration on and off and asynchronous ticks; the
+exported state holds what the oracle's run holds at T; a run of a pool
+exports the same state as a lone run; malformed states are refused before
+anything is written."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+P = lambda p: int(p * 2**32)          # noqa: E731
+MAGIC = 0x53475348
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_10861_amd as hs
+    hs.load_library()
+    return hs
+
+
+def oracle_for(orc, c):
+    model = {"int": 0, "float": 1, "tag": 2}[c.fitness_model]
+    return orc.Run(c.grid_w, c.grid_h, c.pop_per_island, c.surface_sites, c.kind,
+                   tournament=c.tournament_size, mut_thr=c.mut_threshold, mut_lo=c.mut_lo,
+                   mut_hi=c.mut_hi, migrants=c.migrants_per_island, seed=c.seed,
+                   fitness_model=model, del_thr=c.del_threshold, ben_thr=c.ben_threshold,
+                   del_sigma=c.del_sigma, ben_sigma=c.ben_sigma, bits=c.differentia_bits,
+                   interval=c.ingest_interval, activity=c.async_activity)
+
+
+def same_state(run, other):
+    for x, y in zip(run.agents(), other.agents()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(run.layout(), other.layout())
+    ob, oo = run.outbox(), other.outbox()
+    assert (ob is None) == (oo is None)
+    if ob is not None:
+        for x, y in zip(ob, oo):
+            assert np.array_equal(x, y)
+
+
+def parse(hs, cfg, state):
+    """(T, trait, counter, surface[A, W], outbox entries [I, E]) of a state."""
+    w = state.view(np.uint32)
+    assert w[0] == MAGIC and w[1] == 1
+    cw = int(w[2]) // 4
+    A, SW, I = cfg.agents, cfg.surface_words, cfg.islands
+    o = 4 + cw
+    trait, counter = w[o:o + A], w[o + A:o + 2 * A]
+    surf = w[o + 2 * A:o + (2 + SW) * A].reshape(SW, A).T
+    E = 8 if cfg.async_activity else 4
+    ob = w[o + (2 + SW) * A:].reshape(I, E)
+    return int(w[3]), trait, counter, surf, ob
+
+
+FLOAT = dict(fitness_model="float", tournament_size=5, del_threshold=1417339207,
+             ben_threshold=128849010)
+# (grid w, h, N, S, kind, config keywords, max_gens_per_launch, T1, T2)
+CASES = {
+    "int-tournament": (8, 6, 32, 64, "hybrid", dict(tournament_size=2, seed=3), 0, 300, 257),
+    "int-neutral-odd-N": (5, 7, 17, 32, "tilted", dict(tournament_size=0, seed=4), 0, 211, 190),
+    "float": (7, 5, 32, 64, "hybrid", dict(seed=5, **FLOAT), 0, 240, 160),
+    "tags": (6, 6, 16, 32, "tilted", dict(fitness_model="tag", tournament_size=0, seed=6),
+             0, 150, 150),
+    "bytes-interval": (6, 5, 32, 8, "steady", dict(differentia_bits=8, ingest_interval=3,
+                                                   seed=7), 0, 299, 200),
+    "no-migration": (4, 4, 32, 64, "hybrid", dict(migrants_per_island=0, seed=8), 0, 120, 80),
+    "small-table": (4, 3, 16, 32, "tilted", dict(ingest_interval=3, seed=9), 7, 50, 37),
+    "async": (7, 5, 16, 64, "hybrid", dict(async_activity=P(0.7), ingest_interval=2, seed=10),
+              600, 310, 250),
+    "async-float": (6, 4, 32, 32, "steady", dict(async_activity=P(0.4), seed=11, **FLOAT),
+                    400, 200, 150),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_resume_equals_uninterrupted(hs, orc, case, tmp_path):
+    W, H, N, S, kind, kw, mg, T1, T2 = CASES[case]
+    cfg = hs.Config(W, H, N, S, kind, **kw)
+    whole = hs.Run(cfg, max_gens_per_launch=mg)
+    whole.step(T1 + T2)
+
+    first = hs.Run(cfg, max_gens_per_launch=mg)
+    first.step(T1)
+    state = first.export_state()
+    assert state.nbytes == load_bytes(hs, first)
+    layout_at_T1 = first.layout()
+    path = tmp_path / "run.state"
+    state.tofile(path)
+    first.close()
+
+    # the exported state is the oracle's run at T1
+    o = oracle_for(orc, cfg)
+    o.step(T1)
+    T, trait, counter, surf, ob = parse(hs, cfg, state)
+    assert T == T1
+    ot, oc, osf = o.agents()
+    assert np.array_equal(trait, ot) and np.array_equal(counter, oc)
+    assert np.array_equal(surf, osf)
+    oob = o.outbox()
+    if oob is None:
+        assert not ob.any()
+    else:
+        s0 = 3 if cfg.async_activity else 2
+        assert np.array_equal(ob[:, 0], oob[0]) and np.array_equal(ob[:, 1], oob[1])
+        assert np.array_equal(ob[:, s0:s0 + cfg.surface_words], oob[3])
+        if cfg.async_activity:
+            assert np.array_equal(ob[:, 2], oob[2])
+
+    # import into a fresh run that has already moved on: its state is replaced
+    resumed = hs.Run(cfg, max_gens_per_launch=mg)
+    resumed.step(3)
+    resumed.import_state(np.fromfile(path, np.uint8))
+    assert resumed.generation == T1
+    assert np.array_equal(resumed.layout(), layout_at_T1)
+    resumed.step(T2)
+    same_state(resumed, whole)
+
+
+def load_bytes(hs, run):
+    return hs.binding.load_library().ga_state_bytes(run._h)
+
+
+def test_resume_from_founders_and_in_pieces(hs):
+    cfg = hs.Config(6, 6, 32, 32, "tilted", tournament_size=2, seed=21)
+    whole = hs.Run(cfg, max_gens_per_launch=64)
+    whole.step(400)
+    run = hs.Run(cfg, max_gens_per_launch=64)
+    state = run.export_state()
+    for n in (0, 1, 63, 64, 65, 7, 200):
+        nxt = hs.Run(cfg, max_gens_per_launch=64)
+        nxt.import_state(state)
+        nxt.step(n)
+        state = nxt.export_state()
+        nxt.close()
+    assert parse(hs, cfg, state)[0] == 400
+    last = hs.Run(cfg, max_gens_per_launch=64)
+    last.import_state(state)
+    same_state(last, whole)
+
+
+def test_state_of_a_pool_run_equals_a_lone_run(hs):
+    cfgs = [(hs.Config(8, 8, 32, 64, "hybrid", tournament_size=2, seed=31), 230),
+            (hs.Config(5, 3, 17, 32, "steady", seed=32, **FLOAT), 170)]
+    pool = hs.Pool(64 << 20, max_runs=4, max_gens_per_launch=50)
+    ids = {pool.admit(c, g): (c, g) for c, g in cfgs}
+    while pool.advance(50):
+        pass
+    for rid, (c, g) in ids.items():
+        pr = pool.run(rid)
+        got = pr.export_state()
+        lone = hs.Run(c, max_gens_per_launch=50)
+        lone.step(g)
+        assert np.array_equal(got, lone.export_state())
+        # a run of a pool refuses to import (its generation target lives there)
+        words = got.view(np.uint32).copy()
+        rc = hs.binding.load_library().ga_import_state(pr._h, words.ctypes.data_as(ctypes.c_void_p),
+                                                       words.nbytes)
+        assert rc == hs.binding.GA_EINVAL
+        lone.close()
+    pool.close()
+
+
+def refused(hs, run, words, status):
+    before = run.agents(), run.generation
+    with pytest.raises(hs.HsgaError) as e:
+        run.import_state(words.view(np.uint8))
+    assert e.value.status == status
+    after = run.agents(), run.generation
+    for x, y in zip(before[0], after[0]):
+        assert np.array_equal(x, y)
+    assert before[1] == after[1]
+
+
+def test_malformed_states_are_refused(hs, orc):
+    cfg = hs.Config(4, 4, 16, 32, "tilted", tournament_size=2, seed=41)
+    src = hs.Run(cfg)
+    src.step(60)
+    good = src.export_state().view(np.uint32)
+    run = hs.Run(cfg)
+    run.step(9)
+    EINVAL, EHORIZON = hs.binding.GA_EINVAL, hs.binding.GA_EHORIZON
+    refused(hs, run, good[:-1], EINVAL)                     # short
+    bad = good.copy(); bad[0] ^= 1; refused(hs, run, bad, EINVAL)        # magic
+    bad = good.copy(); bad[1] = 2; refused(hs, run, bad, EINVAL)         # version
+    other = hs.Run(hs.Config(4, 4, 16, 32, "tilted", tournament_size=2, seed=42))
+    other.step(60)
+    refused(hs, run, other.export_state().view(np.uint32), EINVAL)      # another seed
+    T, trait, counter, surf, ob = parse(hs, cfg, good.view(np.uint8))
+    off = 4 + int(good[2]) // 4 + cfg.agents
+    bad = good.copy(); bad[off + 5] = T + 1; refused(hs, run, bad, EINVAL)   # counter != T
+    bad = good.copy(); bad[off + 5] = T - 1; refused(hs, run, bad, EINVAL)
+    ob_off = 4 + int(good[2]) // 4 + (2 + cfg.surface_words) * cfg.agents
+    bad = good.copy(); bad[ob_off + 4 * 3] = 5; refused(hs, run, bad, EINVAL)  # direction
+    # the untouched state still imports
+    run.import_state(good.view(np.uint8))
+    same_state(run, src)
+    # a generation count past the site rule's horizon (tilted, 4 byte sites)
+    tiny = hs.Config(2, 2, 4, 4, "tilted", differentia_bits=8, seed=44)
+    top = orc.horizon_gen(1, 4, 1) + 1
+    last = hs.Run(tiny)
+    last.step(top)
+    with pytest.raises(hs.HsgaError):
+        last.step(1)
+    bad = last.export_state().view(np.uint32).copy()
+    bad[3] = top + 1
+    refused(hs, hs.Run(tiny), bad, EHORIZON)
+    ok = hs.Run(tiny)
+    ok.import_state(last.export_state())
+    same_state(ok, last)
+
+
+def test_malformed_async_states_are_refused(hs):
+    cfg = hs.Config(4, 4, 16, 64, "hybrid", async_activity=P(0.6), seed=43)
+    src = hs.Run(cfg, max_gens_per_launch=300)
+    src.step(250)
+    good = src.export_state().view(np.uint32)
+    T, trait, counter, surf, ob = parse(hs, cfg, good.view(np.uint8))
+    assert len(np.unique(counter)) > 1 and counter.max() <= T
+    run = hs.Run(cfg, max_gens_per_launch=300)
+    EINVAL = hs.binding.GA_EINVAL
+    off = 4 + int(good[2]) // 4 + cfg.agents
+    bad = good.copy(); bad[off + 7] = T + 1; refused(hs, run, bad, EINVAL)   # counter > T
+    ob_off = 4 + int(good[2]) // 4 + (2 + cfg.surface_words) * cfg.agents
+    bad = good.copy(); bad[ob_off + 8 * 2 + 2] = T + 1; refused(hs, run, bad, EINVAL)
+    # a table too small for the state's tick count
+    small = hs.Run(cfg, max_gens_per_launch=200)
+    refused(hs, small, good, EINVAL)
+    # counters below T are the asynchronous norm
+    run.import_state(good.view(np.uint8))
+    same_state(run, src)
+    run.step(50)
+    src.step(50)
+    same_state(run, src)
