@@ -180,11 +180,14 @@ uint64_t orc_horizon(uint32_t kind, uint32_t S)
  * overwritten, pruning happens by overwrite.  Reading: while the sub-surface
  * is filling (u < m) item u goes to its own site u; afterwards it goes to the
  * lowest site whose item has left D(u).  L holds global deposit times.
- * Returns the site, or -1 if no site is evictable (beyond the horizon).     */
+ * Returns the site, or -1 for an item past the horizon (the retention
+ * target is not defined there) or if no site is evictable.                 */
 int orc_place(uint32_t kind, uint32_t S, const uint32_t *L, uint32_t T)
 {
     uint32_t policy, m, offset;
     uint64_t u;
+    if ((uint64_t)T > orc_horizon(kind, S))
+        return -1;
     sub_surface(kind, S, T, &policy, &m, &u, &offset);
     if (u < m)
         return (int)(offset + u);
@@ -206,6 +209,8 @@ int orc_layout(uint32_t kind, uint32_t S, uint32_t T, uint32_t *L)
 {
     for (uint32_t k = 0; k < S; k++)
         L[k] = ORC_EMPTY;
+    if ((uint64_t)T > orc_horizon(kind, S) + 1)   /* item T - 1 past the horizon */
+        return -1;
     for (uint64_t t = 0; t < T; t++) {
         int site = orc_place(kind, S, L, (uint32_t)t);
         if (site < 0)

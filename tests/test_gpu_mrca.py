@@ -81,7 +81,7 @@ def test_founders_and_fill_phase(hs, orc):
         assert np.array_equal(lb, olb) and np.array_equal(ub, oub)
 
 
-def test_past_horizon_is_reported(hs):
+def test_past_horizon_is_reported(hs, orc):
     import torch
     # hybrid S = 32: the last placeable deposit is 2 * (2^16 - 2) + 2; a
     # counter c holds deposits 0 .. c-1, so c = that + 2 is past the horizon
@@ -93,6 +93,11 @@ def test_past_horizon_is_reported(hs):
     ok = torch.full((4,), 2 * (2**16 - 2) + 3, dtype=torch.int32, device="cuda")
     hs.mrca_bounds("hybrid", 32, ok, s, workspace=ws)
     assert hs.mrca_status(ws) == 0
+    # the oracle draws the same line
+    surf = np.zeros((4, 1), np.uint32)
+    with pytest.raises(ValueError):
+        orc.mrca_allpairs(2, 32, hs.as_u32(c), surf)
+    orc.mrca_allpairs(2, 32, hs.as_u32(ok), surf)
 
 
 def test_treatment_pair_full_scale_sample(hs, orc):

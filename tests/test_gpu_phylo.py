@@ -81,7 +81,7 @@ def test_full_sample_of_a_large_run(hs, orc):
     check(hs, orc, KIND["hybrid"], 64, hs.as_u32(cnt), hs.as_u32(srf))
 
 
-def test_refused(hs):
+def test_refused(hs, orc):
     got = hs.phylo_metrics(0, 32, dev(np.array([7, 8, 7], np.uint32)),
                            dev(np.zeros((3, 1), np.uint32)))
     assert got["status"] == 1 and got["sum_branch_length"] == 0
@@ -89,6 +89,9 @@ def test_refused(hs):
     got = hs.phylo_metrics(2, 32, dev(np.full(4, past, np.uint32)),
                            dev(np.zeros((4, 1), np.uint32)))
     assert got["status"] == 2
+    with pytest.raises(ValueError):                 # the oracle refuses it too
+        orc.phylo_metrics(2, 32, np.full(4, past, np.uint32), np.zeros((4, 1), np.uint32))
+    orc.phylo_metrics(2, 32, np.full(4, past - 1, np.uint32), np.zeros((4, 1), np.uint32))
     with pytest.raises(hs.HsgaError):
         hs.phylo_metrics(0, 48, dev(np.zeros(2, np.uint32)), dev(np.zeros((2, 1), np.uint32)))
 

@@ -167,3 +167,30 @@ def test_site_rule_is_one_write_per_generation_over_a_long_run(orc):
     seq = orc.site_sequence(1, 32, 0, 20000)
     assert seq.min() >= 0 and seq.max() < 32
     assert np.array_equal(seq[:32], np.arange(32))
+
+
+@pytest.mark.parametrize("kind,S", [(1, 4), (1, 8), (2, 8), (2, 16), (1, 16)])
+def test_no_placement_past_the_horizon(orc, kind, S):
+    """The retention target is defined up to the horizon only: the last
+    placeable item is the horizon itself; the next one, and a layout that
+    would hold it, are refused rather than placed."""
+    h = orc.horizon(kind, S)
+    L = orc.layout(kind, S, h + 1)                  # items 0 .. h
+    assert orc.place(kind, S, L, h + 1) == -1
+    with pytest.raises(ValueError):
+        orc.layout(kind, S, h + 2)
+    with pytest.raises(ValueError):
+        orc.site_sequence(kind, S, h - 2, 4)
+    assert len(orc.site_sequence(kind, S, h - 2, 3)) == 3
+    # the queries (byte differentiae: 4 or 8 sites) refuse annotations whose
+    # counter holds such an item
+    if S * 8 not in (32, 64):
+        return
+    c_ok = np.full(3, h + 1, np.uint32)
+    surf = np.zeros((3, S * 8 // 32), np.uint32)
+    orc.mrca_allpairs(kind, S, c_ok, surf, bits=8)
+    orc.phylo_metrics(kind, S, c_ok, surf, bits=8)
+    with pytest.raises(ValueError):
+        orc.mrca_allpairs(kind, S, c_ok + 1, surf, bits=8)
+    with pytest.raises(ValueError):
+        orc.phylo_metrics(kind, S, c_ok + 1, surf, bits=8)
