@@ -163,3 +163,34 @@ def test_served_results_equal_alone(hs):
         assert res.latency > 0
     s = rep.summary()
     assert s["requests"] == len(reqs) and s["latency_p99_s"] >= s["latency_p50_s"]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_cancel_and_resubmit(hs, use_graph):
+    """A run released mid-way (a cancelled request) leaves the runs beside
+    it unchanged; the same request admitted again, into the memory the
+    cancelled one held, ends as the request run alone."""
+    a = hs.Config(8, 8, 32, 64, "hybrid", tournament_size=2, seed=51)
+    b = hs.Config(6, 5, 32, 32, "tilted", seed=52)
+    pool = hs.Pool(32 << 20, max_runs=4, max_gens_per_launch=40, use_graph=use_graph)
+    ra = pool.admit(a, 300)
+    rb = pool.admit(b, 200)
+    free0 = pool.info()["free_bytes"]
+    for _ in range(3):
+        pool.advance(40)
+    pool.release(rb)                        # cancelled with work still enqueued
+    assert pool.info()["free_bytes"] == free0 + pool.footprint(b)
+    rb2 = pool.admit(b, 200)
+    assert pool.info()["free_bytes"] == free0
+    while pool.advance(40):
+        pass
+    for rid, c, g in ((ra, a, 300), (rb2, b, 200)):
+        alone = hs.Run(c)
+        alone.step(g)
+        got = pool.run(rid)
+        for x, y in zip(got.agents(), alone.agents()):
+            assert np.array_equal(x, y)
+        assert np.array_equal(got.layout(), alone.layout())
+        assert np.array_equal(got.export_state(), alone.export_state())
+        alone.close()
+    pool.close()
