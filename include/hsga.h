@@ -116,8 +116,10 @@ typedef struct ga_run ga_run;
  * Runs (Asynchronous Island-model Genetic Algorithm; Genome Model).
  *
  * Device state of a run, carved from the caller's arena:
- *   - two ping-pong populations, structure of arrays: trait[A],
- *     counter[A], surface word planes [S/32][A] (A = w*h*N agents);
+ *   - two ping-pong populations, structure of arrays: trait[A], surface
+ *     word planes [S/32][A] (A = w*h*N agents), and for asynchronous runs
+ *     counter[A].  A synchronous run keeps no counter plane: every agent's
+ *     counter is the generation count T, which the read calls report;
  *   - two ping-pong outboxes, 32 bytes reserved per island (a synchronous
  *     run's entry uses 16: direction, trait, surface words, since every
  *     emigrant's counter is the generation count);
@@ -171,7 +173,8 @@ int ga_sync(ga_run *run);
 int ga_generation(const ga_run *run, uint32_t *T);
 
 /* Blocking copy of agents [first, first + count) of the current
- * population into host buffers: trait[count], counter[count],
+ * population into host buffers: trait[count], counter[count] (T for every
+ * agent of a synchronous run),
  * surface_words[count * W] (agent-major, W = S * differentia_bits / 32
  * surface words per agent).  Any pointer may be NULL.
  * Errors: GA_EINVAL (range), GA_EDEVICE.                                   */

@@ -31,12 +31,18 @@ int hip_fail(hipError_t e, const char* what) {
 
 const char* last_error() { return g_last_error.c_str(); }
 
-Carve carve(uint32_t I, uint32_t N, uint32_t SW, uint32_t gens) {
-    const size_t A = (size_t)I * N;
+Carve carve(const ga_config& cfg, uint32_t gens) {
+    const size_t I = (size_t)cfg.grid_w * cfg.grid_h;
+    const size_t A = I * cfg.pop_per_island;
+    const size_t SW = surface_words(cfg);
     Carve c;
     size_t off = 0;
     c.trait = off;   off += 2 * align_up(A * 4);
-    c.counter = off; off += 2 * align_up(A * 4);
+    c.counter = 0;
+    if (cfg.async_activity) {
+        c.counter = off;
+        off += 2 * align_up(A * 4);
+    }
     c.surf = off;    off += 2 * align_up(SW * A * 4);
     c.outbox = off;  off += 2 * align_up((size_t)I * hsga::kOutboxWords * 4);
     c.layout = off;  off += align_up(64 * 4);
@@ -103,7 +109,7 @@ uint32_t default_agents_per_thread(uint32_t N) {
 
 int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipStream_t stream) {
     const uint32_t I = cfg->grid_w * cfg->grid_h;
-    const Carve c = carve(I, cfg->pop_per_island, surface_words(*cfg), gens);
+    const Carve c = carve(*cfg, gens);
     r->cfg = *cfg;
     r->I = I;
     r->N = cfg->pop_per_island;
@@ -114,7 +120,9 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
     const size_t A = r->A;
     for (int b = 0; b < 2; ++b) {
         r->trait[b] = reinterpret_cast<uint32_t*>(base + c.trait + b * align_up(A * 4));
-        r->counter[b] = reinterpret_cast<uint32_t*>(base + c.counter + b * align_up(A * 4));
+        r->counter[b] = cfg->async_activity ? reinterpret_cast<uint32_t*>(
+                                                  base + c.counter + b * align_up(A * 4))
+                                            : nullptr;
         r->surf[b] = reinterpret_cast<uint32_t*>(base + c.surf + b * align_up(r->SW * A * 4));
         r->outbox[b] = reinterpret_cast<uint32_t*>(
             base + c.outbox + b * align_up((size_t)I * hsga::kOutboxWords * 4));
@@ -221,7 +229,7 @@ size_t ga_footprint_bytes(const ga_config* in, uint32_t max_gens_per_launch) {
     ga_config cfg;
     if (validate(in, &cfg) != GA_OK) return 0;
     const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
-    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, surface_words(cfg), gens).total;
+    return carve(cfg, gens).total;
 }
 
 int ga_create(const ga_config* in, void* dev_arena, size_t arena_bytes,
@@ -235,8 +243,7 @@ int ga_create(const ga_config* in, void* dev_arena, size_t arena_bytes,
     if (!dev_arena) return fail(GA_EINVAL, "arena is NULL");
     if ((uintptr_t)dev_arena % kAlign) return fail(GA_EINVAL, "arena not 256-byte aligned");
     const uint32_t gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
-    const uint32_t I = cfg->grid_w * cfg->grid_h;
-    const Carve c = carve(I, cfg->pop_per_island, surface_words(*cfg), gens);
+    const Carve c = carve(*cfg, gens);
     if (arena_bytes < c.total)
         return fail(GA_ENOMEM, "arena of " + std::to_string(arena_bytes) + " bytes, need " +
                                    std::to_string(c.total));
@@ -355,9 +362,11 @@ int ga_read_agents(ga_run* r, uint32_t first, uint32_t count, uint32_t* trait, u
         e = hipMemcpy(trait, r->trait[cur] + first, (size_t)count * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy trait");
     }
-    if (counter) {
+    if (counter && r->counter[cur]) {
         e = hipMemcpy(counter, r->counter[cur] + first, (size_t)count * 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy counter");
+    } else if (counter) {
+        std::fill(counter, counter + count, r->T);   // synchronous: every counter is T
     }
     if (surface_words) {
         std::vector<uint32_t> plane(count);
@@ -450,11 +459,16 @@ int ga_export_state(ga_run* r, void* host, size_t bytes) {
     uint32_t* at = w + kStateHeaderWords + sizeof(ga_config) / 4;
     const int cur = r->T & 1;
     const size_t A = r->A;
+    // a synchronous run keeps no counter plane: every counter is T
     const struct { const uint32_t* src; size_t words; } planes[] = {
         {r->trait[cur], A}, {r->counter[cur], A}, {r->surf[cur], r->SW * A}};
     for (const auto& pl : planes) {
-        e = hipMemcpy(at, pl.src, pl.words * 4, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy state");
+        if (pl.src) {
+            e = hipMemcpy(at, pl.src, pl.words * 4, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy state");
+        } else {
+            std::fill(at, at + pl.words, r->T);
+        }
         at += pl.words;
     }
     const size_t ob = (size_t)r->I * entry_words(r);
@@ -513,7 +527,7 @@ int ga_import_state(ga_run* r, const void* host, size_t bytes) {
         {r->trait[cur], trait, A}, {r->counter[cur], counter, A}, {r->surf[cur], surf, r->SW * A},
         {r->outbox[cur], ob, outbox ? (size_t)r->I * E : 0}};
     for (const auto& pl : planes) {
-        if (pl.words == 0) continue;
+        if (pl.words == 0 || !pl.dst) continue;      // no counter plane when synchronous
         e = hipMemcpy(pl.dst, pl.src, pl.words * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy state");
     }

@@ -50,14 +50,15 @@ struct Carve {
     size_t trait, counter, surf, outbox, layout, sites, total;
 };
 
-// Byte offsets of each buffer of a run in its arena (SW surface words per
-// agent).
-Carve carve(uint32_t I, uint32_t N, uint32_t SW, uint32_t gens);
-
 // Surface words per agent of a validated config.
 inline uint32_t surface_words(const ga_config& c) {
     return c.surface_sites * c.differentia_bits / 32;
 }
+
+// Byte offsets of each buffer of a run of a validated config in its arena.
+// Only asynchronous runs keep counter planes: in a synchronous run every
+// counter is the generation count (counter == 0 and no bytes then).
+Carve carve(const ga_config& cfg, uint32_t gens);
 
 // GA_OK, or GA_EINVAL with the reason in ga_last_error().
 // Check a caller's config (either accepted struct_size) and, if out is not

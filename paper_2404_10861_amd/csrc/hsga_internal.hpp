@@ -89,7 +89,8 @@ size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW);
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW, bool float_births,
                       uint32_t block_threads, uint32_t apt);
 
-// tags: founders' trait words are random 16-bit founder tags (key k0, k1).
+// tags: founders' trait words are random 16-bit founder tags (key k0, k1);
+// counter may be nullptr (a synchronous run keeps no counter plane).
 hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, uint32_t A,
                            uint32_t SW, uint32_t* layout, uint32_t S, bool tags, uint32_t k0,
                            uint32_t k1, hipStream_t stream);

@@ -14,7 +14,8 @@ namespace hsga {
 
 // ---------------------------------------------------------------------------
 // Founders (Genome Model; Distributed Phylogenetic Tracking): trait 0,
-// counter 0, every site 0, and an empty layout.  Founders carry no
+// counter 0 (written only when the run keeps a counter plane), every site
+// 0, and an empty layout.  Founders carry no
 // differentia; item g is deposited by generation g's births.  With founder
 // tags (Results, Clade Reconstruction Trial) the trait word is instead a
 // random 16-bit identifier: the low half of the first word of Philox block
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(256) void founders_kernel(uint32_t* __restrict__ tr
     const uint32_t first = blockIdx.x * blockDim.x + threadIdx.x;
     for (uint32_t a = first; a < A; a += stride) {
         trait[a] = tags ? philox4x32_10(make_uint4(a, 0u, 0u, kFounder), k0, k1).x & 0xffffu : 0u;
-        counter[a] = 0u;
+        if (counter) counter[a] = 0u;
         for (uint32_t w = 0; w < SW; ++w) surf[(size_t)w * A + a] = 0u;
     }
     if (first < S) layout[first] = kEmpty;
@@ -103,7 +104,8 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 //     copied from LDS, trait mutation, counter + 1 and the differentia bit
 //     written at this generation's site.  After the loop the thread holding
 //     the island's emigrant posts its copy to the outbox for g + 1.
-//     Children leave with one 16-byte store per plane, counters included.
+//     Children leave with one 16-byte store per plane (the counter plane
+//     only for asynchronous ticks).
 // Immigration slots: bits 6d .. 6d+5 = slot for direction d.  Emigration
 // word: bits 0..7 = slot, 8..10 = direction (4: none, an idle island).
 // Plan word (asynchronous ticks): bit 31 = the island is active.
@@ -390,7 +392,8 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
         }
     }
     store_lanes<APT>(p.out_trait + a0 + la0, ctr);
-    store_lanes<APT>(p.out_counter + a0 + la0, ccn);
+    // a synchronous run keeps no counter plane: every counter is g + 1
+    if constexpr (ASYNC) store_lanes<APT>(p.out_counter + a0 + la0, ccn);
 #pragma unroll
     for (int w = 0; w < SW; ++w) store_lanes<APT>(p.out_surf + w * A + a0 + la0, csf[w]);
 }

@@ -180,7 +180,7 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
 size_t ga_pool_footprint(const ga_pool* p, const ga_config* in) {
     ga_config cfg;
     if (!p || validate(in, &cfg) != GA_OK) return 0;
-    return carve(cfg.grid_w * cfg.grid_h, cfg.pop_per_island, surface_words(cfg), p->gens).total;
+    return carve(cfg, p->gens).total;
 }
 
 int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint32_t* id) {

@@ -9,6 +9,7 @@ namespace hsga {
 // ---------------------------------------------------------------------------
 // Stratified end-of-run sample (Results, On-hardware Trial): agent k is
 // drawn uniformly from the k-th of n equal strata; every agent when A <= n.
+// counter == nullptr: a synchronous run, whose every counter is T.
 __global__ __launch_bounds__(256) void sample_kernel(const uint32_t* __restrict__ counter,
                                                     const uint32_t* __restrict__ surf, uint32_t A,
                                                     uint32_t SW, uint32_t n, uint32_t T,
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(256) void sample_kernel(const uint32_t* __restrict_
         a = lo + word_below(w.x, hi - lo);
     }
     idx_out[k] = a;
-    counter_out[k] = counter[a];
+    counter_out[k] = counter ? counter[a] : T;
     for (uint32_t w = 0; w < SW; ++w) surf_out[(size_t)k * SW + w] = surf[(size_t)w * A + a];
 }
 

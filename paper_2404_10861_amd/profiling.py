@@ -149,6 +149,7 @@ def cmd_traffic(a):
         "bytes_per_launch": fetch_b + write_b,
         "algorithmic_bytes_per_launch": a.bytes_per_launch,
         "traffic_over_algorithmic": (fetch_b + write_b) / a.bytes_per_launch,
+        "design_bytes_per_launch": a.design_bytes_per_launch,
         "commands": a.cmd,
     }
     with open(a.out, "w") as f:
@@ -166,8 +167,12 @@ def cmd_traffic(a):
               f"- HBM bytes per launch: read {fetch_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB "
               f"= {(fetch_b + write_b) / 1e6:.1f} MB",
               f"- algorithmic bytes per launch: {a.bytes_per_launch / 1e6:.1f} MB; measured / "
-              f"algorithmic = {rec['traffic_over_algorithmic']:.3f}",
-              f"- kernel source hash: {rec['kernel_hash']}", ""]
+              f"algorithmic = {rec['traffic_over_algorithmic']:.3f}"]
+    if a.design_bytes_per_launch:
+        lines.append(f"- design bytes per launch (what this code has to move): "
+                     f"{a.design_bytes_per_launch / 1e6:.1f} MB; measured / design = "
+                     f"{(fetch_b + write_b) / a.design_bytes_per_launch:.3f}")
+    lines += [f"- kernel source hash: {rec['kernel_hash']}", ""]
     with open(a.md, "w") as f:
         f.write("\n".join(lines))
     print("\n".join(lines))
@@ -246,6 +251,7 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--kernel", default="step_kernel")
     t.add_argument("--bytes-per-launch", type=float, required=True)
+    t.add_argument("--design-bytes-per-launch", type=float, default=0.0)
     t.add_argument("--out", required=True)
     t.add_argument("--md", required=True)
     t.add_argument("--title", default="")

@@ -58,9 +58,14 @@ def test_footprint_without_gpu():
     import paper_2404_10861_amd as hs
     cfg = hs.Config(512, 1024, 32, 64, "hybrid")
     n = hs.footprint_bytes(cfg)
-    # two populations of 16 B records plus outboxes, layout and schedule
-    assert n >= 2 * cfg.agents * 16 + 2 * cfg.islands * 32
-    assert n < 2 * cfg.agents * 16 + 2 * cfg.islands * 32 + (1 << 20)
+    # a synchronous run: two populations of trait and surface words (no
+    # counter plane: every counter is the generation count), plus outboxes,
+    # layout and schedule
+    assert n >= 2 * cfg.agents * 12 + 2 * cfg.islands * 32
+    assert n < 2 * cfg.agents * 12 + 2 * cfg.islands * 32 + (1 << 20)
+    # an asynchronous run keeps its counter planes as well
+    acfg = hs.Config(512, 1024, 32, 64, "hybrid", async_activity=1 << 31)
+    assert hs.footprint_bytes(acfg) == n + 2 * cfg.agents * 4
     with pytest.raises(hs.HsgaError):
         hs.footprint_bytes(hs.Config(0, 4))
 

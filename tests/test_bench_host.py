@@ -29,6 +29,18 @@ def test_algorithmic_bytes_of_the_paper_scale_step():
     assert bench.algorithmic_bytes_per_generation(spec) == want
 
 
+
+def test_design_bytes_of_the_paper_scale_step():
+    """A synchronous step keeps no counter plane: trait and 64 one-bit sites
+    (12 bytes) read and written per agent, one 16-byte outbox entry written
+    and read per island."""
+    import bench
+    from paper_2404_10861_amd import workloads as wl
+    agents, islands = 512 * 1024 * 32, 512 * 1024
+    want = 2 * agents * 12 + 2 * islands * 16
+    assert want == 419_430_400
+    assert bench.design_bytes_per_generation(wl.c2()) == want
+
 def test_traffic_is_reported_only_for_the_profiled_code(monkeypatch):
     import bench
     from paper_2404_10861_amd import profiling
