@@ -262,8 +262,7 @@ def main(argv=None) -> int:
         run.set_kernel_timing(timed)
         run.step(spec.generations)
         _, cnt, srf = run.sample(n_sample)
-        hs.mrca_bounds(spec.surface_kind, spec.surface_sites, cnt, srf, workspace=ws,
-                       stream=stream, lb=lb, ub=ub)
+        run.mrca_bounds(cnt, srf, workspace=ws, lb=lb, ub=ub)
         return run
 
     copy_gbs = attainable_copy_gbs(torch, hs, dev, stream)

@@ -371,6 +371,27 @@ int hstrat_phylo_tree_ex(const hstrat_scheme *scheme, uint32_t n,
                          uint64_t *out, void *workspace, size_t workspace_bytes,
                          void *hip_stream);
 
+/* Queries on annotations taken from a run (typically its ga_sample), with
+ * the run's own annotation scheme, enqueued on the run's stream.  Results
+ * are those of hstrat_mrca_bounds_ex and hstrat_phylo_tree_ex.  A layout
+ * is a function of the scheme and the generation count alone (Distributed
+ * Phylogenetic Tracking: deposit times follow from the site index and the
+ * count).  So when every counter equals the run's generation count T, the
+ * run's own layout at T is used instead of replaying the site rule from
+ * the empty layout, which is one placement per generation.  Otherwise
+ * (a sample taken before later steps, drifted asynchronous counters) the
+ * query replays as the hstrat_ calls do.  ga_phylo_tree with leaf_parent
+ * NULL computes the metrics only (node_parent and node_time unused).
+ * Errors as the hstrat_ calls, and GA_EINVAL for a NULL run.               */
+int ga_mrca_bounds(ga_run *run, uint32_t n, const uint32_t *counter,
+                   const uint32_t *surface_words, uint32_t *lb, uint32_t *ub,
+                   void *workspace, size_t workspace_bytes);
+
+int ga_phylo_tree(ga_run *run, uint32_t n, const uint32_t *counter,
+                  const uint32_t *surface_words, uint32_t *leaf_parent,
+                  uint32_t *node_parent, uint32_t *node_time, uint64_t *out,
+                  void *workspace, size_t workspace_bytes);
+
 /* ------------------------------------------------------------------------
  * Batched and served runs: a pool of runs of any sizes, surfaces and
  * treatments sharing one caller-owned device arena and one stream.  An

@@ -115,8 +115,7 @@ def plain_fifo_server(reqs, dev, stream, sample: int = 1024, time_scale: float =
             n = cnt.shape[0]
             lv = lb[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32, device=dev)
             uv = ub[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32, device=dev)
-            hs.mrca_bounds(r.surface_kind, r.surface_sites, cnt, srf, workspace=ws, stream=stream,
-                           lb=lv, ub=uv)
+            run.mrca_bounds(cnt, srf, workspace=ws, lb=lv, ub=uv)
             lv.cpu()
             uv.cpu()
             run.close()
@@ -183,10 +182,9 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096, labels=None,
         e2 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         if allpairs:
-            hs.mrca_bounds(s.surface_kind, s.surface_sites, cnt, srf, workspace=ws,
-                           stream=stream, lb=lb, ub=ub)
+            run.mrca_bounds(cnt, srf, workspace=ws, lb=lb, ub=ub)
         e1.record(stream)
-        phylo = hs.phylo_metrics(s.surface_kind, s.surface_sites, cnt, srf, stream=stream)
+        phylo = run.phylo_tree(cnt, srf, tree=False)
         e2.record(stream)
         torch.cuda.synchronize(dev)
         wall = time.perf_counter() - t0

@@ -35,6 +35,7 @@ EXPORTS = (
     "ga_pool_set_launch", "ga_pool_info", "ga_pool_destroy",
     "hstrat_phylo_workspace_bytes", "hstrat_phylo_metrics",
     "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
+    "ga_mrca_bounds", "ga_phylo_tree",
 )
 
 
@@ -142,6 +143,10 @@ def load_library():
                                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "hstrat_phylo_tree_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp,
                                                 _vp, _vp, ctypes.c_size_t, _vp]),
+        "ga_mrca_bounds": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.c_size_t]),
+        "ga_phylo_tree": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         ctypes.c_size_t]),
         "hstrat_mrca_bounds_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp,
                                                  ctypes.c_size_t, _vp]),
         "hstrat_phylo_metrics_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp, _vp, _vp, _vp,
@@ -320,6 +325,62 @@ class RunHandle:
         _check(lib.ga_export_state(self._h, _ptr(words), nbytes))
         return words.view(np.uint8)
 
+    def mrca_bounds(self, counter: torch.Tensor, surface_words: torch.Tensor,
+                    workspace: "MrcaWorkspace | None" = None, lb=None, ub=None):
+        """mrca_bounds of annotations taken from this run, with its scheme and
+        on its stream: when every counter is the run's generation count, the
+        run's own layout replaces the replay of the site rule."""
+        n = counter.shape[0]
+        if counter.dtype != torch.int32 or surface_words.dtype != torch.int32:
+            raise ValueError("counter and surface_words must be int32 tensors")
+        with torch.cuda.stream(self.stream):
+            counter = counter.contiguous()
+            surface_words = surface_words.contiguous()
+            if workspace is None or workspace.n < n or workspace.S < self.S:
+                workspace = MrcaWorkspace(self.S, n, self.device)
+            if lb is None:
+                lb = torch.empty((n, n), dtype=torch.int32, device=self.device)
+            if ub is None:
+                ub = torch.empty((n, n), dtype=torch.int32, device=self.device)
+            _check(load_library().ga_mrca_bounds(
+                self._h, n, _vp(counter.data_ptr()), _vp(surface_words.data_ptr()),
+                _vp(lb.data_ptr()), _vp(ub.data_ptr()), _vp(workspace.ptr), workspace.nbytes))
+        return lb, ub
+
+    def phylo_tree(self, counter: torch.Tensor, surface_words: torch.Tensor,
+                   tree: bool = True) -> dict:
+        """phylo_tree (tree=False: phylo_metrics) of annotations taken from
+        this run, with its scheme and on its stream, using the run's own
+        layout when every counter is its generation count."""
+        n = counter.shape[0]
+        if counter.dtype != torch.int32 or surface_words.dtype != torch.int32:
+            raise ValueError("counter and surface_words must be int32 tensors")
+        lib = load_library()
+        with torch.cuda.stream(self.stream):
+            counter = counter.contiguous()
+            surface_words = surface_words.contiguous()
+            need = int(lib.hstrat_phylo_workspace_bytes(self.S, n))
+            buf, ptr = _aligned_bytes(need, self.device)
+            out = torch.zeros(6, dtype=torch.int64, device=self.device)
+            leaf = node_parent = node_time = None
+            if tree:
+                leaf = torch.empty(n, dtype=torch.int32, device=self.device)
+                node_parent = torch.empty(max(n - 1, 1), dtype=torch.int32, device=self.device)
+                node_time = torch.empty(max(n - 1, 1), dtype=torch.int32, device=self.device)
+            ptr_of = lambda t: _vp(t.data_ptr()) if t is not None else None   # noqa: E731
+            _check(lib.ga_phylo_tree(self._h, n, _vp(counter.data_ptr()),
+                                     _vp(surface_words.data_ptr()), ptr_of(leaf),
+                                     ptr_of(node_parent), ptr_of(node_time),
+                                     _vp(out.data_ptr()), _vp(ptr), need))
+            res = _phylo_result(out.cpu().numpy().view(np.uint64), n)
+            if tree:
+                res.update({"leaf_parent": as_u32(leaf),
+                            "node_parent": as_u32(node_parent)[:n - 1],
+                            "node_time": as_u32(node_time)[:n - 1],
+                            "T": int(counter[0].item()) & 0xFFFFFFFF})
+            del buf
+        return res
+
     def sample(self, n: int, out=None):
         """Stratified sample on the device: (idx, counter, surface[n, S/32])
         as int32 CUDA tensors holding the uint32 bit patterns."""
@@ -409,6 +470,7 @@ class PoolRun(RunHandle):
         _check(load_library().ga_pool_run(pool._h, run_id, ctypes.byref(h)))
         self._h = h
         self.id = run_id
+        self.stream = pool.stream
         self._setup(cfg, pool.device)
 
 
@@ -589,6 +651,11 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
                                                _vp(_stream_handle(stream))))
         w = out.cpu().numpy().view(np.uint64)
         del buf
+    return _phylo_result(w, n)
+
+
+def _phylo_result(w, n: int) -> dict:
+    """The six result words of a reconstruction and the derived means."""
     res = {"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
            "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5])}
     npairs = n * (n - 1) // 2

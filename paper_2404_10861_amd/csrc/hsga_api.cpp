@@ -599,6 +599,46 @@ int hstrat_mrca_bounds_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_
     return GA_OK;
 }
 
+int ga_mrca_bounds(ga_run* r, uint32_t n, const uint32_t* counter,
+                   const uint32_t* surface_words, uint32_t* lb, uint32_t* ub, void* workspace,
+                   size_t workspace_bytes) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    const hsga::Scheme sc{r->cfg.surface_kind, r->S, r->cfg.differentia_bits,
+                          r->cfg.ingest_interval};
+    if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
+    if (!counter || !surface_words || !lb || !ub || !workspace)
+        return fail(GA_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < hsga::MrcaWorkspace::bytes(sc.S, n))
+        return fail(GA_ENOMEM, "workspace too small");
+    // on the run's stream: the layout is read after the steps enqueued so
+    // far and before any later ones advance it
+    hipError_t e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace, r->stream,
+                                     hsga::LayoutHint{r->layout, r->T});
+    if (e != hipSuccess) return hip_fail(e, "mrca launch");
+    return GA_OK;
+}
+
+int ga_phylo_tree(ga_run* r, uint32_t n, const uint32_t* counter, const uint32_t* surface_words,
+                  uint32_t* leaf_parent, uint32_t* node_parent, uint32_t* node_time,
+                  uint64_t* out, void* workspace, size_t workspace_bytes) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    const hsga::Scheme sc{r->cfg.surface_kind, r->S, r->cfg.differentia_bits,
+                          r->cfg.ingest_interval};
+    if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
+    if (!counter || !surface_words || !out || !workspace ||
+        (leaf_parent && n > 1 && (!node_parent || !node_time)))
+        return fail(GA_EINVAL, "NULL buffer");
+    if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
+    if (workspace_bytes < hsga::phylo_workspace_bytes(sc.S, n))
+        return fail(GA_ENOMEM, "workspace too small");
+    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, r->stream,
+                                      leaf_parent, node_parent, node_time,
+                                      hsga::LayoutHint{r->layout, r->T});
+    if (e != hipSuccess) return hip_fail(e, "phylo launch");
+    return GA_OK;
+}
+
 int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
                        const uint32_t* surface_words, uint32_t* lb, uint32_t* ub, void* workspace,
                        size_t workspace_bytes, void* hip_stream) {

@@ -130,16 +130,24 @@ struct MrcaWorkspace {
     }
 };
 
+// A run's own layout (device, S words in ingest units) after the ingests of
+// generation count T; the queries use it instead of replaying the site rule
+// when every annotation's counter is T.
+struct LayoutHint {
+    const uint32_t* layout = nullptr;
+    uint32_t T = 0;
+};
+
 size_t phylo_workspace_bytes(uint32_t S, uint32_t n);
 // leaf_parent (n), node_parent and node_time (n - 1), all device: the tree
 // itself; NULL leaf_parent computes the metrics only.
 hipError_t launch_phylo(const Scheme& sc, uint32_t n, const uint32_t* counter,
                         const uint32_t* surf, uint64_t* out, void* workspace, hipStream_t stream,
                         uint32_t* leaf_parent = nullptr, uint32_t* node_parent = nullptr,
-                        uint32_t* node_time = nullptr);
+                        uint32_t* node_time = nullptr, LayoutHint hint = {});
 
 hipError_t launch_mrca(const Scheme& sc, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
-                       hipStream_t stream);
+                       hipStream_t stream, LayoutHint hint = {});
 
 }  // namespace hsga

@@ -78,20 +78,36 @@ __device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uin
 // One wavefront: classify the counters; when all are equal, replay the
 // shared layout once (in ingest units), order its sites by deposit time and
 // tabulate the bounds, in generations, for every possible first-mismatch
-// rank.
+// rank.  A run's own layout (hint, S words in ingest units, the layout after
+// the ingests of generation count hint_T) replaces the replay when every
+// counter is hint_T: the layout is a function of the scheme and the count
+// alone, so both give the same words.
 __global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
                                                          const uint32_t* __restrict__ counter,
-                                                         uint32_t* __restrict__ ws) {
+                                                         uint32_t* __restrict__ ws,
+                                                         const uint32_t* __restrict__ hint,
+                                                         uint32_t hint_T) {
     const uint32_t lane = threadIdx.x;
     const uint32_t S = sc.S;
     const uint32_t T0 = counter[0];
     const uint64_t hz = horizon_of(sc.kind, S);
     bool same = true, past = false;
-    for (uint32_t k = lane; k < n; k += 64) {
-        const uint32_t c = counter[k];
-        const uint32_t ing = ingests_of(c, sc.interval);
-        same = same && c == T0;
-        past = past || ing > kMaxReplayGenerations || (ing > 0 && (uint64_t)(ing - 1) > hz);
+    // 16 loads in flight per lane before any is used
+    constexpr uint32_t kBatch = 16;
+    for (uint32_t k0 = lane; k0 < n; k0 += 64 * kBatch) {
+        uint32_t c[kBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kBatch; ++j) {
+            const uint32_t k = k0 + 64 * j;
+            c[j] = k < n ? counter[k] : T0;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kBatch; ++j) {
+            const uint32_t ing = ingests_of(c[j], sc.interval);
+            same = same && c[j] == T0;
+            past = past || ing > kMaxReplayGenerations ||
+                   (ing > 0 && (uint64_t)(ing - 1) > hz);
+        }
     }
     const bool any_past = __ballot(past) != 0;
     const bool all_same = __ballot(!same) == 0;
@@ -102,7 +118,9 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
         }
         return;
     }
-    const uint32_t held = replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
+    const uint32_t held = hint && T0 == hint_T
+                              ? (lane < S ? hint[lane] : kEmpty)
+                              : replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
     const uint32_t rank = time_rank(held, lane, S);
     const uint32_t F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
     __shared__ uint32_t times[64];
@@ -226,6 +244,7 @@ __global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc, uint32_t n,
 
 // General route, all ordered pairs: merge the two ascending time lists,
 // comparing differentiae on common times until the first mismatch.
+constexpr uint32_t kGeneralPairRows = 512;   // grid rows of the general pairs kernel
 __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
     uint32_t S, uint32_t diff_log2, uint32_t n, const uint32_t* __restrict__ counter,
     const uint32_t* __restrict__ surf, const uint32_t* __restrict__ times,
@@ -233,43 +252,47 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
     uint32_t* __restrict__ ub) {
     if (ws[kWsStatus] != kWsStatusMixed) return;
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t a = blockIdx.y;
     if (b >= n) return;
     const uint32_t SW = (S << diff_log2) >> 5;
-    const uint64_t sa = surface64(surf, SW, a);
     const uint64_t sb = surface64(surf, SW, b);
     const uint64_t mask = diff_log2 ? 0xffull : 1ull;
-    const uint32_t* ta = times + (size_t)a * S;
     const uint32_t* tb = times + (size_t)b * S;
-    const uint8_t* ka = sites + (size_t)a * S;
     const uint8_t* kb = sites + (size_t)b * S;
-    uint32_t i = 0, k = 0;
-    bool have_last = false, mismatch = false;
-    uint32_t last = 0, tstar = 0;
-    while (i < S && k < S) {
-        const uint32_t x = ta[i], y = tb[k];
-        if (x == kEmpty || y == kEmpty) break;
-        if (x == y) {
-            if (((sa >> ((uint32_t)ka[i] << diff_log2)) & mask) !=
-                ((sb >> ((uint32_t)kb[k] << diff_log2)) & mask)) {
-                mismatch = true;
-                tstar = x;
-                break;
+    const uint32_t Tb = counter[b];
+    // rows a = blockIdx.y, blockIdx.y + gridDim.y, ...: a small grid, so that
+    // the shared-counter route, which skips this kernel, pays little for it
+    for (uint32_t a = blockIdx.y; a < n; a += gridDim.y) {
+        const uint64_t sa = surface64(surf, SW, a);
+        const uint32_t* ta = times + (size_t)a * S;
+        const uint8_t* ka = sites + (size_t)a * S;
+        uint32_t i = 0, k = 0;
+        bool have_last = false, mismatch = false;
+        uint32_t last = 0, tstar = 0;
+        while (i < S && k < S) {
+            const uint32_t x = ta[i], y = tb[k];
+            if (x == kEmpty || y == kEmpty) break;
+            if (x == y) {
+                if (((sa >> ((uint32_t)ka[i] << diff_log2)) & mask) !=
+                    ((sb >> ((uint32_t)kb[k] << diff_log2)) & mask)) {
+                    mismatch = true;
+                    tstar = x;
+                    break;
+                }
+                have_last = true;
+                last = x;
+                ++i;
+                ++k;
+            } else if (x < y) {
+                ++i;
+            } else {
+                ++k;
             }
-            have_last = true;
-            last = x;
-            ++i;
-            ++k;
-        } else if (x < y) {
-            ++i;
-        } else {
-            ++k;
         }
+        const uint32_t Ta = counter[a];
+        const size_t off = (size_t)a * n + b;
+        ub[off] = mismatch ? tstar : (Ta < Tb ? Ta : Tb);
+        lb[off] = have_last ? last + 1u : 0u;
     }
-    const uint32_t Ta = counter[a], Tb = counter[b];
-    const size_t off = (size_t)a * n + b;
-    ub[off] = mismatch ? tstar : (Ta < Tb ? Ta : Tb);
-    lb[off] = have_last ? last + 1u : 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -586,7 +609,7 @@ size_t phylo_workspace_bytes(uint32_t S, uint32_t n) {
 hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
                         const uint32_t* surf, uint64_t* out, void* workspace,
                         hipStream_t stream, uint32_t* leaf_parent, uint32_t* node_parent,
-                        uint32_t* node_time) {
+                        uint32_t* node_time, LayoutHint hint) {
     const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
     uint8_t* base = static_cast<uint8_t*>(workspace);
     uint32_t* ws = reinterpret_cast<uint32_t*>(base);
@@ -603,7 +626,8 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
     uint32_t levels = 1;
     while (levels < kPhyloMaxLevels && (2u << (levels - 1)) <= m) ++levels;
     const uint32_t gn = (n + 255) / 256;
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws,
+                       hint.layout, hint.T);
     hipLaunchKernelGGL(mrca_rank_kernel, dim3(gn), dim3(256), 0, stream, scm.S, diff_log2, n,
                        surf, ws, ranked);
     hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
@@ -631,7 +655,7 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
 
 hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
-                       hipStream_t stream) {
+                       hipStream_t stream, LayoutHint hint) {
     const uint32_t S = scm.S;
     const uint32_t diff_log2 = scm.bits == 8 ? 3u : 0u;
     uint8_t* base = static_cast<uint8_t*>(workspace);
@@ -642,15 +666,17 @@ hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
     const size_t times_bytes = ((size_t)n * S * 4 + 255) & ~(size_t)255;
     uint8_t* sites = base + MrcaWorkspace::kHeader + ranked_bytes + times_bytes;
 
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws);
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws,
+                       hint.layout, hint.T);
     hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S,
                        diff_log2, n, surf, ws, ranked);
     hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
                        dim3(256), 0, stream, n, diff_log2, ranked, ws, lb, ub);
     hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, scm, n, counter, ws,
                        times, sites);
-    hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, n), dim3(256), 0, stream,
-                       S, diff_log2, n, counter, surf, times, sites, ws, lb, ub);
+    const uint32_t rows = n < kGeneralPairRows ? n : kGeneralPairRows;
+    hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, rows), dim3(256), 0,
+                       stream, S, diff_log2, n, counter, surf, times, sites, ws, lb, ub);
     return hipGetLastError();
 }
 

@@ -149,9 +149,7 @@ def serve(pool: hs.Pool, requests, chunk_gens: int = 256, sample: int = 1024,
                                                                        device=dev)
                 ub_v = ub_dev[:n, :n] if n == sample else torch.empty((n, n), dtype=torch.int32,
                                                                        device=dev)
-                hs.mrca_bounds(spec.surface_kind, spec.surface_sites, cnt, srf,
-                               workspace=ws, stream=stream, lb=lb_v, ub=ub_v,
-                               bits=spec.differentia_bits, interval=spec.ingest_interval)
+                run.mrca_bounds(cnt, srf, workspace=ws, lb=lb_v, ub=ub_v)
                 lb_h = lb_v.to("cpu", non_blocking=False)
                 ub_h = ub_v.to("cpu", non_blocking=False)
                 res = Served(index=i, arrival=arr, admitted=adm,

@@ -1,0 +1,147 @@
+"""GPU parity of the run-bound queries (ga_mrca_bounds, ga_phylo_tree),
+zero tolerance: with every counter equal to the run's generation count they
+use the run's own layout instead of replaying the site rule, and give the
+replaying queries' and the oracle's results; otherwise (a sample taken
+before later steps, drifted asynchronous counters) they replay.  Runs of
+every kind and annotation scheme, pool runs and runs resumed from a
+state."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ("steady", "tilted", "hybrid")
+P = lambda p: int(p * 2**32)          # noqa: E731
+
+
+@pytest.fixture(scope="module")
+def hs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_10861_amd as hs
+    hs.load_library()
+    return hs
+
+
+def check_against_replay_and_oracle(hs, orc, run, cfg, cnt, srf):
+    import torch
+    kind = KINDS.index(cfg.kind) if isinstance(cfg.kind, str) else cfg.kind
+    bits, interval = cfg.differentia_bits, cfg.ingest_interval
+    run.stream.synchronize()           # the sample was written on the run's stream
+    lb, ub = run.mrca_bounds(cnt, srf)
+    run.stream.synchronize()
+    rlb, rub = hs.mrca_bounds(kind, cfg.surface_sites, cnt, srf, bits=bits, interval=interval)
+    torch.cuda.synchronize()
+    assert np.array_equal(hs.as_u32(lb), hs.as_u32(rlb))
+    assert np.array_equal(hs.as_u32(ub), hs.as_u32(rub))
+    cnt_h, srf_h = hs.as_u32(cnt), hs.as_u32(srf)
+    olb, oub = orc.mrca_allpairs(kind, cfg.surface_sites, cnt_h, srf_h, bits=bits,
+                                 interval=interval)
+    assert np.array_equal(hs.as_u32(lb), olb) and np.array_equal(hs.as_u32(ub), oub)
+    got = run.phylo_tree(cnt, srf)
+    if len(np.unique(cnt_h)) == 1:
+        assert got["status"] == 0
+        assert hs.newick(got) == orc.phylo_newick(kind, cfg.surface_sites, cnt_h, srf_h,
+                                                  bits=bits, interval=interval)
+        metrics = run.phylo_tree(cnt, srf, tree=False)
+        for k in ("sum_branch_length", "pair_sum", "root_time", "internal_nodes", "status"):
+            assert metrics[k] == got[k]
+    else:
+        assert got["status"] == 1                      # counters differ: no tree
+
+
+SCHEMES = [("steady", 32, 1, 1), ("tilted", 64, 1, 1), ("hybrid", 64, 1, 1),
+           ("hybrid", 32, 1, 3), ("steady", 8, 8, 2), ("tilted", 4, 8, 1), ("tilted", 32, 1, 5)]
+
+
+@pytest.mark.parametrize("kind,S,bits,interval", SCHEMES)
+def test_run_queries_use_the_runs_layout(hs, orc, kind, S, bits, interval):
+    cfg = hs.Config(12, 10, 32, S, kind, tournament_size=2, seed=S + interval,
+                    differentia_bits=bits, ingest_interval=interval)
+    G = min(1500, orc.horizon_gen(KINDS.index(kind), S, interval) + 1)
+    run = hs.Run(cfg)
+    run.step(G)
+    _, cnt, srf = run.sample(700)
+    check_against_replay_and_oracle(hs, orc, run, cfg, cnt, srf)
+
+
+def test_a_sample_older_than_the_run_is_replayed(hs, orc):
+    cfg = hs.Config(10, 10, 32, 64, "hybrid", tournament_size=2, seed=5)
+    run = hs.Run(cfg)
+    run.step(800)
+    _, cnt, srf = run.sample(500)
+    cnt, srf = cnt.clone(), srf.clone()
+    run.step(37)                       # the run's layout has moved on
+    check_against_replay_and_oracle(hs, orc, run, cfg, cnt, srf)
+    # the run's current sample still takes its own layout
+    _, cnt2, srf2 = run.sample(500)
+    check_against_replay_and_oracle(hs, orc, run, cfg, cnt2, srf2)
+
+
+def test_queries_enqueued_before_later_steps(hs, orc):
+    """Stream order: a query enqueued before further steps reads the layout
+    of its own generation, not the one the later steps reach."""
+    cfg = hs.Config(16, 16, 32, 32, "tilted", tournament_size=0, seed=8)
+    run = hs.Run(cfg)
+    run.step(600)
+    _, cnt, srf = run.sample(400)
+    lb, ub = run.mrca_bounds(cnt, srf)
+    run.step(300)                      # enqueued behind the query
+    run.sync()
+    olb, oub = orc.mrca_allpairs(1, 32, hs.as_u32(cnt), hs.as_u32(srf))
+    assert np.array_equal(hs.as_u32(lb), olb) and np.array_equal(hs.as_u32(ub), oub)
+
+
+@pytest.mark.parametrize("activity", [0.6, 1.0])
+def test_asynchronous_runs(hs, orc, activity):
+    thr = 0xFFFFFFFF if activity == 1.0 else P(activity)
+    cfg = hs.Config(8, 8, 32, 64, "hybrid", seed=12, async_activity=thr)
+    run = hs.Run(cfg, max_gens_per_launch=400)
+    run.step(400)
+    _, cnt, srf = run.sample(300)
+    if activity == 1.0:
+        assert len(np.unique(hs.as_u32(cnt))) == 1    # every island ran every tick
+    else:
+        assert len(np.unique(hs.as_u32(cnt))) > 1
+    check_against_replay_and_oracle(hs, orc, run, cfg, cnt, srf)
+
+
+def test_pool_runs_and_resumed_runs(hs, orc):
+    cfgs = [(hs.Config(8, 8, 32, 64, "hybrid", tournament_size=2, seed=31), 430),
+            (hs.Config(6, 5, 32, 8, "steady", seed=32, differentia_bits=8, ingest_interval=3),
+             300)]
+    pool = hs.Pool(64 << 20, max_runs=4, max_gens_per_launch=64)
+    ids = {pool.admit(c, g): (c, g) for c, g in cfgs}
+    while pool.advance(64):
+        pass
+    for rid, (c, g) in ids.items():
+        pr = pool.run(rid)
+        _, cnt, srf = pr.sample(256)
+        check_against_replay_and_oracle(hs, orc, pr, c, cnt, srf)
+        # a fresh run resumed from the pool run's state rebuilt its layout
+        resumed = hs.Run(c)
+        resumed.import_state(pr.export_state())
+        _, cnt2, srf2 = resumed.sample(256)
+        check_against_replay_and_oracle(hs, orc, resumed, c, cnt2, srf2)
+        resumed.close()
+    pool.close()
+
+
+def test_errors(hs):
+    import torch
+    cfg = hs.Config(4, 4, 16, 32, "tilted", seed=3)
+    run = hs.Run(cfg)
+    run.step(10)
+    _, cnt, srf = run.sample(20)
+    ws = hs.MrcaWorkspace(32, 2)                        # too small for 20 annotations
+    lib = hs.binding.load_library()
+    lb = torch.empty((20, 20), dtype=torch.int32, device="cuda")
+    rc = lib.ga_mrca_bounds(run._h, 20, hs.binding._vp(cnt.data_ptr()),
+                            hs.binding._vp(srf.data_ptr()), hs.binding._vp(lb.data_ptr()),
+                            hs.binding._vp(lb.data_ptr()), hs.binding._vp(ws.ptr), ws.nbytes)
+    assert rc == hs.binding.GA_ENOMEM
+    rc = lib.ga_mrca_bounds(None, 20, hs.binding._vp(cnt.data_ptr()),
+                            hs.binding._vp(srf.data_ptr()), hs.binding._vp(lb.data_ptr()),
+                            hs.binding._vp(lb.data_ptr()), hs.binding._vp(ws.ptr), ws.nbytes)
+    assert rc == hs.binding.GA_EINVAL
