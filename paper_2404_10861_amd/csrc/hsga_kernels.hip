@@ -3,8 +3,10 @@
 // generation step, its batched form), and their launchers.  The end-of-run
 // queries live in hsga_query.hip.
 //
-// Device state is structure-of-arrays: trait[A], counter[A] and the S/32
-// surface word planes [S/32][A], agent a = island * N + slot.  Consecutive
+// Device state is structure-of-arrays: trait[A], the S/32 surface word
+// planes [S/32][A] and, for asynchronous runs only, counter[A] (in a
+// synchronous run every counter is the generation number), agent a =
+// island * N + slot.  Consecutive
 // lanes own consecutive agents, so every population read and write is a
 // contiguous 256-byte wavefront access per plane.
 #include "hsga_device.hpp"
@@ -437,10 +439,10 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     Lanes<APT> tr, ct, sf[SW];
     if (mine) {
         tr = load_lanes<APT>(p.in_trait + a0 + la0);
-        // the counter plane is read only by asynchronous ticks: in
-        // synchronous generations every agent's counter is the generation
-        // number (founders 0, each birth one above a parent of the same
-        // generation), so the step needs no copy of it
+        // only asynchronous runs keep a counter plane: in synchronous
+        // generations every agent's counter is the generation number
+        // (founders 0, each birth one above a parent of the same
+        // generation)
         if (ASYNC) ct = load_lanes<APT>(p.in_counter + a0 + la0);
 #pragma unroll
         for (int w = 0; w < SW; ++w) sf[w] = load_lanes<APT>(p.in_surf + w * A + a0 + la0);
