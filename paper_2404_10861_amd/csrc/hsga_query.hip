@@ -334,29 +334,95 @@ __global__ __launch_bounds__(256) void phylo_keys_kernel(uint32_t n, uint32_t np
     idx[i] = i < n ? i : 0xffffffffu;
 }
 
-// One workgroup: bitonic sort of (key, index) over npad (a power of two)
-// entries held in global memory.
-__global__ __launch_bounds__(1024) void phylo_sort_kernel(uint32_t npad,
-                                                         const uint32_t* __restrict__ ws,
-                                                         uint64_t* __restrict__ keys,
-                                                         uint32_t* __restrict__ idx) {
+// Bitonic sort of (key, index) over npad (a power of two) entries, ascending
+// by key then index.  The network is the usual one: for k = 2, 4, .., npad
+// and j = k/2, .., 1, entries i and i + j (i with bit j clear) are ordered
+// ascending where bit k of i is clear and descending where it is set.
+// Stages with j < kSortChunk stay inside aligned chunks of kSortChunk
+// entries, so each workgroup runs them in LDS: all stages of k <= the chunk
+// at once (phylo_sort_local_kernel), and for each larger k its strides
+// below the chunk after the strides at or above it, which take one launch
+// each over the whole array (phylo_sort_global_kernel).
+constexpr uint32_t kSortChunk = 2048;
+
+__device__ __forceinline__ void sort_exchange(uint64_t& ka, uint32_t& ia, uint64_t& kb,
+                                              uint32_t& ib, bool up) {
+    const bool greater = ka > kb || (ka == kb && ia > ib);
+    if (greater == up) {
+        const uint64_t tk = ka;
+        ka = kb;
+        kb = tk;
+        const uint32_t ti = ia;
+        ia = ib;
+        ib = ti;
+    }
+}
+
+// One chunk of `chunk` entries (a power of two, at most kSortChunk) per
+// workgroup of chunk / 2 threads.  k_only = 0: every stage with k <= chunk;
+// otherwise the stages j = chunk/2 .. 1 of k = k_only.
+__global__ __launch_bounds__(kSortChunk / 2) void phylo_sort_local_kernel(
+    uint32_t chunk, uint32_t k_only, const uint32_t* __restrict__ ws, uint64_t* __restrict__ keys,
+    uint32_t* __restrict__ idx) {
     if (ws[kWsStatus] != 0) return;
-    for (uint32_t k = 2; k <= npad; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = threadIdx.x; t < npad / 2; t += blockDim.x) {
-                const uint32_t i = (t / j) * 2 * j + (t % j);
-                const uint32_t l = i + j;
-                const bool up = (i & k) == 0;
-                const uint64_t ki = keys[i], kl = keys[l];
-                const uint32_t ii = idx[i], il = idx[l];
-                const bool greater = ki > kl || (ki == kl && ii > il);
-                if (greater == up) {
-                    keys[i] = kl; keys[l] = ki;
-                    idx[i] = il; idx[l] = ii;
-                }
-            }
+    __shared__ uint64_t sk[kSortChunk];
+    __shared__ uint32_t si[kSortChunk];
+    const uint32_t base = blockIdx.x * chunk;
+    const uint32_t t = threadIdx.x;
+    sk[t] = keys[base + t];
+    si[t] = idx[base + t];
+    sk[t + chunk / 2] = keys[base + t + chunk / 2];
+    si[t + chunk / 2] = idx[base + t + chunk / 2];
+    __syncthreads();
+    const uint32_t k_first = k_only ? k_only : 2u;
+    const uint32_t k_last = k_only ? k_only : chunk;
+    for (uint32_t k = k_first; k <= k_last; k <<= 1) {
+        for (uint32_t j = (k_only ? chunk : k) >> 1; j > 0; j >>= 1) {
+            const uint32_t i = (t / j) * 2 * j + (t % j);
+            const bool up = ((base + i) & k) == 0;
+            sort_exchange(sk[i], si[i], sk[i + j], si[i + j], up);
             __syncthreads();
         }
+    }
+    keys[base + t] = sk[t];
+    idx[base + t] = si[t];
+    keys[base + t + chunk / 2] = sk[t + chunk / 2];
+    idx[base + t + chunk / 2] = si[t + chunk / 2];
+}
+
+// Stage (k, j) over the whole array, one pair per thread (npad / 2 threads).
+__global__ __launch_bounds__(256) void phylo_sort_global_kernel(uint32_t npad, uint32_t k,
+                                                                uint32_t j,
+                                                                const uint32_t* __restrict__ ws,
+                                                                uint64_t* __restrict__ keys,
+                                                                uint32_t* __restrict__ idx) {
+    if (ws[kWsStatus] != 0) return;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npad / 2) return;
+    const uint32_t i = (t / j) * 2 * j + (t % j);
+    const uint32_t l = i + j;
+    uint64_t ki = keys[i], kl = keys[l];
+    uint32_t ii = idx[i], il = idx[l];
+    sort_exchange(ki, ii, kl, il, (i & k) == 0);
+    keys[i] = ki;
+    keys[l] = kl;
+    idx[i] = ii;
+    idx[l] = il;
+}
+
+void launch_phylo_sort(uint32_t npad, const uint32_t* ws, uint64_t* keys, uint32_t* idx,
+                       hipStream_t stream) {
+    if (npad < 2) return;
+    const uint32_t chunk = npad < kSortChunk ? npad : kSortChunk;
+    const uint32_t chunks = npad / chunk;
+    hipLaunchKernelGGL(phylo_sort_local_kernel, dim3(chunks), dim3(chunk / 2), 0, stream, chunk,
+                       0u, ws, keys, idx);
+    for (uint32_t k = 2 * chunk; k <= npad; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= chunk; j >>= 1)
+            hipLaunchKernelGGL(phylo_sort_global_kernel, dim3((npad / 2 + 255) / 256), dim3(256),
+                               0, stream, npad, k, j, ws, keys, idx);
+        hipLaunchKernelGGL(phylo_sort_local_kernel, dim3(chunks), dim3(chunk / 2), 0, stream,
+                           chunk, k, ws, keys, idx);
     }
 }
 
@@ -632,8 +698,7 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
                        surf, ws, ranked);
     hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
                        stream, n, (uint32_t)npad, diff_log2, ranked, ws, keys, idx);
-    hipLaunchKernelGGL(phylo_sort_kernel, dim3(1), dim3(1024), 0, stream, (uint32_t)npad, ws,
-                       keys, idx);
+    launch_phylo_sort((uint32_t)npad, ws, keys, idx, stream);
     hipLaunchKernelGGL(phylo_depth_kernel, dim3(gn), dim3(256), 0, stream, n, diff_log2, ws, keys,
                        tab, acc);
     for (uint32_t k = 1; k < levels; ++k)
