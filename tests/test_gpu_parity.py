@@ -168,6 +168,12 @@ def test_determinism_across_runs(hs):
     b.step(300)
     for x, y in zip(a.agents(), b.agents()):
         assert np.array_equal(x, y)
+    # another seed: other draws, so other traits and annotations
+    c = hs.Run(hs.Config(16, 16, 32, 64, "hybrid", seed=100))
+    c.step(300)
+    ta, _, sa = a.agents()
+    tc, _, sc = c.agents()
+    assert not np.array_equal(ta, tc) and not np.array_equal(sa, sc)
 
 
 @pytest.mark.parametrize("kind", ["steady", "tilted", "hybrid"])
