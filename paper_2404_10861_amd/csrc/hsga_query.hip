@@ -91,7 +91,9 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
     const uint32_t S = sc.S;
     const uint32_t T0 = counter[0];
     const uint64_t hz = horizon_of(sc.kind, S);
-    bool same = true, past = false;
+    // past_hz: an item past the site rule's horizon; long: more ingests
+    // than a replay may take (no limit when the run's layout is used)
+    bool same = true, past_hz = false, long_replay = false;
     // 16 loads in flight per lane before any is used
     constexpr uint32_t kBatch = 16;
     for (uint32_t k0 = lane; k0 < n; k0 += 64 * kBatch) {
@@ -105,12 +107,13 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
         for (uint32_t j = 0; j < kBatch; ++j) {
             const uint32_t ing = ingests_of(c[j], sc.interval);
             same = same && c[j] == T0;
-            past = past || ing > kMaxReplayGenerations ||
-                   (ing > 0 && (uint64_t)(ing - 1) > hz);
+            past_hz = past_hz || (ing > 0 && (uint64_t)(ing - 1) > hz);
+            long_replay = long_replay || ing > kMaxReplayGenerations;
         }
     }
-    const bool any_past = __ballot(past) != 0;
     const bool all_same = __ballot(!same) == 0;
+    const bool hinted = all_same && hint && T0 == hint_T;
+    const bool any_past = __ballot(past_hz || (!hinted && long_replay)) != 0;
     if (any_past || !all_same) {
         if (lane == 0) {
             ws[kWsStatus] = any_past ? kWsStatusHorizon : kWsStatusMixed;
@@ -118,9 +121,8 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
         }
         return;
     }
-    const uint32_t held = hint && T0 == hint_T
-                              ? (lane < S ? hint[lane] : kEmpty)
-                              : replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
+    const uint32_t held = hinted ? (lane < S ? hint[lane] : kEmpty)
+                                 : replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
     const uint32_t rank = time_rank(held, lane, S);
     const uint32_t F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
     __shared__ uint32_t times[64];

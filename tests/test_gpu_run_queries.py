@@ -145,3 +145,37 @@ def test_errors(hs):
                             hs.binding._vp(srf.data_ptr()), hs.binding._vp(lb.data_ptr()),
                             hs.binding._vp(lb.data_ptr()), hs.binding._vp(ws.ptr), ws.nbytes)
     assert rc == hs.binding.GA_EINVAL
+
+
+def test_runs_past_the_replay_bound(hs, orc):
+    """A replaying query refuses counters above 2^24 (one placement per
+    generation); the run-bound query uses the run's layout and answers.  The
+    run reaches T = 2^24 + 123 by importing a state, whose import rebuilds
+    the layout on the device."""
+    cfg = hs.Config(1, 1, 4, 64, "hybrid", seed=7)
+    T = (1 << 24) + 123
+    state = hs.Run(cfg).export_state().view(np.uint32).copy()
+    off = 4 + int(state[2]) // 4
+    A = cfg.agents
+    rng = np.random.default_rng(5)
+    state[3] = T
+    state[off + A:off + 2 * A] = T                                  # counters
+    state[off + 2 * A:off + 4 * A] = rng.integers(0, 2**32, 2 * A, dtype=np.uint64)
+    state[off + 2 * A + 1] = state[off + 2 * A]                    # two equal words
+    run = hs.Run(cfg, max_gens_per_launch=1 << 16)
+    run.import_state(state.view(np.uint8))
+    assert run.generation == T
+    assert np.array_equal(run.layout(), orc.layout(2, 64, T))
+    _, cnt, srf = run.sample(A)
+    ws = hs.MrcaWorkspace(64, A)
+    lb, ub = run.mrca_bounds(cnt, srf, workspace=ws)
+    assert hs.mrca_status(ws, run.stream) == 0
+    olb, oub = orc.mrca_allpairs(2, 64, hs.as_u32(cnt), hs.as_u32(srf))
+    assert np.array_equal(hs.as_u32(lb), olb) and np.array_equal(hs.as_u32(ub), oub)
+    tree = run.phylo_tree(cnt, srf)
+    assert tree["status"] == 0
+    assert hs.newick(tree) == orc.phylo_newick(2, 64, hs.as_u32(cnt), hs.as_u32(srf))
+    # the replaying query refuses these counters
+    ws2 = hs.MrcaWorkspace(64, A)
+    hs.mrca_bounds("hybrid", 64, cnt, srf, workspace=ws2, stream=run.stream)
+    assert hs.mrca_status(ws2, run.stream) == hs.binding.GA_EHORIZON
