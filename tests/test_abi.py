@@ -102,3 +102,18 @@ def test_config_versions_and_float_validation_without_gpu():
             hs.footprint_bytes(hs.Config(8, 8, 32, 32, "tilted", **kw))
     with pytest.raises(hs.HsgaError):
         hs.footprint_bytes(hs.Config(8, 8, 32, 32, "tilted", tournament_size=5))
+
+
+def test_checkpoint_and_run_query_arguments_without_gpu():
+    """Host-side argument checks of the checkpoint and run-bound query entry
+    points: a NULL run is refused before any device work."""
+    if not os.path.exists(LIB):
+        pytest.skip("libhsga.so not built")
+    import paper_2404_10861_amd.binding as b
+    lib = b.load_library()
+    assert lib.ga_state_bytes(None) == 0
+    assert lib.ga_export_state(None, None, 0) == b.GA_EINVAL
+    assert lib.ga_import_state(None, None, 0) == b.GA_EINVAL
+    assert lib.ga_mrca_bounds(None, 1, None, None, None, None, None, 0) == b.GA_EINVAL
+    assert b"run is NULL" in lib.ga_last_error()
+    assert lib.ga_phylo_tree(None, 1, None, None, None, None, None, None, None, 0) == b.GA_EINVAL
