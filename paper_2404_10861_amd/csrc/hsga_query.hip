@@ -227,7 +227,7 @@ __global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n, uint32_t
 // General route (counters differ): one wavefront per annotation replays its
 // own layout and stores its retained deposit generations in ascending order
 // with their sites.
-__global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc, uint32_t n,
+__global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc,
                                                          const uint32_t* __restrict__ counter,
                                                          const uint32_t* __restrict__ ws,
                                                          uint32_t* __restrict__ times,
@@ -317,7 +317,8 @@ __global__ __launch_bounds__(256) void mrca_general_pairs_kernel(
 //   pairs (a, b) meet at the shallowest boundary between them, so the sum
 //   over pairs of T - tau(MRCA) is a sum over all boundary ranges of their
 //   minimum, counted by nearest-smaller spans.
-constexpr uint32_t kPhyloOutWords = 6;   // sbl, pair sum, root, internal, status, n
+// Six result words: sum of branch lengths, pair sum, root time, internal
+// nodes, status, n.
 
 // Sort keys: rank 0 most significant (bit-reversed for one-bit
 // differentiae, byte-reversed for bytes).
@@ -739,7 +740,7 @@ hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
                        diff_log2, n, surf, ws, ranked);
     hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
                        dim3(256), 0, stream, n, diff_log2, ranked, ws, lb, ub);
-    hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, scm, n, counter, ws,
+    hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, scm, counter, ws,
                        times, sites);
     const uint32_t rows = n < kGeneralPairRows ? n : kGeneralPairRows;
     hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, rows), dim3(256), 0,
