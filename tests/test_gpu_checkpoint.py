@@ -240,3 +240,29 @@ def test_malformed_async_states_are_refused(hs):
     run.step(50)
     src.step(50)
     same_state(run, src)
+
+
+@pytest.mark.parametrize("kind,S,T", [("hybrid", 32, None), ("tilted", 32, 3_000_017),
+                                      ("steady", 64, 5_000_011), ("hybrid", 64, 4_000_037),
+                                      ("tilted", 64, 2_500_001)])
+def test_layouts_far_out_and_at_the_horizon(hs, orc, kind, S, T):
+    """The device's site rule replayed from the empty layout to a generation
+    count in the millions (or to hybrid-32's horizon) by importing a state
+    there, against the oracle's layout; then steps continue from it."""
+    k = ("steady", "tilted", "hybrid").index(kind)
+    cfg = hs.Config(1, 1, 4, S, kind, seed=9)
+    top = orc.horizon_gen(k, S, 1) + 1                   # last count a run reaches
+    if T is None:
+        T = top - 1
+    state = hs.Run(cfg).export_state().view(np.uint32).copy()
+    off = 4 + int(state[2]) // 4
+    state[3] = T
+    state[off + cfg.agents:off + 2 * cfg.agents] = T
+    run = hs.Run(cfg, max_gens_per_launch=1 << 16)
+    run.import_state(state.view(np.uint8))
+    assert np.array_equal(run.layout(), orc.layout(k, S, T))
+    run.step(1)
+    assert np.array_equal(run.layout(), orc.layout(k, S, T + 1))
+    if T + 1 == top:
+        with pytest.raises(hs.HsgaError):
+            run.step(1)
