@@ -131,12 +131,14 @@ typedef struct ga_run ga_run;
 
 /* Arena bytes needed by ga_create for this configuration; 0 if invalid.
  * max_gens_per_launch bounds the generations ga_step schedules at once
- * (0 selects the default of 4096).                                         */
+ * (0 selects the default of 4096).  Synchronous runs need no counter
+ * planes, so an asynchronous configuration needs 8 bytes per agent more. */
 size_t ga_footprint_bytes(const ga_config *cfg, uint32_t max_gens_per_launch);
 
 /* Validate cfg, carve the arena (dev_arena: device pointer, 256-byte
  * aligned, arena_bytes >= ga_footprint_bytes) and enqueue the founders on
- * hip_stream: trait 0, counter 0, all sites 0, empty layout, no outboxes.
+ * hip_stream: trait 0, counter 0 (stored only by asynchronous runs), all
+ * sites 0, empty layout, no outboxes.
  * Founders carry no differentia; generation g's births deposit item g.
  * Errors: GA_EINVAL (struct_size not 56/80/88, S * differentia_bits not 32 or
  * 64, differentia_bits not 1/8, N = 0 or > 64, empty grid, mut_lo >
