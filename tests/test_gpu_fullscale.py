@@ -72,6 +72,12 @@ def test_full_size_runs_match_oracle(hs, orc, W, H, N, S, kind, tour, G):
     sbl, pairs, root, internal, ed = orc.phylo_metrics(kinds[kind], S, cnt_h, srf_h)
     assert (got["sum_branch_length"], got["pair_sum"], got["root_time"],
             got["internal_nodes"]) == (sbl, pairs, root, internal)
+    # the benchmark's own route: the run-bound query takes the run's layout
+    rlb, rub = run.mrca_bounds(cnt, srf)
+    assert np.array_equal(hs.as_u32(rlb), olb) and np.array_equal(hs.as_u32(rub), oub)
+    rt = run.phylo_tree(cnt, srf, tree=False)
+    assert (rt["sum_branch_length"], rt["pair_sum"], rt["root_time"],
+            rt["internal_nodes"]) == (sbl, pairs, root, internal)
 
 
 def test_full_size_float_trial_matches_oracle(hs, orc):
