@@ -216,6 +216,13 @@ def main(argv=None) -> int:
                 r["mrca_pairs_per_s"] = r["mrca_pairs"] / (r["mrca_query_ms"] / 1000.0)
             if samples is not None:
                 res["cpu_baseline_query"] = cpu_baseline_query(spec_sel, *samples["selection"])
+            # the same two runs as one two-run pool (batched launches): whether
+            # a 4.2 M-agent generation alone leaves the chip room for another
+            b = benchmarks.batched_vs_plain([spec_sel, wl.c3(False)], dev,
+                                            torch.cuda.current_stream(dev))
+            res["pair_as_one_pool"] = {k: b[k] for k in (
+                "plain_sequential_replications_per_s", "batched_replications_per_s",
+                "batched_over_plain", "tuned", "all_runs_finished")}
             metric = "agent-replications/sec (treatment pair) and MRCA query time"
             value = res["selection"]["replications_per_s"]
         elif args.mode == "batched":
