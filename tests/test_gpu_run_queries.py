@@ -107,11 +107,12 @@ def test_asynchronous_runs(hs, orc, activity):
     check_against_replay_and_oracle(hs, orc, run, cfg, cnt, srf)
 
 
-def test_pool_runs_and_resumed_runs(hs, orc):
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_pool_runs_and_resumed_runs(hs, orc, use_graph):
     cfgs = [(hs.Config(8, 8, 32, 64, "hybrid", tournament_size=2, seed=31), 430),
             (hs.Config(6, 5, 32, 8, "steady", seed=32, differentia_bits=8, ingest_interval=3),
              300)]
-    pool = hs.Pool(64 << 20, max_runs=4, max_gens_per_launch=64)
+    pool = hs.Pool(64 << 20, max_runs=4, max_gens_per_launch=64, use_graph=use_graph)
     ids = {pool.admit(c, g): (c, g) for c, g in cfgs}
     while pool.advance(64):
         pass
