@@ -75,32 +75,32 @@ __device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uin
     return held;
 }
 
-// One wavefront: classify the counters; when all are equal, replay the
-// shared layout once (in ingest units), order its sites by deposit time and
-// tabulate the bounds, in generations, for every possible first-mismatch
-// rank.  A run's own layout (hint, S words in ingest units, the layout after
+// Classify the counters (four wavefronts); when all are equal, wavefront 0
+// replays the shared layout once (in ingest units), orders its sites by
+// deposit time and tabulates the bounds, in generations, for every possible
+// first-mismatch rank.  A run's own layout (hint, S words in ingest units, the layout after
 // the ingests of generation count hint_T) replaces the replay when every
 // counter is hint_T: the layout is a function of the scheme and the count
 // alone, so both give the same words.
-__global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
-                                                         const uint32_t* __restrict__ counter,
-                                                         uint32_t* __restrict__ ws,
-                                                         const uint32_t* __restrict__ hint,
-                                                         uint32_t hint_T) {
-    const uint32_t lane = threadIdx.x;
+constexpr uint32_t kPrepareThreads = 256;   // 4 wavefronts classify; wave 0 does the rest
+__global__ __launch_bounds__(kPrepareThreads) void mrca_prepare_kernel(
+    Scheme sc, uint32_t n, const uint32_t* __restrict__ counter, uint32_t* __restrict__ ws,
+    const uint32_t* __restrict__ hint, uint32_t hint_T) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
     const uint32_t S = sc.S;
     const uint32_t T0 = counter[0];
     const uint64_t hz = horizon_of(sc.kind, S);
     // past_hz: an item past the site rule's horizon; long: more ingests
     // than a replay may take (no limit when the run's layout is used)
     bool same = true, past_hz = false, long_replay = false;
-    // 16 loads in flight per lane before any is used
+    // 16 loads in flight per thread before any is used
     constexpr uint32_t kBatch = 16;
-    for (uint32_t k0 = lane; k0 < n; k0 += 64 * kBatch) {
+    for (uint32_t k0 = tid; k0 < n; k0 += kPrepareThreads * kBatch) {
         uint32_t c[kBatch];
 #pragma unroll
         for (uint32_t j = 0; j < kBatch; ++j) {
-            const uint32_t k = k0 + 64 * j;
+            const uint32_t k = k0 + kPrepareThreads * j;
             c[j] = k < n ? counter[k] : T0;
         }
 #pragma unroll
@@ -111,28 +111,42 @@ __global__ __launch_bounds__(64) void mrca_prepare_kernel(Scheme sc, uint32_t n,
             long_replay = long_replay || ing > kMaxReplayGenerations;
         }
     }
-    const bool all_same = __ballot(!same) == 0;
+    // the four wavefronts' findings, combined through LDS
+    __shared__ uint32_t flags[kPrepareThreads / 64];
+    const uint32_t f_wave = (__ballot(!same) != 0 ? 1u : 0u) | (__ballot(past_hz) != 0 ? 2u : 0u) |
+                            (__ballot(long_replay) != 0 ? 4u : 0u);
+    if (lane == 0) flags[tid >> 6] = f_wave;
+    __syncthreads();
+    uint32_t f = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kPrepareThreads / 64; ++w) f |= flags[w];
+    const bool all_same = (f & 1u) == 0;
     const bool hinted = all_same && hint && T0 == hint_T;
-    const bool any_past = __ballot(past_hz || (!hinted && long_replay)) != 0;
-    if (any_past || !all_same) {
-        if (lane == 0) {
+    const bool any_past = (f & 2u) != 0 || (!hinted && (f & 4u) != 0);
+    if (any_past || !all_same) {                 // the same decision in every thread
+        if (tid == 0) {
             ws[kWsStatus] = any_past ? kWsStatusHorizon : kWsStatusMixed;
             ws[kWsT] = T0;
         }
         return;
     }
-    const uint32_t held = hinted ? (lane < S ? hint[lane] : kEmpty)
-                                 : replay_layout(sc.kind, S, ingests_of(T0, sc.interval), lane);
-    const uint32_t rank = time_rank(held, lane, S);
-    const uint32_t F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
     __shared__ uint32_t times[64];
-    if (lane < S) {
-        const uint32_t gen = held == kEmpty ? kEmpty : held * sc.interval;   // deposit generation
-        times[rank] = gen;
-        ws[kWsPerm + rank] = lane;
-        ws[kWsTimes + rank] = gen;
+    uint32_t F = 0;
+    if (tid < 64) {                              // wavefront 0: lane = site
+        const uint32_t held = hinted ? (lane < S ? hint[lane] : kEmpty)
+                                     : replay_layout(sc.kind, S, ingests_of(T0, sc.interval),
+                                                     lane);
+        const uint32_t rank = time_rank(held, lane, S);
+        F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
+        if (lane < S) {
+            const uint32_t gen = held == kEmpty ? kEmpty : held * sc.interval;   // deposit generation
+            times[rank] = gen;
+            ws[kWsPerm + rank] = lane;
+            ws[kWsTimes + rank] = gen;
+        }
     }
     __syncthreads();
+    if (tid >= 64) return;
     // first mismatch at rank r: ub = times[r], lb = times[r-1] + 1 (0 if r = 0);
     // no mismatch (entry 64): ub = T, lb = times[F-1] + 1 (0 if F = 0)
     ws[kWsLbTab + lane] = lane == 0 ? 0u : (lane < S ? times[lane - 1] + 1u : 0u);
@@ -695,8 +709,8 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
     uint32_t levels = 1;
     while (levels < kPhyloMaxLevels && (2u << (levels - 1)) <= m) ++levels;
     const uint32_t gn = (n + 255) / 256;
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws,
-                       hint.layout, hint.T);
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(kPrepareThreads), 0, stream, scm, n,
+                       counter, ws, hint.layout, hint.T);
     hipLaunchKernelGGL(mrca_rank_kernel, dim3(gn), dim3(256), 0, stream, scm.S, diff_log2, n,
                        surf, ws, ranked);
     hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
@@ -734,8 +748,8 @@ hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
     const size_t times_bytes = ((size_t)n * S * 4 + 255) & ~(size_t)255;
     uint8_t* sites = base + MrcaWorkspace::kHeader + ranked_bytes + times_bytes;
 
-    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(64), 0, stream, scm, n, counter, ws,
-                       hint.layout, hint.T);
+    hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(kPrepareThreads), 0, stream, scm, n,
+                       counter, ws, hint.layout, hint.T);
     hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S,
                        diff_log2, n, surf, ws, ranked);
     hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
