@@ -137,6 +137,38 @@ def test_births_follow_the_step_definition(orc, W, H):
     assert total_immigrants == (G - 1) * r.I
 
 
+def test_immigrants_become_parents(orc):
+    """Immigrants overwrite members before the births (migration first), so
+    some children descend from a neighbour island's emigrant: under neutral
+    selection each birth picks any member of the island after immigration
+    with probability 1/N, so the children with a parent from another island
+    number about the immigrants written, about one per island per
+    generation (each emigrant goes to one of the four neighbours)."""
+    W, H, N, G = 4, 4, 8, 100
+    r = orc.Run(W, H, N, 32, KIND["tilted"], tournament=0, seed=13, pedigree_gens=G)
+    r.step(G)
+    foreign = 0
+    for g in range(2, G + 1):          # generation 0 has no outbox to read
+        parent, _ = r.pedigree(g)
+        foreign += int(np.sum(parent.astype(np.int64) // N != np.arange(r.A) // N))
+    expect = r.I * (G - 1)
+    assert 0.8 * expect < foreign < 1.15 * expect, (foreign, expect)
+
+
+def test_emigrant_directions_are_uniform(orc):
+    """Each generation's emigrant goes to a uniformly chosen one of the four
+    cardinal neighbours."""
+    r = orc.Run(4, 4, 8, 32, KIND["steady"], seed=17)
+    counts = np.zeros(4)
+    for _ in range(100):
+        r.step(1)
+        d = r.outbox()[0]
+        counts += np.bincount(d.astype(np.int64), minlength=4)[:4]
+    expect = counts.sum() / 4
+    chi2 = float(np.sum((counts - expect) ** 2 / expect))
+    assert chi2 < 16.27, counts     # 3 degrees of freedom, p = 0.001
+
+
 def test_mutation_statistics(orc):
     r = orc.Run(8, 8, 32, 32, 0, tournament=0, seed=21, pedigree_gens=100)
     prev_t = r.agents()[0]
