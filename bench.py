@@ -9,8 +9,9 @@ are generated on the device; the paper's workloads are synthetic too).
 
 Prints one JSON line:
   value     agent-replications/s over the timed steps (births only)
-  roofline  the step kernel's algorithmic HBM bytes per launch over its
-            average launch duration (HIP events on the run's stream);
+  roofline  the step kernel's algorithmic HBM bytes per launch (what a
+            synchronous generation must move) over its average launch
+            duration (HIP events on the run's stream);
             traffic: the HBM bytes per launch that rocprofv3 counted for
             the same code (profiles/), null once the code has changed
   cpu_baseline  the plain C oracle on a bounded sample of the same
@@ -41,21 +42,32 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_c2_traffic.json")
 
 
 def algorithmic_bytes_per_generation(spec) -> int:
-    """Read every parent record, write every child record; each island's
-    outbox entry (record + direction word) is written once and read once."""
-    rec = 8 + spec.surface_sites // 8
-    islands = spec.grid_w * spec.grid_h
-    return 2 * spec.agents * rec + 2 * islands * (rec + 4)
-
-
-def design_bytes_per_generation(spec) -> int:
-    """The bytes a synchronous step of this design has to move: trait and
-    surface words of every parent read and of every child written (there
-    is no counter plane, every counter being the generation number), and
-    each island's 16-byte outbox entry written once and read once."""
+    """The bytes one synchronous generation has to move: the trait and
+    surface words of every parent read and of every child written (a
+    record of 4 + S/8 bytes: every counter is the generation number, so
+    none is stored), and each island's 16-byte migrant entry (direction,
+    trait, surface words) written once and read once."""
     rec = 4 + spec.surface_sites // 8
     islands = spec.grid_w * spec.grid_h
     return 2 * spec.agents * rec + 2 * islands * 16
+
+
+def record_model_bytes_per_generation(spec) -> int:
+    """The same generation priced with a stored 32-bit counter in every
+    record (8 + S/8 bytes) and a 32-byte migrant entry per island: what a
+    design that keeps per-agent counters would move (asynchronous ticks
+    do)."""
+    rec = 8 + spec.surface_sites // 8
+    islands = spec.grid_w * spec.grid_h
+    return 2 * spec.agents * rec + islands * 32
+
+
+def batch_bytes_per_generation(spec) -> int:
+    """algorithmic_bytes_per_generation for any run of a batch (migrant
+    entries only when migration is on)."""
+    rec = 4 + spec.surface_sites * spec.differentia_bits // 8
+    islands = spec.grid_w * spec.grid_h
+    return 2 * spec.agents * rec + (2 * islands * 16 if spec.migrants_per_island else 0)
 
 
 def measured_traffic(spec):
@@ -166,8 +178,12 @@ def main(argv=None) -> int:
                     help="served mode: seconds of arrivals (before time scaling)")
     ap.add_argument("--no-pools", action="store_true",
                     help="plain mode: skip the batched and served summaries")
-    ap.add_argument("--served-window", type=float, default=20.0,
-                    help="plain mode: seconds of served-workload arrivals in the summary")
+    ap.add_argument("--batch-block", type=int, default=0,
+                    help="batched mode: this workgroup size instead of the autotuner's "
+                         "choice (profiling)")
+    ap.add_argument("--served-window", type=float, default=120.0,
+                    help="plain mode: seconds of served-workload arrivals in the summary "
+                         "(default: the whole 120 s request list)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -226,11 +242,21 @@ def main(argv=None) -> int:
             metric = "agent-replications/sec (treatment pair) and MRCA query time"
             value = res["selection"]["replications_per_s"]
         elif args.mode == "batched":
-            res = benchmarks.batched_vs_plain(wl.c4(), dev, torch.cuda.current_stream(dev))
+            specs = wl.c4_saved()
+            if args.generations:          # profiling: shorter runs of the same set
+                for sp in specs:
+                    sp.generations = args.generations
+            stream = torch.cuda.current_stream(dev)
+            copy_gbs = attainable_copy_gbs(torch, hs, dev, stream)
+            res = benchmarks.batched_vs_plain(specs, dev, stream, tune=not args.batch_block,
+                                              block_threads=args.batch_block or 256)
+            res["algorithmic_bytes_per_generation"] = sum(
+                batch_bytes_per_generation(sp) for sp in specs)
+            res["attainable_copy_GBs"] = copy_gbs
             metric = "agent-replications/sec (batched vs sequential plain)"
             value = res["batched_replications_per_s"]
         else:
-            reqs = wl.c5(duration=args.duration)
+            reqs = wl.c5_saved(duration=args.duration)
             res = benchmarks.served_vs_plain(
                 reqs, dev, time_scale=args.time_scale, plain=not args.no_plain,
                 progress=lambda text: print(text, file=sys.stderr, flush=True))
@@ -299,7 +325,7 @@ def main(argv=None) -> int:
     reps = spec.agents * spec.generations * args.steps
     value = reps / elapsed
     bytes_per_launch = algorithmic_bytes_per_generation(spec)
-    design_bytes = design_bytes_per_generation(spec)
+    record_bytes = record_model_bytes_per_generation(spec)
     avg_launch_s = kern_ms / 1000.0 / max(launches, 1)
     achieved_gbs = bytes_per_launch / avg_launch_s / 1e9
     traffic = measured_traffic(spec)
@@ -337,14 +363,15 @@ def main(argv=None) -> int:
             "kernel": "step_kernel<2, kBirthIntTournament, migration, 4 agents per thread>",
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "bytes_per_replication": bytes_per_launch / spec.agents,
             "attainable_copy_GBs": copy_gbs,
             "frac_of_attainable": achieved_gbs / copy_gbs,
-            "note": "algorithmic bytes count 16-byte records (trait, counter, 64 sites) read "
-                    "and written; a synchronous step keeps no counter plane, so it moves the "
-                    "design bytes below, and rocprofv3 counts the traffic",
-            "design_bytes_per_launch": design_bytes,
-            "design_GBs": design_bytes / avg_launch_s / 1e9,
-            "design_frac_of_attainable": design_bytes / avg_launch_s / 1e9 / copy_gbs,
+            "note": "algorithmic bytes: 12-byte records (trait, 64 one-bit sites; every "
+                    "counter is the generation number) read and written, and one 16-byte "
+                    "migrant entry written and read per island; record_model_* prices a "
+                    "stored counter and 32-byte entries, which this step does not move",
+            "record_model_bytes_per_launch": record_bytes,
+            "record_model_GBs": record_bytes / avg_launch_s / 1e9,
             "traffic_GBs": traffic / avg_launch_s / 1e9 if traffic else None,
             "traffic_frac_of_attainable":
                 traffic / avg_launch_s / 1e9 / copy_gbs if traffic else None,
@@ -373,8 +400,8 @@ def pool_summary(torch, dev, stream, window_s: float) -> dict:
     the same requests, with p50/p99 run latency."""
     from paper_2404_10861_amd import benchmarks
     from paper_2404_10861_amd import workloads as wl
-    b = benchmarks.batched_vs_plain(wl.c4(), dev, stream)
-    reqs = wl.c5(duration=window_s)
+    b = benchmarks.batched_vs_plain(wl.c4_saved(), dev, stream)
+    reqs = wl.c5_saved(duration=window_s)
     v = benchmarks.served_vs_plain(
         reqs, dev, progress=lambda text: print(text, file=sys.stderr, flush=True))
     return {
@@ -385,17 +412,22 @@ def pool_summary(torch, dev, stream, window_s: float) -> dict:
             "batched_over_plain": b["batched_over_plain"],
         },
         "served": {
-            "workload": f"{len(reqs)} requests arriving over {window_s:g} s (the served "
-                        "workload's first arrivals)",
+            "workload": f"{len(reqs)} requests arriving over {window_s:g} s in real time "
+                        "(Poisson, 20/s; the saved served request list)",
+            "offered_replications_per_s": v["offered_replications_per_s"],
             "replications_per_s": v["served"]["replications_per_s"],
             "latency_p50_s": v["served"]["latency_p50_s"],
             "latency_p99_s": v["served"]["latency_p99_s"],
+            "plain_replications_per_s": v["plain_fifo"]["replications_per_s"],
             "plain_latency_p50_s": v["plain_fifo"]["latency_p50_s"],
             "plain_latency_p99_s": v["plain_fifo"]["latency_p99_s"],
             "served_over_plain_throughput": v["served_over_plain_throughput"],
-            "note": "real-time arrivals offer less work than either server can do, so both "
-                    "keep up (throughput ratio 1) and the served loop's gain is its latency; "
-                    "saturated (--mode served --time-scale 0.1) it also does more work",
+            "served_over_plain_p99_latency": v["plain_fifo"]["latency_p99_s"] /
+                                             v["served"]["latency_p99_s"],
+            "note": "both servers complete the offered load as it arrives, so their "
+                    "throughputs over the window are the offered load (ratio near 1); the "
+                    "served loop's gain at this load is latency.  Saturated arrivals "
+                    "(--mode served --time-scale 0.1) measure the throughput gain",
         },
     }
 

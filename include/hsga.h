@@ -103,10 +103,8 @@ typedef struct ga_config {
     uint32_t async_activity;      /* 0: synchronous generations.  Otherwise
                                      asynchronous ticks: on each tick an
                                      island runs a generation with
-                                     probability async_activity / 2^32, agents
-                                     keep their own counters, and a run may
-                                     take at most max_gens_per_launch ticks
-                                     in total (its site table)                */
+                                     probability async_activity / 2^32 and
+                                     agents keep their own counters          */
     uint32_t reserved;            /* must be 0                                 */
 } ga_config;
 
@@ -123,16 +121,19 @@ typedef struct ga_run ga_run;
  *   - two ping-pong outboxes, 32 bytes reserved per island (a synchronous
  *     run's entry uses 16: direction, trait, surface words, since every
  *     emigrant's counter is the generation count);
- *   - the run's surface layout (deposit time of each site) and a site
- *     schedule of max_gens_per_launch words.
+ *   - the run's surface layout (deposit time of each site) and, for a
+ *     synchronous run, a site schedule of max_gens_per_launch words (an
+ *     asynchronous run holds the site rule's constant-time tables there,
+ *     about 19 KB).
  * An agent record is (uint32 trait, uint32 generation counter, S one-bit
  * differentia sites); site k is bit k&31 of surface word k>>5.
  * ------------------------------------------------------------------------ */
 
 /* Arena bytes needed by ga_create for this configuration; 0 if invalid.
  * max_gens_per_launch bounds the generations ga_step schedules at once
- * (0 selects the default of 4096).  Synchronous runs need no counter
- * planes, so an asynchronous configuration needs 8 bytes per agent more. */
+ * (0 selects the default of 4096; asynchronous runs ignore it).
+ * Synchronous runs need no counter planes, so an asynchronous configuration
+ * needs 8 bytes per agent more. */
 size_t ga_footprint_bytes(const ga_config *cfg, uint32_t max_gens_per_launch);
 
 /* Validate cfg, carve the arena (dev_arena: device pointer, 256-byte
@@ -161,11 +162,14 @@ int ga_create(const ga_config *cfg, void *dev_arena, size_t arena_bytes,
  * islands run their own loops and drift apart) advance n ticks instead: an
  * island active on a tick takes the emigrants its neighbours posted on the
  * previous tick and breeds, each birth depositing at the site its parent's
- * own counter selects (an O(1) lookup in the run's site table); an idle
- * island keeps its members and posts nothing.
+ * own counter selects (a constant-time lookup in the site rule's tables,
+ * the same sites as hstrat_sites); an idle island keeps its members and
+ * posts nothing.
  * Errors: GA_EHORIZON if generation (tick) T + n - 1 is past the site
- * rule's horizon (nothing is enqueued), GA_EINVAL if an asynchronous run
- * would pass max_gens_per_launch ticks, GA_EDEVICE.                       */
+ * rule's horizon (nothing is enqueued), GA_EINVAL if run is a pool's
+ * (pools advance with ga_pool_advance), GA_EDEVICE.  After GA_EDEVICE some of the n
+ * generations may be enqueued and the run's state is undefined: ga_step
+ * refuses the run (GA_EDEVICE) until ga_import_state replaces its state.  */
 int ga_step(ga_run *run, uint32_t n);
 
 /* Block until all work enqueued for the run has finished. */
@@ -238,19 +242,22 @@ int ga_export_state(ga_run *run, void *host, size_t bytes);
 /* Blocking: replace the state of run, which must have been created with
  * the configuration the state was exported under (compared byte for byte
  * after validation; max_gens_per_launch may differ), by the state in host.
- * The layout and, for asynchronous runs, the site table are rebuilt by
- * replaying the site rule up to T.  The state is checked before anything
+ * The layout is rebuilt from the site rule's closed form at T (a function
+ * of the scheme and T alone).  The state is checked before anything
  * is written: every counter must equal T (synchronous) or be at most T
  * (asynchronous), every outbox direction must be 0..4 and every
  * asynchronous outbox counter at most T.
+ * A successful import also clears the refusal that a failed ga_step left.
  * Errors: GA_EINVAL (NULL or misaligned buffer, size, format or
- * configuration mismatch, a counter or direction outside those ranges, an
- * asynchronous T above the run's max_gens_per_launch, a run of a pool),
+ * configuration mismatch, a counter or direction outside those ranges, a
+ * run of a pool),
  * GA_EHORIZON (T past the site rule's horizon + 1), GA_EDEVICE.             */
 int ga_import_state(ga_run *run, const void *host, size_t bytes);
 
 /* Release the host handle.  Does not free (or touch) the arena; work still
- * enqueued on the stream keeps using it, so sync first when reusing it.    */
+ * enqueued on the stream keeps using it, so sync first when reusing it.
+ * A handle of a pool's run (ga_pool_run) is left alone: ga_pool_release
+ * frees it; the call only records that error for ga_last_error().          */
 void ga_destroy(ga_run *run);
 
 /* Text of the calling thread's last failure ("" if none). */
@@ -310,6 +317,43 @@ int hstrat_mrca_bounds_ex(const hstrat_scheme *scheme, uint32_t n,
                           const uint32_t *counter, const uint32_t *surface_words,
                           uint32_t *lb, uint32_t *ub, void *workspace,
                           size_t workspace_bytes, void *hip_stream);
+
+/* Host, constant time per site: the deposit generation held by each of the
+ * scheme's sites in an annotation with counter T (Distributed Phylogenetic
+ * Tracking: deposit times follow from the site index and the generation
+ * count alone; Surface-based Hereditary Stratigraphy Algorithms: the
+ * surface is indexed in constant time), GA_EMPTY_SITE for a site not
+ * filled yet.  layout: host, sites words.  The same layout as replaying the
+ * placements from the empty surface, computed from per-epoch tables of the
+ * rule (built once per surface kind and size) in O(sites).
+ * The differentia width does not enter, so any surface of 2..64 sites is
+ * accepted (hybrid: an even number, at least 4).
+ * Errors: GA_EINVAL (kind, sites, interval 0, NULL), GA_EHORIZON (T holds
+ * an item past the horizon).                                               */
+int hstrat_layout(const hstrat_scheme *scheme, uint32_t T, uint32_t *layout);
+
+/* Host, constant time per item: the site that each of the rule's items
+ * tau0 .. tau0 + n - 1 (ingest units: item tau is deposited at generation
+ * tau * ingest_interval) is written to, into sites (host, n words).  The
+ * same sites as placing every earlier item in turn; an asynchronous run's
+ * births look sites up this way on the device.  Surfaces as for
+ * hstrat_layout.  Errors: GA_EINVAL, GA_EHORIZON (an item past the
+ * horizon).                                                                */
+int hstrat_sites(const hstrat_scheme *scheme, uint32_t tau0, uint32_t n, uint32_t *sites);
+
+/* Host: the MRCA-generation bounds of one pair of one-bit annotations
+ * deposited every generation (Distributed Phylogenetic Tracking: two
+ * annotations' mismatching differentiae delimit their common ancestry), by
+ * the definition above, with the layouts of hstrat_layout.  sa, sb: host,
+ * S/32 surface words each; lb, ub: host, one word each.
+ * Errors: GA_EINVAL (kind, S, NULL), GA_EHORIZON.                          */
+int hstrat_mrca_bounds_pair(uint32_t kind, uint32_t S, uint32_t Ta, const uint32_t *sa,
+                            uint32_t Tb, const uint32_t *sb, uint32_t *lb, uint32_t *ub);
+
+/* hstrat_mrca_bounds_pair for any annotation scheme (sa, sb: W = sites *
+ * differentia_bits / 32 words each).                                       */
+int hstrat_mrca_bounds_pair_ex(const hstrat_scheme *scheme, uint32_t Ta, const uint32_t *sa,
+                               uint32_t Tb, const uint32_t *sb, uint32_t *lb, uint32_t *ub);
 
 /* Blocking: status of the last hstrat_mrca_bounds run on this workspace
  * (GA_OK, or GA_EHORIZON when a counter was past the horizon, in which

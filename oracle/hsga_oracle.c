@@ -29,10 +29,11 @@
  *     invariants and the pedigree.
  *   - The MRCA bounds are pinned against the true pedigree on tiny runs.
  *
- * Build:  gcc -O2 -std=c11 -ffp-contract=off -shared -fPIC -o liboracle.so
+ * Build:  gcc -O2 -std=c11 -ffp-contract=off -pthread -shared -fPIC -o liboracle.so
  *         hsga_oracle.c -lm
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -353,6 +354,11 @@ static float f32_of(uint32_t u)
  * Genome Model).  Islands sit on a W x H torus, island i = y*W + x, agent
  * a = i*N + j.  An agent record is (trait, generation counter, S one-bit
  * differentia sites); site k is bit k&31 of surface word k>>5.              */
+/* One island's members during a step (after immigration): N records. */
+typedef struct {
+    uint32_t *trait, *counter, *surf, *src;
+} orc_island;
+
 typedef struct {
     uint32_t W, H, N, S, kind, tournament, mut_thr, mut_span, migrants;
     int32_t mut_lo;
@@ -381,8 +387,11 @@ typedef struct {
     uint32_t ped_gens;
     uint32_t *ped_parent;             /* (ped_gens) * A                        */
     uint8_t *ped_bit;                 /* (ped_gens) * A                        */
-    /* scratch */
-    uint32_t *q_trait, *q_counter, *q_surf, *q_src;
+    /* scratch: one island's members (q; one per thread when threaded) and
+     * the next population (n_*)                                           */
+    orc_island q;
+    uint32_t threads;                 /* island-parallel threads (0, 1: none) */
+    orc_island *tq;                   /* threads x island scratch             */
     uint32_t *n_trait, *n_counter, *n_surf, *n_src;
 } orc_run;
 
@@ -403,6 +412,19 @@ static uint32_t opposite(uint32_t d)
     return d ^ 1u;   /* north<->south, west<->east */
 }
 
+static int island_alloc(orc_island *q, uint32_t N, uint32_t SW)
+{
+    q->trait = calloc(N, 4); q->counter = calloc(N, 4);
+    q->surf = calloc((size_t)N * SW, 4); q->src = calloc(N, 4);
+    return q->trait && q->counter && q->surf && q->src;
+}
+
+static void island_free(orc_island *q)
+{
+    free(q->trait); free(q->counter); free(q->surf); free(q->src);
+    q->trait = q->counter = q->surf = q->src = NULL;
+}
+
 void orc_destroy(void *handle)
 {
     orc_run *r = (orc_run *)handle;
@@ -413,7 +435,11 @@ void orc_destroy(void *handle)
     free(r->ob_src);
     free(r->tab);
     free(r->ped_parent); free(r->ped_bit);
-    free(r->q_trait); free(r->q_counter); free(r->q_surf); free(r->q_src);
+    island_free(&r->q);
+    if (r->tq)
+        for (uint32_t k = 0; k < r->threads; k++)
+            island_free(&r->tq[k]);
+    free(r->tq);
     free(r->n_trait); free(r->n_counter); free(r->n_surf); free(r->n_src);
     free(r);
 }
@@ -473,13 +499,12 @@ void *orc_create_ex(uint32_t W, uint32_t H, uint32_t N, uint32_t S, uint32_t kin
     r->ob_dir = calloc(I, 4); r->ob_trait = calloc(I, 4);
     r->ob_counter = calloc(I, 4); r->ob_surf = calloc(I * SW, 4);
     r->ob_src = calloc(I, 4);
-    r->q_trait = calloc(N, 4); r->q_counter = calloc(N, 4);
-    r->q_surf = calloc(N * SW, 4); r->q_src = calloc(N, 4);
+    int q_ok = island_alloc(&r->q, N, (uint32_t)SW);
     r->n_trait = calloc(A, 4); r->n_counter = calloc(A, 4);
     r->n_surf = calloc(A * SW, 4); r->n_src = calloc(A, 4);
     if (!r->trait || !r->counter || !r->surf || !r->src || !r->ob_dir ||
         !r->ob_trait || !r->ob_counter || !r->ob_surf || !r->ob_src ||
-        !r->q_trait || !r->q_counter || !r->q_surf || !r->q_src ||
+        !q_ok ||
         !r->n_trait || !r->n_counter || !r->n_surf || !r->n_src) {
         orc_destroy(r);
         return NULL;
@@ -563,8 +588,8 @@ int orc_set_fitness(void *handle, uint32_t model, uint32_t tournament,
  * tick in asynchronous ones), reading the island's members Q: the parent's
  * index in Q, the child's trait word and the differentia drawn (the low
  * `bits` bits of the drawn word).                                          */
-static void draw_birth(orc_run *r, uint32_t i, uint32_t j, uint32_t g, uint32_t *p_out,
-                       uint32_t *trait_out, uint32_t *val_out)
+static void draw_birth(const orc_run *r, const orc_island *q, uint32_t i, uint32_t j,
+                       uint32_t g, uint32_t *p_out, uint32_t *trait_out, uint32_t *val_out)
 {
     const uint32_t N = r->N;
     uint32_t w[4], p, child_trait, bit;
@@ -572,19 +597,19 @@ static void draw_birth(orc_run *r, uint32_t i, uint32_t j, uint32_t g, uint32_t 
     if (r->model == ORC_FOUNDER_TAG) {
         /* neutral; the tag is inherited unchanged */
         p = orc_mulhi(w[0], N);
-        child_trait = r->q_trait[p];
+        child_trait = q->trait[p];
         bit = w[3];
     } else if (r->model == ORC_INT_TRAIT) {
         p = orc_mulhi(w[0], N);
         if (r->tournament == 2) {
             uint32_t b = orc_mulhi(w[1], N);
-            if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])
+            if ((int32_t)q->trait[b] > (int32_t)q->trait[p])
                 p = b;
         }
         uint32_t delta = 0;
         if (w[2] < r->mut_thr)
             delta = (uint32_t)((int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo);
-        child_trait = r->q_trait[p] + delta;
+        child_trait = q->trait[p] + delta;
         bit = w[3];
     } else {
         /* float treatments: candidates from words w0..w3, v0; the
@@ -597,11 +622,11 @@ static void draw_birth(orc_run *r, uint32_t i, uint32_t j, uint32_t g, uint32_t 
         p = orc_mulhi(words[0], N);
         for (uint32_t c = 1; c < k; c++) {
             uint32_t b = orc_mulhi(words[c], N);
-            if (f32_of(r->q_trait[b]) > f32_of(r->q_trait[p]))
+            if (f32_of(q->trait[b]) > f32_of(q->trait[p]))
                 p = b;
         }
-        double f = (double)f32_of(r->q_trait[p]);
-        child_trait = r->q_trait[p];
+        double f = (double)f32_of(q->trait[p]);
+        child_trait = q->trait[p];
         if (v[1] < r->del_thr)
             child_trait = f32_bits((float)(f - (double)r->del_sigma *
                                                   orc_half_normal(v[2], v[3])));
@@ -613,6 +638,159 @@ static void draw_birth(orc_run *r, uint32_t i, uint32_t j, uint32_t g, uint32_t 
     *p_out = p;
     *trait_out = child_trait;
     *val_out = bit & (r->bits == 8 ? 0xffu : 1u);
+}
+
+/* Island i of generation g: its members of P_g (and the immigrants
+ * addressed to it) into the scratch q, then its N births into the next
+ * population (n_*).  Reads only P_g and O_g, writes only island i's slots
+ * of the next population and of the pedigree, so islands are independent
+ * within a generation.  Returns 0, or -2 on a broken invariant.           */
+static int breed_island(orc_run *r, orc_island *q, uint32_t i, uint32_t g, int site,
+                        int ingest)
+{
+    const uint32_t N = r->N, SW = r->SW;
+    uint32_t w[4];
+    /* Q := this island's members of P_g */
+    for (uint32_t j = 0; j < N; j++) {
+        uint32_t a = i * N + j;
+        q->trait[j] = r->trait[a];
+        q->counter[j] = r->counter[a];
+        for (uint32_t s = 0; s < SW; s++)
+            q->surf[j * SW + s] = r->surf[(size_t)a * SW + s];
+        q->src[j] = a;
+    }
+
+    /* Immigration: each neighbour's emigrant that was sent our way
+     * replaces a randomly chosen member; applied north, south, west,
+     * east.  Genomes are copied, not moved.                             */
+    if (r->migrants && r->has_outbox) {
+        orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);
+        for (uint32_t d = 0; d < 4; d++) {
+            uint32_t nb = neighbour(r, i, d);
+            if (r->ob_dir[nb] == opposite(d)) {
+                uint32_t slot = orc_mulhi(w[d], N);
+                q->trait[slot] = r->ob_trait[nb];
+                q->counter[slot] = r->ob_counter[nb];
+                for (uint32_t s = 0; s < SW; s++)
+                    q->surf[slot * SW + s] = r->ob_surf[(size_t)nb * SW + s];
+                q->src[slot] = r->ob_src[nb];
+            }
+        }
+    }
+
+    /* Births: each slot of the next generation gets a parent by
+     * tournament selection (the higher trait of two uniform draws; a tie
+     * keeps the first draw) or, when neutral, by one uniform draw; the
+     * child copies the parent's record, mutates its trait with
+     * probability mut_thr / 2^32 by a uniform integer in
+     * [mut_lo, mut_hi], increments the generation counter, and writes a
+     * fresh one-bit differentia at this generation's site.              */
+    for (uint32_t j = 0; j < N; j++) {
+        uint32_t a = i * N + j;
+        uint32_t p, child_trait, bit;
+        draw_birth(r, q, i, j, g, &p, &child_trait, &bit);
+        uint32_t T = q->counter[p];
+        if (T != g)
+            return -2;
+        r->n_trait[a] = child_trait;
+        r->n_counter[a] = T + 1;
+        for (uint32_t s = 0; s < SW; s++)
+            r->n_surf[(size_t)a * SW + s] = q->surf[p * SW + s];
+        if (ingest) {
+            uint32_t per_word = 32 / r->bits;
+            uint32_t shift = ((uint32_t)site % per_word) * r->bits;
+            uint32_t mask = (r->bits == 8 ? 0xffu : 1u) << shift;
+            uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / per_word];
+            *word = (*word & ~mask) | (bit << shift);
+        }
+        r->n_src[a] = q->src[p];
+        if (g < r->ped_gens) {
+            r->ped_parent[(size_t)g * r->A + a] = q->src[p];
+            r->ped_bit[(size_t)g * r->A + a] = (uint8_t)bit;
+        }
+    }
+    return 0;
+}
+
+/* Island-parallel births, used to time the oracle on many host cores:
+ * the islands are split into contiguous ranges, one per thread, each thread
+ * with its own island scratch; joining the threads is the one barrier per
+ * generation.  Islands are independent within a generation (breed_island),
+ * so the result is the serial one.                                         */
+#define ORC_MAX_THREADS 256
+
+typedef struct {
+    orc_run *r;
+    orc_island *q;
+    uint32_t i0, i1, g;
+    int site, ingest, rc;
+} orc_task;
+
+static void *breed_range(void *arg)
+{
+    orc_task *t = (orc_task *)arg;
+    for (uint32_t i = t->i0; i < t->i1 && t->rc == 0; i++)
+        t->rc = breed_island(t->r, t->q, i, t->g, t->site, t->ingest);
+    return NULL;
+}
+
+static int breed_threaded(orc_run *r, uint32_t g, int site, int ingest)
+{
+    const uint32_t n = r->threads;
+    pthread_t tid[ORC_MAX_THREADS];
+    int started[ORC_MAX_THREADS];
+    orc_task task[ORC_MAX_THREADS];
+    for (uint32_t k = 0; k < n; k++) {
+        task[k].r = r;
+        task[k].q = &r->tq[k];
+        task[k].i0 = (uint32_t)((uint64_t)r->I * k / n);
+        task[k].i1 = (uint32_t)((uint64_t)r->I * (k + 1) / n);
+        task[k].g = g;
+        task[k].site = site;
+        task[k].ingest = ingest;
+        task[k].rc = 0;
+        started[k] = pthread_create(&tid[k], NULL, breed_range, &task[k]) == 0;
+        if (!started[k])
+            breed_range(&task[k]);   /* no thread: this range in the caller */
+    }
+    int rc = 0;
+    for (uint32_t k = 0; k < n; k++) {
+        if (started[k])
+            pthread_join(tid[k], NULL);
+        if (rc == 0)
+            rc = task[k].rc;
+    }
+    return rc;
+}
+
+/* Breed synchronous generations on `threads` host threads (0 or 1: one).
+ * Asynchronous ticks stay serial.  Returns 0, or -1 if invalid or out of
+ * memory.                                                                  */
+int orc_set_threads(void *handle, uint32_t threads)
+{
+    orc_run *r = (orc_run *)handle;
+    if (threads > ORC_MAX_THREADS)
+        return -1;
+    if (r->tq) {
+        for (uint32_t k = 0; k < r->threads; k++)
+            island_free(&r->tq[k]);
+        free(r->tq);
+        r->tq = NULL;
+    }
+    r->threads = 0;
+    if (threads <= 1)
+        return 0;
+    r->tq = (orc_island *)calloc(threads, sizeof(orc_island));
+    if (!r->tq)
+        return -1;
+    r->threads = threads;
+    for (uint32_t k = 0; k < threads; k++) {
+        if (!island_alloc(&r->tq[k], r->N, r->SW)) {
+            orc_set_threads(handle, 0);
+            return -1;
+        }
+    }
+    return 0;
 }
 
 /* One generation, (P_g, O_g) -> (P_{g+1}, O_{g+1}), island by island, in the
@@ -642,65 +820,15 @@ static int step_one(orc_run *r)
             return -1;
     }
 
-    for (uint32_t i = 0; i < r->I; i++) {
-        /* Q := this island's members of P_g */
-        for (uint32_t j = 0; j < N; j++) {
-            uint32_t a = i * N + j;
-            r->q_trait[j] = r->trait[a];
-            r->q_counter[j] = r->counter[a];
-            for (uint32_t s = 0; s < SW; s++)
-                r->q_surf[j * SW + s] = r->surf[(size_t)a * SW + s];
-            r->q_src[j] = a;
-        }
-
-        /* Immigration: each neighbour's emigrant that was sent our way
-         * replaces a randomly chosen member; applied north, south, west,
-         * east.  Genomes are copied, not moved.                             */
-        if (r->migrants && r->has_outbox) {
-            orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);
-            for (uint32_t d = 0; d < 4; d++) {
-                uint32_t nb = neighbour(r, i, d);
-                if (r->ob_dir[nb] == opposite(d)) {
-                    uint32_t slot = orc_mulhi(w[d], N);
-                    r->q_trait[slot] = r->ob_trait[nb];
-                    r->q_counter[slot] = r->ob_counter[nb];
-                    for (uint32_t s = 0; s < SW; s++)
-                        r->q_surf[slot * SW + s] = r->ob_surf[(size_t)nb * SW + s];
-                    r->q_src[slot] = r->ob_src[nb];
-                }
-            }
-        }
-
-        /* Births: each slot of the next generation gets a parent by
-         * tournament selection (the higher trait of two uniform draws; a tie
-         * keeps the first draw) or, when neutral, by one uniform draw; the
-         * child copies the parent's record, mutates its trait with
-         * probability mut_thr / 2^32 by a uniform integer in
-         * [mut_lo, mut_hi], increments the generation counter, and writes a
-         * fresh one-bit differentia at this generation's site.              */
-        for (uint32_t j = 0; j < N; j++) {
-            uint32_t a = i * N + j;
-            uint32_t p, child_trait, bit;
-            draw_birth(r, i, j, g, &p, &child_trait, &bit);
-            uint32_t T = r->q_counter[p];
-            if (T != g)
-                return -2;
-            r->n_trait[a] = child_trait;
-            r->n_counter[a] = T + 1;
-            for (uint32_t s = 0; s < SW; s++)
-                r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];
-            if (ingest) {
-                uint32_t per_word = 32 / r->bits;
-                uint32_t shift = ((uint32_t)site % per_word) * r->bits;
-                uint32_t mask = (r->bits == 8 ? 0xffu : 1u) << shift;
-                uint32_t *word = &r->n_surf[(size_t)a * SW + (uint32_t)site / per_word];
-                *word = (*word & ~mask) | (bit << shift);
-            }
-            r->n_src[a] = r->q_src[p];
-            if (g < r->ped_gens) {
-                r->ped_parent[(size_t)g * r->A + a] = r->q_src[p];
-                r->ped_bit[(size_t)g * r->A + a] = (uint8_t)bit;
-            }
+    if (r->threads > 1) {
+        int rc = breed_threaded(r, g, site, ingest);
+        if (rc)
+            return rc;
+    } else {
+        for (uint32_t i = 0; i < r->I; i++) {
+            int rc = breed_island(r, &r->q, i, g, site, ingest);
+            if (rc)
+                return rc;
         }
     }
 
@@ -789,6 +917,7 @@ int orc_set_async(void *handle, uint32_t activity)
 static int step_async(orc_run *r)
 {
     const uint32_t N = r->N, SW = r->SW, k = r->g;
+    orc_island *q = &r->q;
     uint32_t w[4];
     if ((uint64_t)k > orc_horizon_gen(r->kind, r->S, r->interval))
         return -1;
@@ -817,11 +946,11 @@ static int step_async(orc_run *r)
         }
         for (uint32_t j = 0; j < N; j++) {
             uint32_t a = i * N + j;
-            r->q_trait[j] = r->trait[a];
-            r->q_counter[j] = r->counter[a];
+            q->trait[j] = r->trait[a];
+            q->counter[j] = r->counter[a];
             for (uint32_t s = 0; s < SW; s++)
-                r->q_surf[j * SW + s] = r->surf[(size_t)a * SW + s];
-            r->q_src[j] = a;
+                q->surf[j * SW + s] = r->surf[(size_t)a * SW + s];
+            q->src[j] = a;
         }
         /* immigrants posted on the previous tick toward this island */
         if (r->migrants && r->has_outbox) {
@@ -830,23 +959,23 @@ static int step_async(orc_run *r)
                 uint32_t nb = neighbour(r, i, d);
                 if (r->ob_dir[nb] == opposite(d)) {
                     uint32_t slot = orc_mulhi(w[d], N);
-                    r->q_trait[slot] = r->ob_trait[nb];
-                    r->q_counter[slot] = r->ob_counter[nb];
+                    q->trait[slot] = r->ob_trait[nb];
+                    q->counter[slot] = r->ob_counter[nb];
                     for (uint32_t s = 0; s < SW; s++)
-                        r->q_surf[slot * SW + s] = r->ob_surf[(size_t)nb * SW + s];
-                    r->q_src[slot] = r->ob_src[nb];
+                        q->surf[slot * SW + s] = r->ob_surf[(size_t)nb * SW + s];
+                    q->src[slot] = r->ob_src[nb];
                 }
             }
         }
         for (uint32_t j = 0; j < N; j++) {
             uint32_t a = i * N + j;
             uint32_t p, child_trait, bit;
-            draw_birth(r, i, j, k, &p, &child_trait, &bit);
-            uint32_t T = r->q_counter[p];
+            draw_birth(r, q, i, j, k, &p, &child_trait, &bit);
+            uint32_t T = q->counter[p];
             r->n_trait[a] = child_trait;
             r->n_counter[a] = T + 1;
             for (uint32_t s = 0; s < SW; s++)
-                r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];
+                r->n_surf[(size_t)a * SW + s] = q->surf[p * SW + s];
             if (T % r->interval == 0) {
                 int site = site_of(r, T / r->interval);
                 if (site < 0) {
@@ -860,7 +989,7 @@ static int step_async(orc_run *r)
                 *word = (*word & ~mask) | (bit << shift);
             }
             if (k < r->ped_gens) {
-                r->ped_parent[(size_t)k * r->A + a] = r->q_src[p];
+                r->ped_parent[(size_t)k * r->A + a] = q->src[p];
                 r->ped_bit[(size_t)k * r->A + a] = (uint8_t)bit;
             }
         }

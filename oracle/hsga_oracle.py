@@ -35,7 +35,7 @@ u8p = ctypes.POINTER(ctypes.c_uint8)
 
 def build() -> str:
     """Compile the oracle (plain C, -O2, scalar) into liboracle.so."""
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-Wall", "-Wextra", "-shared",
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-pthread", "-Wall", "-Wextra", "-shared",
            "-fPIC", "-o", LIB + ".tmp", SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
@@ -77,6 +77,8 @@ def load():
     lib.orc_create_ex.restype = ctypes.c_void_p
     lib.orc_set_async.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
     lib.orc_set_async.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    lib.orc_set_threads.restype = ctypes.c_int
     lib.orc_horizon_gen.argtypes = [ctypes.c_uint32] * 3
     lib.orc_horizon_gen.restype = ctypes.c_uint64
     lib.orc_mrca_rows_x.argtypes = ([ctypes.c_uint32] * 5 + [u32p, u32p, ctypes.c_uint32, u32p,
@@ -202,7 +204,7 @@ class Run:
     def __init__(self, W, H, N, S, kind, tournament=2, mut_thr=42949672,
                  mut_lo=-8, mut_hi=8, migrants=1, seed=1, pedigree_gens=0,
                  fitness_model=INT_TRAIT, del_thr=0, ben_thr=0, del_sigma=1.0,
-                 ben_sigma=1.0, bits=1, interval=1, activity=0):
+                 ben_sigma=1.0, bits=1, interval=1, activity=0, threads=0):
         lib = load()
         h = lib.orc_create_ex(W, H, N, S, kind,
                               tournament if fitness_model == INT_TRAIT else 0,
@@ -218,6 +220,9 @@ class Run:
         if lib.orc_set_async(h, activity):
             self.close()
             raise ValueError("invalid asynchronous configuration")
+        if lib.orc_set_threads(h, threads):
+            self.close()
+            raise ValueError("invalid thread count")
         self.W, self.H, self.N, self.S, self.kind = W, H, N, S, kind
         self.bits, self.interval = bits, interval
         self.I = W * H

@@ -29,7 +29,8 @@ def _arena_for(cfgs, gens, dev):
     return buf, buf[off:off + need]
 
 
-def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool = True) -> dict:
+def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool = True,
+                     block_threads: int = 256) -> dict:
     cfgs = [hs.Config(**s.config_kwargs()) for s in specs]
     reps = sum(s.replications for s in specs)
     # (i) sequential plain runs, one arena reused in stream order
@@ -57,11 +58,11 @@ def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool 
     for s, c in zip(specs, cfgs):
         if pool.admit(c, s.generations) is None:
             raise RuntimeError("pool sized too small")
-    choice = {"block_threads": 64, "gens_per_launch": 64, "use_graph": True}
+    choice = {"block_threads": block_threads, "gens_per_launch": 64, "use_graph": True}
     if tune:
         choice = autotune.tune_online(pool, key=autotune.signature(specs), use_cache=False)
     else:
-        pool.set_launch(64, True)
+        pool.set_launch(block_threads, True)
     G = choice["gens_per_launch"]
     while pool.advance(G):
         pass

@@ -36,6 +36,7 @@ EXPORTS = (
     "hstrat_phylo_workspace_bytes", "hstrat_phylo_metrics",
     "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
     "ga_mrca_bounds", "ga_phylo_tree",
+    "hstrat_layout", "hstrat_mrca_bounds_pair", "hstrat_mrca_bounds_pair_ex", "hstrat_sites",
 )
 
 
@@ -119,6 +120,13 @@ def load_library():
         "hstrat_mrca_bounds": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                               _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "hstrat_mrca_status": (ctypes.c_int, [_vp, _vp]),
+        "hstrat_layout": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp]),
+        "hstrat_sites": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp]),
+        "hstrat_mrca_bounds_pair": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32,
+                                                   ctypes.c_uint32, _vp, ctypes.c_uint32, _vp,
+                                                   _vp, _vp]),
+        "hstrat_mrca_bounds_pair_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp,
+                                                      ctypes.c_uint32, _vp, _vp, _vp]),
         "ga_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
         "ga_kernel_time": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
@@ -188,7 +196,7 @@ class Config:
     8); ingest_interval n deposits every n-th generation only.
     async_activity p * 2^32 (0: synchronous) runs asynchronous ticks: each
     island runs a generation with probability p per tick, agents keep their
-    own counters (at most max_gens_per_launch ticks per run)."""
+    own counters."""
     grid_w: int
     grid_h: int
     pop_per_island: int = 32
@@ -750,6 +758,47 @@ def newick(tree: dict) -> str:
     import sys
     sys.setrecursionlimit(max(sys.getrecursionlimit(), 4 * n + 100))
     return text(("node", root), None) + ";"
+
+
+def layout(kind, S: int, T: int, bits: int = 1, interval: int = 1) -> np.ndarray:
+    """Deposit generation held by each site of an annotation with counter T
+    (host, constant time per site; EMPTY_SITE when unfilled)."""
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    sc = _scheme(kind, S, bits, interval)
+    L = np.zeros(S, np.uint32)
+    _check(load_library().hstrat_layout(ctypes.byref(sc), T, _ptr(L)))
+    return L
+
+
+def sites(kind, S: int, tau0: int, n: int) -> np.ndarray:
+    """Sites of the rule's items tau0 .. tau0 + n - 1 (host, constant time
+    per item)."""
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    sc = _scheme(kind, S, 1, 1)
+    out = np.zeros(n, np.uint32)
+    _check(load_library().hstrat_sites(ctypes.byref(sc), tau0, n, _ptr(out)))
+    return out
+
+
+def mrca_bounds_pair(kind, S: int, Ta: int, sa, Tb: int, sb, bits: int = 1,
+                     interval: int = 1) -> tuple:
+    """(lb, ub) of one pair of annotations on the host."""
+    if isinstance(kind, str):
+        kind = KINDS[kind]
+    a = np.ascontiguousarray(sa, np.uint32)
+    b = np.ascontiguousarray(sb, np.uint32)
+    lb, ub = ctypes.c_uint32(), ctypes.c_uint32()
+    lib = load_library()
+    if bits == 1 and interval == 1:
+        _check(lib.hstrat_mrca_bounds_pair(kind, S, Ta, _ptr(a), Tb, _ptr(b),
+                                           ctypes.byref(lb), ctypes.byref(ub)))
+    else:
+        sc = _scheme(kind, S, bits, interval)
+        _check(lib.hstrat_mrca_bounds_pair_ex(ctypes.byref(sc), Ta, _ptr(a), Tb, _ptr(b),
+                                              ctypes.byref(lb), ctypes.byref(ub)))
+    return lb.value, ub.value
 
 
 def mrca_status(workspace: MrcaWorkspace, stream=None) -> int:

@@ -13,7 +13,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhsga.so")
 SOURCES = [os.path.join(CSRC, f)
-           for f in ("hsga_kernels.hip", "hsga_query.hip", "hsga_api.cpp", "hsga_pool.cpp")]
+           for f in ("hsga_kernels.hip", "hsga_query.hip", "hsga_api.cpp", "hsga_pool.cpp",
+                     "hsga_rule.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

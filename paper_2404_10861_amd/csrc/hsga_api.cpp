@@ -46,7 +46,8 @@ Carve carve(const ga_config& cfg, uint32_t gens) {
     c.surf = off;    off += 2 * align_up(SW * A * 4);
     c.outbox = off;  off += 2 * align_up((size_t)I * hsga::kOutboxWords * 4);
     c.layout = off;  off += align_up(64 * 4);
-    c.sites = off;   off += align_up((size_t)gens * 4);
+    c.sites = off;
+    off += cfg.async_activity ? align_up(2 * sizeof(hsga::RuleTable)) : align_up((size_t)gens * 4);
     c.total = off;
     return c;
 }
@@ -128,10 +129,10 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
             base + c.outbox + b * align_up((size_t)I * hsga::kOutboxWords * 4));
     }
     r->layout = reinterpret_cast<uint32_t*>(base + c.layout);
-    r->sites = reinterpret_cast<uint32_t*>(base + c.sites);
+    r->sites = cfg->async_activity ? nullptr : reinterpret_cast<uint32_t*>(base + c.sites);
+    r->rules = cfg->async_activity ? reinterpret_cast<hsga::RuleTable*>(base + c.sites) : nullptr;
     r->gens = gens;
     r->T = 0;
-    r->tab_filled = 0;
     r->horizon = hsga::horizon_gen_of(cfg->surface_kind, r->S, cfg->ingest_interval);
     r->apt = default_agents_per_thread(r->N);
     r->block = r->apt == 4 ? 64u : 256u;   // small tiles: more workgroups in flight per CU
@@ -141,6 +142,30 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
                                          (uint32_t)cfg->seed, (uint32_t)(cfg->seed >> 32),
                                          r->stream);
     if (e != hipSuccess) return hip_fail(e, "founders launch");
+    if (cfg->async_activity) {
+        // an asynchronous birth looks its site up from its parent's counter
+        // in the rule's tables (the host's cached copies outlive the copy)
+        const hsga::RuleTable* rules[2] = {nullptr, nullptr};
+        if (!hsga::scheme_rules(cfg->surface_kind, r->S, rules))
+            return fail(GA_EINVAL, "no site rule tables for this surface");
+        const int n = cfg->surface_kind == GA_HYBRID ? 2 : 1;
+        for (int k = 0; k < n; ++k) {
+            e = hipMemcpyAsync(r->rules + k, rules[k], sizeof(hsga::RuleTable),
+                               hipMemcpyHostToDevice, r->stream);
+            if (e != hipSuccess) return hip_fail(e, "site rule tables upload");
+        }
+    }
+    return GA_OK;
+}
+
+int set_run_layout(ga_run* r, uint32_t T) {
+    // the layout after the run's ingests up to generation (tick) T, in
+    // ingest units, from the rule's closed form
+    uint32_t L[64];
+    hsga::scheme_layout_items(r->cfg.surface_kind, r->S,
+                              hsga::ingests_of(T, r->cfg.ingest_interval), L);
+    hipError_t e = hsga::launch_set_layout(r->layout, L, r->S, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "layout launch");
     return GA_OK;
 }
 
@@ -157,10 +182,12 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t tau0) {
     p.ob_in = r->outbox[src];
     p.ob_out = r->outbox[dst];
     const uint32_t n = cfg.ingest_interval;
-    p.site = g % n == 0 ? r->sites + (g / n - tau0) : nullptr;
+    p.site = g % n == 0 && r->sites ? r->sites + (g / n - tau0) : nullptr;
     p.diff_log2 = cfg.differentia_bits == 8 ? 3u : 0u;
     p.async_thr = cfg.async_activity;
-    p.site_tab = r->sites;
+    p.rules = r->rules;
+    p.kind = cfg.surface_kind;
+    p.S = r->S;
     p.interval = n;
     p.W = cfg.grid_w;
     p.H = cfg.grid_h;
@@ -221,6 +248,8 @@ hipEvent_t take_event(ga_run* r) {
     return e;
 }
 
+int step_enqueue(ga_run* r, uint32_t n);
+
 }  // namespace
 
 extern "C" {
@@ -260,7 +289,23 @@ int ga_create(const ga_config* in, void* dev_arena, size_t arena_bytes,
 
 int ga_step(ga_run* r, uint32_t n) {
     if (!r) return fail(GA_EINVAL, "run is NULL");
+    if (r->pooled) return fail(GA_EINVAL, "a run of a pool advances with ga_pool_advance");
+    if (r->broken)
+        return fail(GA_EDEVICE, "an earlier ga_step failed part-way; import a state first");
     if (n == 0) return GA_OK;
+    // a failure after the first launch leaves the run between generations
+    // (its layout already advanced): refuse further steps until a state is
+    // imported
+    const int rc = step_enqueue(r, n);
+    if (rc == GA_EDEVICE) r->broken = true;
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int step_enqueue(ga_run* r, uint32_t n) {
     if ((uint64_t)r->T + n - 1 > r->horizon)
         return fail(GA_EHORIZON, "generation " + std::to_string((uint64_t)r->T + n - 1) +
                                      " is past the site rule's horizon " +
@@ -269,22 +314,8 @@ int ga_step(ga_run* r, uint32_t n) {
     const uint32_t model = birth_model(cfg);
     const bool mig = cfg.migrants_per_island != 0;
     if (cfg.async_activity) {
-        // asynchronous ticks: extend the site table to every ingest a
-        // counter can reach by the last tick, then one launch per tick
-        const uint64_t need = hsga::ingests_of((uint32_t)std::min<uint64_t>(
-                                                   (uint64_t)r->T + n, 0xffffffffull),
-                                               cfg.ingest_interval);
-        if ((uint64_t)r->T + n > r->gens)
-            return fail(GA_EINVAL, "an asynchronous run is limited to " +
-                                       std::to_string(r->gens) +
-                                       " ticks (max_gens_per_launch)");
-        if (need > r->tab_filled) {
-            hipError_t e = hsga::launch_site_schedule(cfg.surface_kind, r->S, r->layout,
-                                                      r->sites + r->tab_filled, r->tab_filled,
-                                                      (uint32_t)need - r->tab_filled, r->stream);
-            if (e != hipSuccess) return hip_fail(e, "site table launch");
-            r->tab_filled = (uint32_t)need;
-        }
+        // asynchronous ticks: one launch per tick; each birth finds its site
+        // from its parent's counter in the rule's tables
         ga_run::Span span{nullptr, nullptr, n};
         if (r->timing) {
             span.start = take_event(r);
@@ -304,7 +335,9 @@ int ga_step(ga_run* r, uint32_t n) {
             r->spans.push_back(span);
         }
         r->T += n;
-        return GA_OK;
+        // the run's layout (what every agent of counter T holds), for the
+        // run-bound queries
+        return set_run_layout(r, r->T);
     }
     while (n > 0) {
         const uint32_t G = n < r->gens ? n : r->gens;
@@ -336,6 +369,10 @@ int ga_step(ga_run* r, uint32_t n) {
     }
     return GA_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int ga_sync(ga_run* r) {
     if (!r) return fail(GA_EINVAL, "run is NULL");
@@ -498,9 +535,6 @@ int ga_import_state(ga_run* r, const void* host, size_t bytes) {
     if ((uint64_t)T > r->horizon + 1)
         return fail(GA_EHORIZON, "state generation " + std::to_string(T) +
                                      " is past the site rule's horizon");
-    if (async && T > r->gens)
-        return fail(GA_EINVAL, "an asynchronous state at tick " + std::to_string(T) +
-                                   " needs max_gens_per_launch >= " + std::to_string(T));
     const size_t A = r->A;
     const uint32_t* trait = w + kStateHeaderWords + sizeof(ga_config) / 4;
     const uint32_t* counter = trait + A;
@@ -531,28 +565,24 @@ int ga_import_state(ga_run* r, const void* host, size_t bytes) {
         e = hipMemcpy(pl.dst, pl.src, pl.words * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy state");
     }
-    // rebuild the layout after ingests_of(T) ingests by replaying the site
-    // rule from the empty layout (in pieces of the site table's capacity;
-    // an asynchronous run keeps the whole table, T <= gens)
-    const std::vector<uint32_t> empty(r->S, GA_EMPTY_SITE);
-    e = hipMemcpy(r->layout, empty.data(), (size_t)r->S * 4, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy layout");
-    const uint32_t tau = hsga::ingests_of(T, r->cfg.ingest_interval);
-    for (uint32_t t0 = 0; t0 < tau; t0 += r->gens) {
-        const uint32_t count = std::min(r->gens, tau - t0);
-        e = hsga::launch_site_schedule(r->cfg.surface_kind, r->S, r->layout,
-                                       r->sites + (async ? t0 : 0), t0, count, r->stream);
-        if (e != hipSuccess) return hip_fail(e, "site schedule launch");
-    }
+    // the layout after ingests_of(T) ingests, from the rule's closed form
+    // (a function of the scheme and T alone, nothing of the state)
+    int rc = set_run_layout(r, T);
+    if (rc != GA_OK) return rc;
     e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    r->tab_filled = async ? tau : 0;
     r->T = T;
+    r->broken = false;
     return GA_OK;
 }
 
 void ga_destroy(ga_run* r) {
     if (!r) return;
+    if (r->pooled) {
+        // the handle lives in the pool's slot table: ga_pool_release frees it
+        (void)fail(GA_EINVAL, "ga_destroy of a run of a pool ignored (use ga_pool_release)");
+        return;
+    }
     for (auto& s : r->spans) {
         (void)hipEventDestroy(s.start);
         (void)hipEventDestroy(s.stop);

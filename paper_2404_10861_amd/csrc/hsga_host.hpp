@@ -21,15 +21,16 @@ struct ga_run {
     uint32_t* surf[2];
     uint32_t* outbox[2];
     uint32_t* layout;
-    uint32_t* sites;
+    uint32_t* sites;     // synchronous: the site schedule of a launch batch
+    hsga::RuleTable* rules;   // asynchronous: the site rule's tables (device)
     uint32_t gens;       // site schedule capacity
     uint32_t T;          // generations (ticks, when asynchronous) enqueued
-    uint32_t tab_filled; // asynchronous: ingests whose sites are in `sites`
     uint64_t horizon;
     uint32_t apt;        // agents per thread (1, 2, 4; divides N)
     uint32_t block;      // workgroup threads
     bool timing;
     bool pooled = false; // a slot of a pool (its generation targets live there)
+    bool broken = false; // a ga_step failed after enqueueing part of its work
     struct Span { hipEvent_t start, stop; uint32_t launches; };
     std::vector<Span> spans;
     std::vector<hipEvent_t> spare;
@@ -57,7 +58,9 @@ inline uint32_t surface_words(const ga_config& c) {
 
 // Byte offsets of each buffer of a run of a validated config in its arena.
 // Only asynchronous runs keep counter planes: in a synchronous run every
-// counter is the generation count (counter == 0 and no bytes then).
+// counter is the generation count (counter == 0 and no bytes then).  A
+// synchronous run's `sites` holds a launch batch's site schedule (gens
+// words); an asynchronous run's holds the site rule's tables instead.
 Carve carve(const ga_config& cfg, uint32_t gens);
 
 // GA_OK, or GA_EINVAL with the reason in ga_last_error().
@@ -70,6 +73,10 @@ int validate(const ga_config* in, ga_config* out);
 int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipStream_t stream);
 
 inline uint32_t tile_islands(uint32_t block, uint32_t apt, uint32_t N) { return block * apt / N; }
+
+// Enqueue the run's layout after the ingests of generation (tick) count T
+// (closed form of the site rule, written by a kernel).
+int set_run_layout(ga_run* r, uint32_t T);
 
 // Parameters of generation g of a run whose current site schedule starts
 // at ingest tau0.

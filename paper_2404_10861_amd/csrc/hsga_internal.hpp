@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hsga_rule.hpp"
+
 namespace hsga {
 
 // An annotation scheme (Distributed Phylogenetic Tracking: one-bit or byte
@@ -45,7 +47,8 @@ struct StepParams {
     uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
     uint32_t diff_log2;        // log2 of the differentia width: 0 (bit) or 3 (byte)
     uint32_t async_thr;        // asynchronous ticks: island activity threshold; 0: synchronous
-    const uint32_t* site_tab;  // asynchronous ticks: site of every ingest so far
+    const RuleTable* rules;    // asynchronous ticks: the surface's site rule tables
+    uint32_t kind, S;          // asynchronous ticks: the surface
     uint32_t interval;         // asynchronous ticks: the ingest interval
     uint32_t tour;             // float model: tournament draws, 1..5
     uint32_t del_thr, ben_thr; // float model: mutation class thresholds
@@ -102,6 +105,10 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 
 // agents_per_thread (1, 2 or 4) must divide N; tile_isl * N <= block_threads *
 // agents_per_thread.
+// Writes a run's layout (S words, given on the host) on the stream.
+hipError_t launch_set_layout(uint32_t* layout, const uint32_t* words, uint32_t S,
+                             hipStream_t stream);
+
 hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
 

@@ -76,6 +76,26 @@ __global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32
     schedule_sites(kind, S, layout, sites, tau0, count);
 }
 
+// A run's layout set from the host through the kernel's arguments (so no
+// host buffer has to outlive the call).
+struct LayoutWords {
+    uint32_t w[64];
+};
+
+__global__ __launch_bounds__(64) void set_layout_kernel(uint32_t* __restrict__ layout,
+                                                        LayoutWords words, uint32_t S) {
+    if (threadIdx.x < S) layout[threadIdx.x] = words.w[threadIdx.x];
+}
+
+hipError_t launch_set_layout(uint32_t* layout, const uint32_t* words, uint32_t S,
+                             hipStream_t stream) {
+    if (S > 64) return hipErrorInvalidValue;
+    LayoutWords lw{};
+    for (uint32_t k = 0; k < S; ++k) lw.w[k] = words[k];
+    hipLaunchKernelGGL(set_layout_kernel, dim3(1), dim3(64), 0, stream, layout, lw, S);
+    return hipGetLastError();
+}
+
 hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
                                 uint32_t tau0, uint32_t count, hipStream_t stream) {
     if (count == 0) return hipSuccess;
@@ -292,12 +312,12 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
             ccn.v[q] = T + 1u;
             uint32_t dep_word = site_word, dep_shift = site_shift;
             if constexpr (ASYNC) {
-                // the parent's own counter picks the item and, through the
-                // site table, its site
+                // the parent's own counter picks the item and, in constant
+                // time through the rule's tables, its site
                 const uint32_t tau = p.interval == 1u ? T : T / p.interval;
                 dep_word = 0xffu;
                 if (tau * p.interval == T) {
-                    const uint32_t site = p.site_tab[tau];
+                    const uint32_t site = scheme_site(p.rules, p.kind, p.S, tau);
                     dep_word = site >> (5u - p.diff_log2);
                     dep_shift = (site << p.diff_log2) & 31u;
                 }
@@ -679,17 +699,19 @@ template <bool WITH_FLOAT>
 __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __restrict__ runs,
                                                          const uint32_t* __restrict__ tile0,
                                                          uint32_t nruns, uint32_t k) {
-    __shared__ uint32_t s_tile0[kMaxBatchRuns + 1];
-    for (uint32_t i = threadIdx.x; i <= nruns; i += blockDim.x) s_tile0[i] = tile0[i];
-    __syncthreads();
     const uint32_t tile = xcd_local_block(blockIdx.x, gridDim.x);
-    // the run owning this tile: last r with tile0[r] <= tile
-    uint32_t lo = 0, hi = nruns;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_tile0[mid] <= tile) lo = mid;
-        else hi = mid;
+    // the run owning this tile: tile0 is ascending, so it is the number of
+    // runs starting at or before the tile, less one -- one load per lane
+    // and a ballot per 64 runs in every wavefront, with no LDS round trip
+    // or barrier before the run's parameters can be fetched
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t before = 0;
+    for (uint32_t b0 = 0; b0 < nruns; b0 += 64) {
+        const uint32_t i = b0 + lane;
+        const bool le = i < nruns && tile0[i] <= tile;
+        before += (uint32_t)__popcll(__ballot(le));
     }
+    const uint32_t lo = before - 1u;       // tile0[0] = 0: at least one run
     const BatchRun& R = runs[lo];
     if (k >= R.gens) return;
     const uint32_t g = R.T0 + k;
@@ -717,12 +739,14 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.tile_isl = R.tile_isl;
     p.div_magic = R.div_magic;
     p.async_thr = 0u;          // batched runs are synchronous
-    p.site_tab = nullptr;
+    p.rules = nullptr;
+    p.kind = R.kind;
+    p.S = R.S;
     p.interval = R.interval;
     p.tour = R.tour;
     p.del_thr = R.del_thr; p.ben_thr = R.ben_thr;
     p.del_sigma = R.del_sigma; p.ben_sigma = R.ben_sigma;
-    const uint32_t t = tile - s_tile0[lo];
+    const uint32_t t = tile - R.tile0;
     const uint32_t model = (R.variant >> 1) & 3u;
     if (model == kBirthIntTournament) step_tile_variant<kBirthIntTournament>(p, t, R.variant);
     else if (WITH_FLOAT && model == kBirthFloat) step_tile_variant<kBirthFloat>(p, t, R.variant);

@@ -35,7 +35,9 @@ adding a uniform integer in [-8, 8], one migrant per island per generation.
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -159,6 +161,41 @@ def c5(duration: float = 120.0, rate: float = 20.0, draw_seed: int = 20240418) -
         reqs.append(RunSpec(w, h, 32, s, kind, 2, g, seed=idx + 1, sample=1024, arrival=t,
                             name=f"C5 request {idx}"))
     return reqs
+
+
+# The batched and served run sets as saved lists (data/, written once by
+# make_workload_lists.py from c4() and c5()): the lists, not the draws, are
+# the workloads, so they do not depend on numpy's generator staying the same.
+DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+C4_LIST = os.path.join(DATA, "c4_runs.json")
+C5_LIST = os.path.join(DATA, "c5_requests.json")
+
+
+def c4_rows(runs: list[RunSpec]) -> list:
+    return [[r.grid_w, r.grid_h, r.pop_per_island, r.surface_sites, r.surface_kind,
+             r.tournament_size, r.generations, r.seed] for r in runs]
+
+
+def c5_rows(reqs: list[RunSpec]) -> list:
+    return [[round(r.arrival, 9), r.grid_w, r.grid_h, r.generations, r.surface_kind,
+             r.surface_sites, r.seed] for r in reqs]
+
+
+def c4_saved() -> list[RunSpec]:
+    """The 64-run batched set as saved."""
+    with open(C4_LIST) as f:
+        rows = json.load(f)["runs"]
+    return [RunSpec(w, h, n, s, k, t, g, seed=sd, name=f"C4 run {sd}")
+            for w, h, n, s, k, t, g, sd in rows]
+
+
+def c5_saved(duration: float = 120.0) -> list[RunSpec]:
+    """The served request list as saved (arrivals before `duration` s)."""
+    with open(C5_LIST) as f:
+        rows = json.load(f)["requests"]
+    return [RunSpec(w, h, 32, s, k, 2, g, seed=sd, sample=1024, arrival=a,
+                    name=f"C5 request {sd - 1}")
+            for a, w, h, g, k, s, sd in rows if a < duration]
 
 
 def offered_replication_rate(reqs: list[RunSpec], duration: float) -> float:

@@ -63,9 +63,14 @@ def test_footprint_without_gpu():
     # layout and schedule
     assert n >= 2 * cfg.agents * 12 + 2 * cfg.islands * 32
     assert n < 2 * cfg.agents * 12 + 2 * cfg.islands * 32 + (1 << 20)
-    # an asynchronous run keeps its counter planes as well
+    # an asynchronous run keeps its counter planes as well, and the site
+    # rule's two constant-time tables (under 20 KB) in place of the
+    # 4,096-generation schedule
     acfg = hs.Config(512, 1024, 32, 64, "hybrid", async_activity=1 << 31)
-    assert hs.footprint_bytes(acfg) == n + 2 * cfg.agents * 4
+    extra = hs.footprint_bytes(acfg) - (n + 2 * cfg.agents * 4)
+    assert -4096 * 4 < extra < 20 * 1024
+    # and no tick bound: the same bytes whatever the launch batch
+    assert hs.footprint_bytes(acfg, 16) == hs.footprint_bytes(acfg, 1 << 20)
     with pytest.raises(hs.HsgaError):
         hs.footprint_bytes(hs.Config(0, 4))
 

@@ -18,28 +18,29 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_algorithmic_bytes_of_the_paper_scale_step():
-    import bench
-    from paper_2404_10861_amd import workloads as wl
-    spec = wl.c2()
-    agents, islands, rec = 512 * 1024 * 32, 512 * 1024, 4 + 4 + 64 // 8
-    # every parent record read and every child record written; each island's
-    # outbox entry (record + direction word) written once and read once
-    want = 2 * agents * rec + 2 * islands * (rec + 4)
-    assert want == 557_842_432
-    assert bench.algorithmic_bytes_per_generation(spec) == want
-
-
-
-def test_design_bytes_of_the_paper_scale_step():
-    """A synchronous step keeps no counter plane: trait and 64 one-bit sites
-    (12 bytes) read and written per agent, one 16-byte outbox entry written
-    and read per island."""
+    """A synchronous step stores no counters (every counter is the
+    generation number): trait and 64 one-bit sites (12 bytes) read and
+    written per agent, one 16-byte migrant entry written and read per
+    island."""
     import bench
     from paper_2404_10861_amd import workloads as wl
     agents, islands = 512 * 1024 * 32, 512 * 1024
     want = 2 * agents * 12 + 2 * islands * 16
     assert want == 419_430_400
-    assert bench.design_bytes_per_generation(wl.c2()) == want
+    assert bench.algorithmic_bytes_per_generation(wl.c2()) == want
+    assert want / agents == 25.0          # bytes per agent-replication
+
+
+def test_record_model_bytes_of_the_paper_scale_step():
+    """The same generation priced with a stored counter per record (16-byte
+    records) and a 32-byte migrant entry per island."""
+    import bench
+    from paper_2404_10861_amd import workloads as wl
+    agents, islands = 512 * 1024 * 32, 512 * 1024
+    want = 2 * agents * 16 + islands * 32
+    assert want == 553_648_128
+    assert bench.record_model_bytes_per_generation(wl.c2()) == want
+
 
 def test_traffic_is_reported_only_for_the_profiled_code(monkeypatch):
     import bench
@@ -47,8 +48,8 @@ def test_traffic_is_reported_only_for_the_profiled_code(monkeypatch):
     from paper_2404_10861_amd import workloads as wl
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)
-    # below the algorithmic bytes: no counter plane read, 16-byte outbox entries
-    assert rec["bytes_per_launch"] < rec["algorithmic_bytes_per_launch"]
+    # measured traffic within 1 % of the bytes the step must move
+    assert abs(rec["bytes_per_launch"] / bench.algorithmic_bytes_per_generation(wl.c2()) - 1) < 0.01
     # reported for the profiled code, null for any other
     monkeypatch.setattr(profiling, "kernel_hash", lambda sources=None: rec["kernel_hash"])
     assert bench.measured_traffic(wl.c2()) == rec["bytes_per_launch"]

@@ -1,7 +1,7 @@
 """GPU parity of asynchronous runs against the oracle (zero tolerance):
 islands active per tick with a given probability, per-agent counters,
-deposits at the site each parent's own counter selects (site-table
-lookups), idle islands posting nothing; all birth models and annotation
+deposits at the site each parent's own counter selects (constant-time
+lookups in the rule's tables), idle islands posting nothing; all birth models and annotation
 schemes, migration on and off, every tick of a small run, launch shapes,
 the synchronous reduction, MRCA bounds of drifting counters, and the
 limits."""
@@ -95,7 +95,7 @@ def test_launch_shapes(hs, orc, block, apt):
 
 
 def test_split_steps(hs, orc):
-    """Ticks enqueued in uneven pieces extend the site table in pieces."""
+    """Ticks enqueued in uneven pieces."""
     c = acfg(hs, 5, 5, 16, 0, 8, P(0.5), bits=8, interval=3, seed=6)
     run = hs.Run(c, max_gens_per_launch=200)
     for n in (1, 5, 2, 30, 7, 55):
@@ -133,13 +133,36 @@ def test_bounds_of_drifting_counters(hs, orc):
     assert hs.phylo_metrics("hybrid", 64, cnt, srf)["status"] == 1
 
 
+@pytest.mark.parametrize("kind,S,bits,interval,ticks", [(2, 64, 1, 1, 3000), (1, 32, 1, 1, 5000),
+                                                         (0, 8, 8, 3, 4000)])
+def test_no_tick_limit(hs, orc, kind, S, bits, interval, ticks):
+    """Births look sites up in the rule's constant-time tables, so a run is
+    not bounded by its launch batch: a run created with 64 generations per
+    launch steps thousands of ticks, in uneven pieces, equal to the oracle
+    (whose lookups replay the placements)."""
+    c = acfg(hs, 6, 5, 16, kind, S, P(0.85), bits, interval, seed=31)
+    run = hs.Run(c, max_gens_per_launch=64)
+    done = 0
+    for piece in (1, 63, 700, ticks - 764):
+        run.step(piece)
+        done += piece
+    assert done == ticks
+    o = oracle_for(orc, c)
+    o.step(ticks)
+    same_state(run, o)
+    counters = run.agents()[1]
+    assert counters.max() > 64 and len(np.unique(counters)) > 5
+
+
 def test_limits(hs):
     c = acfg(hs, 4, 4, 8, 1, 32, P(0.5))
-    run = hs.Run(c, max_gens_per_launch=50)
-    run.step(50)
-    with pytest.raises(hs.HsgaError):
-        run.step(1)
     pool = hs.Pool(8 << 20, max_runs=2, max_gens_per_launch=16)
     with pytest.raises(hs.HsgaError):
         pool.admit(c, 10)
     pool.close()
+    # the horizon still binds: hybrid-8 byte surfaces place 2 (2^4 - 2) + 2 items
+    h = acfg(hs, 2, 2, 4, 2, 8, P(0.5), bits=8)
+    run = hs.Run(h)
+    with pytest.raises(hs.HsgaError) as e:
+        run.step(2 * (2**4 - 2) + 2 + 2)
+    assert e.value.status == hs.GA_EHORIZON

@@ -131,13 +131,31 @@ def test_treatment_pair_scaled_down_full_length(hs, orc, tournament):
     assert_same_state(g, o)
 
 
-def test_paper_scale_prefix(hs, orc):
-    """The 16.8 M-agent hybrid workload, every word after 3 generations, in
-    the launch configuration the benchmark uses."""
-    g, o = make_pair(hs, orc, 512, 1024, 32, 64, "hybrid", seed=1)
-    g.step(3)
-    o.step(3)
-    assert_same_state(g, o)
+def test_paper_scale_past_the_fill_phase(hs, orc):
+    """The 16.8 M-agent hybrid-64 workload in the launch configuration the
+    benchmark times, every word after 100 generations: both 32-site halves
+    fill by generation 63, so generations 64..99 overwrite evicted sites
+    on the full torus.  Then the benchmark's query route (a 4,096-agent
+    stratified sample, all 16.8 M ordered pairs of MRCA bounds from the
+    run's own layout) against the oracle, pair for pair.  The oracle runs
+    its island-parallel births on 16 host threads."""
+    import os
+    cfg = hs.Config(512, 1024, 32, 64, "hybrid", seed=1)
+    g = hs.Run(cfg, max_gens_per_launch=10000)
+    o = orc.Run(512, 1024, 32, 64, KIND["hybrid"], seed=1,
+                threads=min(16, os.cpu_count() or 1))
+    g.step(100)
+    o.step(100)
+    assert_same_state(g, o, "at generation 100")
+    layout = o.layout()
+    assert np.all(layout != orc.EMPTY) and layout.max() == 99
+    _, cnt, srf = g.sample(4096)
+    lb, ub = g.mrca_bounds(cnt, srf)
+    idx = orc.sample(1, cfg.agents, 4096, 100)
+    _, oc, os_ = o.agents()
+    olb, oub = orc.mrca_allpairs(KIND["hybrid"], 64, oc[idx], os_[idx])
+    assert np.array_equal(hs.as_u32(lb), olb)
+    assert np.array_equal(hs.as_u32(ub), oub)
 
 
 def test_horizon_is_refused(hs):

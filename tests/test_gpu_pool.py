@@ -138,9 +138,11 @@ def test_runs_stop_at_their_own_counts(hs):
     assert pool.info()["active"] == 0
 
 
-def test_served_results_equal_alone(hs):
+def test_served_results_equal_alone(hs, orc):
     """A burst of requests arriving while others are on the GPU: each
-    result (final records, sample, MRCA matrices) equals the request alone."""
+    result (final records, sample, MRCA matrices) equals the request alone
+    and the oracle's run of the request (its records, its stratified sample
+    and the all-pairs bounds of that sample)."""
     from paper_2404_10861_amd import serve
     reqs = []
     for i, (w, h, s, kind, g) in enumerate([(8, 8, 32, "steady", 300), (16, 12, 64, "hybrid", 900),
@@ -161,6 +163,18 @@ def test_served_results_equal_alone(hs):
         assert np.array_equal(res.sample_idx, idx)
         assert np.array_equal(res.lb, lb) and np.array_equal(res.ub, ub)
         assert res.latency > 0
+        o = orc.Run(spec.grid_w, spec.grid_h, spec.pop_per_island, spec.surface_sites,
+                    KIND[spec.surface_kind], spec.tournament_size, seed=spec.seed,
+                    threads=4)
+        o.step(spec.generations)
+        ot, oc, os_ = o.agents()
+        for x, y in zip(got, (ot, oc, os_)):
+            assert np.array_equal(x, y)
+        want_idx = orc.sample(spec.seed, spec.agents, 64, spec.generations)
+        assert np.array_equal(res.sample_idx, want_idx)
+        olb, oub = orc.mrca_allpairs(KIND[spec.surface_kind], spec.surface_sites,
+                                     oc[want_idx], os_[want_idx])
+        assert np.array_equal(res.lb, olb) and np.array_equal(res.ub, oub)
     s = rep.summary()
     assert s["requests"] == len(reqs) and s["latency_p99_s"] >= s["latency_p50_s"]
 

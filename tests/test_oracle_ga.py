@@ -243,3 +243,29 @@ def test_invalid_configs_rejected(orc):
         orc.Run(4, 4, 8, 32, 0, mut_lo=3, mut_hi=2)
     with pytest.raises(ValueError):
         orc.Run(4, 4, 8, 32, 3)
+
+
+@pytest.mark.parametrize("kw", [dict(kind=2, S=64, tournament=2),
+                                dict(kind=1, S=32, tournament=0, N=17),
+                                dict(kind=0, S=8, bits=8, interval=3, tournament=2)])
+def test_island_threaded_oracle_equals_serial(orc, kw):
+    """The island-parallel births (one barrier per generation) give the
+    serial oracle's result word for word, pedigree included."""
+    kw = dict(kw)
+    N = kw.pop("N", 8)
+    kind, S = kw.pop("kind"), kw.pop("S")
+    G = 60
+    runs = [orc.Run(5, 3, N, S, kind, seed=29, pedigree_gens=G, threads=t, **kw)
+            for t in (0, 4, 15)]
+    for r in runs:
+        r.step(G)
+    want = runs[0].agents()
+    for r in runs[1:]:
+        for x, y in zip(want, r.agents()):
+            assert np.array_equal(x, y)
+        assert np.array_equal(runs[0].layout(), r.layout())
+        for x, y in zip(runs[0].outbox(), r.outbox()):
+            assert np.array_equal(x, y)
+        for g in (1, G // 2, G):
+            for x, y in zip(runs[0].pedigree(g), r.pedigree(g)):
+                assert np.array_equal(x, y)

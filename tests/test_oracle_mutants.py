@@ -46,28 +46,28 @@ MUTANTS = {
         "*policy = ORC_TILTED; *u = T / 2; *offset = 0;",
         [("test_oracle_site_rule", "test_hybrid_is_half_steady_half_tilted", {"S": 32})]),
     "tournament compares traits unsigned": (
-        "if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])",
-        "if (r->q_trait[b] > r->q_trait[p])",
+        "if ((int32_t)q->trait[b] > (int32_t)q->trait[p])",
+        "if (q->trait[b] > q->trait[p])",
         [("test_oracle_ga", "test_selection_raises_mean_trait", {})]),
     "tournament keeps the lower trait": (
-        "if ((int32_t)r->q_trait[b] > (int32_t)r->q_trait[p])",
-        "if ((int32_t)r->q_trait[b] < (int32_t)r->q_trait[p])",
+        "if ((int32_t)q->trait[b] > (int32_t)q->trait[p])",
+        "if ((int32_t)q->trait[b] < (int32_t)q->trait[p])",
         [("test_oracle_ga", "test_selection_raises_mean_trait", {})]),
     "mutation range one value too wide": (
         "(int32_t)orc_mulhi(w[3], r->mut_span) + r->mut_lo",
         "(int32_t)orc_mulhi(w[3], r->mut_span + 1) + r->mut_lo",
         [("test_oracle_ga", "test_mutation_statistics", {})]),
     "differentia written one site off": (
-        "            if (ingest) {\n                uint32_t per_word = 32 / r->bits;\n"
-        "                uint32_t shift = ((uint32_t)site % per_word) * r->bits;",
-        "            if (ingest) {\n                uint32_t per_word = 32 / r->bits;\n"
-        "                uint32_t shift = ((uint32_t)(site ^ 1) % per_word) * r->bits;",
+        "        if (ingest) {\n            uint32_t per_word = 32 / r->bits;\n"
+        "            uint32_t shift = ((uint32_t)site % per_word) * r->bits;",
+        "        if (ingest) {\n            uint32_t per_word = 32 / r->bits;\n"
+        "            uint32_t shift = ((uint32_t)(site ^ 1) % per_word) * r->bits;",
         [("test_oracle_ga", "test_pedigree_consistency", {"kind": 0})]),
     "immigrants never written into the island": (
-        "        if (r->migrants && r->has_outbox) {\n"
-        "            orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);",
-        "        if (0 && r->migrants && r->has_outbox) {\n"
-        "            orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);",
+        "    if (r->migrants && r->has_outbox) {\n"
+        "        orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);",
+        "    if (0 && r->migrants && r->has_outbox) {\n"
+        "        orc_philox(0, i, g, ORC_IMMIGRATE, r->seed, w);",
         [("test_oracle_ga", "test_immigrants_become_parents", {})]),
     "emigrants sent north or south only": (
         "            uint32_t a = i * N + e;\n            r->ob_dir[i] = w[1] >> 30;\n"
@@ -107,10 +107,10 @@ MUTANTS = {
         [("test_oracle_float", "test_purifying_only_never_gains", {})]),
     "asynchronous child counter taken from the tick": (
         "            r->n_counter[a] = T + 1;\n            for (uint32_t s = 0; s < SW; s++)\n"
-        "                r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];\n"
+        "                r->n_surf[(size_t)a * SW + s] = q->surf[p * SW + s];\n"
         "            if (T % r->interval == 0) {",
         "            r->n_counter[a] = k + 1;\n            for (uint32_t s = 0; s < SW; s++)\n"
-        "                r->n_surf[(size_t)a * SW + s] = r->q_surf[p * SW + s];\n"
+        "                r->n_surf[(size_t)a * SW + s] = q->surf[p * SW + s];\n"
         "            if (T % r->interval == 0) {",
         [("test_oracle_async", "test_births_raise_the_parents_own_counter", {})]),
     "tree leaf edges left out of the branch length": (
@@ -146,7 +146,7 @@ def test_planted_mistake_is_caught(tmp_path, name, pin_modules):
     mutant_c = tmp_path / "mutant.c"
     mutant_c.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
-    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-w", "-shared", "-fPIC",
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-pthread", "-w", "-shared", "-fPIC",
                     "-o", str(lib), str(mutant_c), "-lm"], check=True)
     mut = _load_module(f"orc_mutant_{abs(hash(name))}", ORACLE_PY)
     mut.LIB = str(lib)

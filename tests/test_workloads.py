@@ -39,3 +39,16 @@ def test_served_request_list():
     # log-uniform generations: median near 1000 * sqrt(20)
     med = np.median([r.generations for r in reqs])
     assert 3500 < med < 5500
+
+
+def test_saved_lists_are_the_generated_ones():
+    """The committed run lists are the workloads; they were written from
+    the seeded generators, which still reproduce them."""
+    assert wl.c4_saved() == wl.c4()
+    saved, drawn = wl.c5_saved(), wl.c5()
+    assert len(saved) == len(drawn) == 2398
+    for x, y in zip(saved, drawn):
+        assert abs(x.arrival - y.arrival) < 1e-8
+        assert (x.grid_w, x.grid_h, x.generations, x.surface_kind, x.surface_sites, x.seed) == \
+            (y.grid_w, y.grid_h, y.generations, y.surface_kind, y.surface_sites, y.seed)
+    assert len(wl.c5_saved(20.0)) == sum(r.arrival < 20.0 for r in drawn)
