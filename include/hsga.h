@@ -355,6 +355,22 @@ int hstrat_mrca_bounds_pair(uint32_t kind, uint32_t S, uint32_t Ta, const uint32
 int hstrat_mrca_bounds_pair_ex(const hstrat_scheme *scheme, uint32_t Ta, const uint32_t *sa,
                                uint32_t Tb, const uint32_t *sb, uint32_t *lb, uint32_t *ub);
 
+/* hstrat_mrca_bounds without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array
+ * of 1,345,536 bytes that the library holds on every device it runs on
+ * until the process ends; this call allocates nothing.  Results are those
+ * of hstrat_mrca_bounds, except that a counter past the site rule's horizon
+ * (which hstrat_mrca_status would report) makes every lb and ub 0xFFFFFFFF,
+ * a value no bound takes.  n <= 4096; the current device must be the one
+ * hip_stream and the buffers belong to.  Every call on a device shares that
+ * device's array, so calls that overlap on one device race: order them on
+ * one stream or synchronise between them.
+ * Errors: GA_EINVAL (kind, S, n = 0 or n > 4096, NULL pointers), GA_EDEVICE. */
+int hstrat_mrca_bounds_noalloc(uint32_t kind, uint32_t S, uint32_t n,
+                               const uint32_t *counter, const uint32_t *surface_words,
+                               uint32_t *lb, uint32_t *ub, void *hip_stream);
+
 /* Blocking: status of the last hstrat_mrca_bounds run on this workspace
  * (GA_OK, or GA_EHORIZON when a counter was past the horizon, in which
  * case lb/ub are unspecified).                                             */

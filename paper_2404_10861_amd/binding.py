@@ -35,7 +35,7 @@ EXPORTS = (
     "ga_pool_set_launch", "ga_pool_info", "ga_pool_destroy",
     "hstrat_phylo_workspace_bytes", "hstrat_phylo_metrics",
     "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
-    "ga_mrca_bounds", "ga_phylo_tree",
+    "ga_mrca_bounds", "ga_phylo_tree", "hstrat_mrca_bounds_noalloc",
     "hstrat_layout", "hstrat_mrca_bounds_pair", "hstrat_mrca_bounds_pair_ex", "hstrat_sites",
 )
 
@@ -127,6 +127,8 @@ def load_library():
                                                    _vp, _vp]),
         "hstrat_mrca_bounds_pair_ex": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp,
                                                       ctypes.c_uint32, _vp, _vp, _vp]),
+        "hstrat_mrca_bounds_noalloc": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32,
+                                                      ctypes.c_uint32, _vp, _vp, _vp, _vp, _vp]),
         "ga_set_kernel_timing": (ctypes.c_int, [_vp, ctypes.c_int]),
         "ga_kernel_time": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),

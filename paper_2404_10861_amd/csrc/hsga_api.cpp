@@ -678,6 +678,22 @@ int hstrat_mrca_bounds(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* co
                                  workspace_bytes, hip_stream);
 }
 
+int hstrat_mrca_bounds_noalloc(uint32_t kind, uint32_t S, uint32_t n, const uint32_t* counter,
+                               const uint32_t* surface_words, uint32_t* lb, uint32_t* ub,
+                               void* hip_stream) {
+    if (S != 32 && S != 64) return fail(GA_EINVAL, "S must be 32 or 64");
+    if (kind > GA_HYBRID) return fail(GA_EINVAL, "unknown surface kind");
+    if (n == 0 || n > hsga::kNoAllocMaxN)
+        return fail(GA_EINVAL, "n must be 1.." + std::to_string(hsga::kNoAllocMaxN) +
+                                   " (the library's static scratch)");
+    if (!counter || !surface_words || !lb || !ub) return fail(GA_EINVAL, "NULL buffer");
+    const hsga::Scheme sc{kind, S, 1, 1};
+    hipError_t e = hsga::launch_mrca_noalloc(sc, n, counter, surface_words, lb, ub,
+                                             static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(e, "mrca launch (static scratch)");
+    return GA_OK;
+}
+
 size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n) {
     return hsga::phylo_workspace_bytes(S, n);
 }

@@ -129,7 +129,7 @@ hipError_t launch_probe_copy(const void* src, void* dst, size_t bytes, hipStream
 // Workspace layout of the MRCA kernels (bytes).
 struct MrcaWorkspace {
     static constexpr size_t kHeader = 2048;   // flags, T, F, rank tables
-    static size_t bytes(uint32_t S, uint32_t n) {
+    static constexpr size_t bytes(uint32_t S, uint32_t n) {
         const size_t ranked = ((size_t)n * 8 + 255) & ~(size_t)255;
         const size_t layouts = ((size_t)n * S * 4 + 255) & ~(size_t)255;
         const size_t sites = ((size_t)n * S + 255) & ~(size_t)255;
@@ -156,5 +156,15 @@ hipError_t launch_phylo(const Scheme& sc, uint32_t n, const uint32_t* counter,
 hipError_t launch_mrca(const Scheme& sc, uint32_t n, const uint32_t* counter,
                        const uint32_t* surf, uint32_t* lb, uint32_t* ub, void* workspace,
                        hipStream_t stream, LayoutHint hint = {});
+
+// launch_mrca with the library's own static device scratch in place of a
+// caller's workspace (at most kNoAllocMaxN annotations of up to 64 sites):
+// no device memory is allocated.  The scratch's address on the current
+// device is looked up once per device.
+constexpr uint32_t kNoAllocMaxN = 4096;
+constexpr size_t kNoAllocScratchBytes = MrcaWorkspace::bytes(64, kNoAllocMaxN);
+hipError_t launch_mrca_noalloc(const Scheme& sc, uint32_t n, const uint32_t* counter,
+                               const uint32_t* surf, uint32_t* lb, uint32_t* ub,
+                               hipStream_t stream);
 
 }  // namespace hsga

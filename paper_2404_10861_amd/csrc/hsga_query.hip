@@ -1,6 +1,8 @@
 // hsga_query.hip -- gfx950 kernels of the end-of-run queries and their
 // launchers: the stratified sample, the MRCA-generation bounds of all pairs,
 // and trie reconstruction (tree metrics and the tree itself).
+#include <mutex>
+
 #include "hsga_device.hpp"
 #include "hsga_internal.hpp"
 
@@ -198,7 +200,23 @@ __global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n, uint32_t
                                                            const uint32_t* __restrict__ ws,
                                                            uint32_t* __restrict__ lb,
                                                            uint32_t* __restrict__ ub) {
-    if (ws[kWsStatus] != 0) return;
+    const uint32_t status = ws[kWsStatus];
+    if (status == kWsStatusHorizon) {
+        // a counter past the horizon: every bound reads 0xFFFFFFFF, a value
+        // no valid bound takes (bounds are at most 2^32 - 2)
+        const uint32_t c0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4u;
+        for (uint32_t rr = 0; rr < kPairRows; ++rr) {
+            const uint32_t a = blockIdx.y * kPairRows + rr;
+            for (uint32_t q = 0; q < 4; ++q) {
+                if (a < n && c0 + q < n) {
+                    lb[(size_t)a * n + c0 + q] = kEmpty;
+                    ub[(size_t)a * n + c0 + q] = kEmpty;
+                }
+            }
+        }
+        return;
+    }
+    if (status != 0) return;
     __shared__ uint32_t lbt[65], ubt[65];
     if (threadIdx.x < 65) {
         lbt[threadIdx.x] = ws[kWsLbTab + threadIdx.x];
@@ -760,6 +778,44 @@ hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
     hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, rows), dim3(256), 0,
                        stream, S, diff_log2, n, counter, surf, times, sites, ws, lb, ub);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free MRCA bounds: the workspace is a static device array that
+// the library holds, one copy per device (the array's name is a host-side
+// stand-in, so kernels take its device address, looked up once per device
+// with that device current).  Every call on a device shares its copy: calls
+// that overlap on one device race.  Nothing in the workspace needs clearing
+// first: the prepare kernel writes every word the later kernels read.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t launch_mrca_noalloc(const Scheme& scm, uint32_t n, const uint32_t* counter,
+                               const uint32_t* surf, uint32_t* lb, uint32_t* ub,
+                               hipStream_t stream) {
+    if (n == 0 || n > kNoAllocMaxN || scm.S > 64) return hipErrorInvalidValue;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    void* ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[dev]) {
+            e = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+            if (e != hipSuccess) {
+                g_scratch_ptr[dev] = nullptr;
+                return e;
+            }
+        }
+        ptr = g_scratch_ptr[dev];
+    }
+    return launch_mrca(scm, n, counter, surf, lb, ub, ptr, stream);
 }
 
 }  // namespace hsga
