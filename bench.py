@@ -102,33 +102,96 @@ def attainable_copy_gbs(torch, hs, dev, stream, nbytes: int = 512 << 20, reps: i
     return 2 * nbytes / (ms / 1000.0) / 1e9
 
 
-def cpu_baseline(spec, budget_s: float = 12.0):
-    """The oracle, single-threaded, on the first generations of the same
-    workload until the time budget is spent."""
-    sys.path.insert(0, os.path.join(ROOT, "oracle"))
-    import hsga_oracle as orc
-    if not os.path.exists(orc.LIB):
-        orc.build()
+def host_cpu() -> dict:
+    """The host's CPU model, its logical CPU count and the CPUs this process
+    may run on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model or "unknown", "nproc": os.cpu_count() or 1,
+            "usable_cpus": usable}
+
+
+def _oracle_rate(orc, spec, threads: int, budget_s: float, max_gens: int = 200) -> tuple:
+    """Births per second of the oracle on the first generations of `spec`
+    from the founders, stopping once the budget is spent."""
     r = orc.Run(spec.grid_w, spec.grid_h, spec.pop_per_island, spec.surface_sites,
                 orc.KINDS[spec.surface_kind], spec.tournament_size, spec.mut_threshold,
-                spec.mut_lo, spec.mut_hi, spec.migrants_per_island, spec.seed)
+                spec.mut_lo, spec.mut_hi, spec.migrants_per_island, spec.seed, threads=threads)
     gens = 0
     t0 = time.perf_counter()
     while True:
         r.step(1)
         gens += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or gens >= 200:
+        if el >= budget_s or gens >= max_gens:
             break
     r.close()
+    return spec.agents * gens / el, gens, el
+
+
+def cpu_baseline(spec, budget_s: float = 6.0):
+    """The oracle on the host's cores: island-parallel on the CPUs this
+    process may use (at most 16, the box's share) and single-threaded, each
+    on the first generations of the paper-scale workload; plus bounded
+    prefixes of the treatment-pair and batched workloads, extrapolated to
+    their full lengths and labelled so."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import hsga_oracle as orc
+    if not os.path.exists(orc.LIB):
+        orc.build()
+    from paper_2404_10861_amd import workloads as wl
+    cpu = host_cpu()
+    threads = max(1, min(16, cpu["usable_cpus"]))
+    rate_t, gens_t, el_t = _oracle_rate(orc, spec, threads, budget_s)
+    rate_1, gens_1, el_1 = _oracle_rate(orc, spec, 1, budget_s)
+    # the treatment pair's selection run and the 64 batched runs: a few
+    # generations each on all threads, extrapolated
+    c3 = wl.c3(True)
+    rate_c3, gens_c3, _ = _oracle_rate(orc, c3, threads, 2.0)
+    c4 = wl.c4_saved()
+    t0 = time.perf_counter()
+    c4_births = 0
+    for sp in c4:
+        r = orc.Run(sp.grid_w, sp.grid_h, sp.pop_per_island, sp.surface_sites,
+                    orc.KINDS[sp.surface_kind], sp.tournament_size, seed=sp.seed,
+                    threads=threads)
+        r.step(2)
+        r.close()
+        c4_births += sp.agents * 2
+    rate_c4 = c4_births / (time.perf_counter() - t0)
+    c4_total = sum(sp.replications for sp in c4)
     return {
-        "value": spec.agents * gens / el,
+        "value": rate_t,
         "unit": "agent-replications/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": (f"{spec.name}: the first {gens} generations from the founders "
-                   f"({spec.agents * gens:,} births in {el:.1f} s), plain C oracle, "
-                   "one thread"),
+        "sample": (f"{spec.name}: the first {gens_t} generations from the founders "
+                   f"({spec.agents * gens_t:,} births in {el_t:.1f} s), plain C oracle, "
+                   f"islands split over {threads} threads, one barrier per generation"),
+        "single_thread": {"value": rate_1, "sample": f"the first {gens_1} generations "
+                                                      f"({el_1:.1f} s), one thread"},
+        **cpu,
+        "other_workloads_extrapolated": {
+            c3.name: {"replications_per_s": rate_c3,
+                      "sample": f"the first {gens_c3} generations on {threads} threads",
+                      "extrapolated_s_for_both_treatments":
+                          2 * c3.replications / rate_c3},
+            "C4 batched, 64 runs run one after another": {
+                "replications_per_s": rate_c4,
+                "sample": f"2 generations of every run on {threads} threads",
+                "extrapolated_s_for_5000_generations": c4_total / rate_c4},
+        },
     }
 
 

@@ -395,14 +395,15 @@ int hstrat_mrca_status(const void *workspace, void *hip_stream);
 size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n);
 
 /* Enqueue the reconstruction.  counter, surface_words: as for
- * hstrat_mrca_bounds (n <= 65535).  out: device, 6 uint64 words:
- *   [0] sum of branch lengths (the mean evolutionary distinctiveness under
- *       fair proportion is this sum / n),
- *   [1] sum over unordered pairs of (T - the time of their tree MRCA)
- *       (mean pairwise distance = 2 * [1] / (n(n-1)/2)),
+ * hstrat_mrca_bounds (n <= 65535).  out: device, 8 uint64 words:
+ *   [0] sum of branch lengths,
+ *   [1] sum over unordered pairs of (T - the time of their tree MRCA),
  *   [2] root time, [3] internal nodes,
  *   [4] status: 0 ok, 1 counters differ (not reconstructed), 2 past the
- *       horizon, [5] n.
+ *       horizon, [5] n,
+ *   [6] mean evolutionary distinctiveness (fair proportion: [0] / n), and
+ *   [7] mean pairwise distance (2 * [1] / (n(n-1)/2); 0 when n = 1), both
+ *       the bits of a binary64 value; 0 when status is not 0.
  * Errors: GA_EINVAL, GA_ENOMEM (workspace), GA_EDEVICE.                    */
 int hstrat_phylo_metrics(uint32_t kind, uint32_t S, uint32_t n,
                          const uint32_t *counter, const uint32_t *surface_words,
@@ -432,6 +433,19 @@ int hstrat_phylo_tree_ex(const hstrat_scheme *scheme, uint32_t n,
                          uint32_t *leaf_parent, uint32_t *node_parent, uint32_t *node_time,
                          uint64_t *out, void *workspace, size_t workspace_bytes,
                          void *hip_stream);
+
+/* Host: the tree of hstrat_phylo_tree_ex (leaf_parent, node_parent,
+ * node_time: host copies, n and n - 1 words; T: the annotations' counter)
+ * as canonical Newick text: leaves named by annotation index, branch
+ * lengths in generations, children ordered by the smallest annotation
+ * index below them, no length on the root, "0;" when n = 1.  *length
+ * receives the text's length; text (host, cap bytes, may be NULL to size
+ * it) receives the text and a terminating NUL.
+ * Errors: GA_EINVAL (NULL, n = 0, parents out of range or not a tree),
+ * GA_ENOMEM (cap too small).                                               */
+int hstrat_phylo_newick(uint32_t n, uint32_t T, const uint32_t *leaf_parent,
+                        const uint32_t *node_parent, const uint32_t *node_time, char *text,
+                        size_t cap, size_t *length);
 
 /* Queries on annotations taken from a run (typically its ga_sample), with
  * the run's own annotation scheme, enqueued on the run's stream.  Results

@@ -724,17 +724,24 @@ typedef struct {
     orc_island *q;
     uint32_t i0, i1, g;
     int site, ingest, rc;
+    int emigrate;                     /* the emigration pass instead of births */
 } orc_task;
+
+static void emigrate_island(orc_run *r, uint32_t i, uint32_t g);
 
 static void *breed_range(void *arg)
 {
     orc_task *t = (orc_task *)arg;
-    for (uint32_t i = t->i0; i < t->i1 && t->rc == 0; i++)
-        t->rc = breed_island(t->r, t->q, i, t->g, t->site, t->ingest);
+    for (uint32_t i = t->i0; i < t->i1 && t->rc == 0; i++) {
+        if (t->emigrate)
+            emigrate_island(t->r, i, t->g);
+        else
+            t->rc = breed_island(t->r, t->q, i, t->g, t->site, t->ingest);
+    }
     return NULL;
 }
 
-static int breed_threaded(orc_run *r, uint32_t g, int site, int ingest)
+static int breed_threaded(orc_run *r, uint32_t g, int site, int ingest, int emigrate)
 {
     const uint32_t n = r->threads;
     pthread_t tid[ORC_MAX_THREADS];
@@ -749,6 +756,7 @@ static int breed_threaded(orc_run *r, uint32_t g, int site, int ingest)
         task[k].site = site;
         task[k].ingest = ingest;
         task[k].rc = 0;
+        task[k].emigrate = emigrate;
         started[k] = pthread_create(&tid[k], NULL, breed_range, &task[k]) == 0;
         if (!started[k])
             breed_range(&task[k]);   /* no thread: this range in the caller */
@@ -799,8 +807,7 @@ int orc_set_threads(void *handle, uint32_t threads)
  * Returns 0, -1 beyond the horizon, -2 on a broken invariant.               */
 static int step_one(orc_run *r)
 {
-    const uint32_t N = r->N, SW = r->SW, g = r->g;
-    uint32_t w[4];
+    const uint32_t g = r->g;
 
     /* The surface site for this generation's births.  Every parent carries
      * counter g, so every birth deposits item g at the same site: the
@@ -821,7 +828,7 @@ static int step_one(orc_run *r)
     }
 
     if (r->threads > 1) {
-        int rc = breed_threaded(r, g, site, ingest);
+        int rc = breed_threaded(r, g, site, ingest, 0);
         if (rc)
             return rc;
     } else {
@@ -832,34 +839,46 @@ static int step_one(orc_run *r)
         }
     }
 
-    /* P_{g+1} becomes current */
-    memcpy(r->trait, r->n_trait, (size_t)r->A * 4);
-    memcpy(r->counter, r->n_counter, (size_t)r->A * 4);
-    memcpy(r->surf, r->n_surf, (size_t)r->A * SW * 4);
-    for (uint32_t a = 0; a < r->A; a++)
-        r->src[a] = a;
+    /* P_{g+1} becomes current (the buffers trade places: every slot of the
+     * next population is written before it is read)                       */
+    uint32_t *tmp;
+    tmp = r->trait; r->trait = r->n_trait; r->n_trait = tmp;
+    tmp = r->counter; r->counter = r->n_counter; r->n_counter = tmp;
+    tmp = r->surf; r->surf = r->n_surf; r->n_surf = tmp;
     if (ingest)
         r->L[site] = tau;
 
-    /* Emigration: a copy of a uniformly chosen member of the new population
-     * goes into the island's outbox, addressed to a uniformly chosen
-     * cardinal neighbour; it is read in the next generation.                */
+    /* Emigration, after every island's births (the outbox the births read
+     * is overwritten): islands are independent here too.                   */
     if (r->migrants) {
-        for (uint32_t i = 0; i < r->I; i++) {
-            orc_philox(0, i, g, ORC_EMIGRATE, r->seed, w);
-            uint32_t e = orc_mulhi(w[0], N);
-            uint32_t a = i * N + e;
-            r->ob_dir[i] = w[1] >> 30;
-            r->ob_trait[i] = r->trait[a];
-            r->ob_counter[i] = r->counter[a];
-            for (uint32_t s = 0; s < SW; s++)
-                r->ob_surf[(size_t)i * SW + s] = r->surf[(size_t)a * SW + s];
-            r->ob_src[i] = a;
+        if (r->threads > 1) {
+            breed_threaded(r, g, site, ingest, 1);
+        } else {
+            for (uint32_t i = 0; i < r->I; i++)
+                emigrate_island(r, i, g);
         }
         r->has_outbox = 1;
     }
     r->g = g + 1;
     return 0;
+}
+
+/* Emigration of island i at step g: a copy of a uniformly chosen member of
+ * the new population goes into the island's outbox, addressed to a
+ * uniformly chosen cardinal neighbour; it is read in the next generation. */
+static void emigrate_island(orc_run *r, uint32_t i, uint32_t g)
+{
+    const uint32_t N = r->N, SW = r->SW;
+    uint32_t w[4];
+    orc_philox(0, i, g, ORC_EMIGRATE, r->seed, w);
+    uint32_t e = orc_mulhi(w[0], N);
+    uint32_t a = i * N + e;
+    r->ob_dir[i] = w[1] >> 30;
+    r->ob_trait[i] = r->trait[a];
+    r->ob_counter[i] = r->counter[a];
+    for (uint32_t s = 0; s < SW; s++)
+        r->ob_surf[(size_t)i * SW + s] = r->surf[(size_t)a * SW + s];
+    r->ob_src[i] = a;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -37,6 +37,7 @@ EXPORTS = (
     "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
     "ga_mrca_bounds", "ga_phylo_tree", "hstrat_mrca_bounds_noalloc",
     "hstrat_layout", "hstrat_mrca_bounds_pair", "hstrat_mrca_bounds_pair_ex", "hstrat_sites",
+    "hstrat_phylo_newick",
 )
 
 
@@ -122,6 +123,9 @@ def load_library():
         "hstrat_mrca_status": (ctypes.c_int, [_vp, _vp]),
         "hstrat_layout": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp]),
         "hstrat_sites": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32, _vp]),
+        "hstrat_phylo_newick": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, _vp, _vp, _vp,
+                                               ctypes.c_char_p, ctypes.c_size_t,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
         "hstrat_mrca_bounds_pair": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32,
                                                    ctypes.c_uint32, _vp, ctypes.c_uint32, _vp,
                                                    _vp, _vp]),
@@ -371,7 +375,7 @@ class RunHandle:
             surface_words = surface_words.contiguous()
             need = int(lib.hstrat_phylo_workspace_bytes(self.S, n))
             buf, ptr = _aligned_bytes(need, self.device)
-            out = torch.zeros(6, dtype=torch.int64, device=self.device)
+            out = torch.zeros(8, dtype=torch.int64, device=self.device)
             leaf = node_parent = node_time = None
             if tree:
                 leaf = torch.empty(n, dtype=torch.int32, device=self.device)
@@ -630,9 +634,9 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
                   stream=None, bits: int = 1, interval: int = 1) -> dict:
     """Trie reconstruction of annotations sharing a counter, on the device.
 
-    Returns the six result words (blocking copy to the host) and the derived
-    means: sum_branch_length, pair_sum, root_time, internal_nodes, status,
-    n, mean_ed (= sum_branch_length / n under fair proportion) and
+    Returns the library's eight result words (blocking copy to the host):
+    sum_branch_length, pair_sum, root_time, internal_nodes, status, n,
+    mean_ed (= sum_branch_length / n under fair proportion) and
     mean_pairwise_distance."""
     if isinstance(kind, str):
         kind = KINDS[kind]
@@ -648,7 +652,7 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
         surface_words = surface_words.contiguous()
         need = int(lib.hstrat_phylo_workspace_bytes(S, n))
         buf, ptr = _aligned_bytes(need, dev)
-        out = torch.zeros(6, dtype=torch.int64, device=dev)
+        out = torch.zeros(8, dtype=torch.int64, device=dev)
         if bits == 1 and interval == 1:
             _check(lib.hstrat_phylo_metrics(kind, S, n, _vp(counter.data_ptr()),
                                             _vp(surface_words.data_ptr()), _vp(out.data_ptr()),
@@ -665,13 +669,12 @@ def phylo_metrics(kind, S: int, counter: torch.Tensor, surface_words: torch.Tens
 
 
 def _phylo_result(w, n: int) -> dict:
-    """The six result words of a reconstruction and the derived means."""
-    res = {"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
-           "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5])}
-    npairs = n * (n - 1) // 2
-    res["mean_ed"] = res["sum_branch_length"] / n
-    res["mean_pairwise_distance"] = 2.0 * res["pair_sum"] / npairs if npairs else 0.0
-    return res
+    """The eight result words of a reconstruction (the last two are the
+    library's binary64 means)."""
+    means = np.ascontiguousarray(w[6:8], np.uint64).view(np.float64)
+    return {"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
+            "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5]),
+            "mean_ed": float(means[0]), "mean_pairwise_distance": float(means[1])}
 
 
 PHYLO_ROOT, PHYLO_NOT_NODE = 0xFFFFFFFF, 0xFFFFFFFE
@@ -696,7 +699,7 @@ def phylo_tree(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
         surface_words = surface_words.contiguous()
         need = int(lib.hstrat_phylo_workspace_bytes(S, n))
         buf, ptr = _aligned_bytes(need, dev)
-        out = torch.zeros(6, dtype=torch.int64, device=dev)
+        out = torch.zeros(8, dtype=torch.int64, device=dev)
         leaf = torch.empty(n, dtype=torch.int32, device=dev)
         node_parent = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
         node_time = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
@@ -710,57 +713,28 @@ def phylo_tree(kind, S: int, counter: torch.Tensor, surface_words: torch.Tensor,
         res = {"leaf_parent": as_u32(leaf), "node_parent": as_u32(node_parent)[:n - 1],
                "node_time": as_u32(node_time)[:n - 1]}
         del buf
-    res.update({"sum_branch_length": int(w[0]), "pair_sum": int(w[1]), "root_time": int(w[2]),
-                "internal_nodes": int(w[3]), "status": int(w[4]), "n": int(w[5]),
-                "T": int(counter[0].item()) & 0xFFFFFFFF})
+    res.update(_phylo_result(w, n))
+    res["T"] = int(counter[0].item()) & 0xFFFFFFFF
     return res
 
 
 def newick(tree: dict) -> str:
-    """Canonical Newick text of a phylo_tree result: leaves are annotation
-    indices, branch lengths generations, children ordered by the smallest
-    annotation index below them, no length on the root."""
-    leaf_parent, node_parent, node_time = (tree["leaf_parent"], tree["node_parent"],
-                                           tree["node_time"])
-    T = tree["T"]
-    n = len(leaf_parent)
-    if n == 1:
-        return "0;"
-    children: dict[int, list] = {}
-    root = None
-    for b, p in enumerate(node_parent):
-        if p == PHYLO_NOT_NODE:
-            continue
-        if p == PHYLO_ROOT:
-            root = b
-        else:
-            children.setdefault(int(p), []).append(("node", b))
-    for a, p in enumerate(leaf_parent):
-        children.setdefault(int(p), []).append(("leaf", a))
-    smallest: dict[int, int] = {}
-
-    def least(kind_id):
-        kind, i = kind_id
-        if kind == "leaf":
-            return i
-        if i not in smallest:
-            smallest[i] = min(least(c) for c in children[i])
-        return smallest[i]
-
-    def text(kind_id, parent_time):
-        kind, i = kind_id
-        if kind == "leaf":
-            body, t = str(i), T
-        else:
-            kids = sorted(children[i], key=least)
-            t = int(node_time[i])
-            body = "(" + ",".join(text(c, t) for c in kids) + ")"
-        return body if parent_time is None else f"{body}:{t - parent_time}"
-
-    import sys
-    sys.setrecursionlimit(max(sys.getrecursionlimit(), 4 * n + 100))
-    return text(("node", root), None) + ";"
-
+    """Canonical Newick text of a phylo_tree result (formatted by the
+    library's hstrat_phylo_newick): leaves are annotation indices, branch
+    lengths generations, children ordered by the smallest annotation index
+    below them, no length on the root."""
+    lib = load_library()
+    n = len(tree["leaf_parent"])
+    leaf = np.ascontiguousarray(tree["leaf_parent"], np.uint32)
+    npar = np.ascontiguousarray(tree["node_parent"], np.uint32)
+    ntime = np.ascontiguousarray(tree["node_time"], np.uint32)
+    length = ctypes.c_size_t()
+    _check(lib.hstrat_phylo_newick(n, tree["T"], _ptr(leaf), _ptr(npar), _ptr(ntime), None, 0,
+                                   ctypes.byref(length)))
+    buf = ctypes.create_string_buffer(length.value + 1)
+    _check(lib.hstrat_phylo_newick(n, tree["T"], _ptr(leaf), _ptr(npar), _ptr(ntime), buf,
+                                   length.value + 1, ctypes.byref(length)))
+    return buf.value.decode()
 
 def layout(kind, S: int, T: int, bits: int = 1, interval: int = 1) -> np.ndarray:
     """Deposit generation held by each site of an annotation with counter T

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhsga.so")
 SOURCES = [os.path.join(CSRC, f)
            for f in ("hsga_kernels.hip", "hsga_query.hip", "hsga_api.cpp", "hsga_pool.cpp",
-                     "hsga_rule.cpp")]
+                     "hsga_rule.cpp", "hsga_tree.cpp")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -47,7 +47,8 @@ Carve carve(const ga_config& cfg, uint32_t gens) {
     c.outbox = off;  off += 2 * align_up((size_t)I * hsga::kOutboxWords * 4);
     c.layout = off;  off += align_up(64 * 4);
     c.sites = off;
-    off += cfg.async_activity ? align_up(2 * sizeof(hsga::RuleTable)) : align_up((size_t)gens * 4);
+    off += cfg.async_activity ? align_up(2 * sizeof(hsga::RuleTable)) + 4 * hsga::kSiteRing
+                              : align_up((size_t)gens * 4);
     c.total = off;
     return c;
 }
@@ -131,6 +132,10 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
     r->layout = reinterpret_cast<uint32_t*>(base + c.layout);
     r->sites = cfg->async_activity ? nullptr : reinterpret_cast<uint32_t*>(base + c.sites);
     r->rules = cfg->async_activity ? reinterpret_cast<hsga::RuleTable*>(base + c.sites) : nullptr;
+    r->ring = cfg->async_activity ? reinterpret_cast<uint32_t*>(
+                                        base + c.sites + align_up(2 * sizeof(hsga::RuleTable)))
+                                  : nullptr;
+    r->ring_hi = 0;
     r->gens = gens;
     r->T = 0;
     r->horizon = hsga::horizon_gen_of(cfg->surface_kind, r->S, cfg->ingest_interval);
@@ -186,6 +191,8 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t tau0) {
     p.diff_log2 = cfg.differentia_bits == 8 ? 3u : 0u;
     p.async_thr = cfg.async_activity;
     p.rules = r->rules;
+    p.ring = r->ring;
+    p.ring_lo = r->ring_hi > hsga::kSiteRing ? r->ring_hi - hsga::kSiteRing : 0u;
     p.kind = cfg.surface_kind;
     p.S = r->S;
     p.interval = n;
@@ -325,6 +332,21 @@ int step_enqueue(ga_run* r, uint32_t n) {
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
         for (uint32_t k = 0; k < n; ++k) {
+            if ((k & (hsga::kSiteRing / 2 - 1)) == 0) {
+                // the ring takes the ingests the next half ring of ticks can
+                // reach (a parent's counter is at most the tick)
+                const uint32_t last = (uint32_t)std::min<uint64_t>(
+                    (uint64_t)r->T + k + hsga::kSiteRing / 2, (uint64_t)r->T + n);
+                const uint32_t hi = hsga::ingests_of(last, cfg.ingest_interval);
+                if (hi > r->ring_hi) {
+                    const uint32_t lo = std::max(r->ring_hi, hi > hsga::kSiteRing
+                                                                 ? hi - hsga::kSiteRing : 0u);
+                    hipError_t e = hsga::launch_fill_site_ring(r->rules, cfg.surface_kind, r->S,
+                                                               r->ring, lo, hi - lo, r->stream);
+                    if (e != hipSuccess) return hip_fail(e, "site ring launch");
+                    r->ring_hi = hi;
+                }
+            }
             const hsga::StepParams p = step_params(r, r->T + k, 0);
             hipError_t e = hsga::launch_step(p, r->SW, model, mig, r->apt, r->block, r->stream);
             if (e != hipSuccess) return hip_fail(e, "step launch");
@@ -569,6 +591,7 @@ int ga_import_state(ga_run* r, const void* host, size_t bytes) {
     // (a function of the scheme and T alone, nothing of the state)
     int rc = set_run_layout(r, T);
     if (rc != GA_OK) return rc;
+    r->ring_hi = 0;     // the next ticks refill the ring
     e = hipStreamSynchronize(r->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     r->T = T;

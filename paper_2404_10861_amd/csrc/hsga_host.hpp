@@ -23,6 +23,9 @@ struct ga_run {
     uint32_t* layout;
     uint32_t* sites;     // synchronous: the site schedule of a launch batch
     hsga::RuleTable* rules;   // asynchronous: the site rule's tables (device)
+    uint32_t* ring;      // asynchronous: sites of the latest kSiteRing ingests
+    uint32_t ring_hi;    // asynchronous: ingests below this are in the ring (the
+                         // last kSiteRing of them)
     uint32_t gens;       // site schedule capacity
     uint32_t T;          // generations (ticks, when asynchronous) enqueued
     uint64_t horizon;
@@ -60,7 +63,8 @@ inline uint32_t surface_words(const ga_config& c) {
 // Only asynchronous runs keep counter planes: in a synchronous run every
 // counter is the generation count (counter == 0 and no bytes then).  A
 // synchronous run's `sites` holds a launch batch's site schedule (gens
-// words); an asynchronous run's holds the site rule's tables instead.
+// words); an asynchronous run's holds the site rule's tables and a ring of
+// the sites of its latest ingests instead.
 Carve carve(const ga_config& cfg, uint32_t gens);
 
 // GA_OK, or GA_EINVAL with the reason in ga_last_error().

@@ -48,6 +48,9 @@ struct StepParams {
     uint32_t diff_log2;        // log2 of the differentia width: 0 (bit) or 3 (byte)
     uint32_t async_thr;        // asynchronous ticks: island activity threshold; 0: synchronous
     const RuleTable* rules;    // asynchronous ticks: the surface's site rule tables
+    const uint32_t* ring;      // asynchronous ticks: sites of ingests ring_lo .. (ring of
+                               // kSiteRing words, ingest tau at tau % kSiteRing)
+    uint32_t ring_lo;
     uint32_t kind, S;          // asynchronous ticks: the surface
     uint32_t interval;         // asynchronous ticks: the ingest interval
     uint32_t tour;             // float model: tournament draws, 1..5
@@ -105,6 +108,14 @@ hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uin
 
 // agents_per_thread (1, 2 or 4) must divide N; tile_isl * N <= block_threads *
 // agents_per_thread.
+// Asynchronous runs keep the sites of their most recent kSiteRing ingests
+// in a ring (filled from the rule's tables) for the common case, a parent
+// counter near the tick; older counters take the tables directly.
+constexpr uint32_t kSiteRing = 4096;
+hipError_t launch_fill_site_ring(const RuleTable* rules, uint32_t kind, uint32_t S,
+                                 uint32_t* ring, uint32_t tau0, uint32_t count,
+                                 hipStream_t stream);
+
 // Writes a run's layout (S words, given on the host) on the stream.
 hipError_t launch_set_layout(uint32_t* layout, const uint32_t* words, uint32_t S,
                              hipStream_t stream);

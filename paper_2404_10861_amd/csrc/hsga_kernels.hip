@@ -76,6 +76,28 @@ __global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32
     schedule_sites(kind, S, layout, sites, tau0, count);
 }
 
+// Sites of ingests tau0 .. tau0 + count - 1 into an asynchronous run's
+// ring, one thread per ingest, from the rule's constant-time tables.
+__global__ __launch_bounds__(256) void fill_site_ring_kernel(const RuleTable* __restrict__ rules,
+                                                            uint32_t kind, uint32_t S,
+                                                            uint32_t* __restrict__ ring,
+                                                            uint32_t tau0, uint32_t count) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t tau = tau0 + i;
+    ring[tau & (kSiteRing - 1u)] = scheme_site(rules, kind, S, tau);
+}
+
+hipError_t launch_fill_site_ring(const RuleTable* rules, uint32_t kind, uint32_t S,
+                                 uint32_t* ring, uint32_t tau0, uint32_t count,
+                                 hipStream_t stream) {
+    if (count == 0) return hipSuccess;
+    if (count > kSiteRing) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fill_site_ring_kernel, dim3((count + 255) / 256), dim3(256), 0, stream,
+                       rules, kind, S, ring, tau0, count);
+    return hipGetLastError();
+}
+
 // A run's layout set from the host through the kernel's arguments (so no
 // host buffer has to outlive the call).
 struct LayoutWords {
@@ -317,7 +339,9 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                 const uint32_t tau = p.interval == 1u ? T : T / p.interval;
                 dep_word = 0xffu;
                 if (tau * p.interval == T) {
-                    const uint32_t site = scheme_site(p.rules, p.kind, p.S, tau);
+                    const uint32_t site = tau >= p.ring_lo
+                                              ? p.ring[tau & (kSiteRing - 1u)]
+                                              : scheme_site(p.rules, p.kind, p.S, tau);
                     dep_word = site >> (5u - p.diff_log2);
                     dep_shift = (site << p.diff_log2) & 31u;
                 }
@@ -740,6 +764,8 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.div_magic = R.div_magic;
     p.async_thr = 0u;          // batched runs are synchronous
     p.rules = nullptr;
+    p.ring = nullptr;
+    p.ring_lo = 0u;
     p.kind = R.kind;
     p.S = R.S;
     p.interval = R.interval;

@@ -623,12 +623,22 @@ __global__ __launch_bounds__(64) void phylo_finish_kernel(uint32_t n,
     if (threadIdx.x != 0) return;
     const uint32_t status = ws[kWsStatus];
     if (status != 0) {
-        out[0] = out[1] = out[2] = out[3] = 0;
+        out[0] = out[1] = out[2] = out[3] = out[6] = out[7] = 0;
     } else {
         out[0] = acc->sbl;
         out[1] = acc->pairs;
         out[2] = n > 1 ? phylo_tau(ws, (uint32_t)acc->dmin) : ws[kWsT];
         out[3] = acc->internal;
+        // the means, as binary64: mean evolutionary distinctiveness under
+        // fair proportion (each edge shared equally by the leaves below it)
+        // is the sum of branch lengths over n; the mean pairwise distance
+        // is twice the pair sum over the n(n-1)/2 pairs (a path runs from
+        // each leaf up to their MRCA)
+        const double pairs = (double)n * (double)(n - 1) * 0.5;
+        const double ed = (double)acc->sbl / (double)n;
+        const double mpd = n > 1 ? 2.0 * (double)acc->pairs / pairs : 0.0;
+        out[6] = (uint64_t)__double_as_longlong(ed);
+        out[7] = (uint64_t)__double_as_longlong(mpd);
     }
     out[4] = status;
     out[5] = n;
