@@ -516,7 +516,26 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         }
     }
     __builtin_amdgcn_s_setprio(0);
-    if (MIGR || ASYNC) {
+    if (MIGR && !ASYNC && 2u * nisl <= blockDim.x) {
+        // one Philox evaluation for both island draws: lanes t < nisl draw
+        // island t's immigration block, lanes nisl .. 2 nisl - 1 the
+        // emigration block of island t - nisl (the same blocks as two
+        // separate passes, without a second divergent evaluation)
+        const bool imm_lane = t < nisl;
+        if (t < 2u * nisl) {
+            const uint32_t il = imm_lane ? t : t - nisl;
+            const uint32_t isl = first_isl + il;
+            const uint4 w4 = philox4x32_10(
+                make_uint4(0u, isl, p.g, imm_lane ? kImmigrate : kEmigrate), p.k0, p.k1);
+            if (!imm_lane) {
+                l_emig[il] = word_below(w4.x, N) | ((w4.y >> 30) << 8);
+            } else if (p.has_inbox) {
+                imm_slots = word_below(w4.x, N) | (word_below(w4.y, N) << 6) |
+                            (word_below(w4.z, N) << 12) | (word_below(w4.w, N) << 18);
+                imm_take = true;
+            }
+        }
+    } else if (MIGR || ASYNC) {
         // asynchronous ticks: an island runs a generation iff its activity
         // draw is below the threshold (plan bit 31); an idle island takes no
         // immigrants and posts no emigrant (direction 4)
