@@ -62,13 +62,14 @@ def store_cache(key: str, choice: dict):
 
 
 def tune_online(pool, key: str | None = None, candidates=DEFAULT_CANDIDATES,
-                use_cache: bool = True) -> dict:
+                use_cache: bool = True, repeats: int = 2) -> dict:
     """Pick the pool's launch shape while advancing its runs.
 
     Returns {"block_threads", "gens_per_launch", "use_graph", "trials"}; the
     pool is left set to the choice.  Candidates are tried until the runs
-    finish; a hipGraph candidate is timed on its second advance (the first
-    one captures the graph).
+    finish; each is timed over `repeats` advances and its fastest counts; a
+    hipGraph candidate's timed advances follow the one that captures the
+    graph.  A candidate timed fewer times (the runs ran out) still counts.
     """
     if use_cache and key is not None:
         hit = load_cache().get(key)
@@ -78,6 +79,7 @@ def tune_online(pool, key: str | None = None, candidates=DEFAULT_CANDIDATES,
             hit["cached"] = True
             return hit
     trials = []
+    done = False
     for block, gens, graph in candidates:
         pool.set_launch(block, graph)
         pool.sync()
@@ -85,14 +87,23 @@ def tune_online(pool, key: str | None = None, candidates=DEFAULT_CANDIDATES,
             if pool.advance(gens) == 0:
                 break
             pool.sync()
-        t0 = time.perf_counter()
-        n = pool.advance(gens)
-        pool.sync()
-        dt = time.perf_counter() - t0
-        if n == 0:
+        # at least two timed advances per candidate (the faster one counts),
+        # so that one noisy advance does not decide
+        times = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            n = pool.advance(gens)
+            pool.sync()
+            dt = time.perf_counter() - t0
+            if n == 0:
+                done = True
+                break
+            times.append(dt / n)
+        if times:
+            trials.append({"block_threads": block, "gens_per_launch": gens, "use_graph": graph,
+                           "s_per_generation": min(times), "timings": times})
+        if done:
             break
-        trials.append({"block_threads": block, "gens_per_launch": gens, "use_graph": graph,
-                       "s_per_generation": dt / n})
     if not trials:
         choice = {"block_threads": 64, "gens_per_launch": 64, "use_graph": False}
     else:

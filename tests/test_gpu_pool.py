@@ -208,3 +208,57 @@ def test_cancel_and_resubmit(hs, use_graph):
         assert np.array_equal(got.export_state(), alone.export_state())
         alone.close()
     pool.close()
+
+
+def test_autotuner_times_each_candidate_twice_and_caches(hs, tmp_path, monkeypatch):
+    """The online autotuner advances the real runs under every candidate
+    shape at least twice, keeps the fastest candidate, caches it under the
+    run set's key, and a second tuning reads the cache; the runs end equal
+    to the same runs alone."""
+    from paper_2404_10861_amd import autotune
+    monkeypatch.setenv("HSGA_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    specs = mixed_specs()[:6]
+    for sp in specs:
+        sp.generations = 2000
+    pool = hs.Pool(256 << 20, max_runs=8, max_gens_per_launch=64)
+    ids = [pool.admit(hs.Config(**sp.config_kwargs()), sp.generations) for sp in specs]
+    key = autotune.signature(specs)
+    cands = ((64, 16, False), (128, 16, True), (256, 16, True))
+    choice = autotune.tune_online(pool, key=key, candidates=cands)
+    assert not choice["cached"] and len(choice["trials"]) == 3
+    assert all(len(t["timings"]) == 2 for t in choice["trials"])
+    best = min(choice["trials"], key=lambda t: t["s_per_generation"])
+    assert choice["block_threads"] == best["block_threads"]
+    assert autotune.load_cache()[key]["block_threads"] == choice["block_threads"]
+    again = autotune.tune_online(pool, key=key, candidates=cands)
+    assert again["cached"] and again["block_threads"] == choice["block_threads"]
+    while pool.advance(64):
+        pass
+    for rid, sp in zip(ids, specs):
+        run = pool.run(rid)
+        assert run.generation == sp.generations
+        same((run.agents(), run.outbox(), run.layout()), alone_state(hs, sp))
+    pool.close()
+
+
+def test_pool_runs_refuse_plain_step_and_destroy(hs):
+    """A pool's run is advanced by the pool only: ga_step refuses it and
+    ga_destroy leaves it alone (the pool frees it on release)."""
+    import ctypes
+    lib = hs.load_library()
+    pool = hs.Pool(32 << 20, max_runs=2, max_gens_per_launch=16)
+    rid = pool.admit(hs.Config(4, 4, 16, 32, "tilted", seed=3), 40)
+    run = pool.run(rid)
+    assert lib.ga_step(run._h, 1) == hs.GA_EINVAL
+    assert b"pool" in lib.ga_last_error()
+    lib.ga_destroy(run._h)                     # ignored
+    assert b"pool" in lib.ga_last_error()
+    while pool.advance(16):
+        pass
+    assert pool.run(rid).generation == 40
+    alone = hs.Run(hs.Config(4, 4, 16, 32, "tilted", seed=3))
+    alone.step(40)
+    for x, y in zip(pool.run(rid).agents(), alone.agents()):
+        assert np.array_equal(x, y)
+    pool.release(rid)
+    pool.close()
