@@ -124,7 +124,8 @@ typedef struct ga_run ga_run;
  *   - the run's surface layout (deposit time of each site) and, for a
  *     synchronous run, a site schedule of max_gens_per_launch words (an
  *     asynchronous run holds the site rule's constant-time tables there,
- *     about 19 KB).
+ *     two of about 25 KB, and a ring of the sites of its next 4,096
+ *     ingests).
  * An agent record is (uint32 trait, uint32 generation counter, S one-bit
  * differentia sites); site k is bit k&31 of surface word k>>5.
  * ------------------------------------------------------------------------ */
@@ -292,7 +293,14 @@ typedef struct hstrat_scheme {
     uint32_t ingest_interval;  /* >= 1                                      */
 } hstrat_scheme;
 
-/* Device workspace bytes hstrat_mrca_bounds needs for n annotations. */
+/* Device workspace bytes hstrat_mrca_bounds needs for n annotations: the
+ * flag word, ranked annotations and per-annotation layouts, then the
+ * surface's site rule tables (about 51 KB), which each call uploads from
+ * pinned host copies the library keeps (made on a scheme's first query)
+ * and the kernels read to lay every annotation out in constant time per
+ * site (Distributed Phylogenetic Tracking: deposit times follow from the
+ * site index and the generation count; Surface-based Hereditary
+ * Stratigraphy Algorithms: constant-time indexing).                       */
 size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n);
 
 /* Enqueue all n*n ordered pairs.  counter: device, n words; surface_words:
@@ -362,7 +370,10 @@ int hstrat_mrca_bounds_pair_ex(const hstrat_scheme *scheme, uint32_t Ta, const u
  * until the process ends; this call allocates nothing.  Results are those
  * of hstrat_mrca_bounds, except that a counter past the site rule's horizon
  * (which hstrat_mrca_status would report) makes every lb and ub 0xFFFFFFFF,
- * a value no bound takes.  n <= 4096; the current device must be the one
+ * a value no bound takes.  Having no room for the site rule's tables, the
+ * kernels replay each layout one placement per ingest, so counters must
+ * stay at or below 2^24 ingests (above, the same 0xFFFFFFFF).
+ * n <= 4096; the current device must be the one
  * hip_stream and the buffers belong to.  Every call on a device shares that
  * device's array, so calls that overlap on one device race: order them on
  * one stream or synchronise between them.
@@ -391,7 +402,8 @@ int hstrat_mrca_status(const void *workspace, void *hip_stream);
  * is the first branching node.
  * ------------------------------------------------------------------------ */
 
-/* Device workspace bytes of hstrat_phylo_metrics for n annotations. */
+/* Device workspace bytes of hstrat_phylo_metrics for n annotations (as
+ * for hstrat_mrca_workspace_bytes, the site rule tables included).       */
 size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n);
 
 /* Enqueue the reconstruction.  counter, surface_words: as for
@@ -453,10 +465,10 @@ int hstrat_phylo_newick(uint32_t n, uint32_t T, const uint32_t *leaf_parent,
  * is a function of the scheme and the generation count alone (Distributed
  * Phylogenetic Tracking: deposit times follow from the site index and the
  * count).  So when every counter equals the run's generation count T, the
- * run's own layout at T is used instead of replaying the site rule from
- * the empty layout, which is one placement per generation.  Otherwise
- * (a sample taken before later steps, drifted asynchronous counters) the
- * query replays as the hstrat_ calls do.  ga_phylo_tree with leaf_parent
+ * run's own layout at T is used as it stands.  Otherwise (a sample taken
+ * before later steps, drifted asynchronous counters) the query lays each
+ * annotation out from the site rule's tables as the hstrat_ calls do;
+ * both give the same words.  ga_phylo_tree with leaf_parent
  * NULL computes the metrics only (node_parent and node_time unused).
  * Errors as the hstrat_ calls, and GA_EINVAL for a NULL run.               */
 int ga_mrca_bounds(ga_run *run, uint32_t n, const uint32_t *counter,

@@ -8,8 +8,10 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "hsga_host.hpp"
@@ -616,9 +618,58 @@ void ga_destroy(ga_run* r) {
 
 const char* ga_last_error(void) { return last_error(); }
 
-size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n) {
-    return hsga::MrcaWorkspace::bytes(S, n);
+namespace {
+// Query workspaces: the MRCA or reconstruction workspace proper, then the
+// surface's site rule tables, which the query kernels read to lay out an
+// annotation in constant time.
+size_t aligned256(size_t x) { return (x + 255) & ~(size_t)255; }
+size_t mrca_total_bytes(uint32_t S, uint32_t n) {
+    return aligned256(hsga::MrcaWorkspace::bytes(S, n)) + hsga::kRuleRegionBytes;
 }
+size_t phylo_total_bytes(uint32_t S, uint32_t n) {
+    return aligned256(hsga::phylo_workspace_bytes(S, n)) + hsga::kRuleRegionBytes;
+}
+
+// Pinned host copies of the cached rule tables, made on first use and kept
+// until the process ends, so that a query's upload of them is an ordinary
+// stream copy (a copy from pageable memory may hold the host until the
+// stream has drained).  Pageable tables when pinned memory is refused.
+std::mutex g_pinned_mutex;
+std::vector<std::pair<const hsga::RuleTable*, hsga::RuleTable*>> g_pinned;
+
+const hsga::RuleTable* pinned_table(const hsga::RuleTable* t) {
+    std::lock_guard<std::mutex> lock(g_pinned_mutex);
+    for (auto& pr : g_pinned)
+        if (pr.first == t) return pr.second ? pr.second : t;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(hsga::RuleTable), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    } else {
+        std::memcpy(p, t, sizeof(hsga::RuleTable));
+    }
+    g_pinned.emplace_back(t, static_cast<hsga::RuleTable*>(p));
+    return p ? static_cast<hsga::RuleTable*>(p) : t;
+}
+
+// Enqueue the upload of the scheme's tables to `region` (kRuleRegionBytes,
+// 256-byte aligned) on `stream`; the LayoutHint that reads them.
+hipError_t upload_rules(const hsga::Scheme& sc, uint8_t* region, hipStream_t stream,
+                        hsga::LayoutHint* hint) {
+    const hsga::RuleTable* tabs[2] = {nullptr, nullptr};
+    if (!hsga::scheme_rules(sc.kind, sc.S, tabs)) return hipErrorInvalidValue;
+    auto* dev = reinterpret_cast<hsga::RuleTable*>(region);
+    for (int k = 0; k < 2 && tabs[k]; ++k) {
+        hipError_t e = hipMemcpyAsync(dev + k, pinned_table(tabs[k]), sizeof(hsga::RuleTable),
+                                      hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return e;
+    }
+    hint->rules = dev;
+    return hipSuccess;
+}
+}  // namespace
+
+size_t hstrat_mrca_workspace_bytes(uint32_t S, uint32_t n) { return mrca_total_bytes(S, n); }
 
 namespace {
 int check_scheme(const hstrat_scheme* sc, hsga::Scheme* out) {
@@ -644,10 +695,14 @@ int hstrat_mrca_bounds_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_
     if (!counter || !surface_words || !lb || !ub || !workspace)
         return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::MrcaWorkspace::bytes(sc.S, n))
-        return fail(GA_ENOMEM, "workspace too small");
-    hipError_t e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace,
-                                     static_cast<hipStream_t>(hip_stream));
+    if (workspace_bytes < mrca_total_bytes(sc.S, n)) return fail(GA_ENOMEM, "workspace too small");
+    const auto stream = static_cast<hipStream_t>(hip_stream);
+    hsga::LayoutHint hint;
+    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
+                                        aligned256(hsga::MrcaWorkspace::bytes(sc.S, n)),
+                                stream, &hint);
+    if (e != hipSuccess) return hip_fail(e, "site rule upload");
+    e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace, stream, hint);
     if (e != hipSuccess) return hip_fail(e, "mrca launch");
     return GA_OK;
 }
@@ -662,12 +717,15 @@ int ga_mrca_bounds(ga_run* r, uint32_t n, const uint32_t* counter,
     if (!counter || !surface_words || !lb || !ub || !workspace)
         return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::MrcaWorkspace::bytes(sc.S, n))
-        return fail(GA_ENOMEM, "workspace too small");
+    if (workspace_bytes < mrca_total_bytes(sc.S, n)) return fail(GA_ENOMEM, "workspace too small");
     // on the run's stream: the layout is read after the steps enqueued so
     // far and before any later ones advance it
-    hipError_t e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace, r->stream,
-                                     hsga::LayoutHint{r->layout, r->T});
+    hsga::LayoutHint hint{r->layout, r->T};
+    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
+                                        aligned256(hsga::MrcaWorkspace::bytes(sc.S, n)),
+                                r->stream, &hint);
+    if (e != hipSuccess) return hip_fail(e, "site rule upload");
+    e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace, r->stream, hint);
     if (e != hipSuccess) return hip_fail(e, "mrca launch");
     return GA_OK;
 }
@@ -683,11 +741,15 @@ int ga_phylo_tree(ga_run* r, uint32_t n, const uint32_t* counter, const uint32_t
         (leaf_parent && n > 1 && (!node_parent || !node_time)))
         return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::phylo_workspace_bytes(sc.S, n))
+    if (workspace_bytes < phylo_total_bytes(sc.S, n))
         return fail(GA_ENOMEM, "workspace too small");
-    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, r->stream,
-                                      leaf_parent, node_parent, node_time,
-                                      hsga::LayoutHint{r->layout, r->T});
+    hsga::LayoutHint hint{r->layout, r->T};
+    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
+                                        aligned256(hsga::phylo_workspace_bytes(sc.S, n)),
+                                r->stream, &hint);
+    if (e != hipSuccess) return hip_fail(e, "site rule upload");
+    e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, r->stream, leaf_parent,
+                           node_parent, node_time, hint);
     if (e != hipSuccess) return hip_fail(e, "phylo launch");
     return GA_OK;
 }
@@ -717,9 +779,7 @@ int hstrat_mrca_bounds_noalloc(uint32_t kind, uint32_t S, uint32_t n, const uint
     return GA_OK;
 }
 
-size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n) {
-    return hsga::phylo_workspace_bytes(S, n);
-}
+size_t hstrat_phylo_workspace_bytes(uint32_t S, uint32_t n) { return phylo_total_bytes(S, n); }
 
 int hstrat_phylo_metrics_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_t* counter,
                             const uint32_t* surface_words, uint64_t* out, void* workspace,
@@ -730,10 +790,16 @@ int hstrat_phylo_metrics_ex(const hstrat_scheme* scheme, uint32_t n, const uint3
     if (n == 0 || n > 65535) return fail(GA_EINVAL, "n must be 1..65535");
     if (!counter || !surface_words || !out || !workspace) return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::phylo_workspace_bytes(sc.S, n))
+    if (workspace_bytes < phylo_total_bytes(sc.S, n))
         return fail(GA_ENOMEM, "workspace too small");
-    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace,
-                                      static_cast<hipStream_t>(hip_stream));
+    const auto stream = static_cast<hipStream_t>(hip_stream);
+    hsga::LayoutHint hint;
+    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
+                                        aligned256(hsga::phylo_workspace_bytes(sc.S, n)),
+                                stream, &hint);
+    if (e != hipSuccess) return hip_fail(e, "site rule upload");
+    e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, stream, nullptr,
+                           nullptr, nullptr, hint);
     if (e != hipSuccess) return hip_fail(e, "phylo launch");
     return GA_OK;
 }
@@ -750,11 +816,16 @@ int hstrat_phylo_tree_ex(const hstrat_scheme* scheme, uint32_t n, const uint32_t
         (n > 1 && (!node_parent || !node_time)))
         return fail(GA_EINVAL, "NULL buffer");
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
-    if (workspace_bytes < hsga::phylo_workspace_bytes(sc.S, n))
+    if (workspace_bytes < phylo_total_bytes(sc.S, n))
         return fail(GA_ENOMEM, "workspace too small");
-    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace,
-                                      static_cast<hipStream_t>(hip_stream), leaf_parent,
-                                      node_parent, node_time);
+    const auto stream = static_cast<hipStream_t>(hip_stream);
+    hsga::LayoutHint hint;
+    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
+                                        aligned256(hsga::phylo_workspace_bytes(sc.S, n)),
+                                stream, &hint);
+    if (e != hipSuccess) return hip_fail(e, "site rule upload");
+    e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, stream, leaf_parent,
+                           node_parent, node_time, hint);
     if (e != hipSuccess) return hip_fail(e, "phylo tree launch");
     return GA_OK;
 }

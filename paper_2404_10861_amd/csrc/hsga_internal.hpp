@@ -154,7 +154,15 @@ struct MrcaWorkspace {
 struct LayoutHint {
     const uint32_t* layout = nullptr;
     uint32_t T = 0;
+    // the surface's site rule tables on the device (one, or two for hybrid)
+    // in scheme_site's order: layouts from their closed form; nullptr:
+    // replayed one placement per ingest
+    const RuleTable* rules = nullptr;
 };
+
+// Bytes a query's workspace keeps for the rule's tables (after the
+// MRCA or reconstruction workspace proper).
+constexpr size_t kRuleRegionBytes = (2 * sizeof(RuleTable) + 255) & ~(size_t)255;
 
 size_t phylo_workspace_bytes(uint32_t S, uint32_t n);
 // leaf_parent (n), node_parent and node_time (n - 1), all device: the tree

@@ -77,6 +77,14 @@ __device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uin
     return held;
 }
 
+// The item lane's site holds after T ingests: from the rule's tables when
+// the query has them (constant time per site), else by the replay.
+__device__ __forceinline__ uint32_t layout_lane(const RuleTable* rules, uint32_t kind, uint32_t S,
+                                                uint32_t T, uint32_t lane) {
+    if (rules) return scheme_item_at(rules, kind, S, T, lane);
+    return replay_layout(kind, S, T, lane);
+}
+
 // Classify the counters (four wavefronts); when all are equal, wavefront 0
 // replays the shared layout once (in ingest units), orders its sites by
 // deposit time and tabulates the bounds, in generations, for every possible
@@ -87,7 +95,7 @@ __device__ __forceinline__ uint32_t replay_layout(uint32_t kind, uint32_t S, uin
 constexpr uint32_t kPrepareThreads = 256;   // 4 wavefronts classify; wave 0 does the rest
 __global__ __launch_bounds__(kPrepareThreads) void mrca_prepare_kernel(
     Scheme sc, uint32_t n, const uint32_t* __restrict__ counter, uint32_t* __restrict__ ws,
-    const uint32_t* __restrict__ hint, uint32_t hint_T) {
+    const uint32_t* __restrict__ hint, uint32_t hint_T, const RuleTable* __restrict__ rules) {
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
     const uint32_t S = sc.S;
@@ -124,7 +132,7 @@ __global__ __launch_bounds__(kPrepareThreads) void mrca_prepare_kernel(
     for (uint32_t w = 0; w < kPrepareThreads / 64; ++w) f |= flags[w];
     const bool all_same = (f & 1u) == 0;
     const bool hinted = all_same && hint && T0 == hint_T;
-    const bool any_past = (f & 2u) != 0 || (!hinted && (f & 4u) != 0);
+    const bool any_past = (f & 2u) != 0 || (!hinted && !rules && (f & 4u) != 0);
     if (any_past || !all_same) {                 // the same decision in every thread
         if (tid == 0) {
             ws[kWsStatus] = any_past ? kWsStatusHorizon : kWsStatusMixed;
@@ -136,8 +144,8 @@ __global__ __launch_bounds__(kPrepareThreads) void mrca_prepare_kernel(
     uint32_t F = 0;
     if (tid < 64) {                              // wavefront 0: lane = site
         const uint32_t held = hinted ? (lane < S ? hint[lane] : kEmpty)
-                                     : replay_layout(sc.kind, S, ingests_of(T0, sc.interval),
-                                                     lane);
+                                     : layout_lane(rules, sc.kind, S,
+                                                   ingests_of(T0, sc.interval), lane);
         const uint32_t rank = time_rank(held, lane, S);
         F = (uint32_t)__popcll(__ballot(lane < S && held != kEmpty));
         if (lane < S) {
@@ -263,12 +271,13 @@ __global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc,
                                                          const uint32_t* __restrict__ counter,
                                                          const uint32_t* __restrict__ ws,
                                                          uint32_t* __restrict__ times,
-                                                         uint8_t* __restrict__ sites) {
+                                                         uint8_t* __restrict__ sites,
+                                                         const RuleTable* __restrict__ rules) {
     if (ws[kWsStatus] != kWsStatusMixed) return;
     const uint32_t a = blockIdx.x;
     const uint32_t lane = threadIdx.x;
     const uint32_t S = sc.S;
-    const uint32_t held = replay_layout(sc.kind, S, ingests_of(counter[a], sc.interval), lane);
+    const uint32_t held = layout_lane(rules, sc.kind, S, ingests_of(counter[a], sc.interval), lane);
     const uint32_t rank = time_rank(held, lane, S);
     if (lane < S) {
         times[(size_t)a * S + rank] = held == kEmpty ? kEmpty : held * sc.interval;
@@ -738,7 +747,7 @@ hipError_t launch_phylo(const Scheme& scm, uint32_t n, const uint32_t* counter,
     while (levels < kPhyloMaxLevels && (2u << (levels - 1)) <= m) ++levels;
     const uint32_t gn = (n + 255) / 256;
     hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(kPrepareThreads), 0, stream, scm, n,
-                       counter, ws, hint.layout, hint.T);
+                       counter, ws, hint.layout, hint.T, hint.rules);
     hipLaunchKernelGGL(mrca_rank_kernel, dim3(gn), dim3(256), 0, stream, scm.S, diff_log2, n,
                        surf, ws, ranked);
     hipLaunchKernelGGL(phylo_keys_kernel, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0,
@@ -777,13 +786,13 @@ hipError_t launch_mrca(const Scheme& scm, uint32_t n, const uint32_t* counter,
     uint8_t* sites = base + MrcaWorkspace::kHeader + ranked_bytes + times_bytes;
 
     hipLaunchKernelGGL(mrca_prepare_kernel, dim3(1), dim3(kPrepareThreads), 0, stream, scm, n,
-                       counter, ws, hint.layout, hint.T);
+                       counter, ws, hint.layout, hint.T, hint.rules);
     hipLaunchKernelGGL(mrca_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, S,
                        diff_log2, n, surf, ws, ranked);
     hipLaunchKernelGGL(mrca_allpairs_kernel, dim3((n + 1023) / 1024, (n + kPairRows - 1) / kPairRows),
                        dim3(256), 0, stream, n, diff_log2, ranked, ws, lb, ub);
     hipLaunchKernelGGL(mrca_layouts_kernel, dim3(n), dim3(64), 0, stream, scm, counter, ws,
-                       times, sites);
+                       times, sites, hint.rules);
     const uint32_t rows = n < kGeneralPairRows ? n : kGeneralPairRows;
     hipLaunchKernelGGL(mrca_general_pairs_kernel, dim3((n + 255) / 256, rows), dim3(256), 0,
                        stream, S, diff_log2, n, counter, surf, times, sites, ws, lb, ub);

@@ -23,24 +23,15 @@ uint32_t ctz64(uint64_t x) { return (uint32_t)__builtin_ctzll(x); }
 // Item t of level h, index c: t + 1 = (2c + 1) 2^h.
 uint64_t level_item(uint32_t h, uint64_t c) { return ((2 * c + 1) << h) - 1; }
 
-// The tables of one sub-surface plus what layouts need: the layout at each
-// steady epoch start, and for tilted epochs the free sites at the start
-// (with the items they still hold) and the events in time order.
+// The tables of one sub-surface and the last local time they cover.
 struct RuleHost {
     RuleTable t;
-    uint64_t last = 0;   // last local time covered
+    uint64_t last = 0;
     struct Event {
         uint64_t u;
         uint32_t key;
         uint32_t site;
     };
-    struct Epoch {
-        std::vector<uint32_t> layout0;   // steady: items at E_j, before E_j is placed
-        uint64_t free0 = 0;              // tilted: free sites at the epoch start
-        std::vector<uint32_t> stale0;    // tilted: the items they hold
-        std::vector<Event> events;       // tilted: time order
-    };
-    std::vector<Epoch> ep;
 };
 
 uint64_t horizon_local(uint32_t policy, uint32_t m) {
@@ -66,14 +57,15 @@ void build_steady(RuleHost& H, uint32_t m) {
         if (E > H.last) break;
         const uint32_t e = j - T.first;
         T.start[e] = (uint32_t)E;
-        RuleHost::Epoch ex;
-        ex.layout0 = L;
         std::vector<uint32_t> pool;
         for (uint32_t k = 0; k < m; ++k)
             if (!retained(kSteady, m, E, L[k])) pool.push_back(k);
-        for (uint32_t k = 0; k < 64; ++k)
+        for (uint32_t k = 0; k < 64; ++k) {
             T.site0[e][k] = k < pool.size() ? (uint8_t)pool[k] : kRuleNoSite;
-        H.ep.push_back(std::move(ex));
+            T.layout0[e][k] = k < m ? L[k] : kRuleEmptyItem;
+            T.pool_pos[e][k] = kRuleNoSite;
+        }
+        for (uint32_t k = 0; k < pool.size(); ++k) T.pool_pos[e][pool[k]] = (uint8_t)k;
         T.n_epochs = e + 1;
         // the layout at the next epoch start: the multiples of 2^j of this
         // epoch on the pool's first sites, its last item on the next one
@@ -107,21 +99,24 @@ void build_tilted(RuleHost& H, uint32_t m) {
         std::memset(chain, kRuleNoSite, sizeof chain);
         uint64_t free_mask = 0;
         std::vector<uint32_t> stale(m, 0);
+        for (uint32_t k = 0; k < 64; ++k) {
+            T.chain_of[e][k] = kRuleNoSite;
+            T.layout0[e][k] = k < m ? (uint32_t)L[k] : kRuleEmptyItem;
+        }
         for (uint32_t k = 0; k < m; ++k) {
             const uint64_t t = L[k];
             if (retained(kTilted, m, u, t)) {
                 const uint32_t h = ctz64(t + 1);
                 const uint64_t c = (t + 1) >> (h + 1);
                 chain[h * r + (uint32_t)(c % r)] = (uint8_t)k;
+                T.chain_of[e][k] = (uint8_t)(h * r + (uint32_t)(c % r));
             } else {
                 free_mask |= 1ull << k;
                 stale[k] = (uint32_t)t;
             }
         }
         std::memcpy(T.site0[e], chain, sizeof chain);
-        RuleHost::Epoch ex;
-        ex.free0 = free_mask;
-        ex.stale0 = stale;
+        std::vector<RuleHost::Event> events;
         const uint64_t u_end = std::min<uint64_t>((1ull << B) - 1, H.last + 1);
         // jump from event to event: between events every item takes its
         // chain's site and nothing else changes
@@ -152,7 +147,7 @@ void build_tilted(RuleHost& H, uint32_t m) {
             const uint32_t s = ctz64(F);
             free_mask = F & ~(1ull << s);
             chain[key] = (uint8_t)s;
-            ex.events.push_back({u, key, s});
+            events.push_back({u, key, s});
             ++u;
         }
         // the layout at the end of the epoch: each chain's newest item
@@ -165,16 +160,24 @@ void build_tilted(RuleHost& H, uint32_t m) {
         }
         for (uint32_t k = 0; k < m; ++k)
             if ((free_mask >> k) & 1) L[k] = stale[k];
-        // events grouped by chain for the constant-time lookup
-        if (n_ev + ex.events.size() > kRuleEvents) {
+        // events grouped by chain for the constant-time lookup, and in time
+        // order for layouts
+        if (n_ev + events.size() > kRuleEvents) {
             T.n_epochs = 0;                 // more events than the table holds
             return;
         }
+        T.evt_begin[e] = (uint16_t)n_ev;
+        for (size_t i = 0; i < events.size(); ++i) {
+            T.evt_u[n_ev + i] = (uint32_t)events[i].u;
+            T.evt_key[n_ev + i] = (uint8_t)events[i].key;
+            T.evt_site[n_ev + i] = (uint8_t)events[i].site;
+        }
+        T.evt_begin[e + 1] = (uint16_t)(n_ev + events.size());
         uint32_t pos = n_ev;
         for (uint32_t key = 0; key <= 64; ++key) {
             T.ev_begin[e][key] = (uint16_t)pos;
             if (key == 64) break;
-            for (const auto& ev : ex.events)
+            for (const auto& ev : events)
                 if (ev.key == key) {
                     T.ev_u[pos] = (uint32_t)ev.u;
                     T.ev_site[pos] = (uint8_t)ev.site;
@@ -182,7 +185,6 @@ void build_tilted(RuleHost& H, uint32_t m) {
                 }
         }
         n_ev = pos;
-        H.ep.push_back(std::move(ex));
         u = (1ull << B) - 1;
     }
 }
@@ -220,49 +222,8 @@ uint64_t rule_last(uint32_t policy, uint32_t m) { return horizon_local(policy, m
 
 void rule_layout(uint32_t policy, uint32_t m, uint64_t U, uint32_t* L) {
     const RuleHost* H = rule_host(policy, m);
-    for (uint32_t k = 0; k < m; ++k) L[k] = k < U ? k : kRuleEmpty;
-    if (!H || U <= m) return;
-    const RuleTable& T = H->t;
-    const uint64_t u = U - 1;                       // the newest item
-    if (policy == kSteady) {
-        const uint32_t j = rule_bitlen(u / (m - 1));
-        const uint32_t e = j - T.first;
-        const RuleHost::Epoch& ex = H->ep[e];
-        for (uint32_t k = 0; k < m; ++k) L[k] = ex.layout0[k];
-        const uint64_t step = 1ull << j;
-        const uint64_t first = ((uint64_t)T.start[e] + step - 1) >> j;
-        const uint64_t cnt = ((u + step - 1) >> j) - first;   // multiples of 2^j in [E_j, u)
-        for (uint64_t k = 0; k < cnt; ++k) L[T.site0[e][k]] = (uint32_t)((first + k) << j);
-        L[T.site0[e][cnt]] = (uint32_t)u;
-        return;
-    }
-    const uint32_t B = rule_bitlen(u + 1);
-    const uint32_t e = B - T.first;
-    const uint32_t r = T.r[e];
-    const RuleHost::Epoch& ex = H->ep[e];
-    uint8_t chain[64];
-    std::memcpy(chain, T.site0[e], sizeof chain);
-    uint64_t free_mask = ex.free0;
-    std::vector<uint32_t> stale = ex.stale0;
-    for (const auto& ev : ex.events) {
-        if (ev.u > u) break;
-        const uint32_t h = ctz64(ev.u + 1);
-        const uint64_t c = (ev.u + 1) >> (h + 1);
-        if (c >= r && chain[ev.key] != kRuleNoSite) {
-            free_mask |= 1ull << chain[ev.key];
-            stale[chain[ev.key]] = (uint32_t)level_item(h, c - r);
-        }
-        free_mask &= ~(1ull << ev.site);
-        chain[ev.key] = (uint8_t)ev.site;
-    }
-    for (uint32_t key = 0; key < B * r; ++key) {
-        if (chain[key] == kRuleNoSite) continue;
-        const uint32_t h = key / r, q = key % r;
-        const uint64_t cmax = ((U >> h) - 1) / 2;
-        L[chain[key]] = (uint32_t)level_item(h, cmax - (cmax + r - q) % r);
-    }
     for (uint32_t k = 0; k < m; ++k)
-        if ((free_mask >> k) & 1) L[k] = stale[k];
+        L[k] = H ? rule_item_at(H->t, U, k) : (k < U ? k : kRuleEmpty);
 }
 
 bool scheme_rules(uint32_t kind, uint32_t S, const RuleTable** out) {

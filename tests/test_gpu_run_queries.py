@@ -148,11 +148,12 @@ def test_errors(hs):
     assert rc == hs.binding.GA_EINVAL
 
 
-def test_runs_past_the_replay_bound(hs, orc):
-    """A replaying query refuses counters above 2^24 (one placement per
-    generation); the run-bound query uses the run's layout and answers.  The
-    run reaches T = 2^24 + 123 by importing a state, whose import rebuilds
-    the layout on the device."""
+def test_counters_in_the_millions(hs, orc):
+    """Counters above 2^24: the run-bound query uses the run's layout, the
+    plain query lays annotations out from the site rule's closed form, and
+    both equal the oracle (which replays every placement), also for mixed
+    counters.  The run reaches T = 2^24 + 123 by importing a state, whose
+    import lays the surface out on the device."""
     cfg = hs.Config(1, 1, 4, 64, "hybrid", seed=7)
     T = (1 << 24) + 123
     state = hs.Run(cfg).export_state().view(np.uint32).copy()
@@ -176,7 +177,21 @@ def test_runs_past_the_replay_bound(hs, orc):
     tree = run.phylo_tree(cnt, srf)
     assert tree["status"] == 0
     assert hs.newick(tree) == orc.phylo_newick(2, 64, hs.as_u32(cnt), hs.as_u32(srf))
-    # the replaying query refuses these counters
+    # the plain query: the same counters, then mixed ones
     ws2 = hs.MrcaWorkspace(64, A)
-    hs.mrca_bounds("hybrid", 64, cnt, srf, workspace=ws2, stream=run.stream)
-    assert hs.mrca_status(ws2, run.stream) == hs.binding.GA_EHORIZON
+    lb2, ub2 = hs.mrca_bounds("hybrid", 64, cnt, srf, workspace=ws2, stream=run.stream)
+    assert hs.mrca_status(ws2, run.stream) == 0
+    assert np.array_equal(hs.as_u32(lb2), olb) and np.array_equal(hs.as_u32(ub2), oub)
+    # 32 annotations in four counter groups (sorted, so the oracle replays
+    # four layouts), half of them sharing the high surface word
+    import torch
+    mixed = np.repeat(np.array([T - 1, T, T + 5, T + 777], np.uint32), 8)
+    words = rng.integers(0, 2**32, (32, 2), dtype=np.uint64).astype(np.uint32)
+    words[::2, 1] = words[0, 1]
+    cm = torch.from_numpy(mixed.view(np.int32)).cuda()
+    sm = torch.from_numpy(words.view(np.int32)).cuda()
+    ws3 = hs.MrcaWorkspace(64, 32)
+    lb3, ub3 = hs.mrca_bounds("hybrid", 64, cm, sm, workspace=ws3, stream=run.stream)
+    assert hs.mrca_status(ws3, run.stream) == 0
+    olb, oub = orc.mrca_allpairs(2, 64, mixed, words)
+    assert np.array_equal(hs.as_u32(lb3), olb) and np.array_equal(hs.as_u32(ub3), oub)
