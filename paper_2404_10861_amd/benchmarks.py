@@ -217,6 +217,20 @@ def treatment_pair(specs, dev, stream, n_sample: int = 4096, labels=None,
             off = ~np.eye(n_sample, dtype=bool)
             rec.update({"mrca_query_ms": e0.elapsed_time(e1), "mrca_pairs": n_sample * n_sample,
                         "mean_lb": float(l_h[off].mean()), "mean_ub": float(u_h[off].mean())})
+            # the same query without the run: the layout from the site rule's
+            # tables (uploaded into the workspace by the call); same bounds
+            lb2, ub2 = torch.empty_like(lb), torch.empty_like(ub)
+            e3 = torch.cuda.Event(enable_timing=True)
+            e4 = torch.cuda.Event(enable_timing=True)
+            e3.record(stream)
+            hs.mrca_bounds(cfg.surface_kind, cfg.surface_sites, cnt, srf, workspace=ws,
+                           stream=stream, lb=lb2, ub=ub2, bits=cfg.differentia_bits,
+                           interval=cfg.ingest_interval)
+            e4.record(stream)
+            torch.cuda.synchronize(dev)
+            rec["mrca_query_from_rule_ms"] = e3.elapsed_time(e4)
+            rec["mrca_query_from_rule_equal"] = bool(torch.equal(lb, lb2) and torch.equal(ub, ub2))
+            del lb2, ub2
         out[label] = rec
         run.close()
     return out
