@@ -574,7 +574,9 @@ int ga_probe_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
  * 4 gives 16-byte population loads and stores).  A workgroup handles a
  * tile of block_threads * agents_per_thread / N whole islands staged in
  * LDS (at most 64 KiB).  0 keeps the current value.  Results do not depend
- * on the shape.  Errors: GA_EINVAL.                                        */
+ * on the shape.  A run starts at 4 agents per thread when N allows, with
+ * 64 threads for integer births and 256 for float births.
+ * Errors: GA_EINVAL.                                                       */
 int ga_set_launch_shape(ga_run *run, uint32_t block_threads,
                         uint32_t agents_per_thread);
 

@@ -87,9 +87,8 @@ __device__ __forceinline__ uint32_t word_below(uint32_t w, uint32_t n) {
 //   cos:   cos(pi/2 U2) by its series through x^18 when U2 < 1/2, else
 //          sin(pi/2 (1 - U2)) by its series through x^19.
 // Contraction is off: every fused multiply-add below is written out.
-__device__ __forceinline__ double exact_pow2(int k) {   // 2^k, |k| < 1023
-    return __longlong_as_double((long long)(1023 + k) << 52);
-}
+constexpr uint64_t kMantissa = 0x000FFFFFFFFFFFFFull;   // binary64 fraction bits
+constexpr uint64_t kExpZero = 0x3FF0000000000000ull;    // biased exponent of 2^0
 
 // The series coefficients of the half-normal evaluation, read through
 // scalar loads (so that a loop over draws keeps them in scalar registers):
@@ -110,10 +109,12 @@ __constant__ double kHalfNormalSeries[31] = {
 __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
 #pragma clang fp contract(off)
     const double* K = kHalfNormalSeries;
-    // ln U1
-    const uint64_t v = 2ull * w_radius + 1ull;
-    int e = 63 - __clzll((long long)v);
-    double m = (double)v * exact_pow2(-e);
+    // ln U1.  v = 2 w_radius + 1 < 2^33 is exact in binary64; its exponent
+    // is floor(log2 v), and setting the exponent to 0 gives v 2^-e exactly
+    const double vd = 2.0 * (double)w_radius + 1.0;
+    const uint64_t vb = (uint64_t)__double_as_longlong(vd);
+    int e = (int)(vb >> 52) - 1023;
+    double m = __longlong_as_double((long long)((vb & kMantissa) | kExpZero));
     if (m > 1.4142135623730951) {
         m = m * 0.5;
         e = e + 1;
@@ -130,21 +131,26 @@ __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
     const double ln_u = __builtin_fma((double)e - 33.0, 0.6931471805599453, (sv + sv) * p);
     // sqrt(-2 ln U1)
     const double y = -2.0 * ln_u;
-    const int ex = (int)((__double_as_longlong(y) >> 52) & 0x7ff) - 1023;   // floor(log2 y)
+    const uint64_t yb = (uint64_t)__double_as_longlong(y);
+    const int ex = (int)((yb >> 52) & 0x7ff) - 1023;                        // floor(log2 y)
     const int kq = ex >> 1;                                                 // floor(ex / 2)
-    const double q = y * exact_pow2(-2 * kq);
+    // q = y 4^-kq exactly: its exponent becomes ex - 2 kq, that is 0 or 1
+    const double q =
+        __longlong_as_double((long long)((yb & kMantissa) | ((uint64_t)(1023 + (ex & 1)) << 52)));
     const double h = 0.5 * q;
     double rs = __builtin_fma(-0.1875, q, 1.125);
 #pragma unroll
     for (int i = 0; i < 6; ++i) rs = __builtin_fma(rs, __builtin_fma(-h, rs * rs, 0.5), rs);
     double sq = q * rs;
     sq = __builtin_fma(__builtin_fma(-sq, sq, q), 0.5 * rs, sq);
-    const double radius = sq * exact_pow2(kq);
-    // cos(pi/2 U2)
+    const double radius = __builtin_ldexp(sq, kq);                          // exact scaling
+    // cos(pi/2 U2).  2 w_angle + 1, or 2^33 - (2 w_angle + 1) in the sine
+    // case, is an exact binary64 integer; the 2^-33 is folded into pi/2
+    // (an exact power-of-two scaling of it, so the product rounds the same)
     const bool use_sin = w_angle >= 0x80000000u;
-    uint64_t va = 2ull * w_angle + 1ull;
-    if (use_sin) va = (1ull << 33) - va;
-    const double x = ((double)va * exact_pow2(-33)) * 1.5707963267948966;
+    const double wad = (double)w_angle;
+    const double va = use_sin ? 8589934591.0 - 2.0 * wad : 2.0 * wad + 1.0;
+    const double x = va * (1.5707963267948966 * 0x1p-33);
     const double x2 = x * x;
     double c;
     if (use_sin) {
