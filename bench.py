@@ -195,6 +195,29 @@ def cpu_baseline(spec, budget_s: float = 6.0):
     }
 
 
+def cpu_baseline_small(spec, gpu_final):
+    """The whole CPU-scale run on the oracle, single-threaded, timed; and
+    whether its final records equal the GPU run's word for word."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import numpy as np
+    import hsga_oracle as orc
+    if not os.path.exists(orc.LIB):
+        orc.build()
+    r = orc.Run(spec.grid_w, spec.grid_h, spec.pop_per_island, spec.surface_sites,
+                orc.KINDS[spec.surface_kind], spec.tournament_size, spec.mut_threshold,
+                spec.mut_lo, spec.mut_hi, spec.migrants_per_island, spec.seed)
+    t0 = time.perf_counter()
+    r.step(spec.generations)
+    el = time.perf_counter() - t0
+    same = all(np.array_equal(np.asarray(a, np.uint32).reshape(-1),
+                              np.asarray(b, np.uint32).reshape(-1))
+               for a, b in zip(r.agents(), gpu_final))
+    r.close()
+    return {"value": spec.replications / el, "unit": "agent-replications/s", "cores": 1,
+            "kind": "oracle", "sample": f"{spec.name}, the whole run ({el:.2f} s), one thread",
+            **host_cpu(), "final_records_equal_gpu": bool(same)}
+
+
 def cpu_baseline_query(spec, counters, surfaces, rows: int = 1024):
     """The oracle's all-pairs MRCA bounds, single-threaded, on the first
     rows of the GPU run's sample (every column), as ordered pairs per
@@ -228,8 +251,8 @@ def main(argv=None) -> int:
     ap.add_argument("--generations", type=int, default=0,
                     help="override the run length (profiling only; not the benchmark)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=("plain", "batched", "served", "pair", "trial", "clade",
-                                       "async"),
+    ap.add_argument("--mode", choices=("plain", "small", "batched", "served", "pair", "trial",
+                                       "clade", "async"),
                     default="plain",
                     help="plain: the paper-scale run (default); batched / served: the run "
                          "sets of the batched and served workloads against sequential plain runs")
@@ -263,7 +286,15 @@ def main(argv=None) -> int:
         dev = torch.device("cuda:0")
         torch.cuda.set_device(dev)
         from paper_2404_10861_amd import benchmarks
-        if args.mode == "async":
+        if args.mode == "small":
+            spec = wl.c1()
+            res = benchmarks.small_run(spec, dev, torch.cuda.current_stream(dev))
+            final = res.pop("_final")
+            if not args.no_cpu_baseline:
+                res["cpu_baseline"] = cpu_baseline_small(spec, final)
+            metric = "agent-replications/sec (CPU-scale run)"
+            value = res["replications_per_s"]
+        elif args.mode == "async":
             spec = wl.c2()
             spec.generations = args.generations or 2000
             res = benchmarks.async_vs_sync(spec, 0.9, dev, torch.cuda.current_stream(dev))

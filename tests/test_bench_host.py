@@ -71,3 +71,25 @@ def test_code_hash_ignores_comments_and_layout_only(tmp_path):
         h[k] = profiling.kernel_hash([str(p)])
     assert h["a"] == h["same"]
     assert h["a"] != h["other"]
+
+
+def test_small_run_baseline_compares_final_records():
+    """The CPU-scale leg times the whole run on the oracle and reports
+    whether the records it is handed equal the oracle's, word for word."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import hsga_oracle as orc
+    import bench
+    from paper_2404_10861_amd import workloads as wl
+    spec = wl.c1()
+    spec.generations = 30
+    r = orc.Run(spec.grid_w, spec.grid_h, spec.pop_per_island, spec.surface_sites,
+                orc.KINDS[spec.surface_kind], spec.tournament_size, spec.mut_threshold,
+                spec.mut_lo, spec.mut_hi, spec.migrants_per_island, spec.seed)
+    r.step(30)
+    final = [np.array(x, copy=True) for x in r.agents()]
+    r.close()
+    rec = bench.cpu_baseline_small(spec, final)
+    assert rec["final_records_equal_gpu"] and rec["cores"] == 1 and rec["value"] > 0
+    final[0][17] ^= 1
+    assert not bench.cpu_baseline_small(spec, final)["final_records_equal_gpu"]
