@@ -216,6 +216,7 @@ hsga::StepParams step_params(const ga_run* r, uint32_t g, uint32_t tau0) {
     p.has_inbox = (cfg.migrants_per_island != 0 && g > 0) ? 1u : 0u;
     p.tile_isl = tile_islands(r->block, r->apt, r->N);
     p.div_magic = ((1u << 20) + r->N - 1) / r->N;
+    hsga::column_magic(cfg.grid_w, &p.w_magic, &p.w_shift);
     p.tour = cfg.tournament_size > 1 ? cfg.tournament_size : 1u;
     p.del_thr = cfg.del_threshold;
     p.ben_thr = cfg.ben_threshold;

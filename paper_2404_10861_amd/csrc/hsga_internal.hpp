@@ -45,6 +45,7 @@ struct StepParams {
     uint32_t has_inbox;        // outboxes of generation g exist
     uint32_t tile_isl;         // islands per workgroup tile
     uint32_t div_magic;        // ceil(2^20 / N): la / N == (la * div_magic) >> 20 for la < 4096
+    uint32_t w_magic, w_shift; // isl / W by multiplication (column_magic)
     uint32_t diff_log2;        // log2 of the differentia width: 0 (bit) or 3 (byte)
     uint32_t async_thr;        // asynchronous ticks: island activity threshold; 0: synchronous
     const RuleTable* rules;    // asynchronous ticks: the surface's site rule tables
@@ -83,8 +84,23 @@ struct BatchRun {
     uint32_t interval;         // one deposit every `interval` generations
     uint32_t diff_log2;        // 0: one-bit differentiae, 3: bytes
     uint32_t tile_isl, div_magic;
+    uint32_t w_magic, w_shift;
     uint32_t tile0;            // first tile of the run in the batched grid
 };
+
+// Division of any 32-bit n by a fixed d >= 1 as a multiply-high and
+// shifts (the round-down method with an add indicator, Granlund and
+// Montgomery 1994): with l = ceil(log2 d), magic = floor(2^32 (2^l - d) / d)
+// + 1 (0 when d is a power of two) and t = mulhi(n, magic),
+// n / d = (t + ((n - t) >> s1)) >> s2, s1 = min(l, 1), s2 = max(l - 1, 0);
+// shift packs s1 | s2 << 8.
+inline void column_magic(uint32_t d, uint32_t* magic, uint32_t* shift) {
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    *magic = (d & (d - 1)) == 0 ? 0u
+                                : (uint32_t)((((1ull << l) - d) << 32) / d + 1);
+    *shift = (l ? 1u : 0u) | ((l ? l - 1 : 0u) << 8);
+}
 
 constexpr uint32_t kMaxBatchRuns = 256;
 

@@ -203,6 +203,15 @@ __device__ __forceinline__ void lds_store_lanes(uint32_t* dst, const Lanes<APT>&
     }
 }
 
+// Column of island isl on a torus W wide: isl mod W, the quotient by the
+// run's multiplier (column_magic).
+__device__ __forceinline__ uint32_t column_of(uint32_t isl, uint32_t W, uint32_t magic,
+                                              uint32_t shift) {
+    const uint32_t t = __umulhi(isl, magic);
+    const uint32_t q = (t + ((isl - t) >> (shift & 0xffu))) >> (shift >> 8);
+    return isl - q * W;
+}
+
 // Island index of a neighbour: 0 north, 1 south, 2 west, 3 east (torus).
 __device__ __forceinline__ uint32_t neighbour_of(uint32_t isl, uint32_t x, uint32_t d, uint32_t W,
                                                  uint32_t I) {
@@ -498,21 +507,28 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
     // cache line), so the immigrants need no second round trip; the loads
     // are issued outside any branch (lanes without an island read entry 0;
     // before the first generation the entries are read but not used) so
-    // that nothing waits for them before the birth draws.
+    // that nothing waits for them before the birth draws.  Only wavefronts
+    // holding an island lane work out neighbour indices (a wave-uniform
+    // test: most wavefronts of a large tile hold none); the loads stay after
+    // the branch, since loads inside it would be waited for at its end.
     constexpr uint32_t OBW = ASYNC ? kOutboxWords : kSyncOutboxWords;
     uint4 in_lo[4], in_hi[4];
     uint32_t imm_slots = 0;        // the four directions' slots, 6 bits each
     bool imm_take = false;         // this lane's island takes immigrants
     if (MIGR) {
-        const bool lane_isl = t < nisl;
-        const uint32_t isl = first_isl + (lane_isl ? t : 0u);
-        const uint32_t x = isl % W;
+        size_t e[4] = {0, 0, 0, 0};
+        if ((uint32_t)__builtin_amdgcn_readfirstlane((int)t) < nisl) {
+            const bool lane_isl = t < nisl;
+            const uint32_t isl = first_isl + (lane_isl ? t : 0u);
+            const uint32_t x = column_of(isl, W, p.w_magic, p.w_shift);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                e[d] = lane_isl ? (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * OBW : 0;
+        }
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            const size_t e =
-                lane_isl ? (size_t)neighbour_of(isl, x, (uint32_t)d, W, p.I) * OBW : 0;
-            in_lo[d] = *reinterpret_cast<const uint4*>(p.ob_in + e);
-            if (ASYNC && SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(p.ob_in + e + 4);
+            in_lo[d] = *reinterpret_cast<const uint4*>(p.ob_in + e[d]);
+            if (ASYNC && SW > 1) in_hi[d] = *reinterpret_cast<const uint4*>(p.ob_in + e[d] + 4);
         }
     }
     __builtin_amdgcn_s_setprio(0);
@@ -781,6 +797,8 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.has_inbox = (mig && g > 0) ? 1u : 0u;
     p.tile_isl = R.tile_isl;
     p.div_magic = R.div_magic;
+    p.w_magic = R.w_magic;
+    p.w_shift = R.w_shift;
     p.async_thr = 0u;          // batched runs are synchronous
     p.rules = nullptr;
     p.ring = nullptr;

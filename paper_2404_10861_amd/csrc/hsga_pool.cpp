@@ -232,6 +232,12 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     for (uint32_t s = 0; s < p->max_runs; ++s)
         if (p->slots[s].used && p->slots[s].run.T < p->slots[s].target) active.push_back(s);
     if (active.empty()) return GA_OK;
+    // runs of one kernel specialisation side by side: their tiles run
+    // together on the CUs, which then share one variant's code in the
+    // instruction cache (the order changes no result)
+    std::stable_sort(active.begin(), active.end(), [&](uint32_t a, uint32_t b) {
+        return variant_of(p->slots[a].run) < variant_of(p->slots[b].run);
+    });
     if (p->staged_pending) {
         hipError_t e = hipEventSynchronize(p->staged);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -275,6 +281,8 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         b.diff_log2 = sp.diff_log2;
         b.tile_isl = sp.tile_isl;
         b.div_magic = sp.div_magic;
+        b.w_magic = sp.w_magic;
+        b.w_shift = sp.w_shift;
         b.tile0 = tiles;
         p->h_tile0[i] = tiles;
         const uint32_t rt = (r.I + sp.tile_isl - 1) / sp.tile_isl;

@@ -195,3 +195,10 @@ def test_counters_in_the_millions(hs, orc):
     assert hs.mrca_status(ws3, run.stream) == 0
     olb, oub = orc.mrca_allpairs(2, 64, mixed, words)
     assert np.array_equal(hs.as_u32(lb3), olb) and np.array_equal(hs.as_u32(ub3), oub)
+    # the reconstruction without the run (the layout from the rule's
+    # tables): the oracle's metrics, on eight annotations sharing T + 777
+    same = torch.from_numpy(mixed[24:].view(np.int32)).cuda()
+    m = hs.phylo_metrics("hybrid", 64, same, sm[24:].contiguous(), stream=run.stream)
+    o = orc.phylo_metrics(2, 64, mixed[24:], words[24:])
+    assert m["status"] == 0
+    assert (m["sum_branch_length"], m["pair_sum"], m["root_time"], m["internal_nodes"]) == o[:4]
