@@ -453,7 +453,9 @@ int hstrat_phylo_tree_ex(const hstrat_scheme *scheme, uint32_t n,
  * index below them, no length on the root, "0;" when n = 1.  *length
  * receives the text's length; text (host, cap bytes, may be NULL to size
  * it) receives the text and a terminating NUL.
- * Errors: GA_EINVAL (NULL, n = 0, parents out of range or not a tree),
+ * Errors: GA_EINVAL (NULL, n = 0, parents out of range or not one tree,
+ * a leaf hanging from a boundary that names no node, a node time below its
+ * parent's or above T),
  * GA_ENOMEM (cap too small).                                               */
 int hstrat_phylo_newick(uint32_t n, uint32_t T, const uint32_t *leaf_parent,
                         const uint32_t *node_parent, const uint32_t *node_time, char *text,

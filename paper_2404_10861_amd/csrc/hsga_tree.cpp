@@ -57,7 +57,28 @@ int hstrat_phylo_newick(uint32_t n, uint32_t T, const uint32_t* leaf_parent,
             for (int64_t c : kids[v])
                 if (c >= 0) stack.push_back((uint32_t)c);
         }
-        if (order.size() > m) return fail(GA_EINVAL, "node parents form a cycle");
+        // one tree: every node reached from the root (nodes in a detached
+        // cycle are not), every leaf hanging from a reached node, and no
+        // branch of negative length
+        std::vector<uint32_t> up(m, kRoot);
+        size_t nodes = 0;
+        for (uint32_t b = 0; b < m; ++b) nodes += node_parent[b] != kNotNode ? 1 : 0;
+        if (order.size() != nodes) return fail(GA_EINVAL, "node parents do not form one tree");
+        for (uint32_t v : order)
+            for (int64_t c : kids[v])
+                if (c >= 0) up[(uint32_t)c] = v;
+        for (uint32_t v : order) {
+            if (v != root && node_time[v] < node_time[up[v]])
+                return fail(GA_EINVAL, "a node older than its parent");
+            if (kids[v].empty() && std::none_of(leaf_parent, leaf_parent + n,
+                                                [v](uint32_t p) { return p == v; }))
+                return fail(GA_EINVAL, "a node with nothing below it");
+        }
+        for (uint32_t a = 0; a < n; ++a) {
+            const uint32_t p = leaf_parent[a];
+            if (node_parent[p] == kNotNode) return fail(GA_EINVAL, "leaf parent names no node");
+            if (T < node_time[p]) return fail(GA_EINVAL, "a node younger than the leaves");
+        }
         for (auto it = order.rbegin(); it != order.rend(); ++it) {
             uint32_t lv = kRoot;
             for (int64_t c : kids[*it])

@@ -43,3 +43,16 @@ def test_malformed_trees_are_refused():
         hs.newick(tree([0, 0, 1], [R, R], [1, 1], 3))          # two roots
     with pytest.raises(hs.HsgaError):
         hs.newick(tree([0, 0, 1], [1, 0], [1, 1], 3))          # no root (a cycle)
+    # a root, and boundaries 2 and 3 parenting each other apart from it
+    with pytest.raises(hs.HsgaError):
+        hs.newick(tree([0, 0, 2, 3, 0], [R, 0, 3, 2], [1, 2, 2, 2], 5))
+    # a leaf hanging from a boundary that names no node
+    with pytest.raises(hs.HsgaError):
+        hs.newick(tree([0, 0, 1], [R, X], [1, 0], 3))
+    # a node older than its parent; a node younger than the leaves
+    with pytest.raises(hs.HsgaError):
+        hs.newick(tree([0, 1, 1], [R, 0], [4, 2], 9))
+    with pytest.raises(hs.HsgaError):
+        hs.newick(tree([0, 1, 1], [R, 0], [4, 12], 9))
+    # the same shapes, well formed, are accepted
+    assert hs.newick(tree([0, 1, 1], [R, 0], [2, 4], 9)) == "(0:7,(1:5,2:5):2);"
