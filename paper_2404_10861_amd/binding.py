@@ -343,7 +343,7 @@ class RunHandle:
                     workspace: "MrcaWorkspace | None" = None, lb=None, ub=None):
         """mrca_bounds of annotations taken from this run, with its scheme and
         on its stream: when every counter is the run's generation count, the
-        run's own layout replaces the replay of the site rule."""
+        run's own layout is used as it stands."""
         n = counter.shape[0]
         if counter.dtype != torch.int32 or surface_words.dtype != torch.int32:
             raise ValueError("counter and surface_words must be int32 tensors")

@@ -23,8 +23,8 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
-    # keep the compiler from forming packed FP32 instructions (none of the
-    # arithmetic here is floating point; the flag is a blanket safeguard)
+    # keep the compiler from forming packed FP32 instructions (the float
+    # treatments' fitness arithmetic is scalar binary32 and binary64)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

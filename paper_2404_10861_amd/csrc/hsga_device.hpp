@@ -305,8 +305,9 @@ __device__ __forceinline__ uint32_t lane_leave_time(uint32_t kind, uint32_t S, u
     return leave_time(kind, S, lane_time);
 }
 
-// The MRCA kernels replay layouts on the device, one placement per
-// ingest; annotations with more ingests than this are refused.
+// Without the rule's tables (the allocation-free query) the MRCA kernels
+// replay layouts on the device, one placement per ingest; annotations with
+// more ingests than this are then refused.
 constexpr uint32_t kMaxReplayGenerations = 1u << 24;
 
 // Deposits made by an annotation with counter T (generations 0, interval,

@@ -165,8 +165,8 @@ struct MrcaWorkspace {
 };
 
 // A run's own layout (device, S words in ingest units) after the ingests of
-// generation count T; the queries use it instead of replaying the site rule
-// when every annotation's counter is T.
+// generation count T; the queries use it as it stands when every
+// annotation's counter is T.
 struct LayoutHint {
     const uint32_t* layout = nullptr;
     uint32_t T = 0;

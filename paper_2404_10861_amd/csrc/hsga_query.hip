@@ -86,12 +86,13 @@ __device__ __forceinline__ uint32_t layout_lane(const RuleTable* rules, uint32_t
 }
 
 // Classify the counters (four wavefronts); when all are equal, wavefront 0
-// replays the shared layout once (in ingest units), orders its sites by
-// deposit time and tabulates the bounds, in generations, for every possible
-// first-mismatch rank.  A run's own layout (hint, S words in ingest units, the layout after
-// the ingests of generation count hint_T) replaces the replay when every
-// counter is hint_T: the layout is a function of the scheme and the count
-// alone, so both give the same words.
+// lays out the shared layout once (in ingest units: from the rule's tables,
+// or by replaying the placements when the caller has none), orders its
+// sites by deposit time and tabulates the bounds, in generations, for every
+// possible first-mismatch rank.  A run's own layout (hint, S words in
+// ingest units, the layout after the ingests of generation count hint_T) is
+// used as it stands when every counter is hint_T: the layout is a function
+// of the scheme and the count alone, so all three give the same words.
 constexpr uint32_t kPrepareThreads = 256;   // 4 wavefronts classify; wave 0 does the rest
 __global__ __launch_bounds__(kPrepareThreads) void mrca_prepare_kernel(
     Scheme sc, uint32_t n, const uint32_t* __restrict__ counter, uint32_t* __restrict__ ws,
@@ -264,9 +265,9 @@ __global__ __launch_bounds__(256) void mrca_allpairs_kernel(uint32_t n, uint32_t
     }
 }
 
-// General route (counters differ): one wavefront per annotation replays its
-// own layout and stores its retained deposit generations in ascending order
-// with their sites.
+// General route (counters differ): one wavefront per annotation lays out
+// its own layout (from the rule's tables, else by replay) and stores its
+// retained deposit generations in ascending order with their sites.
 __global__ __launch_bounds__(64) void mrca_layouts_kernel(Scheme sc,
                                                          const uint32_t* __restrict__ counter,
                                                          const uint32_t* __restrict__ ws,
