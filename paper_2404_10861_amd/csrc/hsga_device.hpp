@@ -106,12 +106,15 @@ __constant__ double kHalfNormalSeries[31] = {
     -1.0 / 2.0, 1.0,
 };
 
-__device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
+// The draw for an angle word of a known case: SIN for w_angle >= 2^31 (the
+// sine series), else the cosine series.
+template <bool SIN>
+__device__ __forceinline__ double half_normal_case(uint32_t w_radius, uint32_t w_angle) {
 #pragma clang fp contract(off)
     const double* K = kHalfNormalSeries;
     // ln U1.  v = 2 w_radius + 1 < 2^33 is exact in binary64; its exponent
     // is floor(log2 v), and setting the exponent to 0 gives v 2^-e exactly
-    const double vd = 2.0 * (double)w_radius + 1.0;
+    const double vd = __builtin_fma(2.0, (double)w_radius, 1.0);
     const uint64_t vb = (uint64_t)__double_as_longlong(vd);
     int e = (int)(vb >> 52) - 1023;
     double m = __longlong_as_double((long long)((vb & kMantissa) | kExpZero));
@@ -147,13 +150,12 @@ __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
     // cos(pi/2 U2).  2 w_angle + 1, or 2^33 - (2 w_angle + 1) in the sine
     // case, is an exact binary64 integer; the 2^-33 is folded into pi/2
     // (an exact power-of-two scaling of it, so the product rounds the same)
-    const bool use_sin = w_angle >= 0x80000000u;
     const double wad = (double)w_angle;
-    const double va = use_sin ? 8589934591.0 - 2.0 * wad : 2.0 * wad + 1.0;
+    const double va = SIN ? __builtin_fma(-2.0, wad, 8589934591.0) : __builtin_fma(2.0, wad, 1.0);
     const double x = va * (1.5707963267948966 * 0x1p-33);
     const double x2 = x * x;
     double c;
-    if (use_sin) {
+    if constexpr (SIN) {
         c = K[11];
 #pragma unroll
         for (int k = 12; k < 21; ++k) c = __builtin_fma(c, x2, K[k]);
@@ -166,18 +168,15 @@ __device__ inline double half_normal(uint32_t w_radius, uint32_t w_angle) {
     return radius * c;
 }
 
+// The fitness after a draw: f - del_sigma |Z| (deleterious) or
+// f + ben_sigma |Z|, in binary64, rounded to binary32.  Written as one
+// product and one sum with the sign folded into the factor: negation is
+// exact and rounding is symmetric, so f + (-s) z rounds as f - s z.
 __device__ __forceinline__ float apply_half_normal(float f, bool deleterious, float del_sigma,
                                                    float ben_sigma, double z) {
 #pragma clang fp contract(off)
-    const double fd = (double)f;
-    return deleterious ? (float)(fd - (double)del_sigma * z) : (float)(fd + (double)ben_sigma * z);
-}
-
-__device__ __forceinline__ float mutate_fitness(float f, bool deleterious, float del_sigma,
-                                                float ben_sigma, uint32_t w_radius,
-                                                uint32_t w_angle) {
-    return apply_half_normal(f, deleterious, del_sigma, ben_sigma,
-                             half_normal(w_radius, w_angle));
+    const double s = deleterious ? -(double)del_sigma : (double)ben_sigma;
+    return (float)((double)f + s * z);
 }
 
 // Number of significant bits.

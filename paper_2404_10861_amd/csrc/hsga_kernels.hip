@@ -277,9 +277,12 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
     // the back) and evaluated after the loop in rounds of the wave's lanes,
     // so the draw runs once per mutating birth rather than once per birth
     // for the whole wave, and no round mixes the two series.
+    // The loop itself has only wave-uniform branches; the mutation class of
+    // each birth is read again from its draw words after the loop, where the
+    // queue is filled.
     constexpr uint32_t QC = 64u * APT;                  // queue capacity of a wave
     uint2* wq = nullptr;
-    uint32_t fneed = 0, fdel = 0, fslot = 0, ncos = 0, nsin = 0;
+    uint32_t fslot = 0, ncos = 0, nsin = 0;
     if constexpr (BM == kBirthFloat)
         wq = reinterpret_cast<uint2*>(lds + ((((2 + SW) * TA + 2 * p.tile_isl) + 3u) & ~3u)) +
              (threadIdx.x >> 6) * QC;
@@ -316,11 +319,7 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                         }
                     }
                 }
-                const bool del = v.y < p.del_thr;
-                const bool ben = !del && p.ben_thr != 0u && v.y >= 0u - p.ben_thr;
                 ctr.v[q] = __float_as_uint(best);        // the draw is applied after the loop
-                fneed |= (del || ben ? 1u : 0u) << q;
-                fdel |= (del ? 1u : 0u) << q;
                 bit = v.w & diff_mask;
             } else {
                 uint32_t ptrait = l_trait[par];
@@ -363,9 +362,21 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
                                   : word;
             }
         }
-        if constexpr (BM == kBirthFloat) {
+    }
+    if constexpr (BM == kBirthFloat) {
+        // mutating births: deleterious below del_thr, beneficial in the top
+        // ben_thr words (idle islands of a tick draw nothing)
+        bool act = true;
+        if constexpr (ASYNC) act = (l_plan[il] >> 31) != 0u;
+        const bool ben_on = p.ben_thr != 0u;
+        const uint32_t ben_lo = 0u - p.ben_thr;
+        auto needs = [&](const uint4& v) {
+            return act && (v.y < p.del_thr || (ben_on && v.y >= ben_lo));
+        };
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
             const uint4 vq = blk[APT + q];
-            const bool nd = (fneed >> q) & 1u;
+            const bool nd = needs(vq);
             const bool sn = vq.w >= 0x80000000u;          // the draw's sine case
             const uint64_t mc = __ballot(nd && !sn);
             const uint64_t ms = __ballot(nd && sn);
@@ -378,8 +389,6 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
             ncos += (uint32_t)__popcll(mc);
             nsin += (uint32_t)__popcll(ms);
         }
-    }
-    if constexpr (BM == kBirthFloat) {
         // the queued draws in rounds of the active lanes (one wavefront: its
         // LDS writes land before its later reads), then each birth's fitness
         const uint64_t ex = __ballot(true);
@@ -387,7 +396,7 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
         for (uint32_t b0 = 0; b0 < ncos; b0 += na) {
             if (b0 + me < ncos) {
                 const uint2 e = wq[b0 + me];
-                const double z = half_normal(e.x, e.y);
+                const double z = half_normal_case<false>(e.x, e.y);
                 const uint64_t zb = (uint64_t)__double_as_longlong(z);
                 wq[b0 + me] = make_uint2((uint32_t)zb, (uint32_t)(zb >> 32));
             }
@@ -396,19 +405,20 @@ __device__ __forceinline__ void step_births(const StepParams& p, uint32_t first_
             if (b0 + me < nsin) {
                 const uint32_t i = QC - 1u - (b0 + me);
                 const uint2 e = wq[i];
-                const double z = half_normal(e.x, e.y);
+                const double z = half_normal_case<true>(e.x, e.y);
                 const uint64_t zb = (uint64_t)__double_as_longlong(z);
                 wq[i] = make_uint2((uint32_t)zb, (uint32_t)(zb >> 32));
             }
         }
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
-            if ((fneed >> q) & 1u) {
+            const uint4 vq = blk[APT + q];
+            if (needs(vq)) {
                 const uint2 e = wq[(fslot >> (8 * q)) & 0xffu];
                 const double z =
                     __longlong_as_double((long long)(((uint64_t)e.y << 32) | e.x));
                 ctr.v[q] = __float_as_uint(apply_half_normal(__uint_as_float(ctr.v[q]),
-                                                             (fdel >> q) & 1u, p.del_sigma,
+                                                             vq.y < p.del_thr, p.del_sigma,
                                                              p.ben_sigma, z));
             }
         }
