@@ -142,7 +142,7 @@ def _oracle_rate(orc, spec, threads: int, budget_s: float, max_gens: int = 200) 
 
 def cpu_baseline(spec, budget_s: float = 6.0):
     """The oracle on the host's cores: island-parallel on the CPUs this
-    process may use (at most 16, the box's share) and single-threaded, each
+    process may use (at most 16) and single-threaded, each
     on the first generations of the paper-scale workload; plus bounded
     prefixes of the treatment-pair and batched workloads, extrapolated to
     their full lengths and labelled so."""
