@@ -93,6 +93,39 @@ def test_batched_matches_oracle(hs, orc):
         assert np.array_equal(pool.run(rid).layout(), o.layout())
 
 
+def test_batched_workload_matches_oracle(hs, orc):
+    """The 64-run batched workload itself (the saved run list, full grid
+    sizes) advanced 40 generations in one pool: every run's records,
+    outbox and layout equal the oracle's, run by run (the oracle on up to
+    16 host threads).  40 generations take the 32-site surfaces past their
+    fill phase."""
+    import os
+    G = 40
+    specs = wl.c4_saved()
+    pool = hs.Pool(2 << 30, max_runs=64, max_gens_per_launch=64, block_threads=256,
+                   use_graph=True)
+    ids = {pool.admit(hs.Config(**s.config_kwargs()), G): s for s in specs}
+    assert None not in ids
+    while pool.advance(64):
+        pass
+    threads = min(16, os.cpu_count() or 1)
+    for rid, s in ids.items():
+        o = orc.Run(s.grid_w, s.grid_h, s.pop_per_island, s.surface_sites, KIND[s.surface_kind],
+                    s.tournament_size, s.mut_threshold, s.mut_lo, s.mut_hi,
+                    s.migrants_per_island, s.seed, threads=threads)
+        o.step(G)
+        run = pool.run(rid)
+        assert run.generation == G
+        for x, y in zip(run.agents(), o.agents()):
+            assert np.array_equal(x, y), s.name
+        assert np.array_equal(run.layout(), o.layout()), s.name
+        ob, oo = run.outbox(), o.outbox()
+        for x, y in zip(ob, oo):
+            assert np.array_equal(x, y), s.name
+        o.close()
+    pool.close()
+
+
 def test_admission_by_footprint(hs):
     small = hs.Config(8, 8, 32, 32, "steady", seed=1)
     big = hs.Config(256, 256, 64, 64, "hybrid", seed=2)
