@@ -121,11 +121,11 @@ typedef struct ga_run ga_run;
  *   - two ping-pong outboxes, 32 bytes reserved per island (a synchronous
  *     run's entry uses 16: direction, trait, surface words, since every
  *     emigrant's counter is the generation count);
- *   - the run's surface layout (deposit time of each site) and, for a
- *     synchronous run, a site schedule of max_gens_per_launch words (an
- *     asynchronous run holds the site rule's constant-time tables there,
- *     two of about 25 KB, and a ring of the sites of its next 4,096
- *     ingests).
+ *   - the run's surface layout (deposit time of each site), the site
+ *     rule's constant-time tables (one or two of about 25 KB, from which
+ *     every deposit site and layout is looked up), and, for a synchronous
+ *     run, a site schedule of max_gens_per_launch words (an asynchronous
+ *     run holds a ring of the sites of its latest 4,096 ingests instead).
  * An agent record is (uint32 trait, uint32 generation counter, S one-bit
  * differentia sites); site k is bit k&31 of surface word k>>5.
  * ------------------------------------------------------------------------ */

@@ -48,9 +48,9 @@ Carve carve(const ga_config& cfg, uint32_t gens) {
     c.surf = off;    off += 2 * align_up(SW * A * 4);
     c.outbox = off;  off += 2 * align_up((size_t)I * hsga::kOutboxWords * 4);
     c.layout = off;  off += align_up(64 * 4);
+    c.rules = off;   off += align_up(2 * sizeof(hsga::RuleTable));
     c.sites = off;
-    off += cfg.async_activity ? align_up(2 * sizeof(hsga::RuleTable)) + 4 * hsga::kSiteRing
-                              : align_up((size_t)gens * 4);
+    off += cfg.async_activity ? 4 * hsga::kSiteRing : align_up((size_t)gens * 4);
     c.total = off;
     return c;
 }
@@ -106,6 +106,44 @@ int validate(const ga_config* in, ga_config* out) {
 }
 
 namespace {
+// Pinned host copies of the cached rule tables, made on first use and kept
+// until the process ends, so that a query's upload of them is an ordinary
+// stream copy (a copy from pageable memory may hold the host until the
+// stream has drained).  Pageable tables when pinned memory is refused.
+std::mutex g_pinned_mutex;
+std::vector<std::pair<const hsga::RuleTable*, hsga::RuleTable*>> g_pinned;
+
+const hsga::RuleTable* pinned_table(const hsga::RuleTable* t) {
+    std::lock_guard<std::mutex> lock(g_pinned_mutex);
+    for (auto& pr : g_pinned)
+        if (pr.first == t) return pr.second ? pr.second : t;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(hsga::RuleTable), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    } else {
+        std::memcpy(p, t, sizeof(hsga::RuleTable));
+    }
+    g_pinned.emplace_back(t, static_cast<hsga::RuleTable*>(p));
+    return p ? static_cast<hsga::RuleTable*>(p) : t;
+}
+
+}  // namespace
+
+// Enqueue the upload of the tables of a surface of `kind` and S sites (one,
+// or two for hybrid) to dev on `stream`, from the pinned host copies.
+hipError_t upload_tables(uint32_t kind, uint32_t S, hsga::RuleTable* dev, hipStream_t stream) {
+    const hsga::RuleTable* tabs[2] = {nullptr, nullptr};
+    if (!hsga::scheme_rules(kind, S, tabs)) return hipErrorInvalidValue;
+    for (int k = 0; k < 2 && tabs[k]; ++k) {
+        hipError_t e = hipMemcpyAsync(dev + k, pinned_table(tabs[k]), sizeof(hsga::RuleTable),
+                                      hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+namespace {
 uint32_t default_agents_per_thread(uint32_t N) {
     return N % 4 == 0 ? 4u : (N % 2 == 0 ? 2u : 1u);
 }
@@ -132,11 +170,9 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
             base + c.outbox + b * align_up((size_t)I * hsga::kOutboxWords * 4));
     }
     r->layout = reinterpret_cast<uint32_t*>(base + c.layout);
+    r->rules = reinterpret_cast<hsga::RuleTable*>(base + c.rules);
     r->sites = cfg->async_activity ? nullptr : reinterpret_cast<uint32_t*>(base + c.sites);
-    r->rules = cfg->async_activity ? reinterpret_cast<hsga::RuleTable*>(base + c.sites) : nullptr;
-    r->ring = cfg->async_activity ? reinterpret_cast<uint32_t*>(
-                                        base + c.sites + align_up(2 * sizeof(hsga::RuleTable)))
-                                  : nullptr;
+    r->ring = cfg->async_activity ? reinterpret_cast<uint32_t*>(base + c.sites) : nullptr;
     r->ring_hi = 0;
     r->gens = gens;
     r->T = 0;
@@ -152,19 +188,11 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
                                          (uint32_t)cfg->seed, (uint32_t)(cfg->seed >> 32),
                                          r->stream);
     if (e != hipSuccess) return hip_fail(e, "founders launch");
-    if (cfg->async_activity) {
-        // an asynchronous birth looks its site up from its parent's counter
-        // in the rule's tables (the host's cached copies outlive the copy)
-        const hsga::RuleTable* rules[2] = {nullptr, nullptr};
-        if (!hsga::scheme_rules(cfg->surface_kind, r->S, rules))
-            return fail(GA_EINVAL, "no site rule tables for this surface");
-        const int n = cfg->surface_kind == GA_HYBRID ? 2 : 1;
-        for (int k = 0; k < n; ++k) {
-            e = hipMemcpyAsync(r->rules + k, rules[k], sizeof(hsga::RuleTable),
-                               hipMemcpyHostToDevice, r->stream);
-            if (e != hipSuccess) return hip_fail(e, "site rule tables upload");
-        }
-    }
+    // the rule's tables: a synchronous run's launch batches take their sites
+    // and layouts from them, an asynchronous birth its site from its
+    // parent's counter
+    e = upload_tables(cfg->surface_kind, r->S, r->rules, r->stream);
+    if (e != hipSuccess) return hip_fail(e, "site rule tables upload");
     return GA_OK;
 }
 
@@ -371,8 +399,8 @@ int step_enqueue(ga_run* r, uint32_t n) {
         const uint32_t G = n < r->gens ? n : r->gens;
         const uint32_t tau0 = hsga::ingests_of(r->T, cfg.ingest_interval);
         const uint32_t count = hsga::ingests_of(r->T + G, cfg.ingest_interval) - tau0;
-        hipError_t e = hsga::launch_site_schedule(cfg.surface_kind, r->S, r->layout, r->sites,
-                                                  tau0, count, r->stream);
+        hipError_t e = hsga::launch_run_sites(r->rules, cfg.surface_kind, r->S, r->sites,
+                                              r->layout, tau0, count, r->stream);
         if (e != hipSuccess) return hip_fail(e, "site schedule launch");
         ga_run::Span span{nullptr, nullptr, G};
         if (r->timing) {
@@ -634,40 +662,13 @@ size_t phylo_total_bytes(uint32_t S, uint32_t n) {
     return aligned256(hsga::phylo_workspace_bytes(S, n)) + hsga::kRuleRegionBytes;
 }
 
-// Pinned host copies of the cached rule tables, made on first use and kept
-// until the process ends, so that a query's upload of them is an ordinary
-// stream copy (a copy from pageable memory may hold the host until the
-// stream has drained).  Pageable tables when pinned memory is refused.
-std::mutex g_pinned_mutex;
-std::vector<std::pair<const hsga::RuleTable*, hsga::RuleTable*>> g_pinned;
-
-const hsga::RuleTable* pinned_table(const hsga::RuleTable* t) {
-    std::lock_guard<std::mutex> lock(g_pinned_mutex);
-    for (auto& pr : g_pinned)
-        if (pr.first == t) return pr.second ? pr.second : t;
-    void* p = nullptr;
-    if (hipHostMalloc(&p, sizeof(hsga::RuleTable), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        p = nullptr;
-    } else {
-        std::memcpy(p, t, sizeof(hsga::RuleTable));
-    }
-    g_pinned.emplace_back(t, static_cast<hsga::RuleTable*>(p));
-    return p ? static_cast<hsga::RuleTable*>(p) : t;
-}
-
 // Enqueue the upload of the scheme's tables to `region` (kRuleRegionBytes,
 // 256-byte aligned) on `stream`; the LayoutHint that reads them.
 hipError_t upload_rules(const hsga::Scheme& sc, uint8_t* region, hipStream_t stream,
                         hsga::LayoutHint* hint) {
-    const hsga::RuleTable* tabs[2] = {nullptr, nullptr};
-    if (!hsga::scheme_rules(sc.kind, sc.S, tabs)) return hipErrorInvalidValue;
     auto* dev = reinterpret_cast<hsga::RuleTable*>(region);
-    for (int k = 0; k < 2 && tabs[k]; ++k) {
-        hipError_t e = hipMemcpyAsync(dev + k, pinned_table(tabs[k]), sizeof(hsga::RuleTable),
-                                      hipMemcpyHostToDevice, stream);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = upload_tables(sc.kind, sc.S, dev, stream);
+    if (e != hipSuccess) return e;
     hint->rules = dev;
     return hipSuccess;
 }

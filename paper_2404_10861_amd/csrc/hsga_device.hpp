@@ -293,7 +293,7 @@ __device__ __forceinline__ void place_items(uint32_t kind, uint32_t S, uint32_t 
     }
 }
 
-// Leave time of the item a lane holds (at the start of a schedule or replay).
+// Leave time of the item a lane holds (at the start of a replay).
 __device__ __forceinline__ uint32_t lane_leave_time(uint32_t kind, uint32_t S, uint32_t lane,
                                                     uint32_t lane_time) {
     if (lane_time == kEmpty || lane >= S) return 0u;

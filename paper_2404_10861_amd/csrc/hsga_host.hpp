@@ -22,7 +22,7 @@ struct ga_run {
     uint32_t* outbox[2];
     uint32_t* layout;
     uint32_t* sites;     // synchronous: the site schedule of a launch batch
-    hsga::RuleTable* rules;   // asynchronous: the site rule's tables (device)
+    hsga::RuleTable* rules;   // the site rule's tables (device)
     uint32_t* ring;      // asynchronous: sites of the latest kSiteRing ingests
     uint32_t ring_hi;    // asynchronous: ingests below this are in the ring (the
                          // last kSiteRing of them)
@@ -51,8 +51,12 @@ const char* last_error();
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Carve {
-    size_t trait, counter, surf, outbox, layout, sites, total;
+    size_t trait, counter, surf, outbox, layout, rules, sites, total;
 };
+
+// Enqueue the upload of the site rule's tables of a surface (one, or two
+// for hybrid) to dev on stream, from pinned host copies the library keeps.
+hipError_t upload_tables(uint32_t kind, uint32_t S, hsga::RuleTable* dev, hipStream_t stream);
 
 // Surface words per agent of a validated config.
 inline uint32_t surface_words(const ga_config& c) {

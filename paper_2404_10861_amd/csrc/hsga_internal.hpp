@@ -70,6 +70,7 @@ struct BatchRun {
     uint32_t* outbox[2];
     uint32_t* sites;           // this batch's site schedule
     uint32_t* layout;          // the run's layout (S words)
+    const RuleTable* rules;    // the surface's site rule tables (device)
     uint32_t W, H, N, I, A;
     uint32_t T0, gens;
     uint32_t k0, k1;
@@ -117,10 +118,12 @@ hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, u
                            uint32_t SW, uint32_t* layout, uint32_t S, bool tags, uint32_t k0,
                            uint32_t k1, hipStream_t stream);
 
-// Sites of ingests tau0 .. tau0 + count - 1 (ingest units), from the run's
-// layout, which is advanced past them.
-hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
-                                uint32_t tau0, uint32_t count, hipStream_t stream);
+// Sites of ingests tau0 .. tau0 + count - 1 (ingest units) into
+// sites[0 .. count - 1], one thread per ingest, and the run's layout after
+// them (S words, ingest units), from the rule's constant-time tables
+// (rules: the surface's one or two tables on the device).
+hipError_t launch_run_sites(const RuleTable* rules, uint32_t kind, uint32_t S, uint32_t* sites,
+                            uint32_t* layout, uint32_t tau0, uint32_t count, hipStream_t stream);
 
 // agents_per_thread (1, 2 or 4) must divide N; tile_isl * N <= block_threads *
 // agents_per_thread.
@@ -140,7 +143,10 @@ hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, b
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
 
 // Batched forms: tile0 holds nruns + 1 prefix offsets of the runs' tiles.
-hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipStream_t stream);
+// Every run's sites for its generations T0 .. T0 + gens - 1 and its layout
+// after them (launch_run_sites per run); max_gens bounds every run's gens.
+hipError_t launch_batch_sites(const BatchRun* runs, uint32_t nruns, uint32_t max_gens,
+                              hipStream_t stream);
 // with_float: some run of the batch uses kBirthFloat (a separate kernel, so
 // that integer-only batches keep the integer kernel's register budget).
 hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,

@@ -54,26 +54,34 @@ hipError_t launch_founders(uint32_t* trait, uint32_t* counter, uint32_t* surf, u
 // counter T, so the surface site is the same for the whole population and
 // is computed once per generation (Results, Surface Algorithm Benchmark:
 // synchronous simulations can cache placements for a whole
-// subpopulation).  One wavefront, lane k = site k: for ingests
-// tau = tau0 .. tau0+count-1 (ingest units; every generation when the
-// interval is 1) the placement is a ballot over the lanes whose item left
-// the target, then a bit scan; the run's layout is carried in registers and
-// written back at the end.
-__device__ __forceinline__ void schedule_sites(uint32_t kind, uint32_t S, uint32_t* layout,
-                                               uint32_t* sites, uint32_t tau0, uint32_t count) {
-    const uint32_t lane = threadIdx.x;
-    uint32_t held = lane < S ? layout[lane] : kEmpty;
-    uint32_t leave = lane_leave_time(kind, S, lane, held);
-    place_items(kind, S, tau0, count, held, leave, lane,
-                [&](uint32_t k, int site) { sites[k] = (uint32_t)site; });
-    if (lane < S) layout[lane] = held;
+// subpopulation).  The sites of a launch batch's ingests come from the
+// rule's constant-time tables, one thread per ingest, and the first
+// wavefront writes the run's layout after them (lane = site), for the
+// run-bound queries and the read calls.
+__device__ __forceinline__ void run_sites(const RuleTable* rules, uint32_t kind, uint32_t S,
+                                          uint32_t* sites, uint32_t* layout, uint32_t tau0,
+                                          uint32_t count, uint32_t k) {
+    if (k < count) sites[k] = scheme_site(rules, kind, S, tau0 + k);
+    if (k < S) layout[k] = scheme_item_at(rules, kind, S, (uint64_t)tau0 + count, k);
 }
 
-__global__ __launch_bounds__(64) void site_schedule_kernel(uint32_t kind, uint32_t S,
-                                                           uint32_t* __restrict__ layout,
-                                                           uint32_t* __restrict__ sites,
-                                                           uint32_t tau0, uint32_t count) {
-    schedule_sites(kind, S, layout, sites, tau0, count);
+__global__ __launch_bounds__(256) void run_sites_kernel(const RuleTable* __restrict__ rules,
+                                                       uint32_t kind, uint32_t S,
+                                                       uint32_t* __restrict__ sites,
+                                                       uint32_t* __restrict__ layout,
+                                                       uint32_t tau0, uint32_t count) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    run_sites(rules, kind, S, sites, layout, tau0, count, k);
+}
+
+hipError_t launch_run_sites(const RuleTable* rules, uint32_t kind, uint32_t S, uint32_t* sites,
+                            uint32_t* layout, uint32_t tau0, uint32_t count,
+                            hipStream_t stream) {
+    if (S > 64) return hipErrorInvalidValue;
+    const uint32_t blocks = count > 256 ? (count + 255) / 256 : 1u;
+    hipLaunchKernelGGL(run_sites_kernel, dim3(blocks), dim3(256), 0, stream, rules, kind, S,
+                       sites, layout, tau0, count);
+    return hipGetLastError();
 }
 
 // Sites of ingests tau0 .. tau0 + count - 1 into an asynchronous run's
@@ -115,14 +123,6 @@ hipError_t launch_set_layout(uint32_t* layout, const uint32_t* words, uint32_t S
     LayoutWords lw{};
     for (uint32_t k = 0; k < S; ++k) lw.w[k] = words[k];
     hipLaunchKernelGGL(set_layout_kernel, dim3(1), dim3(64), 0, stream, layout, lw, S);
-    return hipGetLastError();
-}
-
-hipError_t launch_site_schedule(uint32_t kind, uint32_t S, uint32_t* layout, uint32_t* sites,
-                                uint32_t tau0, uint32_t count, hipStream_t stream) {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(site_schedule_kernel, dim3(1), dim3(64), 0, stream, kind, S, layout,
-                       sites, tau0, count);
     return hipGetLastError();
 }
 
@@ -726,18 +726,20 @@ hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, b
 // ---------------------------------------------------------------------------
 // Batched forms: many runs of different sizes, surfaces, treatments and
 // agents per thread in one launch per generation, sharing step_tile and
-// schedule_sites with the plain forms.
-__global__ __launch_bounds__(64) void batch_site_schedule_kernel(
-    const BatchRun* __restrict__ runs) {
-    const BatchRun& R = runs[blockIdx.x];
+// run_sites with the plain forms.
+__global__ __launch_bounds__(256) void batch_sites_kernel(const BatchRun* __restrict__ runs) {
+    const BatchRun& R = runs[blockIdx.y];
     const uint32_t tau0 = ingests_of(R.T0, R.interval);
     const uint32_t count = ingests_of(R.T0 + R.gens, R.interval) - tau0;
-    schedule_sites(R.kind, R.S, R.layout, R.sites, tau0, count);
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    run_sites(R.rules, R.kind, R.S, R.sites, R.layout, tau0, count, k);
 }
 
-hipError_t launch_batch_site_schedule(const BatchRun* runs, uint32_t nruns, hipStream_t stream) {
+hipError_t launch_batch_sites(const BatchRun* runs, uint32_t nruns, uint32_t max_gens,
+                              hipStream_t stream) {
     if (nruns == 0) return hipSuccess;
-    hipLaunchKernelGGL(batch_site_schedule_kernel, dim3(nruns), dim3(64), 0, stream, runs);
+    const uint32_t blocks = max_gens > 256 ? (max_gens + 255) / 256 : 1u;
+    hipLaunchKernelGGL(batch_sites_kernel, dim3(blocks, nruns), dim3(256), 0, stream, runs);
     return hipGetLastError();
 }
 

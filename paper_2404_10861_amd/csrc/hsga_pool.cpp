@@ -110,7 +110,7 @@ uint32_t variant_of(const ga_run& r) {
 
 int enqueue_launches(ga_pool* p, uint32_t nruns, uint32_t tiles, uint32_t gens, size_t lds,
                      bool with_float) {
-    hipError_t e = hsga::launch_batch_site_schedule(p->d_table, nruns, p->stream);
+    hipError_t e = hsga::launch_batch_sites(p->d_table, nruns, gens, p->stream);
     if (e != hipSuccess) return hip_fail(e, "batched site schedule launch");
     for (uint32_t k = 0; k < gens; ++k) {
         e = hsga::launch_batch_step(p->d_table, p->d_tile0, nruns, tiles, k, p->block, lds,
@@ -265,6 +265,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         }
         b.sites = r.sites;
         b.layout = r.layout;
+        b.rules = r.rules;
         b.W = sp.W; b.H = sp.H; b.N = sp.N; b.I = sp.I; b.A = sp.A;
         b.T0 = r.T;
         b.gens = g;

@@ -60,15 +60,15 @@ def test_footprint_without_gpu():
     n = hs.footprint_bytes(cfg)
     # a synchronous run: two populations of trait and surface words (no
     # counter plane: every counter is the generation count), plus outboxes,
-    # layout and schedule
-    assert n >= 2 * cfg.agents * 12 + 2 * cfg.islands * 32
-    assert n < 2 * cfg.agents * 12 + 2 * cfg.islands * 32 + (1 << 20)
-    # an asynchronous run keeps its counter planes as well, and the site
-    # rule's two constant-time tables (about 25 KB each) and a ring of 4,096
-    # sites in place of the 4,096-generation schedule
+    # layout, the site rule's two constant-time tables (about 25 KB each)
+    # and the schedule of a launch batch (4 bytes per generation)
+    base = 2 * cfg.agents * 12 + 2 * cfg.islands * 32
+    assert base + 40 * 1024 + 4096 * 4 < n < base + (1 << 20)
+    assert hs.footprint_bytes(cfg, 8192) - n == 4096 * 4
+    # an asynchronous run keeps its counter planes as well, and a ring of
+    # 4,096 sites in place of the 4,096-generation schedule
     acfg = hs.Config(512, 1024, 32, 64, "hybrid", async_activity=1 << 31)
-    extra = hs.footprint_bytes(acfg) - (n + 2 * cfg.agents * 4)
-    assert 40 * 1024 < extra < 64 * 1024
+    assert hs.footprint_bytes(acfg) - (n + 2 * cfg.agents * 4) == 0
     # and no tick bound: the same bytes whatever the launch batch
     assert hs.footprint_bytes(acfg, 16) == hs.footprint_bytes(acfg, 1 << 20)
     with pytest.raises(hs.HsgaError):
