@@ -122,3 +122,25 @@ def test_checkpoint_and_run_query_arguments_without_gpu():
     assert lib.ga_mrca_bounds(None, 1, None, None, None, None, None, 0) == b.GA_EINVAL
     assert b"run is NULL" in lib.ga_last_error()
     assert lib.ga_phylo_tree(None, 1, None, None, None, None, None, None, None, 0) == b.GA_EINVAL
+
+
+def test_missing_library_fails_loudly():
+    """No CPU fallback: without the built library every entry point of the
+    binding refuses to run."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_2404_10861_amd.binding as b\n"
+        "b.LIB_PATH = '/nonexistent/libhsga.so'\n"
+        "b._lib = None\n"
+        "import paper_2404_10861_amd as hs\n"
+        "try:\n"
+        "    hs.footprint_bytes(hs.Config(8, 8, 32, 32, 'steady'))\n"
+        "except RuntimeError as e:\n"
+        "    print('refused:', e)\n"
+        "else:\n"
+        "    print('ran')\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "refused: HIP library not built" in r.stdout
