@@ -270,3 +270,30 @@ def test_layouts_far_out_and_at_the_horizon(hs, orc, kind, S, T):
     if T + 1 == top:
         with pytest.raises(hs.HsgaError):
             run.step(1)
+
+
+@pytest.mark.parametrize("kind,S", [("steady", 64), ("tilted", 64), ("hybrid", 64),
+                                    ("steady", 32)])
+def test_device_sites_near_the_32_bit_limit(hs, orc, kind, S):
+    """Counts near 2^31 and near the end of 32-bit counters: a run imported
+    there takes its sites and layouts from the rule's tables on the device;
+    40 steps of it follow the oracle's placement rule, continued one item
+    at a time from the starting layout (which the host closed form gives,
+    itself checked against the oracle's replay)."""
+    k = ("steady", "tilted", "hybrid").index(kind)
+    cfg = hs.Config(1, 1, 4, S, kind, seed=5)
+    top = orc.horizon_gen(k, S, 1) + 1
+    for T in (1 << 31, min(top, (1 << 32) - 1) - 41):
+        state = hs.Run(cfg).export_state().view(np.uint32).copy()
+        off = 4 + int(state[2]) // 4
+        state[3] = T
+        state[off + cfg.agents:off + 2 * cfg.agents] = T
+        run = hs.Run(cfg, max_gens_per_launch=64)
+        run.import_state(state.view(np.uint8))
+        L = hs.layout(kind, S, T).copy()
+        assert np.array_equal(run.layout(), L)
+        for t in range(T, T + 40):
+            L[orc.place(k, S, L, t)] = t
+            run.step(1)
+            assert np.array_equal(run.layout(), L), (kind, S, t)
+        run.close()
