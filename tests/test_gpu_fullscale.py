@@ -1,5 +1,6 @@
-"""Full-size GPU parity over many generations (opt-in: set
-HSGA_FULL_PARITY=1; the oracle needs minutes of host time): the
+"""Full-size GPU parity over many generations (about two and a half
+minutes, mostly the oracle on up to 16 host threads; HSGA_SKIP_FULL=1
+skips them for quick runs): the
 paper-scale workload (512x1024 islands x 32, hybrid-64, tournament of two)
 for 300 generations, the treatment pair's torus (256x256 x 64, tilted-32)
 for 2,000 generations of each treatment, the float trial (750x750 x 32,
@@ -16,8 +17,8 @@ import numpy as np
 import pytest
 
 pytestmark = [pytest.mark.gpu,
-              pytest.mark.skipif(os.environ.get("HSGA_FULL_PARITY") != "1",
-                                 reason="opt-in: HSGA_FULL_PARITY=1")]
+              pytest.mark.skipif(os.environ.get("HSGA_SKIP_FULL") == "1",
+                                 reason="HSGA_SKIP_FULL=1")]
 
 
 @pytest.fixture(scope="module")
@@ -28,6 +29,11 @@ def hs():
     import paper_2404_10861_amd as hs
     hs.load_library()
     return hs
+
+
+# the oracle's island-parallel mode for synchronous runs (the same words
+# as one thread; asynchronous ticks stay serial)
+THREADS = min(16, os.cpu_count() or 1)
 
 
 def oracle_steps(o, G, label):
@@ -53,7 +59,7 @@ def test_full_size_runs_match_oracle(hs, orc, W, H, N, S, kind, tour, G):
     run = hs.Run(cfg)
     run.step(G)
     run.sync()
-    o = orc.Run(W, H, N, S, kinds[kind], tournament=tour, seed=1)
+    o = orc.Run(W, H, N, S, kinds[kind], tournament=tour, seed=1, threads=THREADS)
     oracle_steps(o, G, f"{W}x{H}x{N} {kind}-{S} tournament {tour}")
     for name, x, y in zip(("trait", "counter", "surface"), run.agents(), o.agents()):
         assert np.array_equal(x, y), name
@@ -90,7 +96,7 @@ def test_full_size_float_trial_matches_oracle(hs, orc):
     run.step(G)
     run.sync()
     o = orc.Run(750, 750, 32, 64, 1, tournament=5, seed=1, fitness_model=orc.FLOAT_FITNESS,
-                del_thr=1417339207, ben_thr=ben)
+                del_thr=1417339207, ben_thr=ben, threads=THREADS)
     oracle_steps(o, G, f"float trial, beneficial threshold {ben}")
     for name, x, y in zip(("fitness", "counter", "surface"), run.agents(), o.agents()):
         assert np.array_equal(x, y), name
@@ -107,7 +113,7 @@ def test_full_size_asynchronous_ticks_match_oracle(hs, orc):
     run = hs.Run(cfg, max_gens_per_launch=G)
     run.step(G)
     run.sync()
-    o = orc.Run(512, 1024, 32, 64, 2, tournament=2, seed=1, activity=act)
+    o = orc.Run(512, 1024, 32, 64, 2, tournament=2, seed=1, activity=act, threads=THREADS)
     oracle_steps(o, G, "asynchronous ticks")
     for name, x, y in zip(("trait", "counter", "surface"), run.agents(), o.agents()):
         assert np.array_equal(x, y), name
