@@ -469,8 +469,9 @@ int hstrat_phylo_newick(uint32_t n, uint32_t T, const uint32_t *leaf_parent,
  * count).  So when every counter equals the run's generation count T, the
  * run's own layout at T is used as it stands.  Otherwise (a sample taken
  * before later steps, drifted asynchronous counters) the query lays each
- * annotation out from the site rule's tables as the hstrat_ calls do;
- * both give the same words.  ga_phylo_tree with leaf_parent
+ * annotation out from the site rule's tables the run holds in its arena;
+ * both give the same words.  The workspace is sized as for the hstrat_
+ * calls (its table region is not used).  ga_phylo_tree with leaf_parent
  * NULL computes the metrics only (node_parent and node_time unused).
  * Errors as the hstrat_ calls, and GA_EINVAL for a NULL run.               */
 int ga_mrca_bounds(ga_run *run, uint32_t n, const uint32_t *counter,

@@ -725,12 +725,10 @@ int ga_mrca_bounds(ga_run* r, uint32_t n, const uint32_t* counter,
     if (workspace_bytes < mrca_total_bytes(sc.S, n)) return fail(GA_ENOMEM, "workspace too small");
     // on the run's stream: the layout is read after the steps enqueued so
     // far and before any later ones advance it
-    hsga::LayoutHint hint{r->layout, r->T};
-    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
-                                        aligned256(hsga::MrcaWorkspace::bytes(sc.S, n)),
-                                r->stream, &hint);
-    if (e != hipSuccess) return hip_fail(e, "site rule upload");
-    e = hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace, r->stream, hint);
+    // the run's own tables (in its arena) lay out annotations of other counts
+    const hsga::LayoutHint hint{r->layout, r->T, r->rules};
+    hipError_t e =
+        hsga::launch_mrca(sc, n, counter, surface_words, lb, ub, workspace, r->stream, hint);
     if (e != hipSuccess) return hip_fail(e, "mrca launch");
     return GA_OK;
 }
@@ -748,13 +746,9 @@ int ga_phylo_tree(ga_run* r, uint32_t n, const uint32_t* counter, const uint32_t
     if ((uintptr_t)workspace % kAlign) return fail(GA_EINVAL, "workspace not 256-byte aligned");
     if (workspace_bytes < phylo_total_bytes(sc.S, n))
         return fail(GA_ENOMEM, "workspace too small");
-    hsga::LayoutHint hint{r->layout, r->T};
-    hipError_t e = upload_rules(sc, static_cast<uint8_t*>(workspace) +
-                                        aligned256(hsga::phylo_workspace_bytes(sc.S, n)),
-                                r->stream, &hint);
-    if (e != hipSuccess) return hip_fail(e, "site rule upload");
-    e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, r->stream, leaf_parent,
-                           node_parent, node_time, hint);
+    const hsga::LayoutHint hint{r->layout, r->T, r->rules};
+    hipError_t e = hsga::launch_phylo(sc, n, counter, surface_words, out, workspace, r->stream,
+                                      leaf_parent, node_parent, node_time, hint);
     if (e != hipSuccess) return hip_fail(e, "phylo launch");
     return GA_OK;
 }
