@@ -344,9 +344,20 @@ def main(argv=None) -> int:
             copy_gbs = attainable_copy_gbs(torch, hs, dev, stream)
             res = benchmarks.batched_vs_plain(specs, dev, stream, tune=not args.batch_block,
                                               block_threads=args.batch_block or 256)
-            res["algorithmic_bytes_per_generation"] = sum(
-                batch_bytes_per_generation(sp) for sp in specs)
+            bytes_gen = sum(batch_bytes_per_generation(sp) for sp in specs)
+            res["algorithmic_bytes_per_generation"] = bytes_gen
             res["attainable_copy_GBs"] = copy_gbs
+            gen_us = res["steady_generation_us"]
+            if gen_us:
+                gbs = bytes_gen / (gen_us * 1e-6) / 1e9
+                res["roofline"] = {
+                    "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS, "frac_of_attainable": gbs / copy_gbs,
+                    "kernel": "batch_step_kernel, the launch groups side by side",
+                    "generation_us": gen_us,
+                    "note": "achieved: the set's algorithmic bytes per generation over the "
+                            "wall time per generation after tuning (HIP events on the "
+                            "pool's stream)"}
             metric = "agent-replications/sec (batched vs sequential plain)"
             value = res["batched_replications_per_s"]
         else:

@@ -486,12 +486,18 @@ int ga_phylo_tree(ga_run *run, uint32_t n, const uint32_t *counter,
 /* ------------------------------------------------------------------------
  * Batched and served runs: a pool of runs of any sizes, surfaces and
  * treatments sharing one caller-owned device arena and one stream.  An
- * advance enqueues one site-schedule launch for all active runs, then one
- * step launch per generation covering every active run's tiles; each run
- * takes the same steps as under ga_step, so its results are identical to
- * running it alone.  Admission is by footprint: a run gets a first-fit
- * range of the arena or is refused.  Runs are identified by small integer
- * ids, reused after release.  All work is ordered on the pool's stream.
+ * advance enqueues one site-schedule launch for all active runs, then per
+ * generation one step launch for each of two groups of runs of about equal
+ * bytes; each run takes the same steps as under ga_step, so its results
+ * are identical to running it alone.  A launch deals every run's tiles
+ * evenly over the chip's 8 XCDs, one contiguous chunk per XCD.  When both
+ * groups hold runs, the second group's launches go to a stream the pool
+ * creates, forked from the pool's stream after the site schedules and
+ * joined back to it at the end of the advance, so that the groups run side
+ * by side.  Admission is by footprint: a run gets a first-fit range of the
+ * arena or is refused.  Runs are identified by small integer ids, reused
+ * after release.  All work is ordered on the pool's stream: work enqueued
+ * on it after an advance sees that advance complete.
  * ------------------------------------------------------------------------ */
 typedef struct ga_pool ga_pool;
 
@@ -549,7 +555,9 @@ int ga_pool_set_launch(ga_pool *pool, uint32_t block_threads, int use_graph);
 int ga_pool_info(const ga_pool *pool, uint32_t *active, uint32_t *admitted,
                  size_t *free_bytes, size_t *largest_free);
 
-/* Release every run and the pool's host state; the arena is untouched. */
+/* Wait for the work enqueued on the pool's stream, then release every run,
+ * the pool's own stream and events, and its host state; the arena is
+ * untouched.                                                              */
 void ga_pool_destroy(ga_pool *pool);
 
 /* ------------------------------------------------------------------------

@@ -26,7 +26,7 @@ import time
 DEFAULT_CANDIDATES = (
     # (block_threads, generations per launch, hipGraph replay)
     (64, 64, False), (64, 64, True), (128, 64, True), (256, 64, True),
-    (64, 256, True), (64, 16, True),
+    (64, 256, True), (256, 256, True), (64, 16, True),
 )
 
 

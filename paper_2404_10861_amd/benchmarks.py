@@ -100,8 +100,18 @@ def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool 
     else:
         pool.set_launch(block_threads, True)
     G = choice["gens_per_launch"]
-    while pool.advance(G):
-        pass
+    # the generations after tuning, timed on the pool's stream: wall time
+    # per generation of every run, the groups' launches side by side
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steady = 0
+    e0.record(pstream)
+    while True:
+        n = pool.advance(G)
+        if not n:
+            break
+        steady += n
+    e1.record(pstream)
     pool.sync()
     t_batch = time.perf_counter() - t0
     done = pool.poll()
@@ -116,6 +126,8 @@ def batched_vs_plain(specs, dev, stream, gens_per_launch: int = 512, tune: bool 
         "batched_s": t_batch,
         "batched_replications_per_s": reps / t_batch,
         "batched_over_plain": t_plain / t_batch,
+        "steady_generations": steady,
+        "steady_generation_us": e0.elapsed_time(e1) * 1000.0 / steady if steady else None,
         "tuned": {k: choice[k] for k in ("block_threads", "gens_per_launch", "use_graph")},
         "tuner_trials": choice.get("trials", []),
         "all_runs_finished": bool(ok),

@@ -86,7 +86,6 @@ struct BatchRun {
     uint32_t diff_log2;        // 0: one-bit differentiae, 3: bytes
     uint32_t tile_isl, div_magic;
     uint32_t w_magic, w_shift;
-    uint32_t tile0;            // first tile of the run in the batched grid
 };
 
 // Division of any 32-bit n by a fixed d >= 1 as a multiply-high and
@@ -142,16 +141,68 @@ hipError_t launch_set_layout(uint32_t* layout, const uint32_t* words, uint32_t S
 hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
 
-// Batched forms: tile0 holds nruns + 1 prefix offsets of the runs' tiles.
-// Every run's sites for its generations T0 .. T0 + gens - 1 and its layout
+// Batched forms.  Every run's sites for its generations T0 .. T0 + gens - 1 and its layout
 // after them (launch_run_sites per run); max_gens bounds every run's gens.
 hipError_t launch_batch_sites(const BatchRun* runs, uint32_t nruns, uint32_t max_gens,
                               hipStream_t stream);
+// One generation of every run: total_tiles workgroups, workgroup b on XCD
+// b mod kXcds as its (b / kXcds)-th.  xcd_tab (2 * kXcds * nruns words):
+// for each XCD x, pre[x][i] = the offset of run i's chunk among x's
+// workgroups (ascending in i, pre[x][0] = 0); then for each XCD x,
+// first[x][i] = run i's first tile in that chunk.  The chunks of run i
+// over all XCDs tile it exactly, and XCD x's chunks fill exactly its
+// ceil((total_tiles - x) / kXcds) workgroups.
 // with_float: some run of the batch uses kBirthFloat (a separate kernel, so
 // that integer-only batches keep the integer kernel's register budget).
-hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,
+constexpr uint32_t kXcds = 8;
+hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* xcd_tab, uint32_t nruns,
                              uint32_t total_tiles, uint32_t k, uint32_t block_threads,
                              size_t lds_bytes, bool with_float, hipStream_t stream);
+
+// Cut each of n runs' tiles (tiles[i], total T) into kXcds contiguous
+// chunks, one per XCD, that fill exactly XCD x's ceil((T - x) / kXcds)
+// workgroups, and write the xcd table launch_batch_step takes.  Each run
+// gives every XCD tiles / kXcds of its tiles, and its tiles % kXcds
+// remaining ones go one each to the XCDs with the most workgroups still
+// unfilled.  The unfilled counts then never differ by more than one
+// between XCDs, so none goes below zero and all reach zero together.
+inline bool deal_tiles(const uint32_t* tiles, uint32_t n, uint32_t T, uint32_t* tab) {
+    constexpr uint32_t X = kXcds;
+    uint32_t left[X], filled[X];
+    for (uint32_t x = 0; x < X; ++x) {
+        left[x] = T > x ? (T - x + X - 1) / X : 0u;
+        filled[x] = 0;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t take[X];
+        for (uint32_t x = 0; x < X; ++x) take[x] = tiles[i] / X;
+        for (uint32_t r = 0; r < tiles[i] % X; ++r) {
+            // the XCD with the most left after what it takes so far, ties
+            // going round from a run-dependent start
+            uint32_t best = X;
+            for (uint32_t d = 0; d < X; ++d) {
+                const uint32_t x = (i + d) % X;
+                if (take[x] != tiles[i] / X) continue;      // has its extra tile
+                if (best == X ||
+                    (int64_t)left[x] - take[x] > (int64_t)left[best] - take[best])
+                    best = x;
+            }
+            ++take[best];
+        }
+        uint32_t first = 0;
+        for (uint32_t x = 0; x < X; ++x) {
+            if (take[x] > left[x]) return false;
+            tab[x * n + i] = filled[x];
+            tab[(X + x) * n + i] = first;
+            first += take[x];
+            filled[x] += take[x];
+            left[x] -= take[x];
+        }
+    }
+    for (uint32_t x = 0; x < X; ++x)
+        if (left[x]) return false;
+    return true;
+}
 
 hipError_t launch_sample(const uint32_t* counter, const uint32_t* surf, uint32_t A, uint32_t SW,
                          uint32_t n, uint32_t T, uint32_t k0, uint32_t k1, uint32_t* idx_out,

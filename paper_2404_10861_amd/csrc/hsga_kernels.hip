@@ -768,22 +768,33 @@ __device__ __forceinline__ void step_tile_variant(const StepParams& p, uint32_t 
 // batches use the instantiation without them, which needs fewer registers.
 template <bool WITH_FLOAT>
 __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __restrict__ runs,
-                                                         const uint32_t* __restrict__ tile0,
+                                                         const uint32_t* __restrict__ xcd_tab,
                                                          uint32_t nruns, uint32_t k) {
-    const uint32_t tile = xcd_local_block(blockIdx.x, gridDim.x);
-    // the run owning this tile: tile0 is ascending, so it is the number of
-    // runs starting at or before the tile, less one -- one load per lane
-    // and a ballot per 64 runs in every wavefront, with no LDS round trip
-    // or barrier before the run's parameters can be fetched
+    // Workgroup b runs on XCD x = b mod 8 as the XCD's j-th workgroup, j =
+    // b / 8 (the dispatcher deals workgroups to the XCDs in turn).  Every
+    // run's tiles are cut into 8 contiguous chunks, one per XCD, so
+    // each XCD gets an equal share of every run: a launch of runs of
+    // unequal cost per tile then finishes on all XCDs together, while torus
+    // neighbours within a chunk still share an L2.  xcd_tab holds, per
+    // XCD, the ascending offsets of the runs' chunks among its workgroups
+    // (nruns words), then per XCD the first tile of each run's chunk.
+    const uint32_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
+    const uint32_t* __restrict__ pre = xcd_tab + x * nruns;
+    // the run owning this workgroup: the number of runs whose chunk starts
+    // at or before j, less one (a run with an empty chunk shares its
+    // offset with the next and is passed over) -- one load per lane and a
+    // ballot per 64 runs in every wavefront, with no LDS round trip or
+    // barrier before the run's parameters can be fetched
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t before = 0;
     for (uint32_t b0 = 0; b0 < nruns; b0 += 64) {
         const uint32_t i = b0 + lane;
-        const bool le = i < nruns && tile0[i] <= tile;
+        const bool le = i < nruns && pre[i] <= j;
         before += (uint32_t)__popcll(__ballot(le));
     }
-    const uint32_t lo = before - 1u;       // tile0[0] = 0: at least one run
+    const uint32_t lo = before - 1u;       // pre[0] = 0: at least one run
     const BatchRun& R = runs[lo];
+    const uint32_t t = xcd_tab[(kXcds + x) * nruns + lo] + (j - pre[lo]);
     if (k >= R.gens) return;
     const uint32_t g = R.T0 + k;
     const uint32_t src = g & 1u, dst = (g + 1u) & 1u;
@@ -821,23 +832,22 @@ __global__ __launch_bounds__(1024) void batch_step_kernel(const BatchRun* __rest
     p.tour = R.tour;
     p.del_thr = R.del_thr; p.ben_thr = R.ben_thr;
     p.del_sigma = R.del_sigma; p.ben_sigma = R.ben_sigma;
-    const uint32_t t = tile - R.tile0;
     const uint32_t model = (R.variant >> 1) & 3u;
     if (model == kBirthIntTournament) step_tile_variant<kBirthIntTournament>(p, t, R.variant);
     else if (WITH_FLOAT && model == kBirthFloat) step_tile_variant<kBirthFloat>(p, t, R.variant);
     else step_tile_variant<kBirthIntNeutral>(p, t, R.variant);
 }
 
-hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* tile0, uint32_t nruns,
+hipError_t launch_batch_step(const BatchRun* runs, const uint32_t* xcd_tab, uint32_t nruns,
                              uint32_t total_tiles, uint32_t k, uint32_t block_threads,
                              size_t lds_bytes, bool with_float, hipStream_t stream) {
     if (nruns == 0 || total_tiles == 0) return hipSuccess;
     if (with_float)
         hipLaunchKernelGGL(batch_step_kernel<true>, dim3(total_tiles), dim3(block_threads),
-                           lds_bytes, stream, runs, tile0, nruns, k);
+                           lds_bytes, stream, runs, xcd_tab, nruns, k);
     else
         hipLaunchKernelGGL(batch_step_kernel<false>, dim3(total_tiles), dim3(block_threads),
-                           lds_bytes, stream, runs, tile0, nruns, k);
+                           lds_bytes, stream, runs, xcd_tab, nruns, k);
     return hipGetLastError();
 }
 

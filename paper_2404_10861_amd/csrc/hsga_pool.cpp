@@ -1,8 +1,9 @@
 // hsga_pool.cpp -- batched and served runs (include/hsga.h, ga_pool_*): a
 // first-fit allocator over the caller's arena, a device-resident run table,
-// and one launch per generation for all active runs (optionally replayed
-// from a captured hipGraph).  The per-run arithmetic is step_tile and
-// schedule_sites, the same device code as the plain runs.
+// and per generation one launch per group of active runs, the groups on
+// streams of their own that run side by side (optionally replayed from
+// captured hipGraphs).  The per-run arithmetic is step_tile and run_sites,
+// the same device code as the plain runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,32 +26,61 @@ struct Slot {
     ga_run run;
 };
 
-struct GraphKey {
-    uint32_t nruns = 0, tiles = 0, gens = 0, block = 0;
+// An advance cuts the active runs, in table order, into kGroups
+// contiguous groups of about equal bytes per generation and gives each
+// group one launch per generation on a stream of its own.  The groups'
+// runs are independent, so the streams run side by side and one group's
+// launch tail (its last, partly filled wave of workgroups, and the gap
+// before its next launch) overlaps the others' work.
+constexpr uint32_t kGroups = 2;
+
+// The runs of one launch: table entries first .. first + count - 1, and
+// their tiles' workgroups dealt over the XCDs in the xcd table from word
+// 2 * kXcds * first on.
+struct Group {
+    uint32_t first = 0, count = 0, tiles = 0;
     size_t lds = 0;
     bool with_float = false;
-    bool operator==(const GraphKey& o) const {
-        return nruns == o.nruns && tiles == o.tiles && gens == o.gens && block == o.block &&
-               lds == o.lds && with_float == o.with_float;
+    bool operator==(const Group& o) const {
+        return first == o.first && count == o.count && tiles == o.tiles && lds == o.lds &&
+               with_float == o.with_float;
     }
 };
 
+// One advance's launches (a group may be empty).
+struct GraphKey {
+    Group grp[kGroups];
+    uint32_t gens = 0, block = 0;
+    bool operator==(const GraphKey& o) const {
+        for (uint32_t q = 0; q < kGroups; ++q)
+            if (!(grp[q] == o.grp[q])) return false;
+        return gens == o.gens && block == o.block;
+    }
+};
+
+// words of the xcd tables (launch_batch_step) of up to max_runs runs
+size_t xcd_words(uint32_t max_runs) { return 2 * (size_t)hsga::kXcds * max_runs; }
+
+// the run table, then the xcd tables
 size_t table_bytes(uint32_t max_runs) {
-    return align_up(sizeof(hsga::BatchRun) * max_runs) + align_up(4 * (size_t)(max_runs + 1));
+    return align_up(sizeof(hsga::BatchRun) * max_runs) + align_up(4 * xcd_words(max_runs));
 }
 
 }  // namespace
 
 struct ga_pool {
     hipStream_t stream;
+    hipStream_t side[kGroups - 1];   // groups 1.. launch here
+    hipEvent_t fork;                 // the sides wait for stream
+    hipEvent_t join[kGroups - 1];    // then stream for each side
     uint8_t* arena;
     size_t arena_bytes;
     uint32_t max_runs, gens;
     hsga::BatchRun* d_table;
-    uint32_t* d_tile0;
+    uint32_t* d_xtab;          // the groups' xcd tables
     size_t data_off;
     hsga::BatchRun* h_table;   // pinned staging
-    uint32_t* h_tile0;         // pinned staging
+    uint32_t* h_xtab;          // pinned staging
     hipEvent_t staged;         // the last table upload has been consumed
     bool staged_pending;
     std::vector<Slot> slots;
@@ -58,7 +88,8 @@ struct ga_pool {
     uint32_t block;
     bool use_graph;
     GraphKey key;
-    hipGraphExec_t exec;
+    bool captured;                   // exec holds key's launches
+    hipGraphExec_t exec[kGroups];    // each group's launches, replayed on its stream
 };
 
 namespace {
@@ -94,10 +125,28 @@ bool take_range(ga_pool* p, size_t bytes, size_t* off) {
 }
 
 void drop_graph(ga_pool* p) {
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    p->exec = nullptr;
+    for (hipGraphExec_t& x : p->exec) {
+        if (x) (void)hipGraphExecDestroy(x);
+        x = nullptr;
+    }
     p->key = GraphKey{};
+    p->captured = false;
 }
+
+void release_handles(ga_pool* p) {
+    for (hipStream_t& x : p->side)
+        if (x) (void)hipStreamDestroy(x);
+    for (hipEvent_t& x : p->join)
+        if (x) (void)hipEventDestroy(x);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->staged) (void)hipEventDestroy(p->staged);
+    (void)hipHostFree(p->h_xtab);
+    (void)hipHostFree(p->h_table);
+}
+
+// words a run reads or writes per agent and generation: its trait and
+// surface words, in and out (the balance of the launch groups)
+uint64_t words_per_generation(const ga_run& r) { return (uint64_t)r.A * (1 + r.SW); }
 
 uint32_t variant_of(const ga_run& r) {
     uint32_t v = 0;
@@ -108,15 +157,87 @@ uint32_t variant_of(const ga_run& r) {
     return v | (apt_log2 << 4);
 }
 
-int enqueue_launches(ga_pool* p, uint32_t nruns, uint32_t tiles, uint32_t gens, size_t lds,
-                     bool with_float) {
-    hipError_t e = hsga::launch_batch_sites(p->d_table, nruns, gens, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "batched site schedule launch");
-    for (uint32_t k = 0; k < gens; ++k) {
-        e = hsga::launch_batch_step(p->d_table, p->d_tile0, nruns, tiles, k, p->block, lds,
-                                    with_float, p->stream);
-        if (e != hipSuccess) return hip_fail(e, "batched step launch");
+hipStream_t stream_of(const ga_pool* p, uint32_t q) { return q ? p->side[q - 1] : p->stream; }
+
+hipError_t launch_group(ga_pool* p, const GraphKey& key, uint32_t q, uint32_t k) {
+    const Group& g = key.grp[q];
+    return hsga::launch_batch_step(p->d_table + g.first, p->d_xtab + xcd_words(g.first), g.count,
+                                   g.tiles, k, p->block, g.lds, g.with_float, stream_of(p, q));
+}
+
+// Group q's launches of every generation, captured on its stream into
+// exec[q]: one linear graph per stream.
+int capture_group(ga_pool* p, const GraphKey& key, uint32_t q) {
+    const hipStream_t s = stream_of(p, q);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (uint32_t k = 0; k < key.gens && le == hipSuccess; ++k) le = launch_group(p, key, q, k);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (le == hipSuccess && e == hipSuccess)
+        e = hipGraphInstantiate(&p->exec[q], graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        p->exec[q] = nullptr;
+        return hip_fail(le != hipSuccess ? le : e, "capture of the batched launches");
     }
+    return GA_OK;
+}
+
+// The site schedules of all runs on the pool's stream, then the groups'
+// launches, groups 1.. on the side streams: forked after the schedules and
+// joined back at the end, so that work enqueued on the pool's stream later
+// sees the whole advance.  Replayed, each stream replays its own group's
+// graph.
+int enqueue_launches(ga_pool* p, const GraphKey& key) {
+    uint32_t nruns = 0;
+    for (const Group& g : key.grp) nruns += g.count;
+    hipError_t e = hsga::launch_batch_sites(p->d_table, nruns, key.gens, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "batched site schedule launch");
+    const bool graph = p->use_graph && p->stream;
+    if (graph && !(p->captured && p->key == key)) {
+        drop_graph(p);
+        for (uint32_t q = 0; q < kGroups; ++q) {
+            if (key.grp[q].count == 0) continue;
+            const int rc = capture_group(p, key, q);
+            if (rc != GA_OK) {
+                drop_graph(p);
+                return rc;
+            }
+        }
+        p->key = key;
+        p->captured = true;
+    }
+    bool forked = false;
+    for (uint32_t q = 1; q < kGroups; ++q) {
+        if (key.grp[q].count == 0) continue;
+        if (!forked) {
+            e = hipEventRecord(p->fork, p->stream);
+            if (e != hipSuccess) return hip_fail(e, "fork to the side streams");
+            forked = true;
+        }
+        e = hipStreamWaitEvent(p->side[q - 1], p->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "fork to the side streams");
+    }
+    hipError_t le = hipSuccess;
+    if (graph) {
+        for (uint32_t q = 0; q < kGroups && le == hipSuccess; ++q)
+            if (key.grp[q].count) le = hipGraphLaunch(p->exec[q], stream_of(p, q));
+    } else {
+        for (uint32_t k = 0; k < key.gens && le == hipSuccess; ++k)
+            for (uint32_t q = 0; q < kGroups && le == hipSuccess; ++q)
+                if (key.grp[q].count) le = launch_group(p, key, q, k);
+    }
+    // joined even after a failed launch, so that the pool's stream orders
+    // whatever was enqueued
+    for (uint32_t q = 1; q < kGroups; ++q) {
+        if (key.grp[q].count == 0) continue;
+        e = hipEventRecord(p->join[q - 1], p->side[q - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->join[q - 1], 0);
+        if (e != hipSuccess) return hip_fail(e, "join from the side streams");
+    }
+    if (le != hipSuccess) return hip_fail(le, graph ? "hipGraphLaunch" : "batched step launch");
     return GA_OK;
 }
 
@@ -144,14 +265,14 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
     p->max_runs = max_runs;
     p->gens = max_gens_per_launch ? max_gens_per_launch : kDefaultGens;
     p->d_table = reinterpret_cast<hsga::BatchRun*>(p->arena);
-    p->d_tile0 = reinterpret_cast<uint32_t*>(p->arena +
-                                             align_up(sizeof(hsga::BatchRun) * max_runs));
+    p->d_xtab = reinterpret_cast<uint32_t*>(p->arena +
+                                            align_up(sizeof(hsga::BatchRun) * max_runs));
     p->data_off = over;
     p->slots.resize(max_runs);
     if (arena_bytes > over) p->free_ranges.emplace(over, arena_bytes - over);
     p->block = 64;
     p->use_graph = false;
-    p->exec = nullptr;
+    p->captured = false;
     p->staged_pending = false;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_table),
                                  sizeof(hsga::BatchRun) * max_runs, hipHostMallocDefault);
@@ -159,7 +280,7 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
         delete p;
         return hip_fail(e, "hipHostMalloc table staging");
     }
-    e = hipHostMalloc(reinterpret_cast<void**>(&p->h_tile0), 4 * (size_t)(max_runs + 1),
+    e = hipHostMalloc(reinterpret_cast<void**>(&p->h_xtab), 4 * xcd_words(max_runs),
                       hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipHostFree(p->h_table);
@@ -167,11 +288,15 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
         return hip_fail(e, "hipHostMalloc tile staging");
     }
     e = hipEventCreateWithFlags(&p->staged, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    for (uint32_t q = 0; q + 1 < kGroups && e == hipSuccess; ++q) {
+        e = hipEventCreateWithFlags(&p->join[q], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side[q], hipStreamNonBlocking);
+    }
     if (e != hipSuccess) {
-        (void)hipHostFree(p->h_table);
-        (void)hipHostFree(p->h_tile0);
+        release_handles(p);
         delete p;
-        return hip_fail(e, "hipEventCreate");
+        return hip_fail(e, "pool event or stream creation");
     }
     *out = p;
     return GA_OK;
@@ -238,18 +363,29 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     std::stable_sort(active.begin(), active.end(), [&](uint32_t a, uint32_t b) {
         return variant_of(p->slots[a].run) < variant_of(p->slots[b].run);
     });
+    // the groups: run i joins the group its bytes' midpoint falls in (the
+    // lower one on a boundary, so that a lone run stays on the pool's
+    // stream)
+    uint64_t total_words = 0;
+    for (uint32_t s : active) total_words += words_per_generation(p->slots[s].run);
     if (p->staged_pending) {
         hipError_t e = hipEventSynchronize(p->staged);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
         p->staged_pending = false;
     }
-    uint32_t tiles = 0, gens = 0;
-    size_t lds = 0;
-    bool with_float = false;
+    GraphKey key;
+    key.block = p->block;
     const uint32_t nruns = (uint32_t)active.size();
+    std::vector<uint32_t> run_tiles(nruns);
+    uint64_t words_before = 0;
     for (uint32_t i = 0; i < nruns; ++i) {
         Slot& s = p->slots[active[i]];
         ga_run& r = s.run;
+        const uint64_t w = words_per_generation(r);
+        const uint32_t q = (uint32_t)std::min<uint64_t>(
+            kGroups - 1, ((2 * words_before + w) * kGroups - 1) / (2 * total_words));
+        words_before += w;
+        Group& grp = key.grp[q];
         r.block = p->block;
         const uint32_t g = std::min(G, s.target - r.T);
         const hsga::StepParams sp = step_params(&r, r.T, hsga::ingests_of(r.T, r.cfg.ingest_interval));
@@ -257,11 +393,11 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         if (sp.tile_isl == 0 || sp.tile_isl > p->block)
             return fail(GA_EINVAL, "tile has more islands than the workgroup has threads");
         hsga::BatchRun& b = p->h_table[i];
-        for (int q = 0; q < 2; ++q) {
-            b.trait[q] = r.trait[q];
-            b.counter[q] = r.counter[q];
-            b.surf[q] = r.surf[q];
-            b.outbox[q] = r.outbox[q];
+        for (int j = 0; j < 2; ++j) {
+            b.trait[j] = r.trait[j];
+            b.counter[j] = r.counter[j];
+            b.surf[j] = r.surf[j];
+            b.outbox[j] = r.outbox[j];
         }
         b.sites = r.sites;
         b.layout = r.layout;
@@ -274,7 +410,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         b.kind = r.cfg.surface_kind;
         b.S = r.S;
         b.variant = variant_of(r);
-        with_float = with_float || birth_model(r.cfg) == hsga::kBirthFloat;
+        grp.with_float = grp.with_float || birth_model(r.cfg) == hsga::kBirthFloat;
         b.tour = sp.tour;
         b.del_thr = sp.del_thr; b.ben_thr = sp.ben_thr;
         b.del_sigma = sp.del_sigma; b.ben_sigma = sp.ben_sigma;
@@ -284,61 +420,44 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         b.div_magic = sp.div_magic;
         b.w_magic = sp.w_magic;
         b.w_shift = sp.w_shift;
-        b.tile0 = tiles;
-        p->h_tile0[i] = tiles;
         const uint32_t rt = (r.I + sp.tile_isl - 1) / sp.tile_isl;
-        tiles += rt;
-        gens = std::max(gens, g);
-        lds = std::max(lds, hsga::step_lds_bytes(sp.tile_isl, r.N, r.SW,
-                                                 birth_model(r.cfg) == hsga::kBirthFloat,
-                                                 p->block, r.apt));
+        run_tiles[i] = rt;
+        grp.tiles += rt;
+        ++grp.count;
+        key.gens = std::max(key.gens, g);
+        grp.lds = std::max(grp.lds, hsga::step_lds_bytes(sp.tile_isl, r.N, r.SW,
+                                                         birth_model(r.cfg) == hsga::kBirthFloat,
+                                                         p->block, r.apt));
     }
-    if (lds > kMaxStepLds) return fail(GA_EINVAL, "batched tiles need more than 64 KiB of LDS");
-    p->h_tile0[nruns] = tiles;
+    // each group's xcd table, group after group
+    uint32_t first = 0;
+    for (uint32_t q = 0; q < kGroups; ++q) {
+        Group& grp = key.grp[q];
+        if (grp.lds > kMaxStepLds)
+            return fail(GA_EINVAL, "batched tiles need more than 64 KiB of LDS");
+        grp.first = first;
+        if (!hsga::deal_tiles(run_tiles.data() + first, grp.count, grp.tiles,
+                        p->h_xtab + xcd_words(first)))
+            return fail(GA_EINVAL, "tiles could not be dealt over the XCDs");
+        first += grp.count;
+    }
     hipError_t e = hipMemcpyAsync(p->d_table, p->h_table, sizeof(hsga::BatchRun) * nruns,
                                   hipMemcpyHostToDevice, p->stream);
     if (e != hipSuccess) return hip_fail(e, "table upload");
-    e = hipMemcpyAsync(p->d_tile0, p->h_tile0, 4 * (size_t)(nruns + 1), hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(p->d_xtab, p->h_xtab, 4 * xcd_words(nruns), hipMemcpyHostToDevice,
                        p->stream);
     if (e != hipSuccess) return hip_fail(e, "tile table upload");
     e = hipEventRecord(p->staged, p->stream);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     p->staged_pending = true;
 
-    const GraphKey key{nruns, tiles, gens, p->block, lds, with_float};
-    int rc = GA_OK;
-    if (p->use_graph && p->stream) {
-        if (!(p->exec && p->key == key)) {
-            drop_graph(p);
-            e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            rc = enqueue_launches(p, nruns, tiles, gens, lds, with_float);
-            hipGraph_t graph = nullptr;
-            e = hipStreamEndCapture(p->stream, &graph);
-            if (rc != GA_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return rc;
-            }
-            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-            e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (e != hipSuccess) {
-                p->exec = nullptr;
-                return hip_fail(e, "hipGraphInstantiate");
-            }
-            p->key = key;
-        }
-        e = hipGraphLaunch(p->exec, p->stream);
-        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    } else {
-        rc = enqueue_launches(p, nruns, tiles, gens, lds, with_float);
-        if (rc != GA_OK) return rc;
-    }
+    const int rc = enqueue_launches(p, key);
+    if (rc != GA_OK) return rc;
     for (uint32_t i = 0; i < nruns; ++i) {
         Slot& s = p->slots[active[i]];
         s.run.T += p->h_table[i].gens;
     }
-    if (gens_enqueued) *gens_enqueued = gens;
+    if (gens_enqueued) *gens_enqueued = key.gens;
     return GA_OK;
 }
 
@@ -418,10 +537,9 @@ int ga_pool_info(const ga_pool* p, uint32_t* active, uint32_t* admitted, size_t*
 
 void ga_pool_destroy(ga_pool* p) {
     if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
     drop_graph(p);
-    (void)hipEventDestroy(p->staged);
-    (void)hipHostFree(p->h_table);
-    (void)hipHostFree(p->h_tile0);
+    release_handles(p);
     delete p;
 }
 

@@ -129,9 +129,16 @@ def cmd_traffic(a):
     w_factor = copy_kib / statistics.median(cw)
     names, sf = _pick(fetch, a.kernel)
     _, sw = _pick(write, a.kernel)
-    # the first dispatch of a run reads no outboxes; use the median
-    fetch_b = statistics.median(sf) * 1024.0 * f_factor
-    write_b = statistics.median(sw) * 1024.0 * w_factor
+    k = a.dispatches_per_launch
+    if k == 1:
+        # the first dispatch of a run reads no outboxes; use the median
+        fetch_kib, write_kib = statistics.median(sf), statistics.median(sw)
+    else:
+        # a launch (a generation) of k dispatches side by side: the mean
+        # dispatch times k
+        fetch_kib, write_kib = k * statistics.fmean(sf), k * statistics.fmean(sw)
+    fetch_b = fetch_kib * 1024.0 * f_factor
+    write_b = write_kib * 1024.0 * w_factor
     rec = {
         "kernel": a.kernel,
         "kernel_names": names,
@@ -163,7 +170,9 @@ def cmd_traffic(a):
               f"{f_factor:.4f} (fetch), {w_factor:.4f} (write)",
               f"- step kernel ({len(sf)} dispatches, median): FETCH_SIZE "
               f"{rec['fetch_kib_per_dispatch_median']:.0f} KiB, WRITE_SIZE "
-              f"{rec['write_kib_per_dispatch_median']:.0f} KiB",
+              f"{rec['write_kib_per_dispatch_median']:.0f} KiB" +
+              (f"; {k} dispatches per launch, counted as {k} x the mean dispatch"
+               if k > 1 else ""),
               f"- HBM bytes per launch: read {fetch_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB "
               f"= {(fetch_b + write_b) / 1e6:.1f} MB",
               f"- algorithmic bytes per launch: {a.bytes_per_launch / 1e6:.1f} MB; measured / "
@@ -252,6 +261,9 @@ def main(argv=None):
     t.add_argument("--kernel", default="step_kernel")
     t.add_argument("--bytes-per-launch", type=float, required=True)
     t.add_argument("--design-bytes-per-launch", type=float, default=0.0)
+    t.add_argument("--dispatches-per-launch", type=int, default=1,
+                   help="dispatches that make one launch's work (a pool generation's "
+                        "launch groups)")
     t.add_argument("--out", required=True)
     t.add_argument("--md", required=True)
     t.add_argument("--title", default="")

@@ -1,6 +1,8 @@
 // Host-only parts of the library under sanitizers: the site rule's closed
-// form (hstrat_layout, hstrat_sites, hstrat_mrca_bounds_pair[_ex]) and the
-// Newick writer (hstrat_phylo_newick), on valid, edge and invalid inputs.
+// form (hstrat_layout, hstrat_sites, hstrat_mrca_bounds_pair[_ex]), the
+// Newick writer (hstrat_phylo_newick), on valid, edge and invalid inputs,
+// and the batched launch's dealing of tiles over the XCDs (deal_tiles,
+// checked by replaying the kernel's lookup for every workgroup).
 // Built by tests/test_host_sanitize.py twice: with AddressSanitizer and
 // UndefinedBehaviorSanitizer (every report fatal), and with
 // ThreadSanitizer, where the same calls run from eight threads at once on
@@ -18,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../include/hsga.h"
+#include "../paper_2404_10861_amd/csrc/hsga_internal.hpp"
 
 namespace hsga_host {
 static thread_local std::string g_error;
@@ -183,6 +186,57 @@ void newick_trees(int count) {
           "newick NULL");
 }
 
+// Random run sets: every workgroup b of the launch, looked up as the batched
+// kernel does (XCD b mod 8, its (b / 8)-th workgroup there), lands on a
+// tile of a run, each tile exactly once, and each run's chunks differ in
+// size by at most one.
+void dealing(int count) {
+    constexpr uint32_t X = hsga::kXcds;
+    for (int it = 0; it < count; ++it) {
+        const uint32_t n = 1 + next_word() % 70;
+        std::vector<uint32_t> tiles(n);
+        uint32_t T = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t kind = next_word() % 4;
+            tiles[i] = kind == 0 ? next_word() % 8 : (kind == 1 ? 1 + next_word() % 40
+                                                               : 1 + next_word() % 3000);
+            T += tiles[i];
+        }
+        std::vector<uint32_t> tab(2 * X * n, 0xdeadbeefu);
+        const bool ok = hsga::deal_tiles(tiles.data(), n, T, tab.data());
+        check(ok, "deal status", n, T);
+        if (!ok) continue;
+        std::vector<uint32_t> base(n + 1, 0);
+        for (uint32_t i = 0; i < n; ++i) base[i + 1] = base[i] + tiles[i];
+        std::vector<char> seen(T, 0);
+        for (uint32_t b = 0; b < T; ++b) {
+            const uint32_t x = b % X, j = b / X;
+            const uint32_t* pre = tab.data() + x * n;
+            uint32_t before = 0;
+            for (uint32_t i = 0; i < n; ++i) before += pre[i] <= j;
+            check(before >= 1, "deal lookup", b, before);
+            if (before < 1) continue;
+            const uint32_t lo = before - 1;
+            const uint32_t t = tab[(X + x) * n + lo] + (j - pre[lo]);
+            check(t < tiles[lo], "deal tile range", lo, t);
+            if (t >= tiles[lo]) continue;
+            check(!seen[base[lo] + t], "deal tile twice", lo, t);
+            seen[base[lo] + t] = 1;
+        }
+        for (uint32_t k = 0; k < T; ++k) check(seen[k], "deal tile missed", k, T);
+        for (uint32_t i = 0; i < n; ++i)
+            for (uint32_t x = 0; x < X; ++x) {
+                const uint32_t next = i + 1 < n ? tab[x * n + i + 1] : 0xffffffffu;
+                check(tab[x * n + i] <= next, "deal offsets ascending", i, x);
+                const uint32_t sz = x + 1 < X ? tab[(X + x + 1) * n + i] - tab[(X + x) * n + i]
+                                              : tiles[i] - tab[(X + x) * n + i];
+                check(sz == tiles[i] / X || sz == tiles[i] / X + 1, "deal chunk size", i, sz);
+            }
+    }
+    uint32_t one = 5, tab[16];
+    check(!hsga::deal_tiles(&one, 1, 6, tab), "deal refuses a wrong total");
+}
+
 void workload(uint64_t seed, int scale) {
     t_state = seed;
     for (const Scheme& sc : schemes()) {
@@ -191,6 +245,7 @@ void workload(uint64_t seed, int scale) {
         pairs(sc);
     }
     newick_trees(20 * scale);
+    dealing(30 * scale);
 }
 
 }  // namespace
