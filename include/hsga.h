@@ -569,8 +569,9 @@ void ga_pool_destroy(ga_pool *pool);
  * the run's stream.                                                        */
 int ga_set_kernel_timing(ga_run *run, int enable);
 
-/* Blocking: total milliseconds and number of step-kernel launches timed
- * since timing was enabled (or last reset with reset = 1).                 */
+/* Blocking: total milliseconds and number of generations stepped by the
+ * timed step-kernel launches since timing was enabled (or last reset with
+ * reset = 1); a launch of the resident form counts its generations.       */
 int ga_kernel_time(ga_run *run, double *ms, uint64_t *launches, int reset);
 
 /* A plain device-to-device copy of `bytes` bytes (multiple of 16; both
@@ -590,6 +591,21 @@ int ga_probe_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
  * Errors: GA_EINVAL.                                                       */
 int ga_set_launch_shape(ga_run *run, uint32_t block_threads,
                         uint32_t agents_per_thread);
+
+/* The resident form of a small synchronous run (on by default): when the
+ * whole torus fits one workgroup's tile (at most 4,096 agents at the run's
+ * agents per thread, on the fewest multiple of 64 threads that holds them,
+ * within 64 KiB of LDS), each launch batch of ga_step is one launch of one
+ * workgroup that takes the run through every generation of the batch,
+ * with a workgroup barrier between generations instead of a kernel
+ * boundary.  Results are the same as one launch per generation, which
+ * enable = 0 selects (the launch shape above then applies).  Asynchronous
+ * runs and runs of a pool never step resident.  Errors: GA_EINVAL.         */
+int ga_set_resident(ga_run *run, int enable);
+
+/* *threads = the resident form's workgroup size for this run, or 0 when
+ * the run steps one launch per generation.  Errors: GA_EINVAL.            */
+int ga_resident_threads(const ga_run *run, uint32_t *threads);
 
 #ifdef __cplusplus
 }

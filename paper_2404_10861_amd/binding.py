@@ -37,7 +37,7 @@ EXPORTS = (
     "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
     "ga_mrca_bounds", "ga_phylo_tree", "hstrat_mrca_bounds_noalloc",
     "hstrat_layout", "hstrat_mrca_bounds_pair", "hstrat_mrca_bounds_pair_ex", "hstrat_sites",
-    "hstrat_phylo_newick",
+    "hstrat_phylo_newick", "ga_set_resident", "ga_resident_threads",
 )
 
 
@@ -137,6 +137,8 @@ def load_library():
         "ga_kernel_time": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
         "ga_set_launch_shape": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
+        "ga_set_resident": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "ga_resident_threads": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
         "ga_probe_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
         "ga_pool_overhead_bytes": (ctypes.c_size_t, [ctypes.c_uint32]),
         "ga_pool_create": (ctypes.c_int, [_vp, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint32,
@@ -464,6 +466,18 @@ class Run(RunHandle):
 
     def set_launch_shape(self, block_threads: int = 0, agents_per_thread: int = 0):
         _check(load_library().ga_set_launch_shape(self._h, block_threads, agents_per_thread))
+
+    def set_resident(self, enable: bool = True):
+        """The resident form for a run that fits one workgroup (default on);
+        False: one launch per generation at the launch shape."""
+        _check(load_library().ga_set_resident(self._h, 1 if enable else 0))
+
+    @property
+    def resident_threads(self) -> int:
+        """Workgroup size of the resident form, 0 if the run does not use it."""
+        t = ctypes.c_uint32()
+        _check(load_library().ga_resident_threads(self._h, ctypes.byref(t)))
+        return t.value
 
     def import_state(self, state):
         """Replace this run's state by one exported from a run of the same

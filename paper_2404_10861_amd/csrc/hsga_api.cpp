@@ -346,6 +346,22 @@ int ga_step(ga_run* r, uint32_t n) {
 
 namespace {
 
+// Workgroup size of the resident form for this run: the fewest multiple of
+// 64 threads that holds every agent at the run's agents per thread, so that
+// the whole torus is one tile; 0 when the run steps one launch per
+// generation instead (the form is off, the run is asynchronous or larger
+// than kResidentMaxAgents, or the tile would not fit the LDS).
+uint32_t resident_block(const ga_run* r) {
+    if (!r->resident || r->cfg.async_activity || r->A > kResidentMaxAgents) return 0;
+    const uint32_t block = ((r->A + r->apt - 1) / r->apt + 63) / 64 * 64;
+    const uint32_t tile_isl = tile_islands(block, r->apt, r->N);
+    if (block > 1024 || tile_isl < r->I || tile_isl > block) return 0;
+    if (hsga::step_lds_bytes(tile_isl, r->N, r->SW, birth_model(r->cfg) == hsga::kBirthFloat,
+                             block, r->apt) > kMaxStepLds)
+        return 0;
+    return block;
+}
+
 int step_enqueue(ga_run* r, uint32_t n) {
     if ((uint64_t)r->T + n - 1 > r->horizon)
         return fail(GA_EHORIZON, "generation " + std::to_string((uint64_t)r->T + n - 1) +
@@ -410,10 +426,20 @@ int step_enqueue(ga_run* r, uint32_t n) {
             e = hipEventRecord(span.start, r->stream);
             if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         }
-        for (uint32_t k = 0; k < G; ++k) {
-            const hsga::StepParams p = step_params(r, r->T + k, tau0);
-            e = hsga::launch_step(p, r->SW, model, mig, r->apt, r->block, r->stream);
-            if (e != hipSuccess) return hip_fail(e, "step launch");
+        const uint32_t rb = resident_block(r);
+        if (rb) {
+            // the whole batch in one workgroup
+            hsga::StepParams p = step_params(r, r->T, tau0);
+            p.tile_isl = tile_islands(rb, r->apt, r->N);
+            e = hsga::launch_resident_step(p, G, r->sites, tau0, r->SW, model, mig, r->apt, rb,
+                                           r->stream);
+            if (e != hipSuccess) return hip_fail(e, "resident step launch");
+        } else {
+            for (uint32_t k = 0; k < G; ++k) {
+                const hsga::StepParams p = step_params(r, r->T + k, tau0);
+                e = hsga::launch_step(p, r->SW, model, mig, r->apt, r->block, r->stream);
+                if (e != hipSuccess) return hip_fail(e, "step launch");
+            }
         }
         if (r->timing) {
             e = hipEventRecord(span.stop, r->stream);
@@ -902,6 +928,18 @@ int ga_set_launch_shape(ga_run* r, uint32_t block_threads, uint32_t agents_per_t
         return fail(GA_EINVAL, "tile needs more than 64 KiB of LDS");
     r->block = block;
     r->apt = apt;
+    return GA_OK;
+}
+
+int ga_set_resident(ga_run* r, int enable) {
+    if (!r) return fail(GA_EINVAL, "run is NULL");
+    r->resident = enable != 0;
+    return GA_OK;
+}
+
+int ga_resident_threads(const ga_run* r, uint32_t* threads) {
+    if (!r || !threads) return fail(GA_EINVAL, "NULL argument");
+    *threads = resident_block(r);
     return GA_OK;
 }
 

@@ -33,6 +33,7 @@ struct ga_run {
     uint32_t block;      // workgroup threads
     bool timing;
     bool pooled = false; // a slot of a pool (its generation targets live there)
+    bool resident = true;  // a synchronous run that fits one workgroup steps resident
     bool broken = false; // a ga_step failed after enqueueing part of its work
     struct Span { hipEvent_t start, stop; uint32_t launches; };
     std::vector<Span> spans;
@@ -44,6 +45,10 @@ namespace hsga_host {
 constexpr uint32_t kDefaultGens = 4096;
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxStepLds = 65536;
+// Largest run that steps in the resident form (one workgroup for the whole
+// torus): past this many agents the generation's births on one CU take
+// longer than a launch over many CUs.
+constexpr uint32_t kResidentMaxAgents = 4096;
 
 int fail(int status, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);

@@ -140,6 +140,14 @@ hipError_t launch_set_layout(uint32_t* layout, const uint32_t* words, uint32_t S
 
 hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream);
+// The resident form: gens generations of a synchronous run whose torus is
+// one tile (p.tile_isl >= p.I at block_threads), in one workgroup, from
+// generation p.g on; sites holds the launch batch's schedule from ingest
+// tau0 (launch_run_sites).
+hipError_t launch_resident_step(const StepParams& p, uint32_t gens, const uint32_t* sites,
+                                uint32_t tau0, uint32_t SW, uint32_t birth_model, bool migration,
+                                uint32_t agents_per_thread, uint32_t block_threads,
+                                hipStream_t stream);
 
 // Batched forms.  Every run's sites for its generations T0 .. T0 + gens - 1 and its layout
 // after them (launch_run_sites per run); max_gens bounds every run's gens.

@@ -636,24 +636,61 @@ __device__ __forceinline__ void step_tile(const StepParams& p, uint32_t tile) {
         __syncthreads();
     }
 
-    // 3. births
+    // 3. births (no barrier follows, so threads without agents may skip
+    // them; the resident form's next generation waits for every thread)
     const uint32_t diff_mask = p.diff_log2 ? 0xffu : 1u;
-    if (!mine) return;
-    if constexpr (BM == kBirthFloat) draws.compute(p, j0, first_isl + il);
-    // draws onto [0, N): a shift when N is a power of two above 1 (a
-    // wave-uniform choice between two copies of the births)
-    const uint32_t n_shift = (N > 1u && (N & (N - 1u)) == 0u) ? 32u - __builtin_ctz(N) : 0u;
-    if (n_shift)
-        step_births<SW, BM, MIGR, APT, ASYNC, true>(p, first_isl, la0, il, j0, draws, site_word,
-                                                    site_shift, diff_mask, n_shift);
-    else
-        step_births<SW, BM, MIGR, APT, ASYNC, false>(p, first_isl, la0, il, j0, draws, site_word,
-                                                     site_shift, diff_mask, n_shift);
+    if (mine) {
+        if constexpr (BM == kBirthFloat) draws.compute(p, j0, first_isl + il);
+        // draws onto [0, N): a shift when N is a power of two above 1 (a
+        // wave-uniform choice between two copies of the births)
+        const uint32_t n_shift =
+            (N > 1u && (N & (N - 1u)) == 0u) ? 32u - __builtin_ctz(N) : 0u;
+        if (n_shift)
+            step_births<SW, BM, MIGR, APT, ASYNC, true>(p, first_isl, la0, il, j0, draws,
+                                                        site_word, site_shift, diff_mask, n_shift);
+        else
+            step_births<SW, BM, MIGR, APT, ASYNC, false>(p, first_isl, la0, il, j0, draws,
+                                                         site_word, site_shift, diff_mask, n_shift);
+    }
 }
 
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
 __global__ __launch_bounds__(1024) void step_kernel(const StepParams p) {
     step_tile<SW, BM, MIGR, APT, ASYNC>(p, xcd_local_block(blockIdx.x, gridDim.x));
+}
+
+// The resident form of a small synchronous run: its whole torus is one
+// tile, and one workgroup takes it through all gens generations of a launch
+// batch, with a workgroup barrier between generations where the plain form
+// has a kernel boundary.  A generation then costs neither a launch nor the
+// chip-wide cache write-back and invalidation between kernels, and its
+// planes and outboxes stay in this CU's caches.  p is generation p.g's;
+// sites holds the batch's schedule from ingest tau0.
+template <int SW, uint32_t BM, bool MIGR, int APT>
+__global__ __launch_bounds__(1024) void resident_step_kernel(StepParams p, const uint32_t gens,
+                                                            const uint32_t* __restrict__ sites,
+                                                            const uint32_t tau0) {
+    for (uint32_t k = 1;; ++k) {
+        step_tile<SW, BM, MIGR, APT, false>(p, 0u);
+        if (k == gens) break;
+        // this generation's children and emigrants are the next one's
+        // parents and immigrants: every thread's stores and LDS reads are
+        // done before any thread loads or stages again
+        __syncthreads();
+        // the ping-pong buffers swap roles (the read side is typed const)
+        uint32_t* t = const_cast<uint32_t*>(p.in_trait);
+        p.in_trait = p.out_trait;
+        p.out_trait = t;
+        t = const_cast<uint32_t*>(p.in_surf);
+        p.in_surf = p.out_surf;
+        p.out_surf = t;
+        t = const_cast<uint32_t*>(p.ob_in);
+        p.ob_in = p.ob_out;
+        p.ob_out = t;
+        ++p.g;
+        p.has_inbox = MIGR ? 1u : 0u;
+        p.site = p.g % p.interval == 0u ? sites + (p.g / p.interval - tau0) : nullptr;
+    }
 }
 
 size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW) {
@@ -668,59 +705,91 @@ size_t step_lds_bytes(uint32_t tile_isl, uint32_t N, uint32_t SW, bool float_bir
     return ((b + 15) & ~(size_t)15) + (size_t)block_threads * apt * 8;   // the draw queues
 }
 
+// rs.gens == 0: one generation over the run's tiles; otherwise the resident
+// form (rs.gens generations of a synchronous run that is one tile).
+struct Resident {
+    uint32_t gens;
+    const uint32_t* sites;
+    uint32_t tau0;
+};
+
 template <int SW, uint32_t BM, bool MIGR, int APT, bool ASYNC>
-static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, hipStream_t stream) {
+static hipError_t launch_step_t(const StepParams& p, uint32_t block_threads, const Resident& rs,
+                                hipStream_t stream) {
     if (p.tile_isl == 0 || p.tile_isl > block_threads) return hipErrorInvalidValue;
     const uint32_t tiles = (p.I + p.tile_isl - 1) / p.tile_isl;
     const size_t lds =
         step_lds_bytes(p.tile_isl, p.N, SW, BM == kBirthFloat, block_threads, APT);
-    hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT, ASYNC>), dim3(tiles), dim3(block_threads),
-                       lds, stream, p);
+    if (rs.gens) {
+        if constexpr (ASYNC) return hipErrorInvalidValue;
+        if (tiles != 1 || !rs.sites) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((resident_step_kernel<SW, BM, MIGR, APT>), dim3(1),
+                           dim3(block_threads), lds, stream, p, rs.gens, rs.sites, rs.tau0);
+    } else {
+        hipLaunchKernelGGL((step_kernel<SW, BM, MIGR, APT, ASYNC>), dim3(tiles),
+                           dim3(block_threads), lds, stream, p);
+    }
     return hipGetLastError();
 }
 
 template <int SW, uint32_t BM, bool MIGR, bool ASYNC>
 static hipError_t launch_step_apt(const StepParams& p, uint32_t apt, uint32_t block_threads,
-                                  hipStream_t stream) {
-    if (apt == 4) return launch_step_t<SW, BM, MIGR, 4, ASYNC>(p, block_threads, stream);
-    if (apt == 2) return launch_step_t<SW, BM, MIGR, 2, ASYNC>(p, block_threads, stream);
-    return launch_step_t<SW, BM, MIGR, 1, ASYNC>(p, block_threads, stream);
+                                  const Resident& rs, hipStream_t stream) {
+    if (apt == 4) return launch_step_t<SW, BM, MIGR, 4, ASYNC>(p, block_threads, rs, stream);
+    if (apt == 2) return launch_step_t<SW, BM, MIGR, 2, ASYNC>(p, block_threads, rs, stream);
+    return launch_step_t<SW, BM, MIGR, 1, ASYNC>(p, block_threads, rs, stream);
 }
 
 template <int SW, uint32_t BM, bool ASYNC>
 static hipError_t launch_step_mig(const StepParams& p, bool migration, uint32_t apt,
-                                  uint32_t block_threads, hipStream_t stream) {
-    return migration ? launch_step_apt<SW, BM, true, ASYNC>(p, apt, block_threads, stream)
-                     : launch_step_apt<SW, BM, false, ASYNC>(p, apt, block_threads, stream);
+                                  uint32_t block_threads, const Resident& rs,
+                                  hipStream_t stream) {
+    return migration ? launch_step_apt<SW, BM, true, ASYNC>(p, apt, block_threads, rs, stream)
+                     : launch_step_apt<SW, BM, false, ASYNC>(p, apt, block_threads, rs, stream);
 }
 
 template <int SW, bool ASYNC>
 static hipError_t launch_step_model(const StepParams& p, uint32_t birth_model, bool migration,
-                                    uint32_t apt, uint32_t block_threads, hipStream_t stream) {
+                                    uint32_t apt, uint32_t block_threads, const Resident& rs,
+                                    hipStream_t stream) {
     if (birth_model == kBirthFloat)
-        return launch_step_mig<SW, kBirthFloat, ASYNC>(p, migration, apt, block_threads, stream);
+        return launch_step_mig<SW, kBirthFloat, ASYNC>(p, migration, apt, block_threads, rs,
+                                                       stream);
     if (birth_model == kBirthIntTournament)
         return launch_step_mig<SW, kBirthIntTournament, ASYNC>(p, migration, apt, block_threads,
-                                                               stream);
-    return launch_step_mig<SW, kBirthIntNeutral, ASYNC>(p, migration, apt, block_threads, stream);
+                                                               rs, stream);
+    return launch_step_mig<SW, kBirthIntNeutral, ASYNC>(p, migration, apt, block_threads, rs,
+                                                        stream);
 }
 
 template <bool ASYNC>
 static hipError_t launch_step_sw(const StepParams& p, uint32_t SW, uint32_t birth_model,
                                  bool migration, uint32_t apt, uint32_t block_threads,
-                                 hipStream_t stream) {
+                                 const Resident& rs, hipStream_t stream) {
     if (SW == 1)
-        return launch_step_model<1, ASYNC>(p, birth_model, migration, apt, block_threads, stream);
-    return launch_step_model<2, ASYNC>(p, birth_model, migration, apt, block_threads, stream);
+        return launch_step_model<1, ASYNC>(p, birth_model, migration, apt, block_threads, rs,
+                                           stream);
+    return launch_step_model<2, ASYNC>(p, birth_model, migration, apt, block_threads, rs, stream);
 }
 
 hipError_t launch_step(const StepParams& p, uint32_t SW, uint32_t birth_model, bool migration,
                        uint32_t agents_per_thread, uint32_t block_threads, hipStream_t stream) {
+    const Resident none{0u, nullptr, 0u};
     if (p.async_thr)
         return launch_step_sw<true>(p, SW, birth_model, migration, agents_per_thread,
-                                    block_threads, stream);
+                                    block_threads, none, stream);
     return launch_step_sw<false>(p, SW, birth_model, migration, agents_per_thread, block_threads,
-                                 stream);
+                                 none, stream);
+}
+
+hipError_t launch_resident_step(const StepParams& p, uint32_t gens, const uint32_t* sites,
+                                uint32_t tau0, uint32_t SW, uint32_t birth_model, bool migration,
+                                uint32_t agents_per_thread, uint32_t block_threads,
+                                hipStream_t stream) {
+    if (gens == 0) return hipSuccess;
+    if (p.async_thr) return hipErrorInvalidValue;
+    return launch_step_sw<false>(p, SW, birth_model, migration, agents_per_thread, block_threads,
+                                 Resident{gens, sites, tau0}, stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -99,6 +99,7 @@ def test_extreme_parameters(hs, orc, params):
 def test_launch_shapes(hs, orc, block, apt):
     c = fcfg(hs, 9, 7, 32, 64, "hybrid", ben_thr=P_BEN * 10)
     run = hs.Run(c)
+    run.set_resident(False)        # the launch shape applies to per-generation launches
     run.set_launch_shape(block, apt)
     run.step(300)
     o = oracle_for(orc, c)

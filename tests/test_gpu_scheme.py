@@ -92,6 +92,7 @@ def test_launch_shapes(hs, orc, block, apt):
     c = cfg(hs, 9, 7, 32, 2, 8, 8, 2, seed=8)
     G = gens_for(orc, 2, 8, 2, 300)
     run = hs.Run(c)
+    run.set_resident(False)        # the launch shape applies to per-generation launches
     run.set_launch_shape(block, apt)
     run.step(G)
     o = oracle_for(orc, c)
