@@ -77,6 +77,32 @@ def test_batched_equals_alone(hs, use_graph, block, chunk):
     pool.close()
 
 
+def test_graph_replays_each_equal_direct_launches(hs):
+    """Two launch groups replayed from captured graphs on two streams,
+    advance after advance (the run set and chunk unchanged, so every
+    advance after the first replays the same graphs), with host reads
+    between replays: each replay's result equals the same pool advanced by
+    direct launches."""
+    specs = mixed_specs()
+    for s in specs:
+        s.generations = 400
+    pools = []
+    for graph in (True, False):
+        pool = hs.Pool(256 << 20, max_runs=32, max_gens_per_launch=64, block_threads=64,
+                       use_graph=graph)
+        pools.append((pool, [pool.admit(hs.Config(**s.config_kwargs()), s.generations)
+                             for s in specs]))
+    (pg, ig), (pd, idd) = pools
+    for k in range(1, 6):
+        assert pg.advance(23) == 23 and pd.advance(23) == 23
+        for a, b in zip(ig, idd):
+            ra, rb = pg.run(a), pd.run(b)
+            assert ra.generation == rb.generation == 23 * k
+            same((ra.agents(), ra.outbox(), ra.layout()), (rb.agents(), rb.outbox(), rb.layout()))
+    pg.close()
+    pd.close()
+
+
 def test_batched_matches_oracle(hs, orc):
     specs = mixed_specs()[:5]
     pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=64)
