@@ -524,7 +524,10 @@ int ga_pool_admit(ga_pool *pool, const ga_config *cfg, uint32_t n_generations,
 
 /* Enqueue up to max_gens generations of every admitted run that has not
  * reached its generation count; *gens_enqueued (may be NULL) receives the
- * largest number enqueued for any run (0 when none is active).            */
+ * largest number enqueued for any run (0 when none is active).  Errors:
+ * GA_EINVAL (a run's tile does not fit), GA_EDEVICE (a launch failed; some
+ * generations may be enqueued, and every later advance of this pool
+ * returns GA_EDEVICE).                                                    */
 int ga_pool_advance(ga_pool *pool, uint32_t max_gens, uint32_t *gens_enqueued);
 
 /* Ids of runs whose last generation has been enqueued and that were not

@@ -89,6 +89,7 @@ struct ga_pool {
     bool use_graph;
     GraphKey key;
     bool captured;                   // exec holds key's launches
+    bool broken;                     // an advance failed after enqueueing work
     hipGraphExec_t exec[kGroups];    // each group's launches, replayed on its stream
 };
 
@@ -273,6 +274,7 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
     p->block = 64;
     p->use_graph = false;
     p->captured = false;
+    p->broken = false;
     p->staged_pending = false;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_table),
                                  sizeof(hsga::BatchRun) * max_runs, hipHostMallocDefault);
@@ -350,6 +352,7 @@ int ga_pool_admit(ga_pool* p, const ga_config* in, uint32_t n_generations, uint3
 
 int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     if (!p) return fail(GA_EINVAL, "pool is NULL");
+    if (p->broken) return fail(GA_EDEVICE, "an earlier advance failed part-way");
     if (gens_enqueued) *gens_enqueued = 0;
     const uint32_t G = std::min(max_gens, p->gens);
     if (G == 0) return GA_OK;
@@ -452,7 +455,12 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     p->staged_pending = true;
 
     const int rc = enqueue_launches(p, key);
-    if (rc != GA_OK) return rc;
+    if (rc != GA_OK) {
+        // some of the runs' generations may be enqueued while their
+        // generation counts stay: no later advance can be consistent
+        p->broken = true;
+        return rc;
+    }
     for (uint32_t i = 0; i < nruns; ++i) {
         Slot& s = p->slots[active[i]];
         s.run.T += p->h_table[i].gens;
