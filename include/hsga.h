@@ -488,8 +488,9 @@ int ga_phylo_tree(ga_run *run, uint32_t n, const uint32_t *counter,
  * treatments sharing one caller-owned device arena and one stream.  An
  * advance enqueues one site-schedule launch for all active runs, then per
  * generation one step launch for each of two groups of runs of about equal
- * bytes; each run takes the same steps as under ga_step, so its results
- * are identical to running it alone.  A launch deals every run's tiles
+ * bytes (one group when a generation reads fewer trait and surface words
+ * than the split size, ga_pool_set_split); each run takes the same steps
+ * as under ga_step, so its results are identical to running it alone.  A launch deals every run's tiles
  * evenly over the chip's 8 XCDs, one contiguous chunk per XCD.  When both
  * groups hold runs, the second group's launches go to a stream the pool
  * creates, forked from the pool's stream after the site schedules and
@@ -553,6 +554,15 @@ int ga_pool_sync(ga_pool *pool);
  * launches when the run set's launch shape repeats (1) or launches
  * directly (0).                                                            */
 int ga_pool_set_launch(ga_pool *pool, uint32_t block_threads, int use_graph);
+
+/* Split size: an advance whose runs read at least min_words trait and
+ * surface words per generation (summed over the active runs) splits them
+ * into its two launch groups; smaller ones launch as one group.  Default
+ * 4 Mi words (16 MiB): below it a generation's launch is short and a
+ * second launch per generation costs more than it hides.  0 always splits
+ * (two or more active runs).  Results do not depend on it.
+ * Errors: GA_EINVAL.                                                      */
+int ga_pool_set_split(ga_pool *pool, uint64_t min_words);
 
 /* Occupancy: active runs, admitted runs, free bytes, largest free range. */
 int ga_pool_info(const ga_pool *pool, uint32_t *active, uint32_t *admitted,

@@ -37,7 +37,7 @@ EXPORTS = (
     "hstrat_mrca_bounds_ex", "hstrat_phylo_metrics_ex", "hstrat_phylo_tree_ex",
     "ga_mrca_bounds", "ga_phylo_tree", "hstrat_mrca_bounds_noalloc",
     "hstrat_layout", "hstrat_mrca_bounds_pair", "hstrat_mrca_bounds_pair_ex", "hstrat_sites",
-    "hstrat_phylo_newick", "ga_set_resident", "ga_resident_threads",
+    "hstrat_phylo_newick", "ga_set_resident", "ga_resident_threads", "ga_pool_set_split",
 )
 
 
@@ -138,6 +138,7 @@ def load_library():
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]),
         "ga_set_launch_shape": (ctypes.c_int, [_vp, ctypes.c_uint32, ctypes.c_uint32]),
         "ga_set_resident": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "ga_pool_set_split": (ctypes.c_int, [_vp, ctypes.c_uint64]),
         "ga_resident_threads": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
         "ga_probe_copy": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, _vp]),
         "ga_pool_overhead_bytes": (ctypes.c_size_t, [ctypes.c_uint32]),
@@ -534,6 +535,11 @@ class Pool:
 
     def set_launch(self, block_threads: int = 0, use_graph: bool = False):
         _check(load_library().ga_pool_set_launch(self._h, block_threads, 1 if use_graph else 0))
+
+    def set_split(self, min_words: int):
+        """Generations reading at least min_words trait and surface words
+        launch as two groups side by side (0: always)."""
+        _check(load_library().ga_pool_set_split(self._h, min_words))
 
     def footprint(self, cfg: Config) -> int:
         c = cfg.to_c()

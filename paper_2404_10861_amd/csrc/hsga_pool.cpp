@@ -31,8 +31,15 @@ struct Slot {
 // group one launch per generation on a stream of its own.  The groups'
 // runs are independent, so the streams run side by side and one group's
 // launch tail (its last, partly filled wave of workgroups, and the gap
-// before its next launch) overlaps the others' work.
+// before its next launch) overlaps the others' work.  Only generations
+// that read at least kSplitWords trait and surface words are split: below
+// that a launch is short, its tail small, and the second launch per
+// generation costs more than it hides (a served run set, about 0.5 M words
+// per generation, had its median latency 10 % longer split in two; the
+// treatment pair, 16.8 M words, and the 64-run batch, 55 M, gain).
+// ga_pool_set_split changes the threshold.
 constexpr uint32_t kGroups = 2;
+constexpr uint64_t kSplitWords = 1u << 22;
 
 // The runs of one launch: table entries first .. first + count - 1, and
 // their tiles' workgroups dealt over the XCDs in the xcd table from word
@@ -90,6 +97,7 @@ struct ga_pool {
     GraphKey key;
     bool captured;                   // exec holds key's launches
     bool broken;                     // an advance failed after enqueueing work
+    uint64_t split_words;            // generations from this size on are split
     hipGraphExec_t exec[kGroups];    // each group's launches, replayed on its stream
 };
 
@@ -275,6 +283,7 @@ int ga_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_runs,
     p->use_graph = false;
     p->captured = false;
     p->broken = false;
+    p->split_words = kSplitWords;
     p->staged_pending = false;
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_table),
                                  sizeof(hsga::BatchRun) * max_runs, hipHostMallocDefault);
@@ -371,6 +380,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
     // stream)
     uint64_t total_words = 0;
     for (uint32_t s : active) total_words += words_per_generation(p->slots[s].run);
+    const uint32_t groups = total_words >= p->split_words ? kGroups : 1u;
     if (p->staged_pending) {
         hipError_t e = hipEventSynchronize(p->staged);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
@@ -386,7 +396,7 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         ga_run& r = s.run;
         const uint64_t w = words_per_generation(r);
         const uint32_t q = (uint32_t)std::min<uint64_t>(
-            kGroups - 1, ((2 * words_before + w) * kGroups - 1) / (2 * total_words));
+            groups - 1, ((2 * words_before + w) * groups - 1) / (2 * total_words));
         words_before += w;
         Group& grp = key.grp[q];
         r.block = p->block;
@@ -519,6 +529,12 @@ int ga_pool_set_launch(ga_pool* p, uint32_t block_threads, int use_graph) {
         return fail(GA_EINVAL, "graph replay needs a created stream, not the null stream");
     p->use_graph = use_graph != 0;
     if (!p->use_graph) drop_graph(p);
+    return GA_OK;
+}
+
+int ga_pool_set_split(ga_pool* p, uint64_t min_words) {
+    if (!p) return fail(GA_EINVAL, "pool is NULL");
+    p->split_words = min_words;
     return GA_OK;
 }
 

@@ -128,8 +128,10 @@ def test_batched_mix_equals_alone(hs):
         (hs.Config(10, 10, 16, 64, "tilted", tournament_size=0, seed=5), 333),
         (fcfg(hs, 1, 1, 8, 32, "hybrid", migrants=0, seed=6), 77),
     ]
-    for use_graph in (False, True):
+    for use_graph, split in ((False, False), (True, False), (False, True), (True, True)):
         pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=64, use_graph=use_graph)
+        if split:
+            pool.set_split(0)      # two launch groups (float and integer runs apart)
         ids = {pool.admit(c, g): (c, g) for c, g in specs}
         assert None not in ids
         while pool.advance(64):

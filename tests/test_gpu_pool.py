@@ -52,12 +52,17 @@ def same(a, b):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("use_graph,block,chunk", [(False, 64, 64), (True, 64, 50),
-                                                   (False, 256, 1000), (True, 128, 17)])
-def test_batched_equals_alone(hs, use_graph, block, chunk):
+@pytest.mark.parametrize("use_graph,block,chunk,split", [
+    (False, 64, 64, True), (True, 64, 50, True), (False, 256, 1000, True), (True, 128, 17, True),
+    (False, 64, 64, False), (True, 128, 17, False)])
+def test_batched_equals_alone(hs, use_graph, block, chunk, split):
+    """split: the runs launch as two groups on two streams (these small
+    sets would otherwise launch as one)."""
     specs = mixed_specs()
     pool = hs.Pool(256 << 20, max_runs=32, max_gens_per_launch=128, block_threads=block,
                    use_graph=use_graph)
+    if split:
+        pool.set_split(0)
     ids = {}
     for s in specs:
         rid = pool.admit(hs.Config(**s.config_kwargs()), s.generations)
@@ -90,6 +95,7 @@ def test_graph_replays_each_equal_direct_launches(hs):
     for graph in (True, False):
         pool = hs.Pool(256 << 20, max_runs=32, max_gens_per_launch=64, block_threads=64,
                        use_graph=graph)
+        pool.set_split(0)          # two launch groups, though the set is small
         pools.append((pool, [pool.admit(hs.Config(**s.config_kwargs()), s.generations)
                              for s in specs]))
     (pg, ig), (pd, idd) = pools
@@ -103,9 +109,12 @@ def test_graph_replays_each_equal_direct_launches(hs):
     pd.close()
 
 
-def test_batched_matches_oracle(hs, orc):
+@pytest.mark.parametrize("split", [False, True])
+def test_batched_matches_oracle(hs, orc, split):
     specs = mixed_specs()[:5]
     pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=64)
+    if split:
+        pool.set_split(0)
     ids = {pool.admit(hs.Config(**s.config_kwargs()), s.generations): s for s in specs}
     while pool.advance(64):
         pass
