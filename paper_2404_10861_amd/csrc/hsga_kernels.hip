@@ -670,26 +670,27 @@ template <int SW, uint32_t BM, bool MIGR, int APT>
 __global__ __launch_bounds__(1024) void resident_step_kernel(StepParams p, const uint32_t gens,
                                                             const uint32_t* __restrict__ sites,
                                                             const uint32_t tau0) {
-    for (uint32_t k = 1;; ++k) {
+    for (uint32_t k = 0; k < gens; ++k) {
+        if (k > 0) {
+            // the previous generation's children and emigrants are this
+            // one's parents and immigrants: every thread's stores and LDS
+            // reads are done before any thread loads or stages again
+            __syncthreads();
+            // the ping-pong buffers swap roles (the read side is typed const)
+            uint32_t* t = const_cast<uint32_t*>(p.in_trait);
+            p.in_trait = p.out_trait;
+            p.out_trait = t;
+            t = const_cast<uint32_t*>(p.in_surf);
+            p.in_surf = p.out_surf;
+            p.out_surf = t;
+            t = const_cast<uint32_t*>(p.ob_in);
+            p.ob_in = p.ob_out;
+            p.ob_out = t;
+            ++p.g;
+            p.has_inbox = MIGR ? 1u : 0u;
+            p.site = p.g % p.interval == 0u ? sites + (p.g / p.interval - tau0) : nullptr;
+        }
         step_tile<SW, BM, MIGR, APT, false>(p, 0u);
-        if (k == gens) break;
-        // this generation's children and emigrants are the next one's
-        // parents and immigrants: every thread's stores and LDS reads are
-        // done before any thread loads or stages again
-        __syncthreads();
-        // the ping-pong buffers swap roles (the read side is typed const)
-        uint32_t* t = const_cast<uint32_t*>(p.in_trait);
-        p.in_trait = p.out_trait;
-        p.out_trait = t;
-        t = const_cast<uint32_t*>(p.in_surf);
-        p.in_surf = p.out_surf;
-        p.out_surf = t;
-        t = const_cast<uint32_t*>(p.ob_in);
-        p.ob_in = p.ob_out;
-        p.ob_out = t;
-        ++p.g;
-        p.has_inbox = MIGR ? 1u : 0u;
-        p.site = p.g % p.interval == 0u ? sites + (p.g / p.interval - tau0) : nullptr;
     }
 }
 
