@@ -110,6 +110,32 @@ def test_graph_replays_each_equal_direct_launches(hs):
 
 
 @pytest.mark.parametrize("split", [False, True])
+def test_many_tiny_runs_equal_alone(hs, split):
+    """150 runs of one to three tiles in one pool: a launch group holds
+    more than 64 runs (the run lookup takes several ballots) and most runs
+    leave most XCDs without a chunk; every run equals the same run alone."""
+    shapes = [(1, 1, 8), (2, 1, 16), (3, 2, 4), (1, 3, 32), (4, 4, 8), (2, 2, 48), (5, 1, 3)]
+    specs = []
+    for r in range(150):
+        w, h, n = shapes[r % len(shapes)]
+        specs.append(wl.RunSpec(w, h, n, (32, 64)[r % 2], ("steady", "tilted", "hybrid")[r % 3],
+                                2 if r % 4 else 0, 60 + (r * 7) % 61, seed=r + 11,
+                                name=f"tiny {r}"))
+    pool = hs.Pool(256 << 20, max_runs=160, max_gens_per_launch=64, block_threads=64)
+    if split:
+        pool.set_split(0)
+    ids = {pool.admit(hs.Config(**s.config_kwargs()), s.generations): s for s in specs}
+    assert None not in ids
+    while pool.advance(64):
+        pass
+    for rid, s in ids.items():
+        run = pool.run(rid)
+        assert run.generation == s.generations
+        same((run.agents(), run.outbox(), run.layout()), alone_state(hs, s))
+    pool.close()
+
+
+@pytest.mark.parametrize("split", [False, True])
 def test_batched_matches_oracle(hs, orc, split):
     specs = mixed_specs()[:5]
     pool = hs.Pool(64 << 20, max_runs=8, max_gens_per_launch=64)
