@@ -600,8 +600,9 @@ int ga_probe_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
  * tile of block_threads * agents_per_thread / N whole islands staged in
  * LDS (at most 64 KiB).  0 keeps the current value.  Results do not depend
  * on the shape.  A run starts at 4 agents per thread when N allows, with
- * 64 threads for integer births on two-word surfaces, 128 on one-word
- * surfaces, and 256 for float births.
+ * 64 threads for synchronous integer births on two-word surfaces, 128 for
+ * integer births on one-word surfaces or in asynchronous ticks, and 256
+ * for float births.
  * Errors: GA_EINVAL.                                                       */
 int ga_set_launch_shape(ga_run *run, uint32_t block_threads,
                         uint32_t agents_per_thread);

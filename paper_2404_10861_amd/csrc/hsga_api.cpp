@@ -179,12 +179,14 @@ int run_init(ga_run* r, const ga_config* cfg, uint8_t* base, uint32_t gens, hipS
     r->horizon = hsga::horizon_gen_of(cfg->surface_kind, r->S, cfg->ingest_interval);
     r->apt = default_agents_per_thread(r->N);
     // integer births with four agents per thread: small tiles, more
-    // workgroups in flight per CU -- 64 threads for two-word surfaces and
-    // 128 for one-word ones (3 and 4 KB of records per tile, which measured
-    // fastest: the treatment pair's selection run 3-6 % faster at 128 than
-    // at 64, the paper-scale run about 1 % slower); float births
+    // workgroups in flight per CU -- 64 threads for synchronous runs on
+    // two-word surfaces, 128 for one-word ones and for asynchronous ticks
+    // (3 to 5 KB of records per tile, which measured fastest: the treatment
+    // pair's selection run 3-6 % faster at 128 than at 64, asynchronous
+    // ticks 1.4-2.2 %, the paper-scale run about 1 % slower); float births
     // (VALU-bound) and the rest: 256 threads, which measured faster for them
-    r->block = r->apt == 4 && birth_model(*cfg) != hsga::kBirthFloat ? (r->SW == 2 ? 64u : 128u)
+    const bool narrow = r->SW == 2 && cfg->async_activity == 0;
+    r->block = r->apt == 4 && birth_model(*cfg) != hsga::kBirthFloat ? (narrow ? 64u : 128u)
                                                                         : 256u;
     r->timing = false;
     hipError_t e = hsga::launch_founders(r->trait[0], r->counter[0], r->surf[0], r->A, r->SW,
