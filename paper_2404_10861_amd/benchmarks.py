@@ -352,6 +352,25 @@ def async_vs_sync(spec, activity: float, dev, stream) -> dict:
             "counter_min": int(counters.min()), "counter_max": int(counters.max()),
             "counter_mean": float(counters.mean()),
         }
+        # the end-of-run query on a 4,096-agent sample: with drifted
+        # counters the annotations differ in age, so every pair takes the
+        # general route (per-annotation layouts, merged time lists)
+        n = 4096
+        _, cnt, srf = run.sample(n)
+        ws = hs.MrcaWorkspace(spec.surface_sites, n, dev)
+        lb = torch.empty((n, n), dtype=torch.int32, device=dev)
+        ub = torch.empty((n, n), dtype=torch.int32, device=dev)
+        run.mrca_bounds(cnt, srf, workspace=ws, lb=lb, ub=ub)      # warm-up
+        torch.cuda.synchronize(dev)
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            run.mrca_bounds(cnt, srf, workspace=ws, lb=lb, ub=ub)
+            torch.cuda.synchronize(dev)
+            best = min(best, time.perf_counter() - t0)
+        out[mode]["mrca_query_ms"] = best * 1e3
+        out[mode]["mrca_pairs_per_s"] = n * n / best
+        out[mode]["sample_counters_distinct"] = int(len(np.unique(hs.as_u32(cnt))))
         run.close()
     out["activity"] = activity
     out["ticks"] = spec.generations
