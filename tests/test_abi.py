@@ -124,6 +124,20 @@ def test_checkpoint_and_run_query_arguments_without_gpu():
     assert lib.ga_phylo_tree(None, 1, None, None, None, None, None, None, None, 0) == b.GA_EINVAL
 
 
+def test_launch_form_arguments_without_gpu():
+    """The resident-form and pool-split settings refuse NULL handles."""
+    if not os.path.exists(LIB):
+        pytest.skip("libhsga.so not built")
+    import ctypes
+    import paper_2404_10861_amd.binding as b
+    lib = b.load_library()
+    assert lib.ga_set_resident(None, 1) == b.GA_EINVAL
+    t = ctypes.c_uint32(7)
+    assert lib.ga_resident_threads(None, ctypes.byref(t)) == b.GA_EINVAL
+    assert lib.ga_pool_set_split(None, 0) == b.GA_EINVAL
+    assert b"pool is NULL" in lib.ga_last_error()
+
+
 def test_missing_library_fails_loudly():
     """No CPU fallback: without the built library every entry point of the
     binding refuses to run."""
