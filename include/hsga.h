@@ -490,9 +490,9 @@ int ga_phylo_tree(ga_run *run, uint32_t n, const uint32_t *counter,
  * generation one step launch for each of two groups of runs of about equal
  * bytes (one group when a generation reads fewer trait and surface words
  * than the split size, ga_pool_set_split); each run takes the same steps
- * as under ga_step, so its results are identical to running it alone.  A launch deals every run's tiles
- * evenly over the chip's 8 XCDs, one contiguous chunk per XCD.  When both
- * groups hold runs, the second group's launches go to a stream the pool
+ * as under ga_step, so its results are identical to running it alone.  A
+ * launch deals every run's tiles evenly over the chip's 8 XCDs, one
+ * contiguous chunk per XCD.  When both groups hold runs, the second group's launches go to a stream the pool
  * creates, forked from the pool's stream after the site schedules and
  * joined back to it at the end of the advance, so that the groups run side
  * by side.  Admission is by footprint: a run gets a first-fit range of the

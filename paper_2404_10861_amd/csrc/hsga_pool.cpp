@@ -401,7 +401,8 @@ int ga_pool_advance(ga_pool* p, uint32_t max_gens, uint32_t* gens_enqueued) {
         Group& grp = key.grp[q];
         r.block = p->block;
         const uint32_t g = std::min(G, s.target - r.T);
-        const hsga::StepParams sp = step_params(&r, r.T, hsga::ingests_of(r.T, r.cfg.ingest_interval));
+        const hsga::StepParams sp =
+            step_params(&r, r.T, hsga::ingests_of(r.T, r.cfg.ingest_interval));
         // the island pass takes one island per thread
         if (sp.tile_isl == 0 || sp.tile_isl > p->block)
             return fail(GA_EINVAL, "tile has more islands than the workgroup has threads");
