@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_c2_traffic.json")
+SQ_FILE = os.path.join(ROOT, "profiles", "step_kernel_c2_sq_counters.json")
 
 
 def algorithmic_bytes_per_generation(spec) -> int:
@@ -81,6 +82,24 @@ def measured_traffic(spec):
     if rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def measured_valu():
+    """The step kernel's VALU figures from the committed rocprofv3 SQ
+    counter summary, or None when it is absent or the kernel changed since."""
+    if not os.path.exists(SQ_FILE):
+        return None
+    with open(SQ_FILE) as f:
+        rec = json.load(f)
+    from paper_2404_10861_amd.profiling import kernel_hash
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return {"issue_estimate": rec["valu_issue_estimate"],
+            "instructions_per_wave": rec["valu_instructions_per_wave"],
+            "resident_waves_per_simd": rec["resident_waves_per_simd"],
+            "wave_time_waiting": rec["wave_time_waiting"],
+            "source": "profiles/step_kernel_c2_sq_counters.json (rocprofv3 SQ counters; "
+                      "issue estimate counts 4 cycles per VALU instruction)"}
 
 
 def attainable_copy_gbs(torch, hs, dev, stream, nbytes: int = 512 << 20, reps: int = 10):
@@ -480,6 +499,7 @@ def main(argv=None) -> int:
             "traffic_GBs": traffic / avg_launch_s / 1e9 if traffic else None,
             "traffic_frac_of_attainable":
                 traffic / avg_launch_s / 1e9 / copy_gbs if traffic else None,
+            "valu": measured_valu(),
         },
         "context": {
             "paper_cs2_replications_per_s": 3.18e11,

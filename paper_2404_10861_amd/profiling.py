@@ -244,6 +244,13 @@ def cmd_sq(a):
     with open(a.md, "w") as f:
         f.write("\n".join(lines))
     print("\n".join(lines))
+    if a.json:
+        rec = {"kernel": a.kernel, "kernel_names": names, "kernel_hash": kernel_hash(),
+               "valu_issue_estimate": valu, "valu_instructions_per_wave": per_wave,
+               "resident_waves_per_simd": waves, "wave_time_waiting": wait,
+               "medians_per_dispatch": vals, "commands": a.cmd}
+        with open(a.json, "w") as f:
+            json.dump(rec, f, indent=1)
 
 
 def main(argv=None):
@@ -280,6 +287,7 @@ def main(argv=None):
     q.add_argument("dirs", nargs="+")
     q.add_argument("--kernel", required=True)
     q.add_argument("--md", required=True)
+    q.add_argument("--json", default="", help="also write the figures as JSON")
     q.add_argument("--title", default="")
     q.add_argument("--cmd", action="append", default=[])
     a = ap.parse_args(argv)

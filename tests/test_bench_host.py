@@ -57,6 +57,19 @@ def test_traffic_is_reported_only_for_the_profiled_code(monkeypatch):
     assert bench.measured_traffic(wl.c2()) is None
 
 
+def test_valu_is_reported_only_for_the_profiled_code(monkeypatch):
+    import bench
+    from paper_2404_10861_amd import profiling
+    with open(bench.SQ_FILE) as f:
+        rec = json.load(f)
+    assert 0 < rec["valu_issue_estimate"] < 1.5 and rec["valu_instructions_per_wave"] > 100
+    monkeypatch.setattr(profiling, "kernel_hash", lambda sources=None: rec["kernel_hash"])
+    v = bench.measured_valu()
+    assert v["issue_estimate"] == rec["valu_issue_estimate"]
+    monkeypatch.setattr(profiling, "kernel_hash", lambda sources=None: "0" * 16)
+    assert bench.measured_valu() is None
+
+
 def test_code_hash_ignores_comments_and_layout_only(tmp_path):
     from paper_2404_10861_amd import profiling
     texts = {
